@@ -1,0 +1,184 @@
+"""Right-Jacobi preconditioned Krylov solvers in complex128.
+
+Part of the CPU oracle (test infrastructure only).
+
+Paper Sec. 4 solves the acoustic system with preconditioned Krylov methods
+(P-BiCGSTAB among them) in complex double precision; the preconditioner
+type is not stated.  Readings taken here:
+
+* Preconditioner: Jacobi, ``D = diag(A)`` (complex), applied on the right,
+  so the iteration runs on ``A D^-1 u = f`` with ``x = D^-1 u`` and the
+  residual it tracks is the true residual ``f - A x``.
+* Stop when the true relative residual ``||f - A x|| / ||f||`` reaches
+  ``tol``; it is recomputed before returning.
+* Inner products ``<a, b> = a^H b``.
+
+GMRES(m) is restarted GMRES with modified Gram-Schmidt Arnoldi and complex
+Givens rotations: for a column pair (a, b), ``rho = sqrt(|a|^2 + |b|^2)``,
+``c = |a| / rho``, ``s = (a/|a|) conj(b) / rho`` (``c = 0, s = 1`` when
+``a = 0``), which maps (a, b) to (a/|a| rho, 0).  A happy breakdown
+(zero subdiagonal) ends the cycle.
+
+BiCGStab is van der Vorst's stabilised bi-conjugate gradient method with
+shadow residual ``r^ = r0``, an early exit when ``||s||`` is small, and a
+restart with ``r^ = r`` when ``rho`` or ``omega`` breaks down.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+class Result:
+    def __init__(self, x, status, iters, matvecs, relres, history):
+        self.x, self.status, self.iters, self.matvecs = x, status, iters, matvecs
+        self.relres, self.history = relres, history
+
+    def __repr__(self):
+        return (f"Result(status={self.status}, iters={self.iters}, "
+                f"matvecs={self.matvecs}, relres={self.relres:.3e})")
+
+
+def _dinv(A, precond):
+    n = A.shape[0]
+    if precond == "jacobi":
+        return 1.0 / A.diagonal().astype(np.complex128)
+    return np.ones(n, dtype=np.complex128)
+
+
+def givens(a, b):
+    """Complex Givens pair (c real, s complex) zeroing b against a."""
+    rho = np.sqrt(abs(a) ** 2 + abs(b) ** 2)
+    if rho == 0.0:
+        return 1.0, 0.0 + 0.0j
+    if a == 0:
+        return 0.0, 1.0 + 0.0j
+    return abs(a) / rho, (a / abs(a)) * np.conj(b) / rho
+
+
+def gmres(A, f, m=30, tol=1e-8, max_matvec=20000, x0=None, precond="jacobi",
+          record_cycles=False):
+    f = np.asarray(f, dtype=np.complex128)
+    n = f.size
+    dinv = _dinv(A, precond)
+    x = np.zeros(n, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128)
+    nf = np.linalg.norm(f)
+    matvecs, iters, hist, cycles = 0, 0, [], []
+    if nf == 0.0:
+        return Result(np.zeros(n, dtype=np.complex128), 0, 0, 0, 0.0, hist)
+    status = 1
+    while True:
+        r = f - A @ x
+        matvecs += 1
+        beta = np.linalg.norm(r)
+        hist.append(beta / nf)
+        if beta / nf <= tol:
+            status = 0
+            break
+        if matvecs >= max_matvec:
+            break
+        V = np.zeros((m + 1, n), dtype=np.complex128)
+        H = np.zeros((m + 1, m), dtype=np.complex128)
+        cs = np.zeros(m)
+        sn = np.zeros(m, dtype=np.complex128)
+        g = np.zeros(m + 1, dtype=np.complex128)
+        g[0] = beta
+        V[0] = r / beta
+        k = 0
+        cyc = []
+        for j in range(m):
+            w = A @ (dinv * V[j])
+            matvecs += 1
+            iters += 1
+            for i in range(j + 1):
+                H[i, j] = np.vdot(V[i], w)
+                w = w - H[i, j] * V[i]
+            hnext = np.linalg.norm(w)
+            H[j + 1, j] = hnext
+            for i in range(j):
+                a, b = H[i, j], H[i + 1, j]
+                H[i, j] = cs[i] * a + sn[i] * b
+                H[i + 1, j] = -np.conj(sn[i]) * a + cs[i] * b
+            cs[j], sn[j] = givens(H[j, j], H[j + 1, j])
+            H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+            H[j + 1, j] = 0.0
+            g[j + 1] = -np.conj(sn[j]) * g[j]
+            g[j] = cs[j] * g[j]
+            k = j + 1
+            cyc.append(abs(g[j + 1]) / nf)
+            if hnext == 0.0 or abs(g[j + 1]) / nf <= tol or matvecs >= max_matvec:
+                break
+            V[j + 1] = w / hnext
+        y = np.zeros(k, dtype=np.complex128)
+        for i in range(k - 1, -1, -1):
+            y[i] = (g[i] - H[i, i + 1:k] @ y[i + 1:k]) / H[i, i]
+        x = x + dinv * (V[:k].T @ y)
+        cycles.append(cyc)
+    res = Result(x, status, iters, matvecs, np.linalg.norm(f - A @ x) / nf, hist)
+    if record_cycles:
+        res.cycles = cycles
+    return res
+
+
+def bicgstab(A, f, tol=1e-8, max_matvec=20000, x0=None, precond="jacobi",
+             max_iters=None):
+    f = np.asarray(f, dtype=np.complex128)
+    n = f.size
+    dinv = _dinv(A, precond)
+    x = np.zeros(n, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128)
+    nf = np.linalg.norm(f)
+    if nf == 0.0:
+        return Result(np.zeros(n, dtype=np.complex128), 0, 0, 0, 0.0, [])
+    matvecs, iters, hist, status = 0, 0, [], 1
+    while status != 0:
+        # (re)start from the true residual of the current iterate
+        r = f - A @ x
+        matvecs += 1
+        hist.append(np.linalg.norm(r) / nf)
+        if hist[-1] <= tol:
+            status = 0
+            break
+        rhat = r.copy()
+        rho_old = alpha = omega = 1.0 + 0.0j
+        v = np.zeros(n, dtype=np.complex128)
+        p = np.zeros(n, dtype=np.complex128)
+        done = False
+        while matvecs + 2 <= max_matvec:
+            if max_iters is not None and iters >= max_iters:
+                break
+            rho = np.vdot(rhat, r)
+            if abs(rho) < 1e-300 * np.linalg.norm(rhat) * np.linalg.norm(r) or omega == 0:
+                rhat = r.copy()
+                rho = np.vdot(rhat, r)
+                rho_old = alpha = omega = 1.0 + 0.0j
+                v[:] = 0
+                p[:] = 0
+            beta = (rho / rho_old) * (alpha / omega)
+            p = r + beta * (p - omega * v)
+            phat = dinv * p
+            v = A @ phat
+            matvecs += 1
+            alpha = rho / np.vdot(rhat, v)
+            s = r - alpha * v
+            iters += 1
+            if np.linalg.norm(s) / nf <= tol:
+                x = x + alpha * phat
+                hist.append(np.linalg.norm(s) / nf)
+                done = True
+                break
+            shat = dinv * s
+            t = A @ shat
+            matvecs += 1
+            tt = np.vdot(t, t)
+            omega = np.vdot(t, s) / tt if tt != 0 else 0.0
+            x = x + alpha * phat + omega * shat
+            r = s - omega * t
+            rho_old = rho
+            hist.append(np.linalg.norm(r) / nf)
+            if hist[-1] <= tol:
+                done = True
+                break
+        if not done:
+            break
+        # recursive residual says converged: the outer loop re-checks the true one
+    rel = np.linalg.norm(f - A @ x) / nf
+    return Result(x, 0 if rel <= tol else 1, iters, matvecs, rel, hist)

@@ -1,0 +1,175 @@
+"""Pins of the oracle's finite-element assembly against closed forms.
+
+Each check here comes from the mathematics of Q1 elements on a box, not from
+the oracle itself: Kronecker closed forms of the element matrices, the exact
+discrete eigenvectors of the rigid box, an exact 1-D reduction of the full
+3-D solve, and the O(h^2) convergence to a manufactured plane wave.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import direct, fem, helmholtz as H
+
+pytestmark = pytest.mark.cpu
+
+
+def M1(h):
+    return (h / 6.0) * np.array([[2.0, 1.0], [1.0, 2.0]])
+
+
+def K1(h):
+    return (1.0 / h) * np.array([[1.0, -1.0], [-1.0, 1.0]])
+
+
+def test_p1_element_matrices_closed_form():
+    hx, hy, hz = 0.37, 0.21, 0.55
+    X = np.array([[[a * hx, b * hy, c * hz] for c in range(2) for b in range(2) for a in range(2)]],
+                 dtype=float)
+    # reorder to local index a + 2b + 4c
+    X = np.array([[[((i >> 0) & 1) * hx, ((i >> 1) & 1) * hy, ((i >> 2) & 1) * hz] for i in range(8)]])
+    Ke, Me = fem.hex_matrices(X + np.array([0.3, -1.1, 2.0]))
+    Mref = np.kron(M1(hz), np.kron(M1(hy), M1(hx)))
+    Kref = (np.kron(M1(hz), np.kron(M1(hy), K1(hx))) + np.kron(M1(hz), np.kron(K1(hy), M1(hx)))
+            + np.kron(K1(hz), np.kron(M1(hy), M1(hx))))
+    assert np.allclose(Me[0], Mref, rtol=1e-15, atol=1e-15 * abs(Mref).max())
+    assert np.allclose(Ke[0], Kref, rtol=1e-14, atol=1e-14 * abs(Kref).max())
+    # a face in the y-z plane (x = const): in-plane axes y (fast), z
+    Xf = np.array([[[0.7, ((i >> 0) & 1) * hy, ((i >> 1) & 1) * hz] for i in range(4)]])
+    Fe = fem.quad_mass(Xf)
+    assert np.allclose(Fe[0], np.kron(M1(hz), M1(hy)), rtol=1e-15, atol=1e-16)
+
+
+def test_p1_element_matrices_affine_rotation_invariant():
+    # mass and stiffness of a rotated box element equal those of the unrotated one
+    hx, hy, hz = 0.2, 0.3, 0.4
+    X = np.array([[((i >> 0) & 1) * hx, ((i >> 1) & 1) * hy, ((i >> 2) & 1) * hz] for i in range(8)])
+    th = 0.7
+    R = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1.0]])
+    K0, M0 = fem.hex_matrices(X[None])
+    K1_, M1_ = fem.hex_matrices((X @ R.T)[None])
+    assert np.allclose(K0, K1_, atol=1e-13)
+    assert np.allclose(M0, M1_, atol=1e-15)
+
+
+@pytest.mark.parametrize("elems", [(20, 12, 10), (5, 3, 4)])
+def test_p2_assembly_invariants(elems):
+    mesh = W.box_mesh(*elems)
+    asm = fem.assemble(mesh)
+    K, M = asm["K"], asm["M"]
+    for Mat in [K, M, asm["Mpatch"]] + asm["B0"]:
+        assert (Mat != Mat.T).nnz == 0           # bitwise symmetric
+    ones = np.ones(mesh["n_nodes"])
+    assert np.abs(K @ ones).max() <= 1e-14 * np.abs(K.data).max()
+    assert abs(M.sum() - 1.8 * 1.2 * 1.0) < 1e-12
+    areas = [1.2, 1.2, 1.8, 1.8, 2.16, 2.16]
+    for w in range(6):
+        assert abs(asm["B0"][w].sum() - areas[w]) < 1e-12
+    nx, ny, nz = elems
+    assert K.nnz == (3 * nx + 1) * (3 * ny + 1) * (3 * nz + 1)
+    # source patch: quads whose centroid lies in [0.6,1.2] x [0.3,0.9]
+    hx, hy = 1.8 / nx, 1.2 / ny
+    cx = (np.arange(nx) + 0.5) * hx
+    cy = (np.arange(ny) + 0.5) * hy
+    area = (((cx >= 0.6) & (cx <= 1.2)).sum() * hx) * (((cy >= 0.3) & (cy <= 0.9)).sum() * hy)
+    assert abs(asm["Mpatch"].sum() - area) < 1e-12
+
+
+def test_p2_patch_sizes_of_workloads():
+    m = W.box_mesh(20, 12, 10)
+    assert W.patch_nodes(m).size == 49
+    asm = fem.assemble(m)
+    assert abs(asm["Mpatch"].sum() - 0.54 * 0.60) < 1e-12
+    m2 = W.box_mesh(80, 48, 40)
+    assert W.patch_nodes(m2).size == 675
+
+
+@pytest.mark.parametrize("elems,modes", [((20, 12, 10), [(1, 0, 0), (0, 1, 0), (2, 1, 3)]),
+                                         ((7, 5, 3), [(1, 1, 1), (3, 0, 2)])])
+def test_p3_discrete_rigid_box_modes(elems, modes):
+    mesh = W.box_mesh(*elems)
+    asm = fem.assemble(mesh)
+    K, M = asm["K"], asm["M"]
+    h = mesh["h"]
+    for m in modes:
+        vecs, lam = [], 0.0
+        for d in range(3):
+            N = elems[d]
+            th = m[d] * np.pi / N
+            vecs.append(np.cos(th * np.arange(N + 1)))
+            lam += (6.0 / h[d] ** 2) * (1.0 - np.cos(th)) / (2.0 + np.cos(th))
+        v = np.kron(vecs[2], np.kron(vecs[1], vecs[0]))
+        Kv, Mv = K @ v, M @ v
+        assert np.linalg.norm(Kv - lam * Mv) <= 1e-12 * max(np.linalg.norm(Kv), np.linalg.norm(lam * Mv), 1e-300) + 1e-13
+
+
+def test_p3_first_mode_frequency_c0():
+    # discrete (1,0,0) mode of the 20x12x10 mesh: 94.54 Hz vs continuum 94.44 Hz
+    h = 1.8 / 20
+    th = np.pi / 20
+    lam = (6.0 / h ** 2) * (1 - np.cos(th)) / (2 + np.cos(th))
+    f = 340.0 * np.sqrt(lam) / (2 * np.pi)
+    assert abs(f - 94.54) < 0.01
+    assert abs(340.0 / (2 * 1.8) - 94.444) < 1e-3
+
+
+def _one_d_exact(N, h, k, g0, beta_xplus):
+    """Exact nodal solution of the 1-D Q1 problem (K - k^2 M + i k beta e_N e_N^T) p = g0 e_0,
+    built from the closed-form interior recurrence p_j = a cos(th (N-j)) + b sin(th (N-j))."""
+    a2 = (k * h) ** 2
+    th = np.arccos((1.0 - a2 / 3.0) / (1.0 + a2 / 6.0))
+    j = np.arange(N + 1)
+    C = np.cos(th * (N - j)).astype(complex)
+    S = np.sin(th * (N - j)).astype(complex)
+
+    def row0(v):
+        return (v[0] - v[1]) / h - k * k * h / 6.0 * (2 * v[0] + v[1])
+
+    def rowN(v):
+        return (v[N] - v[N - 1]) / h - k * k * h / 6.0 * (2 * v[N] + v[N - 1]) + 1j * k * beta_xplus * v[N]
+
+    Msys = np.array([[row0(C), row0(S)], [rowN(C), rowN(S)]])
+    ab = np.linalg.solve(Msys, np.array([g0, 0.0], dtype=complex))
+    return ab[0] * C + ab[1] * S
+
+
+@pytest.mark.parametrize("beta_xplus", [0.0, 0.3 + 0.1j])
+def test_p4_exact_one_d_reduction(beta_xplus):
+    nx, ny, nz = 12, 3, 2
+    mesh = W.box_mesh(nx, ny, nz)
+    beta = np.zeros(6, dtype=complex)
+    beta[1] = beta_xplus
+    S = H.System(mesh, beta)
+    k = W.wavenumber(120.0)
+    A = S.operator(k)
+    g0 = 0.7 - 0.4j
+    f = S.asm["B0"][0] @ np.full(mesh["n_nodes"], g0)
+    p = direct.SparseLU(A).solve(f)
+    exact = _one_d_exact(nx, 1.8 / nx, k, g0, beta_xplus)
+    i = np.arange(mesh["n_nodes"]) % (nx + 1)
+    assert np.abs(p - exact[i]).max() <= 1e-10 * np.abs(exact).max()
+    pb = direct.banded_solve(A, f, mesh["xyz"])
+    assert np.abs(pb - exact[i]).max() <= 1e-10 * np.abs(exact).max()
+
+
+def test_p5_manufactured_plane_wave_second_order():
+    d = np.array([1.0, 2.0, 2.0]) / 3.0
+    k = W.wavenumber(200.0)
+    beta = np.array([0.5, 0.4 + 0.1j, 0.3, 0.2 - 0.05j, 0.6, 0.45])
+    normals = [(-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
+    errs = []
+    for lev in range(3):
+        s = 2 ** lev
+        mesh = W.box_mesh(9 * s, 6 * s, 5 * s)
+        S = H.System(mesh, beta)
+        pex = np.exp(-1j * k * (mesh["xyz"] @ d))
+        f = np.zeros(mesh["n_nodes"], dtype=complex)
+        for w in range(6):
+            # dp/dn + i k beta p = g on wall w, with dp/dn = -i k (d.n) p
+            gw = 1j * k * (beta[w] - d @ np.array(normals[w], float)) * pex
+            f += S.asm["B0"][w] @ gw
+        p = direct.SparseLU(S.operator(k)).solve(f)
+        errs.append(np.abs(p - pex).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(rates - 2.0) < 0.2), (errs, rates)
