@@ -1,0 +1,256 @@
+/*
+ * hz.h -- C ABI of the MI355X (gfx950) complex Helmholtz solver library.
+ *
+ * The library solves the finite-element Helmholtz system of the acoustic
+ * part of the paper (Sec. 3.2: Fourier transform of the homogeneous wave
+ * equation gives  -w^2 psi - c^2 lap(psi) = 0, discretised by finite
+ * elements on the compartment mesh), with the solver components of its
+ * Sec. 4: a CSR-type sparse matrix in complex double precision, a
+ * sparse matrix-vector product, rewritten basic linear-algebra kernels,
+ * preconditioned Krylov methods (BiCGStab; restarted GMRES is added), and
+ * a non-overlapping Schwarz domain decomposition with Robin (absorbing)
+ * transmission conditions.
+ *
+ * Discrete problem.  On Q1 (trilinear hexahedral) elements, with
+ * k = 2 pi freq / c:
+ *
+ *     A(k) p = f,   A(k) = K - k^2 M + i k^2 M_eta + i k B_beta
+ *
+ *     K_ab      = int grad(phi_a).grad(phi_b)          (stiffness)
+ *     M_ab      = int phi_a phi_b                      (mass)
+ *     M_eta     = sum_e eta_e M_e                      (absorption field)
+ *     B_beta    = sum_w beta_w B0_w, B0_w,ab = int_{wall w} phi_a phi_b
+ *     f         = M_patch g   (Neumann data g on the source faces)
+ *
+ * beta_w is the normalised outward admittance of wall w (Re beta >= 0
+ * absorbs), eta_e a per-element loss factor (element wavenumber squared
+ * k^2 (1 - i eta_e)).  A is complex symmetric (A^T = A).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Return value: HZ_OK (0) on success; > 0: a result was written but is
+ *    flagged (not converged, breakdown); < 0: error, nothing was written.
+ *    hz_last_error() gives a message for the calling thread.
+ *  - Pointers named *_dev are device pointers (HIP global memory of the
+ *    context's device), owned by the caller, contiguous, 16-byte aligned
+ *    for complex data.  All other pointers are host pointers, owned by the
+ *    caller, only read during the call unless stated.
+ *  - Complex numbers are pairs of IEEE doubles (re, im), the element layout
+ *    of std::complex<double> and torch.complex128.
+ *  - Node ids and ordering of every vector are the caller's node order.
+ *  - Work is ordered on the HIP stream given to hz_assemble (0 = the null
+ *    stream).  Entry points that return an info struct or host scalars
+ *    synchronise that stream before returning.
+ *  - One context must not be used by two threads at the same time.
+ */
+#ifndef HZ_H_
+#define HZ_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } hz_c128;
+
+typedef struct hz_ctx_s* hz_ctx;
+
+enum {
+  HZ_OK = 0,
+  HZ_NOT_CONVERGED = 1,   /* best iterate written; tolerance not reached  */
+  HZ_BREAKDOWN = 2,       /* best iterate written; Krylov breakdown       */
+  HZ_ERR_INVALID = -1,    /* null pointer, bad size, NaN/Inf input        */
+  HZ_ERR_HIP = -2,        /* HIP runtime error                            */
+  HZ_ERR_OOM = -3,        /* device allocation failed                     */
+  HZ_ERR_STATE = -4       /* call order violated (e.g. no frequency set)  */
+};
+
+enum { HZ_GMRES = 0, HZ_BICGSTAB = 1, HZ_SCHWARZ = 2 };
+enum { HZ_FP64 = 0, HZ_MIXED = 1 };
+enum { HZ_JACOBI = 0, HZ_NONE = 1 };
+
+/* Mesh of trilinear hexahedra.  All arrays are host arrays read during
+ * hz_assemble only.
+ *   xyz       [n_nodes][3]   node coordinates (m)
+ *   hex       [n_elems][8]   element nodes in tensor order: local node
+ *                            a + 2 b + 4 c sits at reference corner
+ *                            (2a-1, 2b-1, 2c-1)
+ *   bface     [n_bfaces][4]  boundary quads, tensor order a + 2 b
+ *   bface_tag [n_bfaces]     wall id 0..5 (x-, x+, y-, y+, z-, z+)
+ *   bface_src [n_bfaces]     1 = the face carries the source (Neumann) datum
+ *   c, rho                   speed of sound (m/s); rho is stored only
+ *   parts[3]                 structured partition counts along x, y, z for
+ *                            the Schwarz method (0 = not used); requires the
+ *                            mesh to be a structured box with node id
+ *                            i + (nx+1) (j + (ny+1) k) and elems[3] set
+ *   elems[3]                 element counts of a structured box (or 0)    */
+typedef struct {
+  int32_t n_nodes, n_elems, n_bfaces;
+  const double* xyz;
+  const int32_t* hex;
+  const int32_t* bface;
+  const int32_t* bface_tag;
+  const uint8_t* bface_src;
+  double c, rho;
+  int32_t elems[3];
+  int32_t parts[3];
+} hz_mesh;
+
+/* Solver options (host struct).
+ *   method      HZ_GMRES, HZ_BICGSTAB or HZ_SCHWARZ
+ *   restart     GMRES restart length m (1..128)
+ *   max_matvec  cap on operator applications (>= 1)
+ *   precision   HZ_FP64: complex128 throughout.  HZ_MIXED: complex64 inner
+ *               Krylov solves on a complex64 copy of the operator, with the
+ *               residual, iterative refinement, Gram-Schmidt coefficients
+ *               and the Hessenberg/Givens step in FP64.
+ *   precond     HZ_JACOBI (right diagonal scaling) or HZ_NONE
+ *   tol         stop when ||f - A p||_2 / ||f||_2 <= tol (true residual,
+ *               recomputed in FP64 at exit)
+ *   inner_tol   relative tolerance of inner (mixed / subdomain) solves
+ *   inner_restart  GMRES restart of the inner complex64 solves
+ *   dd_alpha    Robin transmission coefficient of the Schwarz method
+ *               (0 + 0i selects the default i k)
+ *   dd_inner    inner Krylov method of the Schwarz local solves            */
+typedef struct {
+  int32_t method;
+  int32_t restart;
+  int32_t max_matvec;
+  int32_t precision;
+  int32_t precond;
+  int32_t inner_restart;
+  double tol;
+  double inner_tol;
+  hz_c128 dd_alpha;
+  int32_t dd_inner;
+  int32_t reserved;
+} hz_solve_opts;
+
+/* Filled by the solve entry points.
+ *   status       same code as the return value
+ *   iters        Krylov iterations (GMRES: Arnoldi steps; BiCGStab:
+ *                iterations of two matvecs; Schwarz: interface iterations)
+ *   matvecs      operator applications at the outer precision
+ *   inner_matvecs  complex64 / subdomain operator applications
+ *   relres_true  ||f - A p|| / ||f|| recomputed in FP64 at exit
+ *   relres_est   the solver's own residual estimate at exit
+ *   seconds      wall time of the call                                    */
+typedef struct {
+  int32_t status, iters, matvecs, inner_matvecs;
+  double relres_true, relres_est, seconds;
+} hz_solve_info;
+
+/* Builds the context: assembles K, M, the per-wall boundary masses B0_w,
+ * the source-face mass M_patch and (if eta != NULL) M_eta on the host from
+ * Q1 elements with 2x2x2 (cells) / 2x2 (faces) Gauss points (paper Sec. 3.2,
+ * finite-element discretisation of the Helmholtz equation), then uploads the
+ * sparse pattern (sliced-ELL, 64-row slices, int32 column indices) and the
+ * values to the device of the calling thread.
+ *   beta   [6] wall admittances (host)
+ *   eta    [n_elems] loss factors (host) or NULL (= zero field)
+ *   hip_stream  hipStream_t to order all work on (NULL = null stream)
+ *   out    receives the context; *out is NULL on error
+ * Errors: HZ_ERR_INVALID (null/invalid mesh, index out of range, NaN),
+ * HZ_ERR_OOM, HZ_ERR_HIP. */
+int hz_assemble(const hz_mesh* mesh, const hz_c128* beta, const double* eta,
+                void* hip_stream, hz_ctx* out);
+
+/* Replaces the wall admittances and/or the absorption field (either may be
+ * NULL to keep it).  Invalidates the current frequency (HZ_ERR_STATE on the
+ * next solve until hz_set_frequency is called again). */
+int hz_set_params(hz_ctx ctx, const hz_c128* beta, const double* eta);
+
+/* Forms A(k) for k = 2 pi freq_hz / c on the device (one pass over the
+ * nonzeros) and its diagonal; later solves and hz_apply use it.
+ * freq_hz must be finite and >= 0.  Errors: HZ_ERR_INVALID, HZ_ERR_HIP. */
+int hz_set_frequency(hz_ctx ctx, double freq_hz);
+
+/* y_dev = A(k) x_dev, complex128, n_nodes entries each (the sparse
+ * matrix-vector product of paper Sec. 4).  x and y must not overlap.
+ * Errors: HZ_ERR_STATE (no frequency set), HZ_ERR_INVALID (null). */
+int hz_apply(hz_ctx ctx, const hz_c128* x_dev, hz_c128* y_dev);
+
+/* Copies diag(A(k)) (n_nodes complex128) to d_dev. */
+int hz_get_diag(hz_ctx ctx, hz_c128* d_dev);
+
+/* f_dev = M_patch g_dev: the load of a Neumann datum g (nodal values,
+ * n_nodes complex128) on the source faces. */
+int hz_load(hz_ctx ctx, const hz_c128* g_dev, hz_c128* f_dev);
+
+/* *out = a^H b over n complex128 entries, accumulated in FP64 with a fixed
+ * reduction order (bitwise reproducible run to run).  Host result. */
+int hz_dotc(hz_ctx ctx, int64_t n, const hz_c128* a_dev, const hz_c128* b_dev,
+            hz_c128* out);
+
+/* Solves A(k) p = f at the current frequency (paper Sec. 4: preconditioned
+ * Krylov methods and the optimised Schwarz method, complex double).
+ *   f_dev  [n_nodes] right-hand side (not modified)
+ *   p_dev  [n_nodes] in: initial guess x0, out: solution (may be all zero)
+ *   info   may be NULL
+ * Returns HZ_OK, HZ_NOT_CONVERGED (max_matvec reached; best iterate in
+ * p_dev), HZ_BREAKDOWN, or an error (HZ_ERR_INVALID for bad options,
+ * null pointers or a non-finite f; HZ_ERR_STATE if no frequency is set). */
+int hz_solve(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* f_dev,
+             hz_c128* p_dev, hz_solve_info* info);
+
+/* Frequency sweep: solves A(k_j) P[:, j] = F[:, j] for j < nfreq (1..64)
+ * with all columns advanced together: one multi-vector sparse product per
+ * Krylov step shares the real K, M (and M_eta) values across columns, and
+ * each restart cycle of the inner solve is replayed from a captured HIP
+ * graph.  The tile shape of the multi-vector product is chosen by a
+ * built-in autotuner at first use for (n, nfreq, precision).
+ *   freqs_host [nfreq] Hz
+ *   F_dev, P_dev  [n_nodes][nfreq] row-major complex128 (column j of row i
+ *          at i * nfreq + j); P is in: x0 (zero allowed), out: solutions
+ *   infos  [nfreq] per-column results (may be NULL)
+ * opts->method must be HZ_GMRES; opts->precision HZ_MIXED (complex64 inner
+ * GMRES + FP64 refinement) or HZ_FP64.  Leaves the context's current
+ * frequency unset (call hz_set_frequency before the next hz_solve). */
+int hz_solve_sweep(hz_ctx ctx, int32_t nfreq, const double* freqs_host,
+                   const hz_c128* F_dev, hz_c128* P_dev,
+                   const hz_solve_opts* opts, hz_solve_info* infos);
+
+/* Adjoint solve and gradient at the current frequency.  With the forward
+ * solution p (A p = f) and the objective's derivative g = dJ/dconj(p)
+ * (for J = sum_r |p_r|^2: g = p on the receivers, 0 elsewhere), solves
+ * A^H lambda = g (as A mu = conj(g), lambda = conj(mu), A being complex
+ * symmetric) and accumulates
+ *     dJ_dbeta[w][0] += 2 k Im(lambda^H B0_w p)      (d/d Re beta_w)
+ *     dJ_dbeta[w][1] += 2 k Re(lambda^H B0_w p)      (d/d Im beta_w)
+ *     dJ_deta_dev[e] += 2 k^2 Im(lambda_e^H M_e p_e)
+ * where J's derivative in a real parameter t is -2 Re(lambda^H dA/dt p).
+ *   p_dev, g_dev    [n_nodes] device inputs
+ *   lambda_dev      [n_nodes] device output (adjoint state)
+ *   dJ_dbeta        [6][2] host, accumulated (may be NULL)
+ *   dJ_deta_dev     [n_elems] device FP64, accumulated (may be NULL)     */
+int hz_solve_adjoint(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* p_dev,
+                     const hz_c128* g_dev, hz_c128* lambda_dev, double* dJ_dbeta,
+                     double* dJ_deta_dev, hz_solve_info* info);
+
+/* Measurement of the sparse product (paper Sec. 4: the product dominates
+ * the solve time).  Runs y = A x of the current operator `reps` times
+ * (1..100000) on the context's stream, bracketed by two HIP events recorded
+ * on that stream, and returns the average duration of one product in
+ * milliseconds.  precision HZ_FP64 times the complex128 product used by
+ * hz_apply and the FP64 solvers; HZ_MIXED the complex64 product of the
+ * mixed-precision inner solves.  x and y are internal buffers.  Host result;
+ * synchronises the stream. */
+int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, double* avg_ms);
+
+/* Sizes of the context: n_nodes, n_elems, stored nonzeros (CSR count),
+ * and the device bytes the context holds. */
+int hz_sizes(hz_ctx ctx, int64_t* n_nodes, int64_t* n_elems, int64_t* nnz,
+             int64_t* device_bytes);
+
+/* Frees the context and its device memory (NULL is ignored). */
+void hz_destroy(hz_ctx ctx);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* hz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HZ_H_ */

@@ -1,0 +1,252 @@
+// Host assembly of the Q1 Helmholtz matrices (paper Sec. 3.2: finite-element
+// discretisation of the Helmholtz equation on the compartment mesh).
+//
+// Rows are assembled independently (row i gathers the element rows of the
+// hexahedra around node i, in ascending element id), which parallelises over
+// threads without write conflicts and sums every entry (i,j) and (j,i) from
+// the same terms in the same order: K, M, M_eta and the wall masses come out
+// bitwise symmetric.
+#include <algorithm>
+#include <cstdarg>
+#include <thread>
+#include <unordered_map>
+
+#include "ctx.h"
+#include "q1.h"
+
+namespace {
+
+template <class F>
+void parallel_for(int64_t n, F f) {
+  unsigned hc = std::thread::hardware_concurrency();
+  int nt = int(hc == 0 ? 1 : (hc > 16 ? 16 : hc));
+  if (n < 20000 || nt == 1) {
+    f(int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  int64_t chunk = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    int64_t b = t * chunk, e = std::min(n, b + chunk);
+    if (b >= e) break;
+    th.emplace_back([=, &f] { f(b, e); });
+  }
+  for (auto& x : th) x.join();
+}
+
+inline int64_t find_col(const HostAsm& a, int32_t row, int32_t col) {
+  const int32_t* b = a.col.data() + a.rowptr[row];
+  const int32_t* e = a.col.data() + a.rowptr[row + 1];
+  const int32_t* p = std::lower_bound(b, e, col);
+  if (p == e || *p != col) return -1;
+  return p - a.col.data();
+}
+
+void gather_hex(const HostAsm& a, int32_t e, double X[8][3]) {
+  for (int l = 0; l < 8; ++l) {
+    int32_t v = a.hex[int64_t(e) * 8 + l];
+    for (int d = 0; d < 3; ++d) X[l][d] = a.xyz[int64_t(v) * 3 + d];
+  }
+}
+
+void assemble_rows(HostAsm& a, const double* eta, bool km) {
+  parallel_for(a.n, [&](int64_t r0, int64_t r1) {
+    for (int64_t i = r0; i < r1; ++i) {
+      for (int64_t q = a.rowptr[i]; q < a.rowptr[i + 1]; ++q) {
+        if (km) { a.K[q] = 0.0; a.M[q] = 0.0; }
+        if (eta) a.Meta[q] = 0.0;
+      }
+      for (int64_t t = a.n2e_ptr[i]; t < a.n2e_ptr[i + 1]; ++t) {
+        int32_t e = a.n2e[t];
+        int loc = -1;
+        for (int l = 0; l < 8; ++l)
+          if (a.hex[int64_t(e) * 8 + l] == int32_t(i)) { loc = l; break; }
+        double X[8][3], Kr[8], Mr[8];
+        gather_hex(a, e, X);
+        q1::hex_rows(X, loc, Kr, Mr);
+        for (int b = 0; b < 8; ++b) {
+          int64_t pos = find_col(a, int32_t(i), a.hex[int64_t(e) * 8 + b]);
+          if (km) { a.K[pos] += Kr[b]; a.M[pos] += Mr[b]; }
+          if (eta) a.Meta[pos] += eta[e] * Mr[b];
+        }
+      }
+    }
+  });
+}
+
+}  // namespace
+
+int host_assemble_meta(HostAsm* a, const double* eta) {
+  if (!eta) {
+    a->Meta.clear();
+    return HZ_OK;
+  }
+  for (int64_t e = 0; e < a->ne; ++e)
+    if (!std::isfinite(eta[e])) return hz_fail(HZ_ERR_INVALID, "eta[%lld] is not finite", (long long)e);
+  a->Meta.assign(a->col.size(), 0.0);
+  assemble_rows(*a, eta, false);
+  return HZ_OK;
+}
+
+int host_assemble(const hz_mesh* m, const double* eta, HostAsm* out) {
+  HostAsm& a = *out;
+  if (!m || !m->xyz || !m->hex || m->n_nodes <= 0 || m->n_elems <= 0 || m->n_bfaces < 0 ||
+      (m->n_bfaces > 0 && (!m->bface || !m->bface_tag || !m->bface_src)))
+    return hz_fail(HZ_ERR_INVALID, "hz_assemble: null or empty mesh arrays");
+  a.n = m->n_nodes;
+  a.ne = m->n_elems;
+  a.nb = m->n_bfaces;
+  a.xyz.assign(m->xyz, m->xyz + int64_t(a.n) * 3);
+  a.hex.assign(m->hex, m->hex + int64_t(a.ne) * 8);
+  for (double v : a.xyz)
+    if (!std::isfinite(v)) return hz_fail(HZ_ERR_INVALID, "hz_assemble: non-finite coordinate");
+  for (int32_t v : a.hex)
+    if (v < 0 || v >= a.n) return hz_fail(HZ_ERR_INVALID, "hz_assemble: element node %d out of range", v);
+  if (a.nb > 0) {
+    a.bface.assign(m->bface, m->bface + int64_t(a.nb) * 4);
+    a.btag.assign(m->bface_tag, m->bface_tag + a.nb);
+    a.bsrc.assign(m->bface_src, m->bface_src + a.nb);
+    for (int32_t v : a.bface)
+      if (v < 0 || v >= a.n) return hz_fail(HZ_ERR_INVALID, "hz_assemble: face node %d out of range", v);
+    for (int32_t t : a.btag)
+      if (t < 0 || t > 5) return hz_fail(HZ_ERR_INVALID, "hz_assemble: wall tag %d not in 0..5", t);
+  }
+
+  // node -> element adjacency, ascending element id
+  a.n2e_ptr.assign(int64_t(a.n) + 1, 0);
+  for (int32_t v : a.hex) a.n2e_ptr[v + 1]++;
+  for (int64_t i = 0; i < a.n; ++i) a.n2e_ptr[i + 1] += a.n2e_ptr[i];
+  a.n2e.assign(a.n2e_ptr[a.n], 0);
+  {
+    std::vector<int64_t> fill(a.n2e_ptr.begin(), a.n2e_ptr.end() - 1);
+    for (int64_t e = 0; e < a.ne; ++e)
+      for (int l = 0; l < 8; ++l) a.n2e[fill[a.hex[e * 8 + l]]++] = int32_t(e);
+  }
+  for (int64_t i = 0; i < a.n; ++i)
+    if (a.n2e_ptr[i + 1] == a.n2e_ptr[i])
+      return hz_fail(HZ_ERR_INVALID, "hz_assemble: node %lld belongs to no element", (long long)i);
+
+  // CSR pattern: union of the nodes of the elements around each node
+  std::vector<int32_t> cnt(a.n);
+  auto row_nodes = [&](int64_t i, int32_t* buf) {
+    int c = 0;
+    for (int64_t t = a.n2e_ptr[i]; t < a.n2e_ptr[i + 1]; ++t)
+      for (int l = 0; l < 8; ++l) buf[c++] = a.hex[int64_t(a.n2e[t]) * 8 + l];
+    std::sort(buf, buf + c);
+    return int(std::unique(buf, buf + c) - buf);
+  };
+  int64_t maxdeg = 0;
+  for (int64_t i = 0; i < a.n; ++i) maxdeg = std::max(maxdeg, a.n2e_ptr[i + 1] - a.n2e_ptr[i]);
+  parallel_for(a.n, [&](int64_t r0, int64_t r1) {
+    std::vector<int32_t> buf(maxdeg * 8);
+    for (int64_t i = r0; i < r1; ++i) cnt[i] = row_nodes(i, buf.data());
+  });
+  a.rowptr.assign(int64_t(a.n) + 1, 0);
+  for (int64_t i = 0; i < a.n; ++i) a.rowptr[i + 1] = a.rowptr[i] + cnt[i];
+  if (a.rowptr[a.n] >= (int64_t(1) << 31) - (int64_t(a.n) * 64))
+    return hz_fail(HZ_ERR_INVALID, "hz_assemble: %lld nonzeros exceed the int32 index range",
+                   (long long)a.rowptr[a.n]);
+  a.col.assign(a.rowptr[a.n], 0);
+  parallel_for(a.n, [&](int64_t r0, int64_t r1) {
+    std::vector<int32_t> buf(maxdeg * 8);
+    for (int64_t i = r0; i < r1; ++i) {
+      int c = row_nodes(i, buf.data());
+      std::copy(buf.data(), buf.data() + c, a.col.data() + a.rowptr[i]);
+    }
+  });
+  a.diag.assign(a.n, -1);
+  for (int64_t i = 0; i < a.n; ++i) a.diag[i] = find_col(a, int32_t(i), int32_t(i));
+
+  // values
+  a.K.assign(a.col.size(), 0.0);
+  a.M.assign(a.col.size(), 0.0);
+  if (eta) {
+    for (int64_t e = 0; e < a.ne; ++e)
+      if (!std::isfinite(eta[e])) return hz_fail(HZ_ERR_INVALID, "eta[%lld] is not finite", (long long)e);
+    a.Meta.assign(a.col.size(), 0.0);
+  }
+  assemble_rows(a, eta, true);
+  for (int64_t i = 0; i < a.n; ++i)
+    if (!(a.K[a.diag[i]] > 0.0) || !(a.M[a.diag[i]] > 0.0))
+      return hz_fail(HZ_ERR_INVALID, "hz_assemble: degenerate element at node %lld (inverted or flat)",
+                     (long long)i);
+
+  // wall boundary masses: entry slots in CSR order of first touch by the faces
+  std::unordered_map<int64_t, int32_t> slot;
+  a.bpos.clear();
+  a.bmass.clear();
+  std::map<int64_t, double> patch;   // (row * n + col) -> value
+  for (int64_t f = 0; f < a.nb; ++f) {
+    double X[4][3], Fe[4][4];
+    for (int l = 0; l < 4; ++l)
+      for (int d = 0; d < 3; ++d) X[l][d] = a.xyz[int64_t(a.bface[f * 4 + l]) * 3 + d];
+    q1::quad_mass(X, Fe);
+    for (int l = 0; l < 4; ++l)
+      for (int o = 0; o < 4; ++o) {
+        int32_t r = a.bface[f * 4 + l], c = a.bface[f * 4 + o];
+        int64_t pos = find_col(a, r, c);
+        if (pos < 0) return hz_fail(HZ_ERR_INVALID, "hz_assemble: boundary face %lld is not an element face", (long long)f);
+        auto it = slot.find(pos);
+        int32_t s;
+        if (it == slot.end()) {
+          s = int32_t(a.bpos.size());
+          slot.emplace(pos, s);
+          a.bpos.push_back(pos);
+          a.bmass.insert(a.bmass.end(), 6, 0.0);
+        } else {
+          s = it->second;
+        }
+        a.bmass[int64_t(s) * 6 + a.btag[f]] += Fe[l][o];
+        if (a.bsrc[f]) patch[int64_t(r) * a.n + c] += Fe[l][o];
+      }
+  }
+  // patch CSR over its rows
+  a.prow.clear(); a.pptr.assign(1, 0); a.pcol.clear(); a.pval.clear();
+  int64_t last = -1;
+  for (auto& kv : patch) {
+    int64_t r = kv.first / a.n;
+    if (r != last) {
+      if (last >= 0) a.pptr.push_back(int32_t(a.pcol.size()));
+      a.prow.push_back(int32_t(r));
+      last = r;
+    }
+    a.pcol.push_back(int32_t(kv.first % a.n));
+    a.pval.push_back(kv.second);
+  }
+  if (last >= 0) a.pptr.push_back(int32_t(a.pcol.size()));
+  return HZ_OK;
+}
+
+void build_sell(const HostAsm& a, int64_t nrows, SellHost* s) {
+  s->n_rows = int32_t(nrows);
+  s->n_slices = ceil_div(nrows, kWave);
+  s->ptr.assign(int64_t(s->n_slices) + 1, 0);
+  for (int32_t sl = 0; sl < s->n_slices; ++sl) {
+    int64_t w = 0;
+    for (int l = 0; l < kWave; ++l) {
+      int64_t i = int64_t(sl) * kWave + l;
+      if (i < a.n) w = std::max(w, a.rowptr[i + 1] - a.rowptr[i]);
+    }
+    s->ptr[sl + 1] = s->ptr[sl] + int32_t(w * kWave);
+  }
+  s->n_pad = s->ptr[s->n_slices];
+  s->col.assign(s->n_pad, 0);
+  s->src.assign(s->n_pad, -1);
+  for (int32_t sl = 0; sl < s->n_slices; ++sl) {
+    int64_t w = (s->ptr[sl + 1] - s->ptr[sl]) / kWave;
+    for (int l = 0; l < kWave; ++l) {
+      int64_t i = int64_t(sl) * kWave + l;
+      for (int64_t k = 0; k < w; ++k) {
+        int64_t p = s->ptr[sl] + k * kWave + l;
+        if (i >= a.n) {
+          s->col[p] = 0;
+        } else if (a.rowptr[i] + k < a.rowptr[i + 1]) {
+          s->col[p] = a.col[a.rowptr[i] + k];
+          s->src[p] = a.rowptr[i] + k;
+        } else {
+          s->col[p] = int32_t(i);
+        }
+      }
+    }
+  }
+}

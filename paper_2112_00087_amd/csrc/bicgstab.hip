@@ -1,0 +1,346 @@
+// Stabilised bi-conjugate gradient method (the paper's P-BiCGSTAB, Sec. 4)
+// on the right-Jacobi operator, for every segment of a segmented system.
+//
+// One iteration of van der Vorst's method is five vector kernels (two of
+// them sparse products with fused inner-product epilogues) and four
+// one-block-per-segment finalize kernels that turn block partials into the
+// Krylov scalars.  The scalars never leave the device; the host only reads
+// the per-segment state every few iterations to decide whether to stop.
+// Every kernel first reads its segment's flags and returns if that segment
+// has converged, so extra queued iterations cost only empty launches.
+#include <chrono>
+
+#include "ops.h"
+
+namespace {
+
+struct BiSt {
+  z_t rho, rho_old, alpha, omega;
+  double rr, ss, thr2, rhat2;
+  int iter, done, early, reset;
+  int nan, pad0;
+};
+
+template <typename T>
+struct BiV {
+  const cx<T>* f;
+  cx<T>* u;
+  cx<T>* r;
+  cx<T>* rhat;
+  cx<T>* p;
+  cx<T>* v;
+  cx<T>* s;
+  cx<T>* t;
+};
+
+template <typename T> __device__ __forceinline__ z_t zd(cx<T> a) { return ccast<double>(a); }
+template <typename T> __device__ __forceinline__ cx<T> zt(z_t a) { return ccast<T>(a); }
+
+// r = f - A u; restart: rhat = r, p = v = 0.  Partial ||r||^2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_resid(Seg L, SellOp<T> A, BiV<T> V, double* part) {
+  Tile t = tile_of(L);
+  z_t y = zd(sell_row(A, t.row, V.u));
+  z_t r = zd(V.f[t.row]) - y;
+  cx<T> rs = zt<T>(r);
+  V.r[t.row] = rs;
+  V.rhat[t.row] = rs;
+  V.p[t.row] = cx<T>{T(0), T(0)};
+  V.v[t.row] = cx<T>{T(0), T(0)};
+  z_t rr = zd(rs);
+  double q[1] = {norm2(rr)};
+  store_partials<1>(q, part, t.tile);
+}
+
+__global__ void k_resid_fin(Seg L, BiSt* st, const double* part) {
+  int s = blockIdx.x;
+  double rr = seg_sum<1>(L, part, s, 0);
+  if (threadIdx.x == 0) {
+    BiSt& S = st[s];
+    S.rr = rr;
+    S.rho = z_t{rr, 0.0};
+    S.rho_old = S.alpha = S.omega = z_t{1.0, 0.0};
+    S.rhat2 = rr;
+    S.early = 0;
+    S.reset = 0;
+    S.nan = !isfinite(rr);
+    S.done = (rr <= S.thr2) || S.nan;
+  }
+}
+
+// p = r + beta (p - omega v), beta = (rho / rho_old) (alpha / omega); on reset rhat = p = r.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_p(Seg L, const BiSt* st, BiV<T> V) {
+  Tile t = tile_of(L);
+  const BiSt& S = st[t.seg];
+  if (S.done) return;
+  cx<T> r = V.r[t.row];
+  if (S.reset) {
+    V.rhat[t.row] = r;
+    V.p[t.row] = r;
+    return;
+  }
+  z_t beta = cdiv(S.rho, S.rho_old) * cdiv(S.alpha, S.omega);
+  z_t p = zd(V.p[t.row]) - S.omega * zd(V.v[t.row]);
+  V.p[t.row] = zt<T>(zd(r) + beta * p);
+}
+
+// v = A p; partial rhat^H v.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_v(Seg L, SellOp<T> A, const BiSt* st, BiV<T> V, double* part) {
+  Tile t = tile_of(L);
+  if (st[t.seg].done) return;
+  cx<T> y = sell_row(A, t.row, V.p);
+  V.v[t.row] = y;
+  z_t a = zd(V.rhat[t.row]), b = zd(y);
+  double q[2] = {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+  store_partials<2>(q, part, t.tile);
+}
+
+__global__ void k_alpha_fin(Seg L, BiSt* st, const double* part) {
+  int s = blockIdx.x;
+  if (st[s].done) return;
+  double re = seg_sum<2>(L, part, s, 0);
+  double im = seg_sum<2>(L, part, s, 1);
+  if (threadIdx.x == 0) {
+    BiSt& S = st[s];
+    S.reset = 0;
+    z_t rv = {re, im};
+    if (norm2(rv) == 0.0 || !isfinite(re) || !isfinite(im)) {
+      S.alpha = z_t{0.0, 0.0};   // minimal-residual step this iteration, restart after it
+      S.reset = 1;
+    } else {
+      S.alpha = cdiv(S.rho, rv);
+    }
+  }
+}
+
+// s = r - alpha v; partial ||s||^2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_s(Seg L, const BiSt* st, BiV<T> V, double* part) {
+  Tile t = tile_of(L);
+  const BiSt& S = st[t.seg];
+  if (S.done) return;
+  z_t s = zd(V.r[t.row]) - S.alpha * zd(V.v[t.row]);
+  cx<T> ss = zt<T>(s);
+  V.s[t.row] = ss;
+  double q[1] = {norm2(zd(ss))};
+  store_partials<1>(q, part, t.tile);
+}
+
+__global__ void k_s_fin(Seg L, BiSt* st, const double* part) {
+  int s = blockIdx.x;
+  if (st[s].done) return;
+  double ss = seg_sum<1>(L, part, s, 0);
+  if (threadIdx.x == 0) {
+    st[s].ss = ss;
+    st[s].early = (ss <= st[s].thr2) ? 1 : 0;
+  }
+}
+
+// t = A s; partials t^H s, t^H t.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_t(Seg L, SellOp<T> A, const BiSt* st, BiV<T> V, double* part) {
+  Tile t = tile_of(L);
+  const BiSt& S = st[t.seg];
+  if (S.done || S.early) return;
+  cx<T> y = sell_row(A, t.row, V.s);
+  V.t[t.row] = y;
+  z_t a = zd(y), b = zd(V.s[t.row]);
+  double q[3] = {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re, norm2(a)};
+  store_partials<3>(q, part, t.tile);
+}
+
+__global__ void k_omega_fin(Seg L, BiSt* st, const double* part) {
+  int s = blockIdx.x;
+  if (st[s].done || st[s].early) return;
+  double re = seg_sum<3>(L, part, s, 0);
+  double im = seg_sum<3>(L, part, s, 1);
+  double tt = seg_sum<3>(L, part, s, 2);
+  if (threadIdx.x == 0) st[s].omega = (tt > 0.0) ? z_t{re / tt, im / tt} : z_t{0.0, 0.0};
+}
+
+// u += alpha p + omega s; r = s - omega t; partials rhat^H r, ||r||^2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_xr(Seg L, const BiSt* st, BiV<T> V, double* part) {
+  Tile t = tile_of(L);
+  const BiSt& S = st[t.seg];
+  if (S.done) return;
+  z_t u = zd(V.u[t.row]) + S.alpha * zd(V.p[t.row]);
+  if (S.early) {
+    V.u[t.row] = zt<T>(u);
+    return;
+  }
+  z_t s = zd(V.s[t.row]);
+  V.u[t.row] = zt<T>(u + S.omega * s);
+  cx<T> r = zt<T>(s - S.omega * zd(V.t[t.row]));
+  V.r[t.row] = r;
+  z_t a = zd(V.rhat[t.row]), b = zd(r);
+  double q[3] = {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re, norm2(b)};
+  store_partials<3>(q, part, t.tile);
+}
+
+__global__ void k_rho_fin(Seg L, BiSt* st, const double* part) {
+  int s = blockIdx.x;
+  BiSt& S = st[s];
+  const int done = S.done, early = S.early;
+  __syncthreads();   // every thread has read the flags before thread 0 rewrites them
+  if (done) return;
+  if (early) {
+    if (threadIdx.x == 0) {
+      S.iter += 1;
+      S.rr = S.ss;
+      S.done = 1;
+      S.early = 0;
+    }
+    return;
+  }
+  double re = seg_sum<3>(L, part, s, 0);
+  double im = seg_sum<3>(L, part, s, 1);
+  double rr = seg_sum<3>(L, part, s, 2);
+  if (threadIdx.x == 0) {
+    S.iter += 1;
+    S.rho_old = S.rho;
+    S.rho = z_t{re, im};
+    S.rr = rr;
+    if (!isfinite(rr) || !isfinite(re) || !isfinite(im)) {
+      S.nan = 1;
+      S.done = 1;
+    } else if (rr <= S.thr2) {
+      S.done = 1;
+    } else if (sqrt(norm2(S.rho)) < 1e-300 * sqrt(S.rhat2 * rr) || norm2(S.omega) == 0.0) {
+      // breakdown: restart the shadow residual from the current residual
+      S.reset = 1;
+      S.rho = z_t{rr, 0.0};
+      S.rho_old = S.alpha = S.omega = z_t{1.0, 0.0};
+      S.rhat2 = rr;
+    }
+  }
+}
+
+__global__ void k_set_thr(int nseg, BiSt* st, const double* fn2, double tol, int reset_iter) {
+  int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= nseg) return;
+  st[s].thr2 = tol * tol * fn2[s];
+  if (reset_iter) st[s].iter = 0;
+}
+
+}  // namespace
+
+template <typename T>
+int bicgstab_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, cx<T>* u,
+                 const KrylovCtl& ctl, KrylovOut* out, const std::string& tag) {
+  int rc = 0;
+  const int64_t nr = S.nrows;
+  const size_t vb = sizeof(cx<T>) * nr;
+  const std::string p = "bicg." + tag + (sizeof(T) == 8 ? ".z." : ".c.");
+  BiV<T> V;
+  V.f = f;
+  V.u = u;
+  cx<T>** vecs[6] = {&V.r, &V.rhat, &V.p, &V.v, &V.s, &V.t};
+  const char* names[6] = {"r", "rhat", "p", "v", "s", "t"};
+  for (int i = 0; i < 6; ++i) {
+    DevBuf* b = ctx->buf(p + names[i], vb, &rc);
+    if (rc) return rc;
+    *vecs[i] = b->as<cx<T>>();
+  }
+  DevBuf* stb = ctx->buf(p + "st", sizeof(BiSt) * S.nseg, &rc);
+  if (rc) return rc;
+  DevBuf* part = ctx->buf(p + "part", sizeof(double) * 3 * S.nblk, &rc);
+  if (rc) return rc;
+  DevBuf* fnb = ctx->buf(p + "fn2", sizeof(double) * S.nseg, &rc);
+  if (rc) return rc;
+  BiSt* st = stb->as<BiSt>();
+  double* pt = part->as<double>();
+  hipStream_t s = ctx->stream;
+  const Seg& L = S.dev;
+
+  // ||f||^2 per segment -> thresholds
+  std::vector<double> fn2;
+  HZ_TRY(seg_norm2_t<T>(ctx, S, f, &fn2));
+  out->fnorm.resize(S.nseg);
+  for (int i = 0; i < S.nseg; ++i) out->fnorm[i] = std::sqrt(fn2[i]);
+  HZ_HIP(hipMemcpyAsync(fnb->p, fn2.data(), sizeof(double) * S.nseg, hipMemcpyHostToDevice, s));
+  HZ_HIP(hipMemsetAsync(stb->p, 0, sizeof(BiSt) * S.nseg, s));
+  k_set_thr<<<ceil_div(S.nseg, kBlock), kBlock, 0, s>>>(S.nseg, st, fnb->as<double>(), ctl.tol, 1);
+  HZ_HIP(hipGetLastError());
+
+  void* hp = nullptr;
+  HZ_TRY(ctx_pinned(ctx, sizeof(BiSt) * S.nseg, &hp));
+  BiSt* hst = static_cast<BiSt*>(hp);
+  const int grid = S.nblk;
+  std::vector<int> restarts(S.nseg, 0);
+  int64_t resid_calls = 0;
+  int chunk = 4;
+
+  auto read_state = [&]() -> int {
+    HZ_HIP(hipMemcpyAsync(hst, st, sizeof(BiSt) * S.nseg, hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    return HZ_OK;
+  };
+  auto enqueue_resid = [&]() -> int {
+    k_resid<T><<<grid, kBlock, 0, s>>>(L, A, V, pt);
+    k_resid_fin<<<S.nseg, kBlock, 0, s>>>(L, st, pt);
+    HZ_HIP(hipGetLastError());
+    ++resid_calls;
+    return HZ_OK;
+  };
+  auto enqueue_iter = [&]() -> int {
+    k_p<T><<<grid, kBlock, 0, s>>>(L, st, V);
+    k_v<T><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    k_alpha_fin<<<S.nseg, kBlock, 0, s>>>(L, st, pt);
+    k_s<T><<<grid, kBlock, 0, s>>>(L, st, V, pt);
+    k_s_fin<<<S.nseg, kBlock, 0, s>>>(L, st, pt);
+    k_t<T><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    k_omega_fin<<<S.nseg, kBlock, 0, s>>>(L, st, pt);
+    k_xr<T><<<grid, kBlock, 0, s>>>(L, st, V, pt);
+    k_rho_fin<<<S.nseg, kBlock, 0, s>>>(L, st, pt);
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+  };
+
+  HZ_TRY(enqueue_resid());
+  HZ_TRY(read_state());
+  for (;;) {
+    bool all_done = true;
+    int max_iter = 0;
+    for (int i = 0; i < S.nseg; ++i) {
+      all_done = all_done && hst[i].done;
+      max_iter = std::max(max_iter, hst[i].iter);
+    }
+    int64_t mv = 2 * int64_t(max_iter) + resid_calls;
+    if (all_done) {
+      // the recursive residuals say converged: confirm with the true residual
+      // (a fresh residual also restarts any segment that drifted)
+      HZ_TRY(enqueue_resid());
+      HZ_TRY(read_state());
+      bool ok = true;
+      for (int i = 0; i < S.nseg; ++i) ok = ok && hst[i].done;
+      if (ok || mv + 1 >= ctl.max_matvec) break;
+      continue;
+    }
+    if (mv + 2 > ctl.max_matvec) break;
+    int n_it = int(std::min<int64_t>(chunk, (ctl.max_matvec - mv) / 2));
+    if (n_it < 1) break;
+    for (int it = 0; it < n_it; ++it) HZ_TRY(enqueue_iter());
+    HZ_TRY(read_state());
+    chunk = std::min(chunk * 2, 64);
+  }
+  out->iters.resize(S.nseg);
+  out->matvecs.resize(S.nseg);
+  out->status.resize(S.nseg);
+  out->relres_est.resize(S.nseg);
+  for (int i = 0; i < S.nseg; ++i) {
+    out->iters[i] = hst[i].iter;
+    out->matvecs[i] = 2 * hst[i].iter + int(resid_calls);
+    double fnv = out->fnorm[i];
+    out->relres_est[i] = fnv > 0 ? std::sqrt(hst[i].rr) / fnv : 0.0;
+    out->status[i] = hst[i].nan ? HZ_BREAKDOWN : (hst[i].done ? HZ_OK : HZ_NOT_CONVERGED);
+  }
+  return HZ_OK;
+}
+
+template int bicgstab_run<double>(hz_ctx, const SegHost&, const SellOp<double>&, const z_t*, z_t*,
+                                  const KrylovCtl&, KrylovOut*, const std::string&);
+template int bicgstab_run<float>(hz_ctx, const SegHost&, const SellOp<float>&, const c_t*, c_t*,
+                                 const KrylovCtl&, KrylovOut*, const std::string&);

@@ -1,0 +1,263 @@
+// extern "C" entry points of the library (declared and documented in hz.h).
+// No C++ exception crosses this boundary.
+#include <chrono>
+#include <new>
+
+#include "ops.h"
+#include "solve.h"
+
+const char* hz_last_error_str();
+int schwarz_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* f, z_t* p, hz_solve_info* info);
+int sweep_solve(hz_ctx ctx, int nfreq, const double* freqs, const z_t* F, z_t* P, const hz_solve_opts& o,
+                hz_solve_info* infos);
+int adjoint_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* p, const z_t* g, z_t* lam, double* dJ_dbeta,
+                  double* dJ_deta, hz_solve_info* info);
+
+#define HZ_GUARD_BEGIN try {
+#define HZ_GUARD_END                                                          \
+  }                                                                           \
+  catch (const std::bad_alloc&) {                                             \
+    return hz_fail(HZ_ERR_OOM, "host allocation failed");                     \
+  }                                                                           \
+  catch (...) {                                                               \
+    return hz_fail(HZ_ERR_INVALID, "unexpected exception in the library");    \
+  }
+
+int validate_opts(const hz_solve_opts* o) {
+  if (!o) return hz_fail(HZ_ERR_INVALID, "opts is NULL");
+  if (o->method < HZ_GMRES || o->method > HZ_SCHWARZ) return hz_fail(HZ_ERR_INVALID, "unknown method %d", o->method);
+  if (o->precision != HZ_FP64 && o->precision != HZ_MIXED)
+    return hz_fail(HZ_ERR_INVALID, "unknown precision %d", o->precision);
+  if (o->precond != HZ_JACOBI && o->precond != HZ_NONE) return hz_fail(HZ_ERR_INVALID, "unknown precond %d", o->precond);
+  if ((o->method == HZ_GMRES || o->method == HZ_SCHWARZ) && (o->restart < 1 || o->restart > 128))
+    return hz_fail(HZ_ERR_INVALID, "restart %d not in 1..128", o->restart);
+  if (o->max_matvec < 1) return hz_fail(HZ_ERR_INVALID, "max_matvec must be >= 1");
+  if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return hz_fail(HZ_ERR_INVALID, "tol must be finite and > 0");
+  if (!(o->inner_tol >= 0.0) || !std::isfinite(o->inner_tol)) return hz_fail(HZ_ERR_INVALID, "bad inner_tol");
+  if (o->inner_restart < 0 || o->inner_restart > 128) return hz_fail(HZ_ERR_INVALID, "inner_restart not in 0..128");
+  return HZ_OK;
+}
+
+static int check_ctx(hz_ctx ctx) {
+  if (!ctx) return hz_fail(HZ_ERR_INVALID, "ctx is NULL");
+  int dev = -1;
+  HZ_HIP(hipGetDevice(&dev));
+  if (dev != ctx->device) HZ_HIP(hipSetDevice(ctx->device));
+  return HZ_OK;
+}
+
+extern "C" {
+
+const char* hz_last_error(void) { return hz_last_error_str(); }
+
+int hz_assemble(const hz_mesh* mesh, const hz_c128* beta, const double* eta, void* hip_stream, hz_ctx* out) {
+  HZ_GUARD_BEGIN
+  if (!out) return hz_fail(HZ_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!mesh || !beta) return hz_fail(HZ_ERR_INVALID, "mesh or beta is NULL");
+  if (!(mesh->c > 0.0) || !std::isfinite(mesh->c)) return hz_fail(HZ_ERR_INVALID, "speed of sound must be > 0");
+  for (int w = 0; w < 6; ++w)
+    if (!std::isfinite(beta[w].re) || !std::isfinite(beta[w].im)) return hz_fail(HZ_ERR_INVALID, "beta not finite");
+  std::unique_ptr<hz_ctx_s> ctx(new hz_ctx_s());
+  // host-side validation and assembly first: bad input never touches the GPU
+  HZ_TRY(host_assemble(mesh, eta, &ctx->h));
+  HZ_HIP(hipGetDevice(&ctx->device));
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  ctx->c = mesh->c;
+  ctx->rho = mesh->rho;
+  for (int d = 0; d < 3; ++d) {
+    ctx->elems[d] = mesh->elems[d];
+    ctx->parts[d] = mesh->parts[d];
+  }
+  ctx->beta.resize(6);
+  for (int w = 0; w < 6; ++w) ctx->beta[w] = std::complex<double>(beta[w].re, beta[w].im);
+  ctx->have_eta = eta != nullptr;
+  HZ_TRY(ctx_upload(ctx.get()));
+  HZ_HIP(hipStreamSynchronize(ctx->stream));
+  *out = ctx.release();
+  return HZ_OK;
+  HZ_GUARD_END
+}
+
+int hz_set_params(hz_ctx ctx, const hz_c128* beta, const double* eta) {
+  HZ_GUARD_BEGIN
+  HZ_TRY(check_ctx(ctx));
+  if (beta) {
+    for (int w = 0; w < 6; ++w)
+      if (!std::isfinite(beta[w].re) || !std::isfinite(beta[w].im)) return hz_fail(HZ_ERR_INVALID, "beta not finite");
+    for (int w = 0; w < 6; ++w) ctx->beta[w] = std::complex<double>(beta[w].re, beta[w].im);
+  }
+  if (eta) {
+    HZ_TRY(host_assemble_meta(&ctx->h, eta));
+    ctx->have_eta = true;
+  }
+  HZ_HIP(hipStreamSynchronize(ctx->stream));
+  HZ_TRY(ctx_upload_params(ctx));
+  ctx->have_freq = false;
+  ctx->scaled = -1;
+  ctx->have_A32 = false;
+  return HZ_OK;
+  HZ_GUARD_END
+}
+
+int hz_set_frequency(hz_ctx ctx, double freq_hz) {
+  HZ_GUARD_BEGIN
+  HZ_TRY(check_ctx(ctx));
+  if (!std::isfinite(freq_hz) || freq_hz < 0.0) return hz_fail(HZ_ERR_INVALID, "frequency must be finite and >= 0");
+  ctx->freq = freq_hz;
+  ctx->k = 2.0 * M_PI * freq_hz / ctx->c;
+  HZ_TRY(op_set_frequency(ctx, op_parts(ctx), ctx->k, 1, false));
+  ctx->scaled = HZ_JACOBI;
+  ctx->have_A32 = false;
+  ctx->have_freq = true;
+  return HZ_OK;
+  HZ_GUARD_END
+}
+
+int hz_apply(hz_ctx ctx, const hz_c128* x_dev, hz_c128* y_dev) {
+  HZ_GUARD_BEGIN
+  HZ_TRY(check_ctx(ctx));
+  if (!x_dev || !y_dev) return hz_fail(HZ_ERR_INVALID, "null vector");
+  if (!ctx->have_freq) return hz_fail(HZ_ERR_STATE, "no frequency set");
+  int rc = 0;
+  const int64_t n = ctx->h.n, nr = ctx->sell.n_rows;
+  DevBuf* t = ctx->buf("apply.x", sizeof(z_t) * nr, &rc);
+  if (rc) return rc;
+  const z_t* x = reinterpret_cast<const z_t*>(x_dev);
+  // a column-scaled operator A D^-1 is applied to D x
+  HZ_TRY(pad_in(ctx, n, nr, x, ctx->scaled == HZ_JACOBI ? ctx->d_d.as<z_t>() : nullptr, t->as<z_t>()));
+  HZ_TRY(op_spmv<double>(ctx->stream, nr, n, op_A(ctx), t->as<z_t>(), reinterpret_cast<z_t*>(y_dev)));
+  return HZ_OK;
+  HZ_GUARD_END
+}
+
+int hz_get_diag(hz_ctx ctx, hz_c128* d_dev) {
+  HZ_GUARD_BEGIN
+  HZ_TRY(check_ctx(ctx));
+  if (!d_dev) return hz_fail(HZ_ERR_INVALID, "null vector");
+  if (!ctx->have_freq) return hz_fail(HZ_ERR_STATE, "no frequency set");
+  return op_copy(ctx->stream, ctx->h.n, ctx->d_d.as<z_t>(), reinterpret_cast<z_t*>(d_dev));
+  HZ_GUARD_END
+}
+
+int hz_load(hz_ctx ctx, const hz_c128* g_dev, hz_c128* f_dev) {
+  HZ_GUARD_BEGIN
+  HZ_TRY(check_ctx(ctx));
+  if (!g_dev || !f_dev) return hz_fail(HZ_ERR_INVALID, "null vector");
+  return op_load(ctx, reinterpret_cast<const z_t*>(g_dev), reinterpret_cast<z_t*>(f_dev));
+  HZ_GUARD_END
+}
+
+int hz_dotc(hz_ctx ctx, int64_t n, const hz_c128* a_dev, const hz_c128* b_dev, hz_c128* out) {
+  HZ_GUARD_BEGIN
+  HZ_TRY(check_ctx(ctx));
+  if (!a_dev || !b_dev || !out || n < 0) return hz_fail(HZ_ERR_INVALID, "bad arguments");
+  int rc = 0;
+  DevBuf* r = ctx->buf("dot.out", sizeof(double) * 2, &rc);
+  if (rc) return rc;
+  HZ_TRY(op_dotc(ctx, n, reinterpret_cast<const z_t*>(a_dev), reinterpret_cast<const z_t*>(b_dev), r->as<double>()));
+  void* hp = nullptr;
+  HZ_TRY(ctx_pinned(ctx, 16, &hp));
+  HZ_HIP(hipMemcpyAsync(hp, r->p, 16, hipMemcpyDeviceToHost, ctx->stream));
+  HZ_HIP(hipStreamSynchronize(ctx->stream));
+  out->re = static_cast<double*>(hp)[0];
+  out->im = static_cast<double*>(hp)[1];
+  return HZ_OK;
+  HZ_GUARD_END
+}
+
+int hz_solve(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* f_dev, hz_c128* p_dev, hz_solve_info* info) {
+  HZ_GUARD_BEGIN
+  HZ_TRY(check_ctx(ctx));
+  HZ_TRY(validate_opts(opts));
+  if (!f_dev || !p_dev) return hz_fail(HZ_ERR_INVALID, "null vector");
+  if (!ctx->have_freq) return hz_fail(HZ_ERR_STATE, "no frequency set (call hz_set_frequency first)");
+  const z_t* f = reinterpret_cast<const z_t*>(f_dev);
+  z_t* p = reinterpret_cast<z_t*>(p_dev);
+  if (opts->method == HZ_SCHWARZ) return schwarz_solve(ctx, *opts, f, p, info);
+  return solve_single(ctx, *opts, f, p, info);
+  HZ_GUARD_END
+}
+
+int hz_solve_sweep(hz_ctx ctx, int32_t nfreq, const double* freqs_host, const hz_c128* F_dev, hz_c128* P_dev,
+                   const hz_solve_opts* opts, hz_solve_info* infos) {
+  HZ_GUARD_BEGIN
+  HZ_TRY(check_ctx(ctx));
+  HZ_TRY(validate_opts(opts));
+  if (nfreq < 1 || nfreq > 64) return hz_fail(HZ_ERR_INVALID, "nfreq %d not in 1..64", nfreq);
+  if (!freqs_host || !F_dev || !P_dev) return hz_fail(HZ_ERR_INVALID, "null argument");
+  if (opts->method != HZ_GMRES) return hz_fail(HZ_ERR_INVALID, "the sweep runs GMRES only");
+  for (int j = 0; j < nfreq; ++j)
+    if (!std::isfinite(freqs_host[j]) || freqs_host[j] < 0) return hz_fail(HZ_ERR_INVALID, "bad frequency");
+  return sweep_solve(ctx, nfreq, freqs_host, reinterpret_cast<const z_t*>(F_dev), reinterpret_cast<z_t*>(P_dev),
+                     *opts, infos);
+  HZ_GUARD_END
+}
+
+int hz_solve_adjoint(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* p_dev, const hz_c128* g_dev,
+                     hz_c128* lambda_dev, double* dJ_dbeta, double* dJ_deta_dev, hz_solve_info* info) {
+  HZ_GUARD_BEGIN
+  HZ_TRY(check_ctx(ctx));
+  HZ_TRY(validate_opts(opts));
+  if (!p_dev || !g_dev || !lambda_dev) return hz_fail(HZ_ERR_INVALID, "null vector");
+  if (!ctx->have_freq) return hz_fail(HZ_ERR_STATE, "no frequency set (call hz_set_frequency first)");
+  return adjoint_solve(ctx, *opts, reinterpret_cast<const z_t*>(p_dev), reinterpret_cast<const z_t*>(g_dev),
+                       reinterpret_cast<z_t*>(lambda_dev), dJ_dbeta, dJ_deta_dev, info);
+  HZ_GUARD_END
+}
+
+int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, double* avg_ms) {
+  HZ_GUARD_BEGIN
+  HZ_TRY(check_ctx(ctx));
+  if (!avg_ms || reps < 1 || reps > 100000) return hz_fail(HZ_ERR_INVALID, "bad arguments");
+  if (precision != HZ_FP64 && precision != HZ_MIXED) return hz_fail(HZ_ERR_INVALID, "bad precision");
+  const bool mixed = precision == HZ_MIXED;
+  HZ_TRY(ensure_operator(ctx, ctx->scaled < 0 ? HZ_JACOBI : ctx->scaled, mixed));
+  int rc = 0;
+  const int64_t nr = ctx->sell.n_rows;
+  const size_t es = mixed ? sizeof(c_t) : sizeof(z_t);
+  DevBuf* xb = ctx->buf("time.x", es * nr, &rc);
+  if (rc) return rc;
+  DevBuf* yb = ctx->buf("time.y", es * nr, &rc);
+  if (rc) return rc;
+  HZ_HIP(hipMemsetAsync(xb->p, 0, es * nr, ctx->stream));
+  hipEvent_t e0, e1;
+  HZ_HIP(hipEventCreate(&e0));
+  HZ_HIP(hipEventCreate(&e1));
+  // one untimed product first
+  if (mixed) HZ_TRY(op_spmv<float>(ctx->stream, nr, nr, op_A32(ctx), xb->as<c_t>(), yb->as<c_t>()));
+  else HZ_TRY(op_spmv<double>(ctx->stream, nr, nr, op_A(ctx), xb->as<z_t>(), yb->as<z_t>()));
+  HZ_HIP(hipEventRecord(e0, ctx->stream));
+  for (int r = 0; r < reps; ++r) {
+    if (mixed) HZ_TRY(op_spmv<float>(ctx->stream, nr, nr, op_A32(ctx), xb->as<c_t>(), yb->as<c_t>()));
+    else HZ_TRY(op_spmv<double>(ctx->stream, nr, nr, op_A(ctx), xb->as<z_t>(), yb->as<z_t>()));
+  }
+  HZ_HIP(hipEventRecord(e1, ctx->stream));
+  HZ_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HZ_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = double(ms) / reps;
+  return HZ_OK;
+  HZ_GUARD_END
+}
+
+int hz_sizes(hz_ctx ctx, int64_t* n_nodes, int64_t* n_elems, int64_t* nnz, int64_t* device_bytes) {
+  if (!ctx) return hz_fail(HZ_ERR_INVALID, "ctx is NULL");
+  if (n_nodes) *n_nodes = ctx->h.n;
+  if (n_elems) *n_elems = ctx->h.ne;
+  if (nnz) *nnz = int64_t(ctx->h.col.size());
+  if (device_bytes) *device_bytes = ctx->dev_bytes;
+  return HZ_OK;
+}
+
+void hz_destroy(hz_ctx ctx) {
+  if (!ctx) return;
+  int dev = -1;
+  if (hipGetDevice(&dev) == hipSuccess && dev != ctx->device) (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+}  // extern "C"

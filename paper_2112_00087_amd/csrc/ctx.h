@@ -1,0 +1,103 @@
+// Context of one assembled mesh: host assembly products, device arrays,
+// the current operator and cached solver workspaces.
+#pragma once
+
+#include <complex>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "krylov.h"
+
+// Sliced ELL with 64-row slices (one wave per slice): slice s holds rows
+// [64 s, 64 s + 64); its entries are stored column-major, entry k of lane l
+// at ptr[s] + 64 k + l.  Short rows are padded with (col = own row, value 0);
+// the lanes of the last slice beyond n_rows are padded with (col 0, value 0).
+struct SellHost {
+  int32_t n_rows = 0, n_slices = 0;
+  int64_t n_pad = 0;                 // stored entries including padding
+  std::vector<int32_t> ptr;          // [n_slices + 1]
+  std::vector<int32_t> col;          // [n_pad]
+  std::vector<int64_t> src;          // [n_pad] CSR position of the entry or -1
+};
+
+// Host-side assembly products (CSR with sorted columns).
+struct HostAsm {
+  int32_t n = 0, ne = 0, nb = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<double> K, M, Meta;    // per CSR entry (Meta empty when eta is NULL)
+  std::vector<int64_t> diag;         // CSR position of (i,i)
+  // boundary entries: CSR position and per-wall face mass, [nbe][6]
+  std::vector<int64_t> bpos;
+  std::vector<double> bmass;
+  // source-patch mass restricted to the patch rows
+  std::vector<int32_t> prow;
+  std::vector<int32_t> pptr, pcol;
+  std::vector<double> pval;
+  // mesh copy
+  std::vector<double> xyz;
+  std::vector<int32_t> hex, bface, btag;
+  std::vector<uint8_t> bsrc;
+  // node -> elements adjacency (ascending element id)
+  std::vector<int64_t> n2e_ptr;
+  std::vector<int32_t> n2e;
+};
+
+int host_assemble(const hz_mesh* mesh, const double* eta, HostAsm* out);
+int host_assemble_meta(HostAsm* a, const double* eta);
+void build_sell(const HostAsm& a, int64_t nrows, SellHost* s);
+
+// A device buffer that remembers its size.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+  int ensure(size_t nbytes);     // grows (contents lost)
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct hz_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  double c = 340.0, rho = 1.2;
+  int32_t elems[3] = {0, 0, 0}, parts[3] = {0, 0, 0};
+  HostAsm h;
+  SellHost sell;
+  int64_t dev_bytes = 0;
+
+  // device pattern + real values in SELL layout
+  DevBuf d_sptr, d_scol, d_K, d_M, d_Meta, d_bidx, d_diag;
+  // boundary entries (SELL position, beta-weighted complex value)
+  DevBuf d_bsell, d_Bb;
+  DevBuf d_bmass;   // [nbe][6] per-wall masses (for gradients)
+  // patch load CSR
+  DevBuf d_prow, d_pptr, d_pcol, d_pval;
+  // mesh on device (gradients)
+  DevBuf d_xyz, d_hex, d_bface, d_btag;
+
+  // current operator
+  bool have_freq = false;
+  double freq = 0.0, k = 0.0;
+  int scaled = -1;                   // precond the operator values are scaled for
+  DevBuf d_A, d_A32, d_d, d_dinv;    // A (maybe column-scaled), complex64 copy, diag, 1/diag
+  bool have_A32 = false;
+
+  std::vector<std::complex<double>> beta;   // [6]
+  bool have_eta = false;
+
+  // scratch for solvers, keyed by name
+  std::map<std::string, std::unique_ptr<DevBuf>> ws;
+  std::unique_ptr<SegHost> single_seg;
+  void* pinned = nullptr;            // small pinned host buffer for status reads
+  size_t pinned_bytes = 0;
+
+  DevBuf* buf(const std::string& name, size_t bytes, int* rc);
+  ~hz_ctx_s();
+};
+
+int ctx_upload(hz_ctx ctx);
+int ctx_upload_params(hz_ctx ctx);
+int ctx_pinned(hz_ctx ctx, size_t bytes, void** out);

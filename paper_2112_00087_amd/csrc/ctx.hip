@@ -1,0 +1,173 @@
+// Context lifecycle: device buffers, upload of the assembled operator parts
+// in sliced-ELL layout, error strings.
+#include <cstdarg>
+#include <cstring>
+
+#include "ops.h"
+
+namespace {
+thread_local char g_err[1024] = "";
+}
+
+void hz_set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int hz_fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+const char* hz_last_error_str() { return g_err; }
+
+int DevBuf::ensure(size_t nbytes) {
+  if (nbytes <= bytes && p) return HZ_OK;
+  if (p) {
+    (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  if (nbytes == 0) nbytes = 16;
+  hipError_t e = hipMalloc(&p, nbytes);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    return hz_fail(e == hipErrorOutOfMemory ? HZ_ERR_OOM : HZ_ERR_HIP, "hipMalloc(%zu): %s", nbytes,
+                   hipGetErrorString(e));
+  }
+  bytes = nbytes;
+  return HZ_OK;
+}
+
+DevBuf* hz_ctx_s::buf(const std::string& name, size_t nbytes, int* rc) {
+  auto& slot = ws[name];
+  if (!slot) slot.reset(new DevBuf());
+  size_t before = slot->bytes;
+  *rc = slot->ensure(nbytes);
+  if (*rc) return nullptr;
+  dev_bytes += int64_t(slot->bytes) - int64_t(before);
+  return slot.get();
+}
+
+hz_ctx_s::~hz_ctx_s() {
+  if (pinned) (void)hipHostFree(pinned);
+}
+
+int ctx_pinned(hz_ctx ctx, size_t bytes, void** out) {
+  if (bytes > ctx->pinned_bytes) {
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    size_t nb = std::max<size_t>(bytes, 4096);
+    HZ_HIP(hipHostMalloc(&ctx->pinned, nb, hipHostMallocDefault));
+    ctx->pinned_bytes = nb;
+  }
+  *out = ctx->pinned;
+  return HZ_OK;
+}
+
+namespace {
+template <typename T>
+int put(hz_ctx ctx, DevBuf& b, const T* src, size_t count) {
+  size_t before = b.bytes;
+  HZ_TRY(b.ensure(sizeof(T) * count));
+  ctx->dev_bytes += int64_t(b.bytes) - int64_t(before);
+  if (count) HZ_HIP(hipMemcpy(b.p, src, sizeof(T) * count, hipMemcpyHostToDevice));
+  return HZ_OK;
+}
+}  // namespace
+
+int ctx_upload_params(hz_ctx ctx) {
+  const HostAsm& a = ctx->h;
+  const int64_t nbe = int64_t(a.bpos.size());
+  std::vector<z_t> Bb(std::max<int64_t>(nbe, 1), z_t{0.0, 0.0});
+  for (int64_t e = 0; e < nbe; ++e) {
+    // accumulate walls in order 0..5
+    double re = 0.0, im = 0.0;
+    for (int w = 0; w < 6; ++w) {
+      double m = a.bmass[e * 6 + w];
+      re += ctx->beta[w].real() * m;
+      im += ctx->beta[w].imag() * m;
+    }
+    Bb[e] = z_t{re, im};
+  }
+  HZ_TRY(put(ctx, ctx->d_Bb, Bb.data(), Bb.size()));
+  if (ctx->have_eta) {
+    std::vector<double> v(ctx->sell.n_pad, 0.0);
+    for (int64_t p = 0; p < ctx->sell.n_pad; ++p)
+      if (ctx->sell.src[p] >= 0) v[p] = a.Meta[ctx->sell.src[p]];
+    HZ_TRY(put(ctx, ctx->d_Meta, v.data(), v.size()));
+  }
+  return HZ_OK;
+}
+
+int ctx_upload(hz_ctx ctx) {
+  const HostAsm& a = ctx->h;
+  SellHost& s = ctx->sell;
+  const int64_t nrows = int64_t(ceil_div(a.n, kBlock)) * kBlock;
+  build_sell(a, nrows, &s);
+  HZ_TRY(put(ctx, ctx->d_sptr, s.ptr.data(), s.ptr.size()));
+  HZ_TRY(put(ctx, ctx->d_scol, s.col.data(), s.col.size()));
+  {
+    std::vector<double> K(s.n_pad, 0.0), M(s.n_pad, 0.0);
+    for (int64_t p = 0; p < s.n_pad; ++p)
+      if (s.src[p] >= 0) {
+        K[p] = a.K[s.src[p]];
+        M[p] = a.M[s.src[p]];
+      }
+    HZ_TRY(put(ctx, ctx->d_K, K.data(), K.size()));
+    HZ_TRY(put(ctx, ctx->d_M, M.data(), M.size()));
+  }
+  {
+    std::vector<int32_t> csr2b(a.col.size(), -1);
+    for (size_t e = 0; e < a.bpos.size(); ++e) csr2b[a.bpos[e]] = int32_t(e);
+    std::vector<int32_t> bidx(s.n_pad, -1);
+    for (int64_t p = 0; p < s.n_pad; ++p)
+      if (s.src[p] >= 0) bidx[p] = csr2b[s.src[p]];
+    HZ_TRY(put(ctx, ctx->d_bidx, bidx.data(), bidx.size()));
+  }
+  {
+    std::vector<int32_t> dpos(a.n);
+    for (int64_t i = 0; i < a.n; ++i)
+      dpos[i] = int32_t(s.ptr[i / kWave] + (a.diag[i] - a.rowptr[i]) * kWave + (i % kWave));
+    HZ_TRY(put(ctx, ctx->d_diag, dpos.data(), dpos.size()));
+  }
+  HZ_TRY(put(ctx, ctx->d_bmass, a.bmass.data(), a.bmass.size()));
+  HZ_TRY(put(ctx, ctx->d_prow, a.prow.data(), a.prow.size()));
+  HZ_TRY(put(ctx, ctx->d_pptr, a.pptr.data(), a.pptr.size()));
+  HZ_TRY(put(ctx, ctx->d_pcol, a.pcol.data(), a.pcol.size()));
+  HZ_TRY(put(ctx, ctx->d_pval, a.pval.data(), a.pval.size()));
+  HZ_TRY(put(ctx, ctx->d_xyz, a.xyz.data(), a.xyz.size()));
+  HZ_TRY(put(ctx, ctx->d_hex, a.hex.data(), a.hex.size()));
+  HZ_TRY(put(ctx, ctx->d_bface, a.bface.data(), a.bface.size()));
+  HZ_TRY(put(ctx, ctx->d_btag, a.btag.data(), a.btag.size()));
+  size_t before = ctx->d_A.bytes + ctx->d_d.bytes + ctx->d_dinv.bytes;
+  HZ_TRY(ctx->d_A.ensure(sizeof(z_t) * s.n_pad));
+  HZ_TRY(ctx->d_d.ensure(sizeof(z_t) * nrows));
+  HZ_TRY(ctx->d_dinv.ensure(sizeof(z_t) * nrows));
+  ctx->dev_bytes += int64_t(ctx->d_A.bytes + ctx->d_d.bytes + ctx->d_dinv.bytes) - int64_t(before);
+  HZ_TRY(ctx_upload_params(ctx));
+  return HZ_OK;
+}
+
+int ctx_single_seg(hz_ctx ctx, SegHost** out) {
+  SegHost* S = ctx->single_seg.get();
+  if (!S) {
+    ctx->single_seg.reset(new SegHost());
+    S = ctx->single_seg.get();
+    S->nseg = 1;
+    S->nrows = ctx->sell.n_rows;
+    S->nblk = int(S->nrows / kBlock);
+    S->seg_blk = {0, S->nblk};
+    S->seg_n = {ctx->h.n};
+    HZ_TRY(seg_upload(ctx, S, "single"));
+  }
+  *out = S;
+  return HZ_OK;
+}

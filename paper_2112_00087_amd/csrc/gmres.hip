@@ -1,0 +1,357 @@
+// Restarted GMRES(m) on the right-Jacobi operator, for every segment of a
+// segmented system (added beside the paper's Sec. 4 solvers).
+//
+// Arnoldi uses classical Gram-Schmidt with one re-orthogonalisation (CGS2):
+// each pass is a multi-dot  h = V^H w  (one read of w per chunk of 8 basis
+// vectors, FP64 accumulation) and a multi-axpy  w -= V h.  The Hessenberg
+// column, the complex Givens rotations and the least-squares solve stay on
+// the device in FP64, so a whole restart cycle is queued without a host
+// round trip; the host reads the per-segment state once per cycle.
+// With storage type float the basis and the operator are complex64 while
+// the Gram-Schmidt coefficients, H and the rotations remain FP64.
+#include "ops.h"
+
+namespace {
+
+constexpr int NV = 8;    // basis vectors per multi-dot chunk
+
+struct GmSt {
+  double beta, thr2, est, inv_next;
+  int k, done, cyc, nan;
+  int iters, pad0;
+};
+
+struct GmArr {         // per-segment small arrays (FP64)
+  z_t* H;              // [(m+1) x m] column-major, per segment
+  double* cs;          // [m]
+  z_t* sn;             // [m]
+  z_t* g;              // [m+1]
+  z_t* y;              // [m]
+  z_t* h1;             // [m+1] first-pass coefficients
+  z_t* h2;             // [m+1] second-pass coefficients
+  int m;
+};
+
+template <typename T> __device__ __forceinline__ z_t zd(cx<T> a) { return ccast<double>(a); }
+
+// V0 = f - A u; partial ||V0||^2
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_resid(Seg L, SellOp<T> A, const cx<T>* __restrict__ f,
+                                                  const cx<T>* __restrict__ u, cx<T>* __restrict__ V0,
+                                                  double* part) {
+  Tile t = tile_of(L);
+  z_t r = zd(f[t.row]) - zd(sell_row(A, t.row, u));
+  cx<T> rs = ccast<T>(r);
+  V0[t.row] = rs;
+  double q[1] = {norm2(zd(rs))};
+  store_partials<1>(q, part, t.tile);
+}
+
+__global__ void k_beta_fin(Seg L, GmSt* st, GmArr G, const double* part) {
+  int s = blockIdx.x;
+  double rr = seg_sum<1>(L, part, s, 0);
+  if (threadIdx.x == 0) {
+    GmSt& S = st[s];
+    double b = sqrt(rr);
+    S.beta = b;
+    S.est = b;
+    S.k = 0;
+    S.nan = !isfinite(rr);
+    S.done = (rr <= S.thr2) || S.nan;
+    S.cyc = S.done;
+    S.inv_next = b > 0.0 ? 1.0 / b : 0.0;
+    z_t* g = G.g + int64_t(s) * (G.m + 1);
+    g[0] = z_t{b, 0.0};
+    for (int i = 1; i <= G.m; ++i) g[i] = z_t{0.0, 0.0};
+  }
+}
+
+// V_j *= inv_next
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_scale(Seg L, const GmSt* st, cx<T>* __restrict__ Vj) {
+  Tile t = tile_of(L);
+  const GmSt& S = st[t.seg];
+  if (S.cyc) return;
+  z_t v = zd(Vj[t.row]);
+  Vj[t.row] = ccast<T>(S.inv_next * v);
+}
+
+// w = A V_j
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_arnoldi_spmv(Seg L, SellOp<T> A, const GmSt* st,
+                                                         const cx<T>* __restrict__ Vj, cx<T>* __restrict__ w) {
+  Tile t = tile_of(L);
+  if (st[t.seg].cyc) return;
+  w[t.row] = sell_row(A, t.row, Vj);
+}
+
+// partial h_i = V_i^H w for i in chunk blockIdx.y (i <= j)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_mdot(Seg L, const GmSt* st, const cx<T>* __restrict__ V,
+                                                 int64_t ld, int j, const cx<T>* __restrict__ w,
+                                                 double* part) {
+  Tile t = tile_of(L);
+  if (st[t.seg].cyc) return;
+  int i0 = blockIdx.y * NV;
+  z_t wv = zd(w[t.row]);
+  double q[2 * NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    int i = i0 + c;
+    z_t a = {0.0, 0.0};
+    if (i <= j) a = zd(V[int64_t(i) * ld + t.row]);
+    q[2 * c] = a.re * wv.re + a.im * wv.im;
+    q[2 * c + 1] = a.re * wv.im - a.im * wv.re;
+  }
+  store_partials<2 * NV>(q, part + int64_t(blockIdx.y) * L.nblk * 2 * NV, t.tile);
+}
+
+// block (s, i): coefficient i of segment s.  pass 1 -> h1; pass 2 -> h2 and H[:, j] = h1 + h2.
+__global__ void k_mdot_fin(Seg L, const GmSt* st, GmArr G, const double* part, int j, int pass) {
+  int s = blockIdx.x, i = blockIdx.y;
+  if (st[s].cyc) return;
+  int c = i / NV, q = i % NV;
+  const double* base = part + int64_t(c) * L.nblk * 2 * NV;
+  double re = seg_sum<2 * NV>(L, base, s, 2 * q);
+  double im = seg_sum<2 * NV>(L, base, s, 2 * q + 1);
+  if (threadIdx.x == 0) {
+    z_t h = {re, im};
+    if (pass == 1) {
+      G.h1[int64_t(s) * (G.m + 1) + i] = h;
+    } else {
+      G.h2[int64_t(s) * (G.m + 1) + i] = h;
+      z_t* H = G.H + int64_t(s) * (G.m + 1) * G.m;
+      H[int64_t(j) * (G.m + 1) + i] = G.h1[int64_t(s) * (G.m + 1) + i] + h;
+    }
+  }
+}
+
+// w -= sum_{i<=j} h_i V_i (h = h1 or h2); optionally partial ||w||^2
+template <typename T, bool NORM>
+__global__ void __launch_bounds__(kBlock) k_axpy(Seg L, const GmSt* st, GmArr G, const cx<T>* __restrict__ V,
+                                                 int64_t ld, int j, int pass, cx<T>* __restrict__ w,
+                                                 double* part) {
+  Tile t = tile_of(L);
+  if (st[t.seg].cyc) return;
+  const z_t* h = (pass == 1 ? G.h1 : G.h2) + int64_t(t.seg) * (G.m + 1);
+  z_t acc = zd(w[t.row]);
+  for (int i = 0; i <= j; ++i) {
+    z_t v = zd(V[int64_t(i) * ld + t.row]);
+    z_t hi = h[i];
+    acc.re -= hi.re * v.re - hi.im * v.im;
+    acc.im -= hi.re * v.im + hi.im * v.re;
+  }
+  cx<T> ws = ccast<T>(acc);
+  w[t.row] = ws;
+  if (NORM) {
+    double q[1] = {norm2(zd(ws))};
+    store_partials<1>(q, part, t.tile);
+  }
+}
+
+// New Hessenberg column j: subdiagonal, previous rotations, new rotation,
+// residual estimate |g_{j+1}|.
+__global__ void k_givens_fin(Seg L, GmSt* st, GmArr G, const double* part, int j) {
+  int s = blockIdx.x;
+  const int cyc = st[s].cyc;
+  __syncthreads();
+  if (cyc) return;
+  double ww = seg_sum<1>(L, part, s, 0);
+  if (threadIdx.x != 0) return;
+  GmSt& S = st[s];
+  const int m = G.m;
+  z_t* H = G.H + int64_t(s) * (m + 1) * m + int64_t(j) * (m + 1);
+  double* cs = G.cs + int64_t(s) * m;
+  z_t* sn = G.sn + int64_t(s) * m;
+  z_t* g = G.g + int64_t(s) * (m + 1);
+  double hn = sqrt(ww);
+  H[j + 1] = z_t{hn, 0.0};
+  for (int i = 0; i < j; ++i) {
+    z_t a = H[i], b = H[i + 1];
+    H[i] = cs[i] * a + sn[i] * b;
+    H[i + 1] = (-1.0 * (conj(sn[i]) * a)) + cs[i] * b;
+  }
+  z_t a = H[j], b = H[j + 1];
+  double rho = sqrt(norm2(a) + norm2(b));
+  double c;
+  z_t sv;
+  if (rho == 0.0) {
+    c = 1.0;
+    sv = z_t{0.0, 0.0};
+  } else if (norm2(a) == 0.0) {
+    c = 0.0;
+    sv = z_t{1.0, 0.0};
+  } else {
+    double aa = sqrt(norm2(a));
+    c = aa / rho;
+    sv = (1.0 / (aa * rho)) * (a * conj(b));
+  }
+  cs[j] = c;
+  sn[j] = sv;
+  H[j] = c * a + sv * b;
+  H[j + 1] = z_t{0.0, 0.0};
+  z_t gj = g[j];
+  g[j + 1] = -1.0 * (conj(sv) * gj);
+  g[j] = c * gj;
+  S.k = j + 1;
+  S.iters += 1;
+  S.est = sqrt(norm2(g[j + 1]));
+  bool bad = !isfinite(hn) || !isfinite(S.est);
+  if (bad) S.nan = 1;
+  if (bad || hn == 0.0 || S.est * S.est <= S.thr2) S.cyc = 1;
+  S.inv_next = hn > 0.0 ? 1.0 / hn : 0.0;
+}
+
+// y = H(0:k,0:k)^-1 g(0:k)
+__global__ void k_solve_fin(const GmSt* st, GmArr G, int nseg) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  const GmSt& S = st[s];
+  if (S.done || S.nan) return;
+  const int m = G.m, k = S.k;
+  const z_t* H = G.H + int64_t(s) * (m + 1) * m;
+  const z_t* g = G.g + int64_t(s) * (m + 1);
+  z_t* y = G.y + int64_t(s) * m;
+  for (int i = k - 1; i >= 0; --i) {
+    z_t acc = g[i];
+    for (int l = i + 1; l < k; ++l) acc = acc - H[int64_t(l) * (m + 1) + i] * y[l];
+    y[i] = cdiv(acc, H[int64_t(i) * (m + 1) + i]);
+  }
+}
+
+// u += sum_{i<k} y_i V_i
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_update(Seg L, const GmSt* st, GmArr G, const cx<T>* __restrict__ V,
+                                                   int64_t ld, cx<T>* __restrict__ u) {
+  Tile t = tile_of(L);
+  const GmSt& S = st[t.seg];
+  if (S.done || S.nan || S.k == 0) return;
+  const z_t* y = G.y + int64_t(t.seg) * G.m;
+  z_t acc = zd(u[t.row]);
+  for (int i = 0; i < S.k; ++i) {
+    z_t v = zd(V[int64_t(i) * ld + t.row]);
+    z_t yi = y[i];
+    acc.re += yi.re * v.re - yi.im * v.im;
+    acc.im += yi.re * v.im + yi.im * v.re;
+  }
+  u[t.row] = ccast<T>(acc);
+}
+
+__global__ void k_init_st(int nseg, GmSt* st, const double* fn2, double tol) {
+  int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= nseg) return;
+  GmSt z = {};
+  z.thr2 = tol * tol * fn2[s];
+  st[s] = z;
+}
+
+}  // namespace
+
+template <typename T>
+int gmres_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, cx<T>* u,
+              const KrylovCtl& ctl, KrylovOut* out, const std::string& tag) {
+  int rc = 0;
+  const int m = ctl.restart;
+  if (m < 1 || m > 128) return hz_fail(HZ_ERR_INVALID, "GMRES restart %d not in 1..128", m);
+  const int64_t ld = S.nrows;
+  const std::string p = "gm." + tag + (sizeof(T) == 8 ? ".z." : ".c.");
+  DevBuf* Vb = ctx->buf(p + "V", sizeof(cx<T>) * ld * (m + 1), &rc);
+  if (rc) return rc;
+  const int nchunk = ceil_div(m + 1, NV);
+  DevBuf* part = ctx->buf(p + "part", sizeof(double) * int64_t(nchunk) * S.nblk * 2 * NV, &rc);
+  if (rc) return rc;
+  DevBuf* stb = ctx->buf(p + "st", sizeof(GmSt) * S.nseg, &rc);
+  if (rc) return rc;
+  const int64_t ns = S.nseg;
+  DevBuf* small = ctx->buf(p + "small",
+                           sizeof(z_t) * ns * ((m + 1) * m + m + (m + 1) + m + 2 * (m + 1)) +
+                               sizeof(double) * ns * m, &rc);
+  if (rc) return rc;
+  DevBuf* fnb = ctx->buf(p + "fn2", sizeof(double) * S.nseg, &rc);
+  if (rc) return rc;
+  GmArr G;
+  G.m = m;
+  z_t* zp = small->as<z_t>();
+  G.H = zp; zp += ns * (m + 1) * m;
+  G.sn = zp; zp += ns * m;
+  G.g = zp; zp += ns * (m + 1);
+  G.y = zp; zp += ns * m;
+  G.h1 = zp; zp += ns * (m + 1);
+  G.h2 = zp; zp += ns * (m + 1);
+  G.cs = reinterpret_cast<double*>(zp);
+  GmSt* st = stb->as<GmSt>();
+  cx<T>* V = Vb->as<cx<T>>();
+  double* pt = part->as<double>();
+  hipStream_t s = ctx->stream;
+  const Seg& L = S.dev;
+
+  std::vector<double> fn2;
+  HZ_TRY(seg_norm2_t<T>(ctx, S, f, &fn2));
+  out->fnorm.resize(S.nseg);
+  for (int i = 0; i < S.nseg; ++i) out->fnorm[i] = std::sqrt(fn2[i]);
+  HZ_HIP(hipMemcpyAsync(fnb->p, fn2.data(), sizeof(double) * S.nseg, hipMemcpyHostToDevice, s));
+  k_init_st<<<ceil_div(S.nseg, kBlock), kBlock, 0, s>>>(S.nseg, st, fnb->as<double>(), ctl.tol);
+  HZ_HIP(hipGetLastError());
+
+  void* hp = nullptr;
+  HZ_TRY(ctx_pinned(ctx, sizeof(GmSt) * S.nseg, &hp));
+  GmSt* hst = static_cast<GmSt*>(hp);
+  std::vector<int64_t> mv(S.nseg, 0);
+  int64_t mv_max = 0;
+  const int grid = S.nblk;
+  for (;;) {
+    // residual of the current iterate; converged segments stop here
+    k_resid<T><<<grid, kBlock, 0, s>>>(L, A, f, u, V, pt);
+    k_beta_fin<<<S.nseg, kBlock, 0, s>>>(L, st, G, pt);
+    HZ_HIP(hipGetLastError());
+    int mc = int(std::min<int64_t>(m, ctl.max_matvec - mv_max - 1));
+    if (mc >= 1) {
+      k_scale<T><<<grid, kBlock, 0, s>>>(L, st, V);
+      for (int j = 0; j < mc; ++j) {
+        cx<T>* w = V + int64_t(j + 1) * ld;
+        dim3 gd(grid, ceil_div(j + 1, NV));
+        dim3 gf(S.nseg, j + 1);
+        k_arnoldi_spmv<T><<<grid, kBlock, 0, s>>>(L, A, st, V + int64_t(j) * ld, w);
+        k_mdot<T><<<gd, kBlock, 0, s>>>(L, st, V, ld, j, w, pt);
+        k_mdot_fin<<<gf, kBlock, 0, s>>>(L, st, G, pt, j, 1);
+        k_axpy<T, false><<<grid, kBlock, 0, s>>>(L, st, G, V, ld, j, 1, w, pt);
+        k_mdot<T><<<gd, kBlock, 0, s>>>(L, st, V, ld, j, w, pt);
+        k_mdot_fin<<<gf, kBlock, 0, s>>>(L, st, G, pt, j, 2);
+        k_axpy<T, true><<<grid, kBlock, 0, s>>>(L, st, G, V, ld, j, 2, w, pt);
+        k_givens_fin<<<S.nseg, kBlock, 0, s>>>(L, st, G, pt, j);
+        k_scale<T><<<grid, kBlock, 0, s>>>(L, st, w);
+        HZ_HIP(hipGetLastError());
+      }
+      k_solve_fin<<<ceil_div(S.nseg, 64), 64, 0, s>>>(st, G, S.nseg);
+      k_update<T><<<grid, kBlock, 0, s>>>(L, st, G, V, ld, u);
+      HZ_HIP(hipGetLastError());
+    }
+    HZ_HIP(hipMemcpyAsync(hst, st, sizeof(GmSt) * S.nseg, hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    bool all_done = true;
+    for (int i = 0; i < S.nseg; ++i) {
+      mv[i] += 1;
+      if (!hst[i].done) mv[i] += hst[i].k;
+      mv_max = std::max(mv_max, mv[i]);
+      all_done = all_done && (hst[i].done || hst[i].nan);
+    }
+    if (all_done || mc < 1 || mv_max >= ctl.max_matvec) break;
+  }
+  out->iters.resize(S.nseg);
+  out->matvecs.resize(S.nseg);
+  out->status.resize(S.nseg);
+  out->relres_est.resize(S.nseg);
+  for (int i = 0; i < S.nseg; ++i) {
+    out->iters[i] = hst[i].iters;
+    out->matvecs[i] = int(mv[i]);
+    double fnv = out->fnorm[i];
+    out->relres_est[i] = fnv > 0 ? hst[i].est / fnv : 0.0;
+    out->status[i] = hst[i].nan ? HZ_BREAKDOWN : (hst[i].done ? HZ_OK : HZ_NOT_CONVERGED);
+  }
+  return HZ_OK;
+}
+
+template int gmres_run<double>(hz_ctx, const SegHost&, const SellOp<double>&, const z_t*, z_t*,
+                               const KrylovCtl&, KrylovOut*, const std::string&);
+template int gmres_run<float>(hz_ctx, const SegHost&, const SellOp<float>&, const c_t*, c_t*,
+                              const KrylovCtl&, KrylovOut*, const std::string&);

@@ -1,0 +1,107 @@
+// Device building blocks shared by the Krylov solvers.
+//
+// Row layout.  A solve works on one system, or on a batch of independent
+// systems ("segments") stacked one after the other, each padded to a whole
+// number of 256-row blocks.  Every vector kernel runs one block per 256 rows,
+// so each block belongs to exactly one segment; reductions write one partial
+// per block and a finalize kernel (one block per segment) sums that segment's
+// partials in block order.  Sums are therefore reproducible bit for bit, and
+// every segment carries its own Krylov scalars and convergence flag: a batch
+// of subdomain solves advances in lock-step but each one is its own Krylov
+// iteration.  Padding rows hold zero matrix rows and zero vector entries.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+struct Seg {
+  int nseg = 0;
+  int nblk = 0;
+  int64_t nrows = 0;              // nblk * kBlock
+  const int* blk_seg = nullptr;   // [nblk]
+  const int* seg_blk = nullptr;   // [nseg + 1]
+};
+
+template <typename T>
+struct SellOp {
+  const int* ptr = nullptr;       // [nrows / 64 + 1] slice offsets
+  const int* col = nullptr;
+  const cx<T>* val = nullptr;
+};
+
+// Non-temporal loads for the streamed matrix data (read once per product):
+// keeps L2 / Infinity Cache for the gathered vector.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ z_t ld_stream(const z_t* p) {
+  d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+  return z_t{v.x, v.y};
+}
+__device__ __forceinline__ c_t ld_stream(const c_t* p) {
+  f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+  return c_t{v.x, v.y};
+}
+__device__ __forceinline__ int ld_stream(const int* p) { return __builtin_nontemporal_load(p); }
+
+// y_row = sum_k A[row, col_k] x[col_k] over the row's sliced-ELL entries.
+template <typename T>
+__device__ __forceinline__ cx<T> sell_row(const SellOp<T>& A, int64_t row, const cx<T>* __restrict__ x) {
+  int slice = int(row >> 6), lane = int(row & 63);
+  int beg = A.ptr[slice];
+  int w = (A.ptr[slice + 1] - beg) >> 6;
+  const int* __restrict__ c = A.col + beg + lane;
+  const cx<T>* __restrict__ v = A.val + beg + lane;
+  cx<T> acc = {T(0), T(0)};
+#pragma unroll 3
+  for (int k = 0; k < w; ++k) {
+    int j = ld_stream(c + (k << 6));
+    cx<T> a = ld_stream(v + (k << 6));
+    cx<T> xv = x[j];
+    cfma(acc, a, xv);
+  }
+  return acc;
+}
+
+// Block geometry of a segmented kernel: logical tile (XCD-contiguous), row, segment.
+struct Tile {
+  int tile;
+  int seg;
+  int64_t row;
+};
+__device__ __forceinline__ Tile tile_of(const Seg& L) {
+  Tile t;
+  t.tile = xcd_tile(blockIdx.x, gridDim.x);
+  t.seg = L.blk_seg[t.tile];
+  t.row = int64_t(t.tile) * kBlock + threadIdx.x;
+  return t;
+}
+
+// Block-sum NQ doubles and store them as partial[tile * NQ + q] (thread 0).
+template <int NQ>
+__device__ __forceinline__ void store_partials(double (&v)[NQ], double* partial, int tile) {
+  __shared__ double lds[kBlock / kWave];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double s = block_sum(v[q], lds);
+    if (threadIdx.x == 0) partial[int64_t(tile) * NQ + q] = s;
+  }
+}
+
+// In a finalize kernel (one block per segment): sum quantity q of this
+// segment's partials; valid in thread 0.
+template <int NQ>
+__device__ __forceinline__ double seg_sum(const Seg& L, const double* partial, int seg, int q) {
+  __shared__ double lds[kBlock / kWave];
+  int b0 = L.seg_blk[seg], b1 = L.seg_blk[seg + 1];
+  return block_sum_strided(partial + int64_t(b0) * NQ + q, b1 - b0, NQ, lds);
+}
+
+// Host-side description of a segmented system on the device.
+struct SegHost {
+  int nseg = 0, nblk = 0;
+  int64_t nrows = 0;
+  std::vector<int> seg_blk;       // host copy [nseg + 1]
+  std::vector<int64_t> seg_n;     // true (unpadded) rows per segment
+  Seg dev;                        // device view
+};

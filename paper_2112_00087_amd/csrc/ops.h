@@ -1,0 +1,81 @@
+// Host-side interface of the operator kernels and solvers.
+#pragma once
+
+#include "ctx.h"
+#include "krylov.h"
+
+// Device pointers of the real operator parts (SELL layout).
+struct OpParts {
+  const double* K = nullptr;
+  const double* M = nullptr;
+  const double* Meta = nullptr;   // NULL: no absorption field
+  const int* bidx = nullptr;      // per stored entry: boundary slot or -1
+  const z_t* Bb = nullptr;        // per boundary slot: sum_w beta_w B0_w
+  const int* diag = nullptr;      // per row: stored position of the diagonal
+};
+
+inline OpParts op_parts(hz_ctx ctx) {
+  OpParts P;
+  P.K = ctx->d_K.as<double>();
+  P.M = ctx->d_M.as<double>();
+  P.Meta = ctx->have_eta ? ctx->d_Meta.as<double>() : nullptr;
+  P.bidx = ctx->d_bidx.as<int>();
+  P.Bb = ctx->d_Bb.as<z_t>();
+  P.diag = ctx->d_diag.as<int>();
+  return P;
+}
+
+inline SellOp<double> op_A(hz_ctx ctx) {
+  SellOp<double> A;
+  A.ptr = ctx->d_sptr.as<int>();
+  A.col = ctx->d_scol.as<int>();
+  A.val = ctx->d_A.as<z_t>();
+  return A;
+}
+inline SellOp<float> op_A32(hz_ctx ctx) {
+  SellOp<float> A;
+  A.ptr = ctx->d_sptr.as<int>();
+  A.col = ctx->d_scol.as<int>();
+  A.val = ctx->d_A32.as<c_t>();
+  return A;
+}
+
+int op_set_frequency(hz_ctx ctx, const OpParts& P, double k, int scale, bool want32);
+template <typename T>
+int op_spmv(hipStream_t s, int64_t nrows, int64_t nout, const SellOp<T>& A, const cx<T>* x, cx<T>* y);
+int op_mul(hipStream_t s, int64_t n, const z_t* a, const z_t* b, z_t* c);
+int op_fill(hipStream_t s, int64_t n, z_t* y, z_t v);
+int op_copy(hipStream_t s, int64_t n, const z_t* x, z_t* y);
+int op_load(hz_ctx ctx, const z_t* g, z_t* f);
+int op_dotc(hz_ctx ctx, int64_t n, const z_t* a, const z_t* b, double* out_dev);
+
+// ---------------------------------------------------------------- solvers
+// Per-segment controls and results of one Krylov run.
+struct KrylovCtl {
+  double tol = 1e-8;              // relative to ||f_seg||
+  int max_matvec = 20000;
+  int restart = 30;               // GMRES
+};
+struct KrylovOut {
+  std::vector<int> iters, matvecs, status;
+  std::vector<double> relres_est, fnorm;
+};
+
+// Solve A u = f on every segment (u: in x0 / out), vectors of the storage
+// type T, reductions and Krylov scalars in FP64.
+template <typename T>
+int bicgstab_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, cx<T>* u,
+                 const KrylovCtl& ctl, KrylovOut* out, const std::string& tag);
+template <typename T>
+int gmres_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, cx<T>* u,
+              const KrylovCtl& ctl, KrylovOut* out, const std::string& tag);
+
+// ||f_seg - A u_seg||^2 per segment (FP64), written to host vector rr.
+int true_residual(hz_ctx ctx, const SegHost& S, const SellOp<double>& A, const z_t* f, const z_t* u,
+                  z_t* r, std::vector<double>* rr);
+template <typename T>
+int seg_norm2_t(hz_ctx ctx, const SegHost& S, const cx<T>* x, std::vector<double>* out);
+
+// Segment layout of the context's single system (one segment, padded rows).
+int ctx_single_seg(hz_ctx ctx, SegHost** out);
+int seg_upload(hz_ctx ctx, SegHost* S, const std::string& tag);

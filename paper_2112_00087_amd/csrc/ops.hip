@@ -1,0 +1,189 @@
+// Operator kernels: forming A(k) (set_frequency), the sparse product, the
+// patch load and a reproducible dot product.
+#include "ops.h"
+
+// ---------------------------------------------------------------- set_frequency
+// Value of A(k) = K - k^2 M + i k^2 M_eta + i k B_beta at stored entry p.
+__device__ __forceinline__ z_t entry_value(int64_t p, const OpParts& P, double k) {
+  double k2 = k * k;
+  z_t a = {P.K[p] - k2 * P.M[p], 0.0};
+  if (P.Meta) a.im += k2 * P.Meta[p];
+  int b = P.bidx[p];
+  if (b >= 0) {
+    z_t bb = P.Bb[b];
+    a.re -= k * bb.im;          // i k (br + i bi) = -k bi + i k br
+    a.im += k * bb.re;
+  }
+  return a;
+}
+
+__global__ void k_diag(int n, int64_t nrows, OpParts P, double k, z_t* __restrict__ d,
+                       z_t* __restrict__ dinv) {
+  int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= nrows) return;
+  if (i < n) {
+    z_t v = entry_value(P.diag[i], P, k);
+    d[i] = v;
+    dinv[i] = crecip(v);
+  } else {
+    d[i] = z_t{1.0, 0.0};
+    dinv[i] = z_t{1.0, 0.0};
+  }
+}
+
+// One pass over the stored entries: A (optionally with column j scaled by
+// dinv[j], i.e. the right-Jacobi operator A D^-1) and its complex64 copy.
+__global__ void k_combine(int64_t npad, const int* __restrict__ col, OpParts P, double k,
+                          const z_t* __restrict__ dinv, int scale, z_t* __restrict__ A,
+                          c_t* __restrict__ A32) {
+  int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < npad; p += stride) {
+    z_t a = entry_value(p, P, k);
+    if (scale) a = a * dinv[col[p]];
+    A[p] = a;
+    if (A32) A32[p] = ccast<float>(a);
+  }
+}
+
+int op_set_frequency(hz_ctx ctx, const OpParts& P, double k, int scale, bool want32) {
+  int n = ctx->h.n;
+  int64_t nrows = ctx->sell.n_rows;
+  k_diag<<<ceil_div(nrows, kBlock), kBlock, 0, ctx->stream>>>(n, nrows, P, k, ctx->d_d.as<z_t>(),
+                                                             ctx->d_dinv.as<z_t>());
+  HZ_HIP(hipGetLastError());
+  int64_t npad = ctx->sell.n_pad;
+  int grid = int(std::min<int64_t>(ceil_div(npad, kBlock), 16384));
+  k_combine<<<grid, kBlock, 0, ctx->stream>>>(npad, ctx->d_scol.as<int>(), P, k,
+                                              ctx->d_dinv.as<z_t>(), scale, ctx->d_A.as<z_t>(),
+                                              want32 ? ctx->d_A32.as<c_t>() : nullptr);
+  HZ_HIP(hipGetLastError());
+  return HZ_OK;
+}
+
+// ---------------------------------------------------------------- products
+// y[row] = (A (s .* x))[row] for rows < nout (s = NULL: no column scaling
+// beyond what the stored values carry; used by the plain apply of a
+// column-scaled operator to undo the scaling).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_spmv(int64_t nout, SellOp<T> A, const cx<T>* __restrict__ x,
+                                                 cx<T>* __restrict__ y) {
+  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  int64_t row = int64_t(tile) * kBlock + threadIdx.x;
+  cx<T> v = sell_row(A, row, x);
+  if (row < nout) y[row] = v;
+}
+
+template <typename T>
+int op_spmv(hipStream_t s, int64_t nrows, int64_t nout, const SellOp<T>& A, const cx<T>* x, cx<T>* y) {
+  k_spmv<T><<<int(nrows / kBlock), kBlock, 0, s>>>(nout, A, x, y);
+  HZ_HIP(hipGetLastError());
+  return HZ_OK;
+}
+template int op_spmv<double>(hipStream_t, int64_t, int64_t, const SellOp<double>&, const z_t*, z_t*);
+template int op_spmv<float>(hipStream_t, int64_t, int64_t, const SellOp<float>&, const c_t*, c_t*);
+
+__global__ void k_mul(int64_t n, const z_t* __restrict__ a, const z_t* __restrict__ b, z_t* __restrict__ c) {
+  int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) c[i] = a[i] * b[i];
+}
+
+int op_mul(hipStream_t s, int64_t n, const z_t* a, const z_t* b, z_t* c) {
+  if (n <= 0) return HZ_OK;
+  k_mul<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, a, b, c);
+  HZ_HIP(hipGetLastError());
+  return HZ_OK;
+}
+
+__global__ void k_fill(int64_t n, z_t* __restrict__ y, z_t v) {
+  int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+
+int op_fill(hipStream_t s, int64_t n, z_t* y, z_t v) {
+  if (n <= 0) return HZ_OK;
+  k_fill<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, y, v);
+  HZ_HIP(hipGetLastError());
+  return HZ_OK;
+}
+
+__global__ void k_copy(int64_t n, const z_t* __restrict__ x, z_t* __restrict__ y) {
+  int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+
+int op_copy(hipStream_t s, int64_t n, const z_t* x, z_t* y) {
+  if (n <= 0) return HZ_OK;
+  k_copy<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, x, y);
+  HZ_HIP(hipGetLastError());
+  return HZ_OK;
+}
+
+// ---------------------------------------------------------------- patch load
+__global__ void k_patch(int np, const int* __restrict__ prow, const int* __restrict__ pptr,
+                        const int* __restrict__ pcol, const double* __restrict__ pval,
+                        const z_t* __restrict__ g, z_t* __restrict__ f) {
+  int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= np) return;
+  z_t acc = {0.0, 0.0};
+  for (int q = pptr[r]; q < pptr[r + 1]; ++q) {
+    z_t gv = g[pcol[q]];
+    acc.re = fma(pval[q], gv.re, acc.re);
+    acc.im = fma(pval[q], gv.im, acc.im);
+  }
+  f[prow[r]] = acc;
+}
+
+int op_load(hz_ctx ctx, const z_t* g, z_t* f) {
+  HZ_TRY(op_fill(ctx->stream, ctx->h.n, f, z_t{0.0, 0.0}));
+  int np = int(ctx->h.prow.size());
+  if (np > 0) {
+    k_patch<<<ceil_div(np, kBlock), kBlock, 0, ctx->stream>>>(np, ctx->d_prow.as<int>(), ctx->d_pptr.as<int>(),
+                                                            ctx->d_pcol.as<int>(), ctx->d_pval.as<double>(), g, f);
+    HZ_HIP(hipGetLastError());
+  }
+  return HZ_OK;
+}
+
+// ---------------------------------------------------------------- dot
+template <typename T>
+__global__ void k_dot_part(int64_t n, const cx<T>* __restrict__ a, const cx<T>* __restrict__ b,
+                           double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  double re = 0.0, im = 0.0;
+  int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+    z_t x = ccast<double>(a[i]), y = ccast<double>(b[i]);
+    re = fma(x.re, y.re, re);
+    re = fma(x.im, y.im, re);
+    im = fma(x.re, y.im, im);
+    im = fma(-x.im, y.re, im);
+  }
+  double sr = block_sum(re, lds);
+  double si = block_sum(im, lds);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sr;
+    part[2 * blockIdx.x + 1] = si;
+  }
+}
+
+__global__ void k_dot_fin(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double lds[kBlock / kWave];
+  double re = block_sum_strided(part, nb, 2, lds);
+  double im = block_sum_strided(part + 1, nb, 2, lds);
+  if (threadIdx.x == 0) {
+    out[0] = re;
+    out[1] = im;
+  }
+}
+
+int op_dotc(hz_ctx ctx, int64_t n, const z_t* a, const z_t* b, double* out_dev /*2*/) {
+  int rc = 0;
+  int g = reduce_grid(n);
+  DevBuf* part = ctx->buf("dot.part", sizeof(double) * 2 * g, &rc);
+  if (rc) return rc;
+  k_dot_part<double><<<g, kBlock, 0, ctx->stream>>>(n, a, b, part->as<double>());
+  HZ_HIP(hipGetLastError());
+  k_dot_fin<<<1, kBlock, 0, ctx->stream>>>(g, part->as<double>(), out_dev);
+  HZ_HIP(hipGetLastError());
+  return HZ_OK;
+}

@@ -1,0 +1,90 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function the header declares, and rejects bad input before touching HIP."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.cpu
+
+hz = pytest.importorskip("paper_2112_00087_amd.hz")
+
+
+@pytest.fixture(scope="module")
+def L():
+    return hz.lib()
+
+
+def test_exports_every_header_symbol(L):
+    import subprocess
+    names = hz.header_symbols()
+    assert {"hz_assemble", "hz_set_frequency", "hz_solve", "hz_solve_sweep", "hz_solve_adjoint"} <= set(names)
+    for name in names:
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", hz.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    assert set(names) <= exported
+
+
+def _mesh_struct(mesh):
+    keep = dict(xyz=np.ascontiguousarray(mesh["xyz"]), hex=np.ascontiguousarray(mesh["hex"], np.int32),
+                bf=np.ascontiguousarray(mesh["bface"], np.int32),
+                tag=np.ascontiguousarray(mesh["bface_tag"], np.int32),
+                src=np.ascontiguousarray(mesh["bface_src"], np.uint8))
+    m = hz.hz_mesh()
+    m.n_nodes, m.n_elems, m.n_bfaces = keep["xyz"].shape[0], keep["hex"].shape[0], keep["bf"].shape[0]
+    m.xyz = keep["xyz"].ctypes.data_as(C.POINTER(C.c_double))
+    m.hex = keep["hex"].ctypes.data_as(C.POINTER(C.c_int32))
+    m.bface = keep["bf"].ctypes.data_as(C.POINTER(C.c_int32))
+    m.bface_tag = keep["tag"].ctypes.data_as(C.POINTER(C.c_int32))
+    m.bface_src = keep["src"].ctypes.data_as(C.POINTER(C.c_uint8))
+    m.c, m.rho = 340.0, 1.2
+    return m, keep
+
+
+def test_assemble_rejects_bad_input_without_gpu(L):
+    out = C.c_void_p(1)
+    beta = hz._beta_array(np.zeros(6))
+    assert L.hz_assemble(None, beta, None, None, C.byref(out)) == hz.HZ_ERR_INVALID
+    assert out.value is None
+    assert "NULL" in hz.last_error()
+    mesh = W.box_mesh(2, 2, 2)
+    m, keep = _mesh_struct(mesh)
+    keep["hex"][0, 3] = 10_000          # node id out of range
+    assert L.hz_assemble(C.byref(m), beta, None, None, C.byref(out)) == hz.HZ_ERR_INVALID
+    assert "out of range" in hz.last_error()
+    m, keep = _mesh_struct(mesh)
+    keep["tag"][0] = 7                  # wall id out of range
+    assert L.hz_assemble(C.byref(m), beta, None, None, C.byref(out)) == hz.HZ_ERR_INVALID
+    m, keep = _mesh_struct(mesh)
+    keep["xyz"][3, 1] = np.nan
+    assert L.hz_assemble(C.byref(m), beta, None, None, C.byref(out)) == hz.HZ_ERR_INVALID
+    m, keep = _mesh_struct(mesh)
+    m.c = -1.0
+    assert L.hz_assemble(C.byref(m), beta, None, None, C.byref(out)) == hz.HZ_ERR_INVALID
+    eta = np.full(mesh["n_elems"], np.inf)
+    m, keep = _mesh_struct(mesh)
+    assert L.hz_assemble(C.byref(m), beta, eta.ctypes.data_as(C.POINTER(C.c_double)), None,
+                         C.byref(out)) == hz.HZ_ERR_INVALID
+    # a face that is not an element face
+    m, keep = _mesh_struct(mesh)
+    keep["bf"][0] = [0, 2, 18, 26]
+    assert L.hz_assemble(C.byref(m), beta, None, None, C.byref(out)) == hz.HZ_ERR_INVALID
+
+
+def test_null_context_and_options(L):
+    o = hz.make_opts()
+    info = hz.hz_solve_info()
+    assert L.hz_solve(None, C.byref(o), None, None, C.byref(info)) == hz.HZ_ERR_INVALID
+    assert L.hz_set_frequency(None, 100.0) == hz.HZ_ERR_INVALID
+    assert L.hz_sizes(None, None, None, None, None) == hz.HZ_ERR_INVALID
+    L.hz_destroy(None)   # ignored
+
+
+def test_opts_struct_layout_matches_header():
+    # 6 int32, 2 double, hz_c128, 2 int32
+    assert C.sizeof(hz.hz_solve_opts) == 6 * 4 + 2 * 8 + 16 + 2 * 4
+    assert C.sizeof(hz.hz_solve_info) == 4 * 4 + 3 * 8
+    assert hz.hz_mesh.xyz.offset == 16
