@@ -22,6 +22,10 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the complex128 product on this workload, from the
+# FETCH_SIZE / WRITE_SIZE passes recorded in profiles/ (calibrated against a
+# 1 GiB device copy); set to None whenever the kernel changes until re-measured.
+MEASURED_TRAFFIC = {"k_spmv<double>": 717.9e6}
 
 
 def log(*a):
@@ -49,6 +53,7 @@ def cpu_baseline(wl, gpu_iters, iters):
     dt = time.perf_counter() - t
     per_iter = dt / max(r.iters, 1)
     return {"value": per_iter * gpu_iters, "unit": "s", "cores": 1, "kind": "oracle",
+            "host_cpus": os.cpu_count(),
             "sample": f"{r.iters} BiCGStab iterations of the same system timed ({dt:.1f} s, "
                       f"{per_iter * 1e3:.1f} ms/iteration), scaled to the GPU's {gpu_iters} iterations"}
 
@@ -62,6 +67,10 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--no-extra", action="store_true", help="only the headline solve and the roofline")
     ap.add_argument("--spmv-reps", type=int, default=200)
+    ap.add_argument("--spmv-only", action="store_true",
+                    help="skip the solves (hardware-counter runs of the product kernel)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB device copy (reference for the traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
@@ -87,17 +96,26 @@ def main():
         model.set_frequency(freq)
         return model.solve(f, **opts)
 
-    for _ in range(args.warmup):
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.spmv_only:
+        model.set_frequency(freq)
+        args.steps = 0
+    for _ in range(args.warmup if not args.spmv_only else 0):
         _, info = step()
         log(f"warmup: {info}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = []
+    infos = [dict(iters=0, relres_true=None)]
     for _ in range(args.steps):
         _, info = step()
         infos.append(info)
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = (time.perf_counter() - t0) / max(args.steps, 1)
     log(f"timed: {dt:.4f} s/solve, {infos[-1]}")
 
     n, nnz = sizes["n_nodes"], sizes["nnz"]
@@ -105,13 +123,13 @@ def main():
     byts = spmv_bytes(n, nnz)
     gbs = byts / (ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+            "frac": gbs / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get("k_spmv<double>"),
             "kernel": "k_spmv<double> (complex128 sliced-ELL product)",
             "avg_kernel_ms": ms, "algorithmic_bytes": byts}
     log(f"spmv: {ms * 1e3:.1f} us, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
 
     extra = {}
-    if not args.no_extra:
+    if not args.no_extra and not args.spmv_only:
         ms32 = model.time_spmv(args.spmv_reps, "mixed")
         b32 = 12 * nnz + 4 * (n + 1) + 16 * n
         extra["spmv_c64_GBs"] = b32 / (ms32 * 1e-3) / 1e9
@@ -121,7 +139,7 @@ def main():
             model.set_frequency(freq)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            _, inf = model.solve(f, tol=1e-8, max_matvec=100000, **o)
+            _, inf = model.solve(f, tol=1e-8, max_matvec=30000, **o)
             torch.cuda.synchronize()
             extra[label] = {"s": time.perf_counter() - t, "status": inf["status"], "iters": inf["iters"],
                             "matvecs": inf["matvecs"], "inner_matvecs": inf["inner_matvecs"],
@@ -129,7 +147,7 @@ def main():
             log(f"{label}: {extra[label]}")
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and not args.spmv_only:
         cpu = cpu_baseline(wl, infos[-1]["iters"], args.cpu_iters)
         log(f"cpu baseline: {cpu}")
 
