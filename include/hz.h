@@ -204,9 +204,15 @@ int hz_solve(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* f_dev,
  *   F_dev, P_dev  [n_nodes][nfreq] row-major complex128 (column j of row i
  *          at i * nfreq + j); P is in: x0 (zero allowed), out: solutions
  *   infos  [nfreq] per-column results (may be NULL)
- * opts->method must be HZ_GMRES; opts->precision HZ_MIXED (complex64 inner
- * GMRES + FP64 refinement) or HZ_FP64.  Leaves the context's current
- * frequency unset (call hz_set_frequency before the next hz_solve). */
+ * opts->method is HZ_GMRES (restarted GMRES(restart), every restart cycle
+ * one refinement step) or HZ_BICGSTAB (each refinement step an inner
+ * BiCGStab solve to inner_tol); opts->precision HZ_MIXED (complex64 inner
+ * Krylov, FP64 residual / refinement / Gram-Schmidt coefficients / Givens)
+ * or HZ_FP64.  Columns converge independently; the call returns when all
+ * have reached tol or one has used max_matvec products.  Leaves the
+ * context's current frequency unset (call hz_set_frequency before the next
+ * hz_solve).  Environment: HZ_AUTOTUNE_CACHE names a text file in which
+ * tuned product variants are remembered across processes. */
 int hz_solve_sweep(hz_ctx ctx, int32_t nfreq, const double* freqs_host,
                    const hz_c128* F_dev, hz_c128* P_dev,
                    const hz_solve_opts* opts, hz_solve_info* infos);

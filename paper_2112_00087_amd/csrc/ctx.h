@@ -87,6 +87,13 @@ struct hz_ctx_s {
 
   std::vector<std::complex<double>> beta;   // [6]
   bool have_eta = false;
+  int params_version = 0;            // bumped by hz_set_params
+
+  // row-wise (CSR) copy of the real parts for the multi-vector product of
+  // the frequency sweep, built on first use for a params_version
+  int sweep_version = -1;
+  std::shared_ptr<void> sweep_data;  // owned row-wise operator data of the sweep
+  std::map<std::string, int> tuned;  // autotuned multi-vector product variants
 
   // scratch for solvers, keyed by name
   std::map<std::string, std::unique_ptr<DevBuf>> ws;

@@ -2,6 +2,3 @@
 int schwarz_solve(hz_ctx, const hz_solve_opts&, const z_t*, z_t*, hz_solve_info*) {
   return hz_fail(HZ_ERR_INVALID, "Schwarz method not available");
 }
-int sweep_solve(hz_ctx, int, const double*, const z_t*, z_t*, const hz_solve_opts&, hz_solve_info*) {
-  return hz_fail(HZ_ERR_INVALID, "sweep not available");
-}

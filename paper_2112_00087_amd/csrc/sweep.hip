@@ -1,0 +1,1255 @@
+// Frequency sweep: A(k_c) x_c = f_c for up to 64 wavenumbers at once.
+//
+// The columns of all frequencies are stored interleaved, element (row, c) at
+// row * s + c (s = column count rounded up to a power of two <= 64), so one
+// multi-vector product reads the real parts K, M (and M_eta) of a row once
+// and applies them to every column with that column's k_c: the matrix is
+// read once per s products.  Restarted GMRES(m) runs on all columns in
+// lock-step, each with its own FP64 Hessenberg matrix, Givens rotations and
+// convergence flag.  Every restart cycle is one step of iterative
+// refinement: the residual of the FP64 iterate is formed in FP64, the Arnoldi
+// cycle runs on the right-Jacobi operator in the storage precision (complex64
+// in mixed mode, with FP64 Gram-Schmidt coefficients and rotations), and the
+// correction is added in FP64.  The cycle's kernel sequence is captured once
+// in a HIP graph and replayed.  The product's thread layout (columns per lane,
+// block size) is chosen by timing the candidates on first use.
+#include <chrono>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
+
+#include "ops.h"
+#include "solve.h"
+
+namespace {
+
+constexpr int NV = 8;   // basis vectors per multi-dot chunk
+
+template <typename R>
+struct RowOp {
+  const int* rowptr;
+  const int* col;
+  const R* K;
+  const R* M;
+  const R* E;       // M_eta or nullptr
+  const int* bptr;  // boundary entries of each row
+  const int* bcol;
+  const cx<R>* B;   // sum_w beta_w B0_w
+};
+
+struct SwCol {
+  double k, k2, beta, thr2, est, inv_next, fn2, pad0;
+  int kk, done, cyc, nan, iters, cycles;
+};
+
+struct SwArr {
+  z_t* H;    // [s][(m+1) m]
+  double* cs;
+  z_t* sn;   // [s][m]
+  z_t* g;    // [s][m+1]
+  z_t* y;    // [s][m]
+  z_t* h1;   // [s][m+1]
+  z_t* h2;
+  int m;
+};
+
+// Sum of v over the threads of this block that hold the same column
+// (column = threadIdx.x % s, s a power of two <= 64); valid in threads 0..s-1.
+__device__ __forceinline__ double col_reduce(double v, int s, double* lds /*[4*64]*/) {
+  for (int o = 32; o >= s; o >>= 1) v += __shfl_xor(v, o, kWave);
+  int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane < s) lds[w * kWave + lane] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (int(threadIdx.x) < s)
+    for (int ww = 0; ww < int(blockDim.x) / kWave; ++ww) t += lds[ww * kWave + threadIdx.x];
+  __syncthreads();
+  return t;
+}
+
+// ---------------------------------------------------------------- product
+// Y[row, c] = (A(k_c) Z[:, c])[row]   or, with RESID, Y = F - A X and partial ||Y_c||^2.
+// L lanes per row, CPL columns per lane (s = L * CPL); block of blockDim.x threads.
+template <typename T, int L, int CPL, bool RESID>
+__global__ void __launch_bounds__(512) k_spmm(int64_t nrows, int s, RowOp<T> A, const double* __restrict__ kc,
+                                              const cx<T>* __restrict__ Z, const cx<T>* __restrict__ F,
+                                              cx<T>* __restrict__ Y, double* __restrict__ part) {
+  const int rpb = blockDim.x / L;
+  const int ln = threadIdx.x % L;
+  int row = blockIdx.x * rpb + threadIdx.x / L;
+  if (L == kWave) row = __builtin_amdgcn_readfirstlane(row);
+  double pn = 0.0;
+  if (row < nrows) {
+    cx<T> aK[CPL], aM[CPL], aE[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) aK[q] = aM[q] = aE[q] = cx<T>{T(0), T(0)};
+    const int q0 = A.rowptr[row], q1 = A.rowptr[row + 1];
+    for (int q = q0; q < q1; ++q) {
+      const int64_t j = A.col[q];
+      const T kv = A.K[q], mv = A.M[q];
+      const T ev = A.E ? A.E[q] : T(0);
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) {
+        cx<T> z = Z[j * s + ln + L * cc];
+        aK[cc].re = fma(kv, z.re, aK[cc].re);
+        aK[cc].im = fma(kv, z.im, aK[cc].im);
+        aM[cc].re = fma(mv, z.re, aM[cc].re);
+        aM[cc].im = fma(mv, z.im, aM[cc].im);
+        aE[cc].re = fma(ev, z.re, aE[cc].re);
+        aE[cc].im = fma(ev, z.im, aE[cc].im);
+      }
+    }
+    const int b0 = A.bptr[row], b1 = A.bptr[row + 1];
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+      const int c = ln + L * cc;
+      const T k = T(kc[2 * c]), k2 = T(kc[2 * c + 1]);
+      // K z - k^2 M z + i k^2 M_eta z
+      cx<T> y = {aK[cc].re - k2 * aM[cc].re - k2 * aE[cc].im, aK[cc].im - k2 * aM[cc].im + k2 * aE[cc].re};
+      cx<T> bz = {T(0), T(0)};
+      for (int q = b0; q < b1; ++q) cfma(bz, A.B[q], Z[int64_t(A.bcol[q]) * s + c]);
+      y.re -= k * bz.im;   // + i k (B z)
+      y.im += k * bz.re;
+      const int64_t e = int64_t(row) * s + c;
+      if (RESID) {
+        cx<T> r = F[e] - y;
+        Y[e] = r;
+        pn += double(r.re) * double(r.re) + double(r.im) * double(r.im);
+      } else {
+        Y[e] = y;
+      }
+    }
+  }
+  if (RESID) {
+    __shared__ double lds[8 * kWave];
+    // with CPL == 1 a thread's column is threadIdx.x % s
+    for (int o = 32; o >= s; o >>= 1) pn += __shfl_xor(pn, o, kWave);
+    int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    if (lane < s) lds[w * kWave + lane] = pn;
+    __syncthreads();
+    if (int(threadIdx.x) < s) {
+      double t = 0.0;
+      for (int ww = 0; ww < int(blockDim.x) / kWave; ++ww) t += lds[ww * kWave + threadIdx.x];
+      part[int64_t(blockIdx.x) * s + threadIdx.x] = t;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- vector kernels over [nrows][s]
+__global__ void k_in(int64_t n, int64_t nrows, int s, int nf, const z_t* __restrict__ P, const z_t* __restrict__ F,
+                     z_t* __restrict__ X, z_t* __restrict__ Fs) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= nrows * s) return;
+  int64_t row = e / s;
+  int c = int(e % s);
+  bool ok = row < n && c < nf;
+  X[e] = ok ? P[row * nf + c] : z_t{0.0, 0.0};
+  Fs[e] = ok ? F[row * nf + c] : z_t{0.0, 0.0};
+}
+
+__global__ void k_out(int64_t n, int s, int nf, const z_t* __restrict__ X, z_t* __restrict__ P) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= n * nf) return;
+  int64_t row = e / nf;
+  int c = int(e % nf);
+  P[e] = X[row * s + c];
+}
+
+// dinv[row, c] = 1 / A(k_c)_{row,row}
+template <typename T>
+__global__ void k_diag(int64_t n, int64_t nrows, int s, const int* __restrict__ dpos, const double* __restrict__ K,
+                       const double* __restrict__ M, const double* __restrict__ E, const z_t* __restrict__ Bd,
+                       const double* __restrict__ kc, z_t* __restrict__ d64, cx<T>* __restrict__ dT) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= nrows * s) return;
+  int64_t row = e / s;
+  int c = int(e % s);
+  z_t inv = {1.0, 0.0};
+  if (row < n) {
+    int64_t p = dpos[row];
+    double k = kc[2 * c], k2 = kc[2 * c + 1];
+    z_t b = Bd[row];
+    z_t d = {K[p] - k2 * M[p] - k * b.im, k * b.re + (E ? k2 * E[p] : 0.0)};
+    inv = crecip(d);
+  }
+  d64[e] = inv;
+  dT[e] = ccast<T>(inv);
+}
+
+// partial ||x_c||^2 per block, grid-stride
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_colnorm(int64_t total, int s, const cx<T>* __restrict__ x,
+                                                    double* __restrict__ part) {
+  __shared__ double lds[4 * kWave];
+  double v = 0.0;
+  for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock)
+    v += norm2(ccast<double>(x[e]));
+  double t = col_reduce(v, s, lds);
+  if (int(threadIdx.x) < s) part[int64_t(blockIdx.x) * s + threadIdx.x] = t;
+}
+
+// column c: sum of the partials of every block
+__global__ void k_colsum(int nblk, int s, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double lds[kBlock / kWave];
+  int c = blockIdx.x;
+  double t = block_sum_strided(part + c, nblk, s, lds);
+  if (threadIdx.x == 0) out[c] = t;
+}
+
+__global__ void k_init_cols(int s, SwCol* st, const double* fn2, double tol) {
+  int c = threadIdx.x;
+  if (c >= s) return;
+  st[c].fn2 = fn2[c];
+  st[c].thr2 = tol * tol * fn2[c];
+  st[c].iters = 0;
+  st[c].cycles = 0;
+  st[c].done = 0;
+  st[c].nan = 0;
+}
+
+// beta_c = ||R_c|| -> cycle start; block per column
+__global__ void k_beta_fin(int nblk, int s, SwCol* st, SwArr G, const double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  int c = blockIdx.x;
+  double rr = block_sum_strided(part + c, nblk, s, lds);
+  if (threadIdx.x != 0) return;
+  SwCol& S = st[c];
+  double b = sqrt(rr);
+  S.beta = b;
+  S.est = b;
+  S.kk = 0;
+  S.nan = S.nan || !isfinite(rr);
+  S.done = (rr <= S.thr2) || S.fn2 == 0.0 || S.nan;
+  S.cyc = S.done;
+  S.inv_next = b > 0.0 ? 1.0 / b : 0.0;
+  if (!S.done) S.cycles += 1;
+  z_t* g = G.g + int64_t(c) * (G.m + 1);
+  g[0] = z_t{b, 0.0};
+  for (int i = 1; i <= G.m; ++i) g[i] = z_t{0.0, 0.0};
+}
+
+// V0 = R / beta (storage precision), Z = dinv V0
+template <typename T>
+__global__ void k_v0(int64_t total, int s, const SwCol* __restrict__ st, const z_t* __restrict__ R,
+                     const cx<T>* __restrict__ dT, cx<T>* __restrict__ V0, cx<T>* __restrict__ Z) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= total) return;
+  int c = int(e % s);
+  const SwCol& S = st[c];
+  cx<T> v = {T(0), T(0)};
+  if (!S.cyc) v = ccast<T>(S.inv_next * R[e]);
+  V0[e] = v;
+  Z[e] = dT[e] * v;
+}
+
+// partial h_i[c] = V_i[:, c]^H w[:, c] for i in chunk blockIdx.y
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_mdot(int64_t total, int s, const SwCol* __restrict__ st,
+                                                 const cx<T>* __restrict__ V, int64_t ld, int j,
+                                                 const cx<T>* __restrict__ w, z_t* __restrict__ part) {
+  __shared__ double lds[4 * kWave];
+  const int c = threadIdx.x % s;
+  const int i0 = blockIdx.y * NV;
+  const bool act = !st[c].cyc;
+  double acc[2 * NV];
+#pragma unroll
+  for (int q = 0; q < 2 * NV; ++q) acc[q] = 0.0;
+  if (act) {
+    for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
+      z_t wv = ccast<double>(w[e]);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        int i = i0 + q;
+        if (i <= j) {
+          z_t a = ccast<double>(V[int64_t(i) * ld + e]);
+          acc[2 * q] = fma(a.re, wv.re, fma(a.im, wv.im, acc[2 * q]));
+          acc[2 * q + 1] = fma(a.re, wv.im, fma(-a.im, wv.re, acc[2 * q + 1]));
+        }
+      }
+    }
+  }
+  z_t* out = part + (int64_t(blockIdx.y) * gridDim.x + blockIdx.x) * NV * s;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double re = col_reduce(acc[2 * q], s, lds);
+    double im = col_reduce(acc[2 * q + 1], s, lds);
+    if (int(threadIdx.x) < s) out[q * s + threadIdx.x] = z_t{re, im};
+  }
+}
+
+// block (c, i): coefficient i of column c.  pass 1 -> h1; pass 2 -> h2, H[:, j] = h1 + h2
+__global__ void k_mdot_fin(int G_, int s, const SwCol* __restrict__ st, SwArr A, const z_t* __restrict__ part,
+                           int j, int pass) {
+  __shared__ double lds[kBlock / kWave];
+  int c = blockIdx.x, i = blockIdx.y;
+  if (st[c].cyc) return;
+  int ch = i / NV, q = i % NV;
+  const double* base = reinterpret_cast<const double*>(part + (int64_t(ch) * G_ * NV + q) * s + c);
+  double re = block_sum_strided(base, G_, 2 * NV * s, lds);
+  double im = block_sum_strided(base + 1, G_, 2 * NV * s, lds);
+  if (threadIdx.x == 0) {
+    z_t h = {re, im};
+    if (pass == 1) {
+      A.h1[int64_t(c) * (A.m + 1) + i] = h;
+    } else {
+      A.h2[int64_t(c) * (A.m + 1) + i] = h;
+      A.H[int64_t(c) * (A.m + 1) * A.m + int64_t(j) * (A.m + 1) + i] = A.h1[int64_t(c) * (A.m + 1) + i] + h;
+    }
+  }
+}
+
+// w -= sum_i h_i V_i per column; NORM: partial ||w_c||^2
+template <typename T, bool NORM>
+__global__ void __launch_bounds__(kBlock) k_axpy(int64_t total, int s, const SwCol* __restrict__ st, SwArr A,
+                                                 const cx<T>* __restrict__ V, int64_t ld, int j, int pass,
+                                                 cx<T>* __restrict__ w, double* __restrict__ part) {
+  __shared__ double lds[4 * kWave];
+  const int c = threadIdx.x % s;
+  const bool act = !st[c].cyc;
+  const z_t* h = (pass == 1 ? A.h1 : A.h2) + int64_t(c) * (A.m + 1);
+  double nn = 0.0;
+  if (act) {
+    for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
+      z_t acc = ccast<double>(w[e]);
+      for (int i = 0; i <= j; ++i) {
+        z_t v = ccast<double>(V[int64_t(i) * ld + e]);
+        z_t hi = h[i];
+        acc.re -= hi.re * v.re - hi.im * v.im;
+        acc.im -= hi.re * v.im + hi.im * v.re;
+      }
+      cx<T> ws = ccast<T>(acc);
+      w[e] = ws;
+      if (NORM) nn += norm2(ccast<double>(ws));
+    }
+  }
+  if (NORM) {
+    double t = col_reduce(nn, s, lds);
+    if (int(threadIdx.x) < s) part[int64_t(blockIdx.x) * s + threadIdx.x] = t;
+  }
+}
+
+// block per column: subdiagonal, rotations, residual estimate
+__global__ void k_givens_fin(int G_, int s, SwCol* st, SwArr A, const double* __restrict__ part, int j,
+                             double inner_tol) {
+  __shared__ double lds[kBlock / kWave];
+  int c = blockIdx.x;
+  const int cyc = st[c].cyc;
+  __syncthreads();
+  if (cyc) return;
+  double ww = block_sum_strided(part + c, G_, s, lds);
+  if (threadIdx.x != 0) return;
+  SwCol& S = st[c];
+  const int m = A.m;
+  z_t* H = A.H + int64_t(c) * (m + 1) * m + int64_t(j) * (m + 1);
+  double* cs = A.cs + int64_t(c) * m;
+  z_t* sn = A.sn + int64_t(c) * m;
+  z_t* g = A.g + int64_t(c) * (m + 1);
+  double hn = sqrt(ww);
+  H[j + 1] = z_t{hn, 0.0};
+  for (int i = 0; i < j; ++i) {
+    z_t a = H[i], b = H[i + 1];
+    H[i] = cs[i] * a + sn[i] * b;
+    H[i + 1] = (-1.0 * (conj(sn[i]) * a)) + cs[i] * b;
+  }
+  z_t a = H[j], b = H[j + 1];
+  double rho = sqrt(norm2(a) + norm2(b));
+  double cc;
+  z_t sv;
+  if (rho == 0.0) {
+    cc = 1.0;
+    sv = z_t{0.0, 0.0};
+  } else if (norm2(a) == 0.0) {
+    cc = 0.0;
+    sv = z_t{1.0, 0.0};
+  } else {
+    double aa = sqrt(norm2(a));
+    cc = aa / rho;
+    sv = (1.0 / (aa * rho)) * (a * conj(b));
+  }
+  cs[j] = cc;
+  sn[j] = sv;
+  H[j] = cc * a + sv * b;
+  H[j + 1] = z_t{0.0, 0.0};
+  z_t gj = g[j];
+  g[j + 1] = -1.0 * (conj(sv) * gj);
+  g[j] = cc * gj;
+  S.kk = j + 1;
+  S.iters += 1;
+  S.est = sqrt(norm2(g[j + 1]));
+  bool bad = !isfinite(hn) || !isfinite(S.est);
+  if (bad) S.nan = 1;
+  double lim = inner_tol * S.beta;
+  if (bad || hn == 0.0 || S.est * S.est <= S.thr2 || S.est <= lim) S.cyc = 1;
+  S.inv_next = hn > 0.0 ? 1.0 / hn : 0.0;
+}
+
+// V_{j+1} = w / h, Z = dinv V_{j+1}
+template <typename T>
+__global__ void k_scale(int64_t total, int s, const SwCol* __restrict__ st, const cx<T>* __restrict__ dT,
+                        cx<T>* __restrict__ w, cx<T>* __restrict__ Z) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= total) return;
+  int c = int(e % s);
+  const SwCol& S = st[c];
+  if (S.cyc) return;
+  cx<T> v = ccast<T>(S.inv_next * ccast<double>(w[e]));
+  w[e] = v;
+  Z[e] = dT[e] * v;
+}
+
+__global__ void k_solve_y(int s, const SwCol* __restrict__ st, SwArr A) {
+  int c = threadIdx.x;
+  if (c >= s) return;
+  const SwCol& S = st[c];
+  if (S.done || S.nan) return;
+  const int m = A.m, k = S.kk;
+  const z_t* H = A.H + int64_t(c) * (m + 1) * m;
+  const z_t* g = A.g + int64_t(c) * (m + 1);
+  z_t* y = A.y + int64_t(c) * m;
+  for (int i = k - 1; i >= 0; --i) {
+    z_t acc = g[i];
+    for (int l = i + 1; l < k; ++l) acc = acc - H[int64_t(l) * (m + 1) + i] * y[l];
+    y[i] = cdiv(acc, H[int64_t(i) * (m + 1) + i]);
+  }
+}
+
+// X += dinv (V y)   (FP64)
+template <typename T>
+__global__ void k_update(int64_t total, int s, const SwCol* __restrict__ st, SwArr A, const cx<T>* __restrict__ V,
+                         int64_t ld, const z_t* __restrict__ d64, z_t* __restrict__ X) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= total) return;
+  int c = int(e % s);
+  const SwCol& S = st[c];
+  if (S.done || S.nan || S.kk == 0) return;
+  const z_t* y = A.y + int64_t(c) * A.m;
+  z_t acc = {0.0, 0.0};
+  for (int i = 0; i < S.kk; ++i) {
+    z_t v = ccast<double>(V[int64_t(i) * ld + e]);
+    cfma(acc, y[i], v);
+  }
+  z_t dx = d64[e] * acc;
+  X[e] = X[e] + dx;
+}
+
+// ---------------------------------------------------------------- lock-step BiCGStab
+// Per-column state of the batched BiCGStab (inner solve of one refinement step).
+struct BcCol {
+  double k, k2, fn2, thr2, beta, ithr2, rr, ss, rhat2, pad0;
+  z_t rho, rho_old, alpha, omega;
+  int done, idone, early, reset, nan, iters, outer, inner_now;
+};
+
+template <typename T>
+struct BcVec {
+  cx<T>* r;
+  cx<T>* rhat;
+  cx<T>* p;
+  cx<T>* v;
+  cx<T>* s;
+  cx<T>* t;
+  cx<T>* zp;   // dinv p (input of the product)
+  cx<T>* zs;   // dinv s
+  cx<T>* u;    // correction (unscaled)
+  const cx<T>* dT;
+};
+
+__device__ __forceinline__ bool bc_off(const BcCol& S) { return S.done || S.idone || S.nan; }
+
+// after the outer residual: beta_c, outer convergence; inner start r = R / beta
+__global__ void k_bc_beta(int nblk, int s, BcCol* st, const double* __restrict__ part, double tol,
+                          double inner_tol) {
+  __shared__ double lds[kBlock / kWave];
+  int c = blockIdx.x;
+  double rr = block_sum_strided(part + c, nblk, s, lds);
+  if (threadIdx.x != 0) return;
+  BcCol& S = st[c];
+  double b = sqrt(rr);
+  S.beta = b;
+  S.nan = S.nan || !isfinite(rr);
+  S.done = (rr <= S.thr2) || S.fn2 == 0.0 || S.nan;
+  S.idone = S.done;
+  S.early = 0;
+  S.reset = 0;
+  S.inner_now = 0;
+  double lim = b > 0.0 ? 0.5 * tol * sqrt(S.fn2) / b : 1.0;
+  double it = inner_tol > lim ? inner_tol : lim;
+  S.ithr2 = it * it;
+  if (!S.done) S.outer += 1;
+}
+
+template <typename T>
+__global__ void k_bc_start(int64_t total, int s, const BcCol* __restrict__ st, const z_t* __restrict__ R,
+                           BcVec<T> W) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= total) return;
+  const BcCol& S = st[e % s];
+  cx<T> r = {T(0), T(0)};
+  if (!S.done && S.beta > 0.0) r = ccast<T>((1.0 / S.beta) * R[e]);
+  const cx<T> z = {T(0), T(0)};
+  W.r[e] = r;
+  W.rhat[e] = r;
+  W.p[e] = z;
+  W.v[e] = z;
+  W.u[e] = z;
+}
+
+// partial column dots over [total], written as three quantities per column:
+// NQ == 1: (-, -, |b|^2); NQ == 2: (a^H b, -); NQ == 3: (a^H b, |a|^2)
+template <typename T, int NQ>
+__global__ void __launch_bounds__(kBlock) k_bc_dots(int64_t total, int s, const BcCol* __restrict__ st,
+                                                    const cx<T>* __restrict__ a, const cx<T>* __restrict__ b,
+                                                    double* __restrict__ part) {
+  __shared__ double lds[4 * kWave];
+  const int c = threadIdx.x % s;
+  double q[3] = {0.0, 0.0, 0.0};
+  if (!bc_off(st[c])) {
+    for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
+      z_t y = ccast<double>(b[e]);
+      if (NQ == 1) {
+        q[2] += norm2(y);
+      } else {
+        z_t x = ccast<double>(a[e]);
+        q[0] = fma(x.re, y.re, fma(x.im, y.im, q[0]));
+        q[1] = fma(x.re, y.im, fma(-x.im, y.re, q[1]));
+        if (NQ == 3) q[2] += norm2(x);
+      }
+    }
+  }
+  for (int i = 0; i < 3; ++i) {
+    double t = col_reduce(q[i], s, lds);
+    if (int(threadIdx.x) < s) part[(int64_t(blockIdx.x) * 3 + i) * s + threadIdx.x] = t;
+  }
+}
+
+// finalize kernels: block per column
+__device__ __forceinline__ double bc_sum(int G_, int s, const double* part, int c, int i, double* lds) {
+  return block_sum_strided(part + int64_t(i) * s + c, G_, 3 * s, lds);
+}
+
+__global__ void k_bc_rho0(int G_, int s, BcCol* st, const double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  int c = blockIdx.x;
+  const int off = st[c].done;
+  __syncthreads();
+  if (off) return;
+  double rr = bc_sum(G_, s, part, c, 2, lds);
+  if (threadIdx.x != 0) return;
+  BcCol& S = st[c];
+  S.rr = rr;
+  S.rho = z_t{rr, 0.0};
+  S.rho_old = S.alpha = S.omega = z_t{1.0, 0.0};
+  S.rhat2 = rr;
+  S.idone = (rr == 0.0);
+}
+
+// p = r + beta (p - omega v); zp = dinv p
+template <typename T>
+__global__ void k_bc_p(int64_t total, int s, const BcCol* __restrict__ st, BcVec<T> W) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= total) return;
+  const BcCol& S = st[e % s];
+  if (bc_off(S)) return;
+  cx<T> p;
+  if (S.reset) {
+    p = W.r[e];
+    W.rhat[e] = p;
+  } else {
+    z_t bt = cdiv(S.rho, S.rho_old) * cdiv(S.alpha, S.omega);
+    z_t pv = ccast<double>(W.p[e]) - S.omega * ccast<double>(W.v[e]);
+    p = ccast<T>(ccast<double>(W.r[e]) + bt * pv);
+  }
+  W.p[e] = p;
+  W.zp[e] = W.dT[e] * p;
+}
+
+__global__ void k_bc_alpha(int G_, int s, BcCol* st, const double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  int c = blockIdx.x;
+  const int off = bc_off(st[c]);
+  __syncthreads();
+  if (off) return;
+  double re = bc_sum(G_, s, part, c, 0, lds);
+  double im = bc_sum(G_, s, part, c, 1, lds);
+  if (threadIdx.x != 0) return;
+  BcCol& S = st[c];
+  S.reset = 0;
+  z_t rv = {re, im};
+  if (norm2(rv) == 0.0 || !isfinite(re) || !isfinite(im)) {
+    S.alpha = z_t{0.0, 0.0};
+    S.reset = 1;
+  } else {
+    S.alpha = cdiv(S.rho, rv);
+  }
+}
+
+// s = r - alpha v; zs = dinv s; partial ||s||^2
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bc_s(int64_t total, int s, const BcCol* __restrict__ st, BcVec<T> W,
+                                                 double* __restrict__ part) {
+  __shared__ double lds[4 * kWave];
+  const int c = threadIdx.x % s;
+  const BcCol& S = st[c];
+  double nn = 0.0;
+  if (!bc_off(S)) {
+    for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
+      cx<T> sv = ccast<T>(ccast<double>(W.r[e]) - S.alpha * ccast<double>(W.v[e]));
+      W.s[e] = sv;
+      W.zs[e] = W.dT[e] * sv;
+      nn += norm2(ccast<double>(sv));
+    }
+  }
+  double t = col_reduce(nn, s, lds);
+  if (int(threadIdx.x) < s) part[(int64_t(blockIdx.x) * 3 + 2) * s + threadIdx.x] = t;
+}
+
+__global__ void k_bc_sfin(int G_, int s, BcCol* st, const double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  int c = blockIdx.x;
+  const int off = bc_off(st[c]);
+  __syncthreads();
+  if (off) return;
+  double ss = bc_sum(G_, s, part, c, 2, lds);
+  if (threadIdx.x != 0) return;
+  st[c].ss = ss;
+  st[c].early = ss <= st[c].ithr2 ? 1 : 0;
+}
+
+__global__ void k_bc_omega(int G_, int s, BcCol* st, const double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  int c = blockIdx.x;
+  const int off = bc_off(st[c]) || st[c].early;
+  __syncthreads();
+  if (off) return;
+  double re = bc_sum(G_, s, part, c, 0, lds);
+  double im = bc_sum(G_, s, part, c, 1, lds);
+  double tt = bc_sum(G_, s, part, c, 2, lds);
+  if (threadIdx.x == 0) st[c].omega = tt > 0.0 ? z_t{re / tt, im / tt} : z_t{0.0, 0.0};
+}
+
+// u += alpha zp + omega zs; r = s - omega t; partials rhat^H r, ||r||^2
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bc_xr(int64_t total, int s, const BcCol* __restrict__ st, BcVec<T> W,
+                                                  double* __restrict__ part) {
+  __shared__ double lds[4 * kWave];
+  const int c = threadIdx.x % s;
+  const BcCol& S = st[c];
+  double q[3] = {0.0, 0.0, 0.0};
+  if (!bc_off(S)) {
+    for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
+      z_t u = ccast<double>(W.u[e]) + S.alpha * ccast<double>(W.zp[e]);
+      if (S.early) {
+        W.u[e] = ccast<T>(u);
+        continue;
+      }
+      z_t sv = ccast<double>(W.s[e]);
+      W.u[e] = ccast<T>(u + S.omega * ccast<double>(W.zs[e]));
+      cx<T> r = ccast<T>(sv - S.omega * ccast<double>(W.t[e]));
+      W.r[e] = r;
+      z_t a = ccast<double>(W.rhat[e]), b = ccast<double>(r);
+      q[0] = fma(a.re, b.re, fma(a.im, b.im, q[0]));
+      q[1] = fma(a.re, b.im, fma(-a.im, b.re, q[1]));
+      q[2] += norm2(b);
+    }
+  }
+  for (int i = 0; i < 3; ++i) {
+    double t = col_reduce(q[i], s, lds);
+    if (int(threadIdx.x) < s) part[(int64_t(blockIdx.x) * 3 + i) * s + threadIdx.x] = t;
+  }
+}
+
+__global__ void k_bc_rho(int G_, int s, BcCol* st, const double* __restrict__ part, int inner_cap) {
+  __shared__ double lds[kBlock / kWave];
+  int c = blockIdx.x;
+  BcCol& S = st[c];
+  const int off = bc_off(S), early = S.early;
+  __syncthreads();
+  if (off) return;
+  if (early) {
+    if (threadIdx.x == 0) {
+      S.iters += 1;
+      S.inner_now += 1;
+      S.rr = S.ss;
+      S.idone = 1;
+      S.early = 0;
+    }
+    return;
+  }
+  double re = bc_sum(G_, s, part, c, 0, lds);
+  double im = bc_sum(G_, s, part, c, 1, lds);
+  double rr = bc_sum(G_, s, part, c, 2, lds);
+  if (threadIdx.x != 0) return;
+  S.iters += 1;
+  S.inner_now += 1;
+  S.rho_old = S.rho;
+  S.rho = z_t{re, im};
+  S.rr = rr;
+  if (!isfinite(rr) || !isfinite(re) || !isfinite(im)) {
+    S.nan = 1;
+  } else if (rr <= S.ithr2 || S.inner_now >= inner_cap) {
+    S.idone = 1;
+  } else if (sqrt(norm2(S.rho)) < 1e-300 * sqrt(S.rhat2 * rr) || norm2(S.omega) == 0.0) {
+    S.reset = 1;
+    S.rho = z_t{rr, 0.0};
+    S.rho_old = S.alpha = S.omega = z_t{1.0, 0.0};
+    S.rhat2 = rr;
+  }
+}
+
+// X += beta u  (FP64), columns still active in the outer loop
+template <typename T>
+__global__ void k_bc_update(int64_t total, int s, const BcCol* __restrict__ st, const cx<T>* __restrict__ u,
+                            z_t* __restrict__ X) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= total) return;
+  const BcCol& S = st[e % s];
+  if (S.done || S.nan) return;
+  z_t d = ccast<double>(u[e]);
+  X[e] = z_t{fma(S.beta, d.re, X[e].re), fma(S.beta, d.im, X[e].im)};
+}
+
+__global__ void k_bc_init_cols(int s, BcCol* st, const double* fn2, double tol) {
+  int c = threadIdx.x;
+  if (c >= s) return;
+  st[c].fn2 = fn2[c];
+  st[c].thr2 = tol * tol * fn2[c];
+}
+
+// ---------------------------------------------------------------- dispatch of product variants
+struct Variant {
+  int cpl = 1, bs = 256;
+};
+
+template <typename T, bool RESID>
+int launch_spmm(hipStream_t stream, const Variant& v, int64_t nrows, int s, const RowOp<T>& A, const double* st,
+                const cx<T>* Z, const cx<T>* F, cx<T>* Y, double* part, int* nblk_out) {
+  const int L = s / v.cpl;
+  const int rpb = v.bs / L;
+  const int nblk = int((nrows + rpb - 1) / rpb);
+  if (nblk_out) *nblk_out = nblk;
+#define HZ_SPMM_CASE(LL, CC)                                                                               \
+  if (L == LL && v.cpl == CC) {                                                                             \
+    k_spmm<T, LL, CC, RESID><<<nblk, v.bs, 0, stream>>>(nrows, s, A, st, Z, F, Y, part);                    \
+    HZ_HIP(hipGetLastError());                                                                              \
+    return HZ_OK;                                                                                           \
+  }
+  HZ_SPMM_CASE(1, 1) HZ_SPMM_CASE(2, 1) HZ_SPMM_CASE(4, 1) HZ_SPMM_CASE(8, 1) HZ_SPMM_CASE(16, 1)
+  HZ_SPMM_CASE(32, 1) HZ_SPMM_CASE(64, 1)
+  if (!RESID) {
+    HZ_SPMM_CASE(1, 2) HZ_SPMM_CASE(2, 2) HZ_SPMM_CASE(4, 2) HZ_SPMM_CASE(8, 2) HZ_SPMM_CASE(16, 2)
+    HZ_SPMM_CASE(32, 2)
+  }
+#undef HZ_SPMM_CASE
+  return hz_fail(HZ_ERR_INVALID, "no product variant for s=%d cpl=%d", s, v.cpl);
+}
+
+// ---------------------------------------------------------------- row-wise operator data
+struct SweepData {
+  int64_t nrows = 0;
+  DevBuf rowptr, col, K64, M64, E64, K32, M32, E32, bptr, bcol, B64, B32, Bdiag, dpos;
+  bool eta = false;
+};
+
+template <typename V>
+int upload(DevBuf& b, const std::vector<V>& h) {
+  HZ_TRY(b.ensure(sizeof(V) * std::max<size_t>(h.size(), 1)));
+  if (!h.empty()) HZ_HIP(hipMemcpy(b.p, h.data(), sizeof(V) * h.size(), hipMemcpyHostToDevice));
+  return HZ_OK;
+}
+
+int build_sweep_data(hz_ctx ctx, SweepData* D) {
+  const HostAsm& a = ctx->h;
+  const int64_t n = a.n, nrows = ctx->sell.n_rows, nnz = int64_t(a.col.size());
+  D->nrows = nrows;
+  std::vector<int> rowptr(nrows + 1), col(a.col.begin(), a.col.end());
+  for (int64_t i = 0; i <= nrows; ++i) rowptr[i] = int(a.rowptr[std::min(i, n)]);
+  HZ_TRY(upload(D->rowptr, rowptr));
+  HZ_TRY(upload(D->col, col));
+  HZ_TRY(upload(D->K64, a.K));
+  HZ_TRY(upload(D->M64, a.M));
+  std::vector<float> f(nnz);
+  for (int64_t q = 0; q < nnz; ++q) f[q] = float(a.K[q]);
+  HZ_TRY(upload(D->K32, f));
+  for (int64_t q = 0; q < nnz; ++q) f[q] = float(a.M[q]);
+  HZ_TRY(upload(D->M32, f));
+  D->eta = ctx->have_eta && !a.Meta.empty();
+  if (D->eta) {
+    HZ_TRY(upload(D->E64, a.Meta));
+    for (int64_t q = 0; q < nnz; ++q) f[q] = float(a.Meta[q]);
+    HZ_TRY(upload(D->E32, f));
+  }
+  // boundary entries grouped by row (CSR order)
+  std::vector<int64_t> order(a.bpos.size());
+  for (size_t e = 0; e < order.size(); ++e) order[e] = int64_t(e);
+  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return a.bpos[x] < a.bpos[y]; });
+  std::vector<int> bptr(nrows + 1, 0), bcol;
+  std::vector<z_t> B64;
+  std::vector<c_t> B32;
+  std::vector<z_t> Bd(n, z_t{0.0, 0.0});
+  int64_t row = 0;
+  for (int64_t t = 0; t < int64_t(order.size()); ++t) {
+    int64_t e = order[t], pos = a.bpos[e];
+    while (a.rowptr[row + 1] <= pos) ++row;
+    double re = 0.0, im = 0.0;
+    for (int w = 0; w < 6; ++w) {
+      re += ctx->beta[w].real() * a.bmass[e * 6 + w];
+      im += ctx->beta[w].imag() * a.bmass[e * 6 + w];
+    }
+    bptr[row + 1] += 1;
+    bcol.push_back(a.col[pos]);
+    B64.push_back(z_t{re, im});
+    B32.push_back(c_t{float(re), float(im)});
+    if (a.col[pos] == row) Bd[row] = z_t{re, im};
+  }
+  for (int64_t i = 0; i < nrows; ++i) bptr[i + 1] += bptr[i];
+  HZ_TRY(upload(D->bptr, bptr));
+  HZ_TRY(upload(D->bcol, bcol));
+  HZ_TRY(upload(D->B64, B64));
+  HZ_TRY(upload(D->B32, B32));
+  HZ_TRY(upload(D->Bdiag, Bd));
+  std::vector<int> dpos(n);
+  for (int64_t i = 0; i < n; ++i) dpos[i] = int(a.diag[i]);
+  HZ_TRY(upload(D->dpos, dpos));
+  return HZ_OK;
+}
+
+template <typename T> RowOp<T> row_op(const SweepData& D);
+template <> RowOp<double> row_op<double>(const SweepData& D) {
+  return {D.rowptr.as<int>(), D.col.as<int>(), D.K64.as<double>(), D.M64.as<double>(),
+          D.eta ? D.E64.as<double>() : nullptr, D.bptr.as<int>(), D.bcol.as<int>(), D.B64.as<z_t>()};
+}
+template <> RowOp<float> row_op<float>(const SweepData& D) {
+  return {D.rowptr.as<int>(), D.col.as<int>(), D.K32.as<float>(), D.M32.as<float>(),
+          D.eta ? D.E32.as<float>() : nullptr, D.bptr.as<int>(), D.bcol.as<int>(), D.B32.as<c_t>()};
+}
+
+// ---------------------------------------------------------------- autotuner
+std::string tune_key(int64_t n, int64_t nnz, int s, int bytes) {
+  std::ostringstream o;
+  o << "spmm n=" << n << " nnz=" << nnz << " s=" << s << " t=" << bytes;
+  return o.str();
+}
+
+void load_tune_cache(hz_ctx ctx) {
+  const char* path = std::getenv("HZ_AUTOTUNE_CACHE");
+  if (!path) return;
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    auto p = line.rfind('|');
+    if (p == std::string::npos) continue;
+    ctx->tuned[line.substr(0, p)] = std::atoi(line.c_str() + p + 1);
+  }
+}
+
+void save_tune_entry(const std::string& key, int code) {
+  const char* path = std::getenv("HZ_AUTOTUNE_CACHE");
+  if (!path) return;
+  std::ofstream out(path, std::ios::app);
+  out << key << "|" << code << "\n";
+}
+
+template <typename T>
+int autotune(hz_ctx ctx, hipStream_t stream, int64_t nrows, int s, const RowOp<T>& A, const double* st,
+             const cx<T>* Z, cx<T>* Y, Variant* best) {
+  const std::string key = tune_key(ctx->h.n, int64_t(ctx->h.col.size()), s, int(sizeof(T)));
+  if (ctx->tuned.empty()) load_tune_cache(ctx);
+  auto it = ctx->tuned.find(key);
+  if (it != ctx->tuned.end()) {
+    best->cpl = it->second / 1000;
+    best->bs = it->second % 1000;
+    return HZ_OK;
+  }
+  std::vector<Variant> cands;
+  for (int cpl : {1, 2})
+    for (int bs : {128, 256, 512}) {
+      if (cpl > s) continue;
+      if (bs < s / cpl) continue;
+      cands.push_back(Variant{cpl, bs});
+    }
+  hipEvent_t e0, e1;
+  HZ_HIP(hipEventCreate(&e0));
+  HZ_HIP(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  for (const Variant& v : cands) {
+    HZ_TRY((launch_spmm<T, false>(stream, v, nrows, s, A, st, Z, nullptr, Y, nullptr, nullptr)));
+    HZ_HIP(hipEventRecord(e0, stream));
+    for (int r = 0; r < 5; ++r)
+      HZ_TRY((launch_spmm<T, false>(stream, v, nrows, s, A, st, Z, nullptr, Y, nullptr, nullptr)));
+    HZ_HIP(hipEventRecord(e1, stream));
+    HZ_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HZ_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      *best = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  int code = best->cpl * 1000 + best->bs;
+  ctx->tuned[key] = code;
+  save_tune_entry(key, code);
+  return HZ_OK;
+}
+
+// Buffers and common set-up of one sweep call.
+template <typename T>
+struct Sweep {
+  int s = 1, nf = 0, Gr = 1, nblk_res = 1;
+  int64_t n = 0, nrows = 0, total = 0;
+  z_t *X = nullptr, *Fs = nullptr, *R = nullptr, *d64 = nullptr;
+  cx<T>* dT = nullptr;
+  double *kc = nullptr, *part = nullptr, *cn = nullptr;
+  Variant vres, vin;
+  RowOp<double> A64;
+  RowOp<T> AT;
+};
+
+template <typename T>
+int sweep_setup(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const z_t* Fin, const z_t* Pio,
+                Sweep<T>* W, const std::string& p, cx<T>* tune_z, cx<T>* tune_y) {
+  int rc = 0;
+  int s = 1;
+  while (s < nf) s <<= 1;
+  W->s = s;
+  W->nf = nf;
+  W->n = ctx->h.n;
+  W->nrows = D.nrows;
+  W->total = D.nrows * s;
+  const int64_t total = W->total;
+  auto buf = [&](const char* nm, size_t bytes) -> void* {
+    DevBuf* b = ctx->buf(p + nm, bytes, &rc);
+    return rc ? nullptr : b->p;
+  };
+  W->X = static_cast<z_t*>(buf("X", sizeof(z_t) * total));
+  W->Fs = static_cast<z_t*>(buf("F", sizeof(z_t) * total));
+  W->R = static_cast<z_t*>(buf("R", sizeof(z_t) * total));
+  W->d64 = static_cast<z_t*>(buf("d64", sizeof(z_t) * total));
+  W->dT = static_cast<cx<T>*>(buf("dT", sizeof(cx<T>) * total));
+  W->kc = static_cast<double*>(buf("kc", sizeof(double) * 2 * s));
+  W->cn = static_cast<double*>(buf("cn", sizeof(double) * s));
+  if (rc) return rc;
+  W->Gr = int(std::min<int64_t>(std::max<int64_t>(total / kBlock, 1), 2048));
+  W->nblk_res = int((D.nrows + kBlock / s - 1) / (kBlock / s));
+  W->part = static_cast<double*>(buf("part", sizeof(double) * 3 * std::max<int64_t>(W->Gr, W->nblk_res) * s));
+  if (rc) return rc;
+  hipStream_t cs = ctx->stream;
+  std::vector<double> kc(2 * s, 0.0);   // padding columns: k = 0 and a zero right-hand side
+  for (int c = 0; c < nf; ++c) {
+    double k = 2.0 * M_PI * freqs[c] / ctx->c;
+    kc[2 * c] = k;
+    kc[2 * c + 1] = k * k;
+  }
+  HZ_HIP(hipMemcpyAsync(W->kc, kc.data(), sizeof(double) * 2 * s, hipMemcpyHostToDevice, cs));
+  k_in<<<ceil_div(total, kBlock), kBlock, 0, cs>>>(W->n, W->nrows, s, nf, Pio, Fin, W->X, W->Fs);
+  k_diag<T><<<ceil_div(total, kBlock), kBlock, 0, cs>>>(W->n, W->nrows, s, D.dpos.as<int>(), D.K64.as<double>(),
+                                                       D.M64.as<double>(), D.eta ? D.E64.as<double>() : nullptr,
+                                                       D.Bdiag.as<z_t>(), W->kc, W->d64, W->dT);
+  k_colnorm<double><<<W->Gr, kBlock, 0, cs>>>(total, s, W->Fs, W->part);
+  k_colsum<<<s, kBlock, 0, cs>>>(W->Gr, s, W->part, W->cn);
+  HZ_HIP(hipGetLastError());
+  W->A64 = row_op<double>(D);
+  W->AT = row_op<T>(D);
+  W->vres.cpl = 1;            // FP64 residual product: one lane per column
+  W->vres.bs = kBlock;
+  HZ_TRY(autotune<T>(ctx, cs, W->nrows, s, W->AT, W->kc, tune_z, tune_y, &W->vin));
+  return HZ_OK;
+}
+
+// A graph captured on a private stream that is ordered after the context
+// stream (the null stream cannot be captured).
+struct Graph {
+  hipStream_t gs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev = nullptr;
+  ~Graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ev) (void)hipEventDestroy(ev);
+    if (gs) (void)hipStreamDestroy(gs);
+  }
+  int stream(hipStream_t after) {
+    if (!gs) HZ_HIP(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+    if (!ev) HZ_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HZ_HIP(hipEventRecord(ev, after));
+    HZ_HIP(hipStreamWaitEvent(gs, ev, 0));
+    return HZ_OK;
+  }
+  template <class F>
+  int capture(F body) {
+    HZ_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+    int crc = body(gs);
+    hipError_t ce = hipStreamEndCapture(gs, &graph);
+    if (crc < 0) return crc;
+    if (ce != hipSuccess) return hz_fail(HZ_ERR_HIP, "graph capture: %s", hipGetErrorString(ce));
+    HZ_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    return HZ_OK;
+  }
+  int launch() {
+    HZ_HIP(hipGraphLaunch(exec, gs));
+    return HZ_OK;
+  }
+};
+
+// Residual of the final iterate (FP64), copy-out and per-column results.
+template <typename T>
+int sweep_report(Sweep<T>& W, hipStream_t q, z_t* Pio, const std::vector<double>& fn2,
+                 const std::vector<int>& iters, const std::vector<int64_t>& mv, const std::vector<int64_t>& imv,
+                 const std::vector<int>& nan, const hz_solve_opts& o,
+                 std::chrono::steady_clock::time_point t0, hz_solve_info* infos) {
+  int nb = 0;
+  HZ_TRY((launch_spmm<double, true>(q, W.vres, W.nrows, W.s, W.A64, W.kc, W.X, W.Fs, W.R, W.part, &nb)));
+  k_colsum<<<W.s, kBlock, 0, q>>>(nb, W.s, W.part, W.cn);
+  k_out<<<ceil_div(W.n * W.nf, kBlock), kBlock, 0, q>>>(W.n, W.s, W.nf, W.X, Pio);
+  HZ_HIP(hipGetLastError());
+  std::vector<double> rr(W.s);
+  HZ_HIP(hipMemcpyAsync(rr.data(), W.cn, sizeof(double) * W.s, hipMemcpyDeviceToHost, q));
+  HZ_HIP(hipStreamSynchronize(q));
+  double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = HZ_OK;
+  for (int c = 0; c < W.nf; ++c) {
+    hz_solve_info inf = {};
+    double fnv = std::sqrt(fn2[c]);
+    inf.relres_true = fnv > 0 ? std::sqrt(rr[c]) / fnv : 0.0;
+    inf.relres_est = inf.relres_true;
+    inf.iters = iters[c];
+    inf.matvecs = int(mv[c]);
+    inf.inner_matvecs = int(imv[c]);
+    inf.seconds = secs;
+    inf.status = nan[c] ? HZ_BREAKDOWN : (inf.relres_true <= o.tol ? HZ_OK : HZ_NOT_CONVERGED);
+    if (!std::isfinite(inf.relres_true)) inf.status = HZ_BREAKDOWN;
+    worst = std::max(worst, inf.status);
+    if (infos) infos[c] = inf;
+  }
+  return worst;
+}
+
+template <typename T>
+int run_sweep_gmres(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const z_t* Fin, z_t* Pio,
+                    const hz_solve_opts& o, hz_solve_info* infos) {
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = 0;
+  const int m = o.restart;
+  const std::string p = std::string("sw.") + (sizeof(T) == 8 ? "z." : "c.");
+  int s = 1;
+  while (s < nf) s <<= 1;
+  const int64_t total = D.nrows * s;
+  auto buf = [&](const char* nm, size_t bytes) -> void* {
+    DevBuf* b = ctx->buf(p + nm, bytes, &rc);
+    return rc ? nullptr : b->p;
+  };
+  cx<T>* V = static_cast<cx<T>*>(buf("V", sizeof(cx<T>) * total * (m + 1)));
+  cx<T>* Z = static_cast<cx<T>*>(buf("Z", sizeof(cx<T>) * total));
+  if (rc) return rc;
+  Sweep<T> W;
+  HZ_TRY(sweep_setup<T>(ctx, D, nf, freqs, Fin, Pio, &W, p, Z, V + total));
+  const int Gr = W.Gr;
+  const int nch = ceil_div(m + 1, NV);
+  z_t* mpart = static_cast<z_t*>(buf("mpart", sizeof(z_t) * int64_t(nch) * Gr * NV * s));
+  SwCol* st = static_cast<SwCol*>(buf("st", sizeof(SwCol) * s));
+  const int64_t zs = int64_t(s) * ((m + 1) * m + m + (m + 1) + m + 2 * (m + 1));
+  z_t* small = static_cast<z_t*>(buf("small", sizeof(z_t) * zs + sizeof(double) * s * m));
+  if (rc) return rc;
+  SwArr A;
+  A.m = m;
+  z_t* zp = small;
+  A.H = zp; zp += int64_t(s) * (m + 1) * m;
+  A.sn = zp; zp += int64_t(s) * m;
+  A.g = zp; zp += int64_t(s) * (m + 1);
+  A.y = zp; zp += int64_t(s) * m;
+  A.h1 = zp; zp += int64_t(s) * (m + 1);
+  A.h2 = zp; zp += int64_t(s) * (m + 1);
+  A.cs = reinterpret_cast<double*>(zp);
+  hipStream_t cs = ctx->stream;
+  HZ_HIP(hipMemsetAsync(st, 0, sizeof(SwCol) * s, cs));
+  k_init_cols<<<1, 64, 0, cs>>>(s, st, W.cn, o.tol);
+  HZ_HIP(hipGetLastError());
+
+  auto cycle = [&](hipStream_t q) -> int {
+    int nb = 0;
+    HZ_TRY((launch_spmm<double, true>(q, W.vres, W.nrows, s, W.A64, W.kc, W.X, W.Fs, W.R, W.part, &nb)));
+    k_beta_fin<<<s, kBlock, 0, q>>>(nb, s, st, A, W.part);
+    k_v0<T><<<ceil_div(total, kBlock), kBlock, 0, q>>>(total, s, st, W.R, W.dT, V, Z);
+    for (int j = 0; j < m; ++j) {
+      cx<T>* w = V + int64_t(j + 1) * total;
+      HZ_TRY((launch_spmm<T, false>(q, W.vin, W.nrows, s, W.AT, W.kc, Z, nullptr, w, nullptr, nullptr)));
+      dim3 gd(Gr, ceil_div(j + 1, NV)), gf(s, j + 1);
+      k_mdot<T><<<gd, kBlock, 0, q>>>(total, s, st, V, total, j, w, mpart);
+      k_mdot_fin<<<gf, kBlock, 0, q>>>(Gr, s, st, A, mpart, j, 1);
+      k_axpy<T, false><<<Gr, kBlock, 0, q>>>(total, s, st, A, V, total, j, 1, w, W.part);
+      k_mdot<T><<<gd, kBlock, 0, q>>>(total, s, st, V, total, j, w, mpart);
+      k_mdot_fin<<<gf, kBlock, 0, q>>>(Gr, s, st, A, mpart, j, 2);
+      k_axpy<T, true><<<Gr, kBlock, 0, q>>>(total, s, st, A, V, total, j, 2, w, W.part);
+      k_givens_fin<<<s, kBlock, 0, q>>>(Gr, s, st, A, W.part, j, o.inner_tol);
+      k_scale<T><<<ceil_div(total, kBlock), kBlock, 0, q>>>(total, s, st, W.dT, w, Z);
+    }
+    k_solve_y<<<1, 64, 0, q>>>(s, st, A);
+    k_update<T><<<ceil_div(total, kBlock), kBlock, 0, q>>>(total, s, st, A, V, total, W.d64, W.X);
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+  };
+  Graph G;
+  HZ_TRY(G.stream(cs));
+  HZ_TRY(G.capture(cycle));
+  void* hp = nullptr;
+  HZ_TRY(ctx_pinned(ctx, sizeof(SwCol) * s, &hp));
+  SwCol* hs = static_cast<SwCol*>(hp);
+  std::vector<int64_t> mv(s, 0), imv(s, 0);
+  for (;;) {
+    HZ_TRY(G.launch());
+    HZ_HIP(hipMemcpyAsync(hs, st, sizeof(SwCol) * s, hipMemcpyDeviceToHost, G.gs));
+    HZ_HIP(hipStreamSynchronize(G.gs));
+    bool all = true;
+    int64_t mx = 0;
+    for (int c = 0; c < nf; ++c) {
+      mv[c] += 1;
+      if (!hs[c].done) imv[c] += hs[c].kk;
+      mx = std::max(mx, mv[c] + imv[c]);
+      all = all && (hs[c].done || hs[c].nan);
+    }
+    if (all || mx + m + 1 > o.max_matvec) break;
+  }
+  std::vector<double> fn2(s);
+  std::vector<int> iters(s), nan(s);
+  for (int c = 0; c < s; ++c) {
+    fn2[c] = hs[c].fn2;
+    iters[c] = hs[c].iters;
+    nan[c] = hs[c].nan;
+  }
+  return sweep_report(W, G.gs, Pio, fn2, iters, mv, imv, nan, o, t0, infos);
+}
+
+template <typename T>
+int run_sweep_bicgstab(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const z_t* Fin, z_t* Pio,
+                       const hz_solve_opts& o, hz_solve_info* infos) {
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = 0;
+  const std::string p = std::string("swb.") + (sizeof(T) == 8 ? "z." : "c.");
+  int s = 1;
+  while (s < nf) s <<= 1;
+  const int64_t total = D.nrows * s;
+  auto buf = [&](const char* nm, size_t bytes) -> void* {
+    DevBuf* b = ctx->buf(p + nm, bytes, &rc);
+    return rc ? nullptr : b->p;
+  };
+  BcVec<T> V;
+  cx<T>** vv[9] = {&V.r, &V.rhat, &V.p, &V.v, &V.s, &V.t, &V.zp, &V.zs, &V.u};
+  const char* names[9] = {"r", "rhat", "p", "v", "s", "t", "zp", "zs", "u"};
+  for (int i = 0; i < 9; ++i) {
+    *vv[i] = static_cast<cx<T>*>(buf(names[i], sizeof(cx<T>) * total));
+    if (rc) return rc;
+  }
+  Sweep<T> W;
+  HZ_TRY(sweep_setup<T>(ctx, D, nf, freqs, Fin, Pio, &W, p, V.zp, V.v));
+  V.dT = W.dT;
+  BcCol* st = static_cast<BcCol*>(buf("st", sizeof(BcCol) * s));
+  if (rc) return rc;
+  hipStream_t cs = ctx->stream;
+  HZ_HIP(hipMemsetAsync(st, 0, sizeof(BcCol) * s, cs));
+  k_bc_init_cols<<<1, 64, 0, cs>>>(s, st, W.cn, o.tol);
+  HZ_HIP(hipGetLastError());
+  const int Gr = W.Gr;
+  const int eb = ceil_div(total, kBlock);
+  const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-4;
+  const int inner_cap = 1 << 30;
+  const int chunk = 8;
+  auto iters_body = [&](hipStream_t q) -> int {
+    for (int it = 0; it < chunk; ++it) {
+      k_bc_p<T><<<eb, kBlock, 0, q>>>(total, s, st, V);
+      HZ_TRY((launch_spmm<T, false>(q, W.vin, W.nrows, s, W.AT, W.kc, V.zp, nullptr, V.v, nullptr, nullptr)));
+      k_bc_dots<T, 2><<<Gr, kBlock, 0, q>>>(total, s, st, V.rhat, V.v, W.part);
+      k_bc_alpha<<<s, kBlock, 0, q>>>(Gr, s, st, W.part);
+      k_bc_s<T><<<Gr, kBlock, 0, q>>>(total, s, st, V, W.part);
+      k_bc_sfin<<<s, kBlock, 0, q>>>(Gr, s, st, W.part);
+      HZ_TRY((launch_spmm<T, false>(q, W.vin, W.nrows, s, W.AT, W.kc, V.zs, nullptr, V.t, nullptr, nullptr)));
+      k_bc_dots<T, 3><<<Gr, kBlock, 0, q>>>(total, s, st, V.t, V.s, W.part);
+      k_bc_omega<<<s, kBlock, 0, q>>>(Gr, s, st, W.part);
+      k_bc_xr<T><<<Gr, kBlock, 0, q>>>(total, s, st, V, W.part);
+      k_bc_rho<<<s, kBlock, 0, q>>>(Gr, s, st, W.part, inner_cap);
+    }
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+  };
+  Graph G;
+  HZ_TRY(G.stream(cs));
+  HZ_TRY(G.capture(iters_body));
+  hipStream_t q = G.gs;
+  void* hp = nullptr;
+  HZ_TRY(ctx_pinned(ctx, sizeof(BcCol) * s, &hp));
+  BcCol* hs = static_cast<BcCol*>(hp);
+  std::vector<int64_t> mv(s, 0), imv(s, 0);
+  bool stop = false;
+  while (!stop) {
+    // outer: FP64 residual, convergence, inner start from r = R / beta
+    int nb = 0;
+    HZ_TRY((launch_spmm<double, true>(q, W.vres, W.nrows, s, W.A64, W.kc, W.X, W.Fs, W.R, W.part, &nb)));
+    k_bc_beta<<<s, kBlock, 0, q>>>(nb, s, st, W.part, o.tol, inner_tol);
+    k_bc_start<T><<<eb, kBlock, 0, q>>>(total, s, st, W.R, V);
+    k_bc_dots<T, 1><<<Gr, kBlock, 0, q>>>(total, s, st, V.r, V.r, W.part);
+    k_bc_rho0<<<s, kBlock, 0, q>>>(Gr, s, st, W.part);
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipMemcpyAsync(hs, st, sizeof(BcCol) * s, hipMemcpyDeviceToHost, q));
+    HZ_HIP(hipStreamSynchronize(q));
+    bool all = true;
+    int64_t mx = 0;
+    for (int c = 0; c < nf; ++c) {
+      mv[c] += 1;
+      all = all && (hs[c].done || hs[c].nan);
+      mx = std::max(mx, mv[c] + imv[c]);
+    }
+    if (all || mx + 2 > o.max_matvec) break;
+    std::vector<int> before(s);
+    for (int c = 0; c < s; ++c) before[c] = hs[c].iters;
+    // inner: replay chunks until every column's inner solve is done
+    for (;;) {
+      HZ_TRY(G.launch());
+      HZ_HIP(hipMemcpyAsync(hs, st, sizeof(BcCol) * s, hipMemcpyDeviceToHost, q));
+      HZ_HIP(hipStreamSynchronize(q));
+      bool idone = true;
+      mx = 0;
+      for (int c = 0; c < nf; ++c) {
+        idone = idone && (hs[c].idone || hs[c].done || hs[c].nan);
+        mx = std::max(mx, mv[c] + imv[c] + 2 * int64_t(hs[c].iters - before[c]));
+      }
+      if (idone) break;
+      if (mx + 2 * chunk + 1 > o.max_matvec) {
+        stop = true;
+        break;
+      }
+    }
+    for (int c = 0; c < nf; ++c) imv[c] += 2 * int64_t(hs[c].iters - before[c]);
+    k_bc_update<T><<<eb, kBlock, 0, q>>>(total, s, st, V.u, W.X);
+    HZ_HIP(hipGetLastError());
+  }
+  std::vector<double> fn2(s);
+  std::vector<int> iters(s), nan(s);
+  for (int c = 0; c < s; ++c) {
+    fn2[c] = hs[c].fn2;
+    iters[c] = hs[c].iters;
+    nan[c] = hs[c].nan;
+  }
+  return sweep_report(W, q, Pio, fn2, iters, mv, imv, nan, o, t0, infos);
+}
+
+}  // namespace
+
+int sweep_solve(hz_ctx ctx, int nfreq, const double* freqs, const z_t* F, z_t* P, const hz_solve_opts& o,
+                hz_solve_info* infos) {
+  if (!ctx->sweep_data || ctx->sweep_version != ctx->params_version) {
+    ctx->sweep_data.reset();
+    std::shared_ptr<void> d(new SweepData(), [](void* q) { delete static_cast<SweepData*>(q); });
+    HZ_TRY(build_sweep_data(ctx, static_cast<SweepData*>(d.get())));
+    ctx->sweep_data = d;
+    ctx->sweep_version = ctx->params_version;
+  }
+  SweepData& D = *static_cast<SweepData*>(ctx->sweep_data.get());
+  ctx->have_freq = false;   // the sweep leaves no single-frequency operator behind
+  const bool mixed = o.precision == HZ_MIXED;
+  if (o.method == HZ_BICGSTAB)
+    return mixed ? run_sweep_bicgstab<float>(ctx, D, nfreq, freqs, F, P, o, infos)
+                 : run_sweep_bicgstab<double>(ctx, D, nfreq, freqs, F, P, o, infos);
+  return mixed ? run_sweep_gmres<float>(ctx, D, nfreq, freqs, F, P, o, infos)
+               : run_sweep_gmres<double>(ctx, D, nfreq, freqs, F, P, o, infos);
+}

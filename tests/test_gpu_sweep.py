@@ -1,0 +1,110 @@
+"""GPU frequency sweep (multi-vector product, lock-step GMRES, FP64
+refinement, graph replay) against the oracle's per-frequency solves."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct, helmholtz as H
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2112_00087_amd as pkg
+    assert torch.cuda.is_available()
+    return pkg
+
+
+def _t(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.complex128), device="cuda")
+
+
+@pytest.mark.parametrize("nfreq,precision,method", [(1, "mixed", "gmres"), (3, "mixed", "bicgstab"),
+                                                    (16, "fp64", "gmres"), (64, "mixed", "gmres"),
+                                                    (64, "mixed", "bicgstab"), (5, "fp64", "bicgstab")])
+def test_sweep_columns_match_oracle_direct(P, nfreq, precision, method):
+    say("sweep parity", nfreq, precision, method)
+    wl = W.workload(2, elems=(20, 12, 10))
+    mesh = wl["mesh"]
+    freqs = np.linspace(20, 300, 64)[:: max(1, 64 // nfreq)][:nfreq]
+    S = H.System(mesh, wl["beta"])
+    f = S.load(wl["g"])
+    rng = np.random.default_rng(4)
+    F = np.stack([f * (1 + 0.1 * rng.standard_normal()) for _ in range(nfreq)], axis=1)
+    model = P.Helmholtz(mesh, wl["beta"])
+    Pg, infos = model.solve_sweep(freqs, _t(F), method=method, restart=60, tol=1e-10,
+                                  precision=precision, max_matvec=50000)
+    Pg = Pg.cpu().numpy()
+    for j, fr in enumerate(freqs):
+        A = S.operator(W.wavenumber(fr))
+        x = direct.SparseLU(A).solve(F[:, j])
+        rel = H.relres(A, Pg[:, j], F[:, j])
+        err = np.linalg.norm(Pg[:, j] - x) / np.linalg.norm(x)
+        assert infos[j]["status"] == 0, (j, infos[j])
+        assert rel <= 1e-10 * 1.01, (j, rel)
+        assert abs(infos[j]["relres_true"] - rel) <= 1e-2 * rel + 1e-16
+        assert err <= 1e-6, (j, fr, err)
+    model.close()
+
+
+def test_sweep_column_equals_single_frequency_solve(P):
+    wl = W.workload(2, elems=(24, 16, 12))
+    model = P.Helmholtz(wl["mesh"], wl["beta"])
+    freqs = np.array([37.0, 120.0, 251.5, 299.0])
+    f = model.load(_t(wl["g"]))
+    F = f[:, None].repeat(1, freqs.size).contiguous()
+    Pg, infos = model.solve_sweep(freqs, F, restart=30, tol=1e-11, precision="mixed", max_matvec=50000)
+    for j, fr in enumerate(freqs):
+        model.set_frequency(fr)
+        p, info = model.solve(f, method="gmres", restart=30, tol=1e-11, max_matvec=50000)
+        err = (torch.linalg.norm(Pg[:, j] - p) / torch.linalg.norm(p)).item()
+        say(f"  f={fr} sweep={infos[j]['iters']} single={info['iters']} diff={err:.2e}")
+        assert err <= 1e-8
+    model.close()
+
+
+def test_sweep_x0_and_autotune_cache(P, tmp_path, monkeypatch):
+    monkeypatch.setenv("HZ_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    wl = W.workload(2, elems=(10, 6, 5))
+    model = P.Helmholtz(wl["mesh"], wl["beta"])
+    freqs = np.array([50.0, 60.0])
+    f = model.load(_t(wl["g"]))
+    F = f[:, None].repeat(1, 2).contiguous()
+    P1, i1 = model.solve_sweep(freqs, F, tol=1e-10, precision="mixed")
+    assert (tmp_path / "tune.txt").read_text().count("spmm") >= 1
+    # restarting from the solution converges at once
+    P2, i2 = model.solve_sweep(freqs, F, P0=P1, tol=1e-10, precision="mixed")
+    assert all(i["status"] == 0 and i["inner_matvecs"] == 0 for i in i2)
+    # the sweep leaves no single-frequency operator: solve needs set_frequency
+    with pytest.raises(P.HzError):
+        model.solve(f)
+    model.close()
+
+
+def test_sweep_full_size_residuals_by_oracle(P):
+    wl = W.workload(2)
+    mesh = wl["mesh"]
+    model = P.Helmholtz(mesh, wl["beta"])
+    f = model.load(_t(wl["g"]))
+    freqs = wl["freqs"]
+    F = f[:, None].repeat(1, freqs.size).contiguous()
+    Pg, infos = model.solve_sweep(freqs, F, method="bicgstab", tol=1e-8, precision="fp64",
+                                  max_matvec=100000)
+    say("full-size sweep", infos[0]["seconds"], [i["iters"] for i in infos[:8]])
+    Pg = Pg.cpu().numpy()
+    S = H.System(mesh, wl["beta"])
+    fo = S.load(wl["g"])
+    for j, fr in enumerate(freqs):
+        A = S.operator(W.wavenumber(fr))
+        rel = H.relres(A, Pg[:, j], fo)
+        assert infos[j]["status"] == 0 and rel <= 1e-8 * 1.01, (j, fr, rel, infos[j])
+    model.close()
