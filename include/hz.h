@@ -111,8 +111,15 @@ typedef struct {
  *   inner_tol   relative tolerance of inner (mixed / subdomain) solves
  *   inner_restart  GMRES restart of the inner complex64 solves
  *   dd_alpha    Robin transmission coefficient of the Schwarz method
- *               (0 + 0i selects the default i k)
- *   dd_inner    inner Krylov method of the Schwarz local solves            */
+ *               (0 + 0i selects the default i k, the absorbing condition)
+ *   dd_inner    Krylov method of the Schwarz subdomain solves (HZ_GMRES or
+ *               HZ_BICGSTAB); for the Schwarz method inner_tol is the
+ *               subdomain solves' relative tolerance (0: 1e-10) and
+ *               precision HZ_MIXED runs them in complex64 with FP64
+ *               refinement; restart is the interface GMRES restart
+ *   dd_richardson  0: interface GMRES; N > 0: exactly N plain Schwarz
+ *               iterations from zero multipliers (status reports whether
+ *               the glued result reached tol)                              */
 typedef struct {
   int32_t method;
   int32_t restart;
@@ -124,7 +131,7 @@ typedef struct {
   double inner_tol;
   hz_c128 dd_alpha;
   int32_t dd_inner;
-  int32_t reserved;
+  int32_t dd_richardson;
 } hz_solve_opts;
 
 /* Filled by the solve entry points.

@@ -88,8 +88,9 @@ int host_assemble_meta(HostAsm* a, const double* eta) {
   return HZ_OK;
 }
 
-int host_assemble(const hz_mesh* m, const double* eta, HostAsm* out) {
+int host_assemble(const hz_mesh* m, const double* eta, HostAsm* out, int ntags) {
   HostAsm& a = *out;
+  a.ntags = ntags;
   if (!m || !m->xyz || !m->hex || m->n_nodes <= 0 || m->n_elems <= 0 || m->n_bfaces < 0 ||
       (m->n_bfaces > 0 && (!m->bface || !m->bface_tag || !m->bface_src)))
     return hz_fail(HZ_ERR_INVALID, "hz_assemble: null or empty mesh arrays");
@@ -109,7 +110,7 @@ int host_assemble(const hz_mesh* m, const double* eta, HostAsm* out) {
     for (int32_t v : a.bface)
       if (v < 0 || v >= a.n) return hz_fail(HZ_ERR_INVALID, "hz_assemble: face node %d out of range", v);
     for (int32_t t : a.btag)
-      if (t < 0 || t > 5) return hz_fail(HZ_ERR_INVALID, "hz_assemble: wall tag %d not in 0..5", t);
+      if (t < 0 || t >= ntags) return hz_fail(HZ_ERR_INVALID, "hz_assemble: wall tag %d not in 0..%d", t, ntags - 1);
   }
 
   // node -> element adjacency, ascending element id
@@ -192,11 +193,11 @@ int host_assemble(const hz_mesh* m, const double* eta, HostAsm* out) {
           s = int32_t(a.bpos.size());
           slot.emplace(pos, s);
           a.bpos.push_back(pos);
-          a.bmass.insert(a.bmass.end(), 6, 0.0);
+          a.bmass.insert(a.bmass.end(), ntags, 0.0);
         } else {
           s = it->second;
         }
-        a.bmass[int64_t(s) * 6 + a.btag[f]] += Fe[l][o];
+        a.bmass[int64_t(s) * ntags + a.btag[f]] += Fe[l][o];
         if (a.bsrc[f]) patch[int64_t(r) * a.n + c] += Fe[l][o];
       }
   }

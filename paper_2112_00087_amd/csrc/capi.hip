@@ -35,6 +35,9 @@ int validate_opts(const hz_solve_opts* o) {
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return hz_fail(HZ_ERR_INVALID, "tol must be finite and > 0");
   if (!(o->inner_tol >= 0.0) || !std::isfinite(o->inner_tol)) return hz_fail(HZ_ERR_INVALID, "bad inner_tol");
   if (o->inner_restart < 0 || o->inner_restart > 128) return hz_fail(HZ_ERR_INVALID, "inner_restart not in 0..128");
+  if (o->dd_richardson < 0) return hz_fail(HZ_ERR_INVALID, "dd_richardson must be >= 0");
+  if (o->method == HZ_SCHWARZ && o->dd_inner != HZ_GMRES && o->dd_inner != HZ_BICGSTAB)
+    return hz_fail(HZ_ERR_INVALID, "dd_inner must be HZ_GMRES or HZ_BICGSTAB");
   return HZ_OK;
 }
 
@@ -72,6 +75,7 @@ int hz_assemble(const hz_mesh* mesh, const hz_c128* beta, const double* eta, voi
   ctx->beta.resize(6);
   for (int w = 0; w < 6; ++w) ctx->beta[w] = std::complex<double>(beta[w].re, beta[w].im);
   ctx->have_eta = eta != nullptr;
+  if (eta) ctx->eta_field.assign(eta, eta + ctx->h.ne);
   HZ_TRY(ctx_upload(ctx.get()));
   HZ_HIP(hipStreamSynchronize(ctx->stream));
   *out = ctx.release();
@@ -90,6 +94,7 @@ int hz_set_params(hz_ctx ctx, const hz_c128* beta, const double* eta) {
   if (eta) {
     HZ_TRY(host_assemble_meta(&ctx->h, eta));
     ctx->have_eta = true;
+    ctx->eta_field.assign(eta, eta + ctx->h.ne);
   }
   HZ_HIP(hipStreamSynchronize(ctx->stream));
   HZ_TRY(ctx_upload_params(ctx));

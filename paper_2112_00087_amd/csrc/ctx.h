@@ -26,11 +26,12 @@ struct SellHost {
 // Host-side assembly products (CSR with sorted columns).
 struct HostAsm {
   int32_t n = 0, ne = 0, nb = 0;
+  int32_t ntags = 6;                 // boundary tags: 6 walls (+ 6 interface directions)
   std::vector<int64_t> rowptr;
   std::vector<int32_t> col;
   std::vector<double> K, M, Meta;    // per CSR entry (Meta empty when eta is NULL)
   std::vector<int64_t> diag;         // CSR position of (i,i)
-  // boundary entries: CSR position and per-wall face mass, [nbe][6]
+  // boundary entries: CSR position and per-tag face mass, [nbe][ntags]
   std::vector<int64_t> bpos;
   std::vector<double> bmass;
   // source-patch mass restricted to the patch rows
@@ -46,7 +47,7 @@ struct HostAsm {
   std::vector<int32_t> n2e;
 };
 
-int host_assemble(const hz_mesh* mesh, const double* eta, HostAsm* out);
+int host_assemble(const hz_mesh* mesh, const double* eta, HostAsm* out, int ntags = 6);
 int host_assemble_meta(HostAsm* a, const double* eta);
 void build_sell(const HostAsm& a, int64_t nrows, SellHost* s);
 
@@ -93,6 +94,9 @@ struct hz_ctx_s {
   // the frequency sweep, built on first use for a params_version
   int sweep_version = -1;
   std::shared_ptr<void> sweep_data;  // owned row-wise operator data of the sweep
+  int dd_version = -1;
+  std::shared_ptr<void> dd_data;     // owned subdomain systems of the Schwarz method
+  std::vector<double> eta_field;     // per-element loss factors (empty: none)
   std::map<std::string, int> tuned;  // autotuned multi-vector product variants
 
   // scratch for solvers, keyed by name

@@ -91,7 +91,7 @@ int ctx_upload_params(hz_ctx ctx) {
     // accumulate walls in order 0..5
     double re = 0.0, im = 0.0;
     for (int w = 0; w < 6; ++w) {
-      double m = a.bmass[e * 6 + w];
+      double m = a.bmass[e * a.ntags + w];
       re += ctx->beta[w].real() * m;
       im += ctx->beta[w].imag() * m;
     }

@@ -41,6 +41,10 @@ inline SellOp<float> op_A32(hz_ctx ctx) {
 }
 
 int op_set_frequency(hz_ctx ctx, const OpParts& P, double k, int scale, bool want32);
+// Forms A(k) (optionally column-scaled by 1/diag) on an explicit sliced-ELL
+// system; rows i >= n or with diag[i] < 0 are padding (d = 1).
+int op_form(hipStream_t s, int64_t n, int64_t nrows, int64_t npad, const int* col, const OpParts& P, double k,
+            int scale, z_t* A, c_t* A32, z_t* d, z_t* dinv);
 template <typename T>
 int op_spmv(hipStream_t s, int64_t nrows, int64_t nout, const SellOp<T>& A, const cx<T>* x, cx<T>* y);
 int op_mul(hipStream_t s, int64_t n, const z_t* a, const z_t* b, z_t* c);

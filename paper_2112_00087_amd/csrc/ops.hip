@@ -21,7 +21,7 @@ __global__ void k_diag(int n, int64_t nrows, OpParts P, double k, z_t* __restric
                        z_t* __restrict__ dinv) {
   int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= nrows) return;
-  if (i < n) {
+  if (i < n && P.diag[i] >= 0) {
     z_t v = entry_value(P.diag[i], P, k);
     d[i] = v;
     dinv[i] = crecip(v);
@@ -45,19 +45,20 @@ __global__ void k_combine(int64_t npad, const int* __restrict__ col, OpParts P, 
   }
 }
 
-int op_set_frequency(hz_ctx ctx, const OpParts& P, double k, int scale, bool want32) {
-  int n = ctx->h.n;
-  int64_t nrows = ctx->sell.n_rows;
-  k_diag<<<ceil_div(nrows, kBlock), kBlock, 0, ctx->stream>>>(n, nrows, P, k, ctx->d_d.as<z_t>(),
-                                                             ctx->d_dinv.as<z_t>());
+int op_form(hipStream_t s, int64_t n, int64_t nrows, int64_t npad, const int* col, const OpParts& P, double k,
+            int scale, z_t* A, c_t* A32, z_t* d, z_t* dinv) {
+  k_diag<<<ceil_div(nrows, kBlock), kBlock, 0, s>>>(int(n), nrows, P, k, d, dinv);
   HZ_HIP(hipGetLastError());
-  int64_t npad = ctx->sell.n_pad;
   int grid = int(std::min<int64_t>(ceil_div(npad, kBlock), 16384));
-  k_combine<<<grid, kBlock, 0, ctx->stream>>>(npad, ctx->d_scol.as<int>(), P, k,
-                                              ctx->d_dinv.as<z_t>(), scale, ctx->d_A.as<z_t>(),
-                                              want32 ? ctx->d_A32.as<c_t>() : nullptr);
+  k_combine<<<grid, kBlock, 0, s>>>(npad, col, P, k, dinv, scale, A, A32);
   HZ_HIP(hipGetLastError());
   return HZ_OK;
+}
+
+int op_set_frequency(hz_ctx ctx, const OpParts& P, double k, int scale, bool want32) {
+  return op_form(ctx->stream, ctx->h.n, ctx->sell.n_rows, ctx->sell.n_pad, ctx->d_scol.as<int>(), P, k, scale,
+                 ctx->d_A.as<z_t>(), want32 ? ctx->d_A32.as<c_t>() : nullptr, ctx->d_d.as<z_t>(),
+                 ctx->d_dinv.as<z_t>());
 }
 
 // ---------------------------------------------------------------- products

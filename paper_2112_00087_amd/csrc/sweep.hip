@@ -792,8 +792,8 @@ int build_sweep_data(hz_ctx ctx, SweepData* D) {
     while (a.rowptr[row + 1] <= pos) ++row;
     double re = 0.0, im = 0.0;
     for (int w = 0; w < 6; ++w) {
-      re += ctx->beta[w].real() * a.bmass[e * 6 + w];
-      im += ctx->beta[w].imag() * a.bmass[e * 6 + w];
+      re += ctx->beta[w].real() * a.bmass[e * a.ntags + w];
+      im += ctx->beta[w].imag() * a.bmass[e * a.ntags + w];
     }
     bptr[row + 1] += 1;
     bcol.push_back(a.col[pos]);

@@ -44,7 +44,7 @@ class hz_solve_opts(C.Structure):
     _fields_ = [("method", C.c_int32), ("restart", C.c_int32), ("max_matvec", C.c_int32),
                 ("precision", C.c_int32), ("precond", C.c_int32), ("inner_restart", C.c_int32),
                 ("tol", C.c_double), ("inner_tol", C.c_double), ("dd_alpha", hz_c128),
-                ("dd_inner", C.c_int32), ("reserved", C.c_int32)]
+                ("dd_inner", C.c_int32), ("dd_richardson", C.c_int32)]
 
 
 class hz_solve_info(C.Structure):
@@ -120,7 +120,8 @@ def check(code, allow_positive=True):
 
 
 def make_opts(method="gmres", restart=30, max_matvec=20000, precision="fp64", precond="jacobi",
-              tol=1e-8, inner_tol=1e-4, inner_restart=30, dd_alpha=0j, dd_inner="gmres"):
+              tol=1e-8, inner_tol=1e-4, inner_restart=30, dd_alpha=0j, dd_inner="gmres",
+              dd_richardson=0):
     o = hz_solve_opts()
     o.method = METHODS[method] if isinstance(method, str) else int(method)
     o.restart = restart
@@ -132,6 +133,7 @@ def make_opts(method="gmres", restart=30, max_matvec=20000, precision="fp64", pr
     o.inner_tol = inner_tol
     o.dd_alpha = hz_c128(complex(dd_alpha).real, complex(dd_alpha).imag)
     o.dd_inner = METHODS[dd_inner] if isinstance(dd_inner, str) else int(dd_inner)
+    o.dd_richardson = int(dd_richardson)
     return o
 
 

@@ -1,0 +1,117 @@
+"""GPU Schwarz decomposition (batched subdomain solves + interface GMRES)
+against the oracle: the global solution, the trivial partition, and the
+iterate of the plain Schwarz iteration."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct, helmholtz as H, schwarz
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2112_00087_amd as pkg
+    assert torch.cuda.is_available()
+    return pkg
+
+
+def _t(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.complex128), device="cuda")
+
+
+def _case(elems, freq, eta=False, seed=2):
+    wl = W.workload(3, elems=elems)
+    mesh = wl["mesh"]
+    rng = np.random.default_rng(seed)
+    et = rng.uniform(0, 0.02, mesh["n_elems"]) if eta else None
+    S = H.System(mesh, wl["beta"], et)
+    k = W.wavenumber(freq)
+    A = S.operator(k)
+    f = S.load(wl["g"])
+    return wl, mesh, et, k, A, f
+
+
+@pytest.mark.parametrize("parts,inner,eta", [((2, 2, 1), "bicgstab", False), ((2, 2, 2), "gmres", True),
+                                             ((3, 1, 2), "bicgstab", True)])
+def test_schwarz_fp64_matches_global_solution(P, parts, inner, eta):
+    say("schwarz fp64", parts, inner, eta)
+    wl, mesh, et, k, A, f = _case((12, 8, 6), 150.0, eta)
+    model = P.Helmholtz(mesh, wl["beta"], et, parts=parts)
+    model.set_frequency(150.0)
+    p, info = model.solve(_t(f), method="schwarz", restart=40, tol=1e-9, inner_tol=1e-12,
+                          dd_inner=inner, max_matvec=5000)
+    say("  ", info)
+    p = p.cpu().numpy()
+    x = direct.SparseLU(A).solve(f)
+    rel = H.relres(A, p, f)
+    assert info["status"] == 0 and rel <= 1e-9 * 1.01
+    assert abs(info["relres_true"] - rel) <= 1e-3 * rel
+    assert np.linalg.norm(p - x) <= 1e-6 * np.linalg.norm(x)
+    model.close()
+
+
+def test_schwarz_trivial_partition_is_global_solve(P):
+    wl, mesh, et, k, A, f = _case((8, 6, 4), 120.0)
+    model = P.Helmholtz(mesh, wl["beta"], parts=(1, 1, 1))
+    model.set_frequency(120.0)
+    p, info = model.solve(_t(f), method="schwarz", tol=1e-10, inner_tol=1e-12, dd_inner="bicgstab")
+    assert info["status"] == 0 and info["iters"] == 0
+    x = direct.SparseLU(A).solve(f)
+    assert np.linalg.norm(p.cpu().numpy() - x) <= 1e-9 * np.linalg.norm(x)
+    model.close()
+
+
+def test_schwarz_plain_iteration_matches_oracle_history(P):
+    wl, mesh, et, k, A, f = _case((8, 6, 4), 90.0)
+    parts = (2, 2, 1)
+    D = schwarz.Schwarz(mesh, parts, wl["beta"], None, k, f)
+    model = P.Helmholtz(mesh, wl["beta"], parts=parts)
+    model.set_frequency(90.0)
+    for n_it in (1, 4, 10):
+        p, info = model.solve(_t(f), method="schwarz", tol=1e-12, inner_tol=1e-13, dd_inner="gmres",
+                              inner_restart=60, dd_richardson=n_it)
+        u, lams, hist = D.richardson(n_it + 1, A, f)
+        err = np.linalg.norm(p.cpu().numpy() - u) / np.linalg.norm(u)
+        say(f"  plain Schwarz {n_it}: rel diff {err:.2e}, oracle relres {hist[-1, 1]:.3e}, gpu {info['relres_true']:.3e}")
+        assert err <= 1e-8
+        assert abs(info["relres_true"] - hist[-1, 1]) <= 1e-6 * hist[-1, 1]
+    model.close()
+
+
+def test_schwarz_mixed_local_solves(P):
+    wl, mesh, et, k, A, f = _case((20, 12, 10), 150.0)
+    model = P.Helmholtz(mesh, wl["beta"], parts=(2, 2, 2))
+    model.set_frequency(150.0)
+    p, info = model.solve(_t(f), method="schwarz", precision="mixed", tol=1e-8, inner_tol=1e-10,
+                          dd_inner="bicgstab", restart=40, max_matvec=5000)
+    say("  mixed schwarz", info)
+    rel = H.relres(A, p.cpu().numpy(), f)
+    x = direct.SparseLU(A).solve(f)
+    assert info["status"] == 0 and rel <= 1e-8 * 1.01
+    assert np.linalg.norm(p.cpu().numpy() - x) <= 1e-6 * np.linalg.norm(x)
+    model.close()
+
+
+def test_schwarz_rejects_unstructured_or_bad_parts(P):
+    wl, mesh, et, k, A, f = _case((4, 3, 2), 100.0)
+    bad = dict(mesh, elems=(0, 0, 0))
+    model = P.Helmholtz(bad, wl["beta"], parts=(2, 1, 1))
+    model.set_frequency(100.0)
+    with pytest.raises(P.HzError):
+        model.solve(_t(f), method="schwarz")
+    model.close()
+    model = P.Helmholtz(mesh, wl["beta"], parts=(9, 1, 1))
+    model.set_frequency(100.0)
+    with pytest.raises(P.HzError):
+        model.solve(_t(f), method="schwarz")
+    model.close()
