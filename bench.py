@@ -9,7 +9,8 @@ are assembled and resident in HBM before the timed region.
 Printed as one JSON line: the solve time (value, s), the sparse product's
 achieved algorithmic bandwidth against the 8 TB/s HBM peak (roofline), the
 oracle's CPU time on a bounded sample (cpu_baseline), and secondary numbers
-(GMRES(50), mixed precision, the batched frequency sweep when available).
+(GMRES(50), mixed precision, the batched 64-frequency sweep against 64
+per-frequency FP64 solves, and on request the Schwarz and adjoint legs).
 """
 from __future__ import annotations
 
@@ -58,6 +59,101 @@ def cpu_baseline(wl, gpu_iters, iters):
                       f"{per_iter * 1e3:.1f} ms/iteration), scaled to the GPU's {gpu_iters} iterations"}
 
 
+def sweep_leg(log_fn, precision="mixed", method="bicgstab"):
+    """Workload 2: 64 frequencies, 80x48x40.  T_A = 64 x (set_frequency + FP64
+    solve), T_B = one batched sweep; both use the same Krylov method."""
+    import torch
+    import workloads as W
+    from paper_2112_00087_amd import Helmholtz
+    wl = W.workload(2)
+    m = Helmholtz(wl["mesh"], wl["beta"])
+    f = m.load(torch.as_tensor(wl["g"], device="cuda"))
+    freqs = wl["freqs"]
+    F = f[:, None].repeat(1, freqs.size).contiguous()
+    opts = dict(method=method, tol=1e-8, max_matvec=200000, restart=30)
+    # warm-up of both paths (autotuner, graph capture, allocations)
+    m.solve_sweep(freqs[:2], F[:, :2].contiguous(), precision=precision, **opts)
+    m.set_frequency(freqs[0])
+    m.solve(f, **opts)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    a_ok, a_iters = 0, []
+    for fr in freqs:
+        m.set_frequency(fr)
+        _, inf = m.solve(f, **opts)
+        a_ok += inf["status"] == 0
+        a_iters.append(inf["iters"])
+    torch.cuda.synchronize()
+    T_A = time.perf_counter() - t
+    log_fn(f"sweep A (64 x FP64 {method}): {T_A:.2f}s, converged {a_ok}/64")
+    t = time.perf_counter()
+    _, infos = m.solve_sweep(freqs, F, precision=precision, **opts)
+    torch.cuda.synchronize()
+    T_B = time.perf_counter() - t
+    b_ok = sum(i["status"] == 0 for i in infos)
+    worst = max(i["relres_true"] for i in infos)
+    log_fn(f"sweep B (batched {precision} {method}): {T_B:.2f}s, converged {b_ok}/64, worst relres {worst:.2e}")
+    m.close()
+    return {"workload": wl["name"], "method": method, "precision_B": precision, "T_A_s": T_A, "T_B_s": T_B,
+            "speedup": T_A / T_B, "converged_A": a_ok, "converged_B": b_ok, "worst_relres_B": worst,
+            "iters_A": a_iters, "iters_B": [i["iters"] for i in infos]}
+
+
+def schwarz_leg(log_fn, max_matvec=300):
+    import torch
+    import workloads as W
+    from paper_2112_00087_amd import Helmholtz
+    wl = W.workload(3)
+    m = Helmholtz(wl["mesh"], wl["beta"], parts=wl["parts"])
+    f = m.load(torch.as_tensor(wl["g"], device="cuda"))
+    m.set_frequency(wl["freqs"][0])
+    out = {"workload": wl["name"]}
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, inf = m.solve(f, method="schwarz", tol=1e-8, inner_tol=1e-10, dd_inner="bicgstab", restart=300,
+                     max_matvec=max_matvec)
+    torch.cuda.synchronize()
+    out["schwarz"] = dict(s=time.perf_counter() - t, **inf)
+    log_fn(f"schwarz: {out['schwarz']}")
+    m.set_frequency(wl["freqs"][0])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, inf = m.solve(f, method="bicgstab", tol=1e-8, max_matvec=200000)
+    torch.cuda.synchronize()
+    out["global_bicgstab"] = dict(s=time.perf_counter() - t, **inf)
+    log_fn(f"global bicgstab on the same system: {out['global_bicgstab']}")
+    m.close()
+    return out
+
+
+def adjoint_leg(log_fn):
+    import torch
+    import workloads as W
+    from paper_2112_00087_amd import Helmholtz
+    from paper_2112_00087_amd.autograd import HelmholtzEnergy
+    wl = W.workload(4)
+    m = Helmholtz(wl["mesh"], wl["beta"], wl["eta"])
+    beta = torch.tensor(np.stack([wl["beta"].real, wl["beta"].imag], 1), dtype=torch.float64, device="cuda",
+                        requires_grad=True)
+    eta = torch.tensor(wl["eta"], dtype=torch.float64, device="cuda", requires_grad=True)
+    rec = torch.as_tensor(wl["receivers"], device="cuda")
+    g = torch.as_tensor(wl["g"], device="cuda")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    J = HelmholtzEnergy.apply(beta, eta, m, wl["freqs"], g, rec, dict(method="bicgstab", tol=1e-8,
+                                                                      max_matvec=200000))
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t
+    J.backward()
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t
+    out = {"workload": wl["name"], "J": J.item(), "forward_s": t_fwd, "forward_backward_s": t_all,
+           "grad_beta_norm": beta.grad.norm().item(), "grad_eta_norm": eta.grad.norm().item()}
+    log_fn(f"adjoint: {out}")
+    m.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +167,9 @@ def main():
                     help="skip the solves (hardware-counter runs of the product kernel)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (reference for the traffic counters)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 64-frequency sweep comparison")
+    ap.add_argument("--schwarz", action="store_true", help="also run the 24-subdomain Schwarz solve")
+    ap.add_argument("--adjoint", action="store_true", help="also run the 16-frequency adjoint gradient")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
@@ -146,6 +245,14 @@ def main():
                             "relres_true": inf["relres_true"]}
             log(f"{label}: {extra[label]}")
 
+    sweep = None
+    if not args.no_sweep and not args.spmv_only:
+        sweep = sweep_leg(log)
+    if args.schwarz and not args.spmv_only:
+        extra["schwarz"] = schwarz_leg(log)
+    if args.adjoint and not args.spmv_only:
+        extra["adjoint"] = adjoint_leg(log)
+
     cpu = None
     if not args.no_cpu and not args.spmv_only:
         cpu = cpu_baseline(wl, infos[-1]["iters"], args.cpu_iters)
@@ -160,6 +267,8 @@ def main():
                    "solver": "bicgstab, right Jacobi", "tol": 1e-8,
                    "iters": infos[-1]["iters"], "relres_true": infos[-1]["relres_true"]},
         "spmv_GBs": gbs,
+        "sweep_speedup": None if sweep is None else sweep["speedup"],
+        "sweep": sweep,
         "roofline": roof,
         "cpu_baseline": cpu,
         "extra": extra,

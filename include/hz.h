@@ -99,7 +99,7 @@ typedef struct {
 
 /* Solver options (host struct).
  *   method      HZ_GMRES, HZ_BICGSTAB or HZ_SCHWARZ
- *   restart     GMRES restart length m (1..128)
+ *   restart     GMRES restart length m (1..128; Schwarz interface GMRES 1..1000)
  *   max_matvec  cap on operator applications (>= 1)
  *   precision   HZ_FP64: complex128 throughout.  HZ_MIXED: complex64 inner
  *               Krylov solves on a complex64 copy of the operator, with the
@@ -110,8 +110,13 @@ typedef struct {
  *               recomputed in FP64 at exit)
  *   inner_tol   relative tolerance of inner (mixed / subdomain) solves
  *   inner_restart  GMRES restart of the inner complex64 solves
- *   dd_alpha    Robin transmission coefficient of the Schwarz method
- *               (0 + 0i selects the default i k, the absorbing condition)
+ *   dd_alpha    Robin transmission coefficient alpha of the Schwarz method
+ *               (interface term alpha M_G).  0 + 0i selects an optimised
+ *               alpha = p + i q: the (p, q) on a log grid that minimises the
+ *               largest convergence factor |(l - alpha)/(l + alpha)| over the
+ *               interface modes xi in [pi/H_sub, pi/h] (l = sqrt(xi^2 - k^2)
+ *               or i sqrt(k^2 - xi^2)), leaving out xi within pi/(2 H_sub)
+ *               of k; i k is the plain absorbing (Despres) choice
  *   dd_inner    Krylov method of the Schwarz subdomain solves (HZ_GMRES or
  *               HZ_BICGSTAB); for the Schwarz method inner_tol is the
  *               subdomain solves' relative tolerance (0: 1e-10) and
@@ -211,12 +216,17 @@ int hz_solve(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* f_dev,
  *   F_dev, P_dev  [n_nodes][nfreq] row-major complex128 (column j of row i
  *          at i * nfreq + j); P is in: x0 (zero allowed), out: solutions
  *   infos  [nfreq] per-column results (may be NULL)
- * opts->method is HZ_GMRES (restarted GMRES(restart), every restart cycle
- * one refinement step) or HZ_BICGSTAB (each refinement step an inner
- * BiCGStab solve to inner_tol); opts->precision HZ_MIXED (complex64 inner
- * Krylov, FP64 residual / refinement / Gram-Schmidt coefficients / Givens)
- * or HZ_FP64.  Columns converge independently; the call returns when all
- * have reached tol or one has used max_matvec products.  Leaves the
+ * opts->method is HZ_GMRES (restarted GMRES(restart) advanced in lock-step,
+ * every restart cycle one refinement step against the FP64 residual) or
+ * HZ_BICGSTAB (one BiCGStab per column; each column's FP64 true residual
+ * replaces its recursive one -- a reliable update -- when the latter has
+ * dropped by the factor inner_tol (complex64, default 0.1) or reached the
+ * target (FP64); converged columns leave the batch, which is compacted to
+ * the next power-of-two width).  opts->precision HZ_MIXED: complex64 Krylov
+ * vectors and operator copy, FP64 residual / refinement / Gram-Schmidt
+ * coefficients / Givens; HZ_FP64: complex128 throughout.  Columns converge
+ * independently; the call returns when all have reached tol or one has used
+ * max_matvec products.  Leaves the
  * context's current frequency unset (call hz_set_frequency before the next
  * hz_solve).  Environment: HZ_AUTOTUNE_CACHE names a text file in which
  * tuned product variants are remembered across processes. */

@@ -54,8 +54,10 @@ __global__ void __launch_bounds__(kBlock) k_resid(Seg L, SellOp<T> A, BiV<T> V, 
 
 __global__ void k_resid_fin(Seg L, BiSt* st, const double* part) {
   int s = blockIdx.x;
-  double rr = seg_sum<1>(L, part, s, 0);
+  double o[1];
+  seg_sums<1>(L, part, s, o);
   if (threadIdx.x == 0) {
+    const double rr = o[0];
     BiSt& S = st[s];
     S.rr = rr;
     S.rho = z_t{rr, 0.0};
@@ -100,9 +102,10 @@ __global__ void __launch_bounds__(kBlock) k_v(Seg L, SellOp<T> A, const BiSt* st
 __global__ void k_alpha_fin(Seg L, BiSt* st, const double* part) {
   int s = blockIdx.x;
   if (st[s].done) return;
-  double re = seg_sum<2>(L, part, s, 0);
-  double im = seg_sum<2>(L, part, s, 1);
+  double o[2];
+  seg_sums<2>(L, part, s, o);
   if (threadIdx.x == 0) {
+    const double re = o[0], im = o[1];
     BiSt& S = st[s];
     S.reset = 0;
     z_t rv = {re, im};
@@ -131,8 +134,10 @@ __global__ void __launch_bounds__(kBlock) k_s(Seg L, const BiSt* st, BiV<T> V, d
 __global__ void k_s_fin(Seg L, BiSt* st, const double* part) {
   int s = blockIdx.x;
   if (st[s].done) return;
-  double ss = seg_sum<1>(L, part, s, 0);
+  double o[1];
+  seg_sums<1>(L, part, s, o);
   if (threadIdx.x == 0) {
+    const double ss = o[0];
     st[s].ss = ss;
     st[s].early = (ss <= st[s].thr2) ? 1 : 0;
   }
@@ -154,10 +159,12 @@ __global__ void __launch_bounds__(kBlock) k_t(Seg L, SellOp<T> A, const BiSt* st
 __global__ void k_omega_fin(Seg L, BiSt* st, const double* part) {
   int s = blockIdx.x;
   if (st[s].done || st[s].early) return;
-  double re = seg_sum<3>(L, part, s, 0);
-  double im = seg_sum<3>(L, part, s, 1);
-  double tt = seg_sum<3>(L, part, s, 2);
-  if (threadIdx.x == 0) st[s].omega = (tt > 0.0) ? z_t{re / tt, im / tt} : z_t{0.0, 0.0};
+  double o[3];
+  seg_sums<3>(L, part, s, o);
+  if (threadIdx.x == 0) {
+    const double re = o[0], im = o[1], tt = o[2];
+    st[s].omega = (tt > 0.0) ? z_t{re / tt, im / tt} : z_t{0.0, 0.0};
+  }
 }
 
 // u += alpha p + omega s; r = s - omega t; partials rhat^H r, ||r||^2.
@@ -195,10 +202,10 @@ __global__ void k_rho_fin(Seg L, BiSt* st, const double* part) {
     }
     return;
   }
-  double re = seg_sum<3>(L, part, s, 0);
-  double im = seg_sum<3>(L, part, s, 1);
-  double rr = seg_sum<3>(L, part, s, 2);
+  double o[3];
+  seg_sums<3>(L, part, s, o);
   if (threadIdx.x == 0) {
+    const double re = o[0], im = o[1], rr = o[2];
     S.iter += 1;
     S.rho_old = S.rho;
     S.rho = z_t{re, im};
@@ -280,7 +287,7 @@ int bicgstab_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* 
   };
   auto enqueue_resid = [&]() -> int {
     k_resid<T><<<grid, kBlock, 0, s>>>(L, A, V, pt);
-    k_resid_fin<<<S.nseg, kBlock, 0, s>>>(L, st, pt);
+    k_resid_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     HZ_HIP(hipGetLastError());
     ++resid_calls;
     return HZ_OK;
@@ -288,13 +295,13 @@ int bicgstab_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* 
   auto enqueue_iter = [&]() -> int {
     k_p<T><<<grid, kBlock, 0, s>>>(L, st, V);
     k_v<T><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
-    k_alpha_fin<<<S.nseg, kBlock, 0, s>>>(L, st, pt);
+    k_alpha_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     k_s<T><<<grid, kBlock, 0, s>>>(L, st, V, pt);
-    k_s_fin<<<S.nseg, kBlock, 0, s>>>(L, st, pt);
+    k_s_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     k_t<T><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
-    k_omega_fin<<<S.nseg, kBlock, 0, s>>>(L, st, pt);
+    k_omega_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     k_xr<T><<<grid, kBlock, 0, s>>>(L, st, V, pt);
-    k_rho_fin<<<S.nseg, kBlock, 0, s>>>(L, st, pt);
+    k_rho_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     HZ_HIP(hipGetLastError());
     return HZ_OK;
   };

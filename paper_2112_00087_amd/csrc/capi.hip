@@ -29,8 +29,10 @@ int validate_opts(const hz_solve_opts* o) {
   if (o->precision != HZ_FP64 && o->precision != HZ_MIXED)
     return hz_fail(HZ_ERR_INVALID, "unknown precision %d", o->precision);
   if (o->precond != HZ_JACOBI && o->precond != HZ_NONE) return hz_fail(HZ_ERR_INVALID, "unknown precond %d", o->precond);
-  if ((o->method == HZ_GMRES || o->method == HZ_SCHWARZ) && (o->restart < 1 || o->restart > 128))
+  if (o->method == HZ_GMRES && (o->restart < 1 || o->restart > 128))
     return hz_fail(HZ_ERR_INVALID, "restart %d not in 1..128", o->restart);
+  if (o->method == HZ_SCHWARZ && (o->restart < 1 || o->restart > 1000))
+    return hz_fail(HZ_ERR_INVALID, "interface restart %d not in 1..1000", o->restart);
   if (o->max_matvec < 1) return hz_fail(HZ_ERR_INVALID, "max_matvec must be >= 1");
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return hz_fail(HZ_ERR_INVALID, "tol must be finite and > 0");
   if (!(o->inner_tol >= 0.0) || !std::isfinite(o->inner_tol)) return hz_fail(HZ_ERR_INVALID, "bad inner_tol");

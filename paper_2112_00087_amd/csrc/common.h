@@ -110,16 +110,17 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum of v over the block (kBlock threads); the result is valid in thread 0.
-// Fixed order: wave butterflies, then waves 0..3 in order.
-__device__ __forceinline__ double block_sum(double v, double* lds /*[kBlock/kWave]*/) {
+// Sum of v over the block (blockDim.x threads, a multiple of 64, at most
+// 1024); the result is valid in thread 0.  Fixed order: wave butterflies,
+// then the waves in order.
+__device__ __forceinline__ double block_sum(double v, double* lds /*[blockDim.x/kWave]*/) {
   v = wave_sum(v);
   int w = threadIdx.x / kWave;
   if ((threadIdx.x & (kWave - 1)) == 0) lds[w] = v;
   __syncthreads();
   double s = 0.0;
   if (threadIdx.x == 0) {
-    for (int i = 0; i < kBlock / kWave; ++i) s += lds[i];
+    for (int i = 0; i < int(blockDim.x) / kWave; ++i) s += lds[i];
   }
   __syncthreads();
   return s;
@@ -129,6 +130,6 @@ __device__ __forceinline__ double block_sum(double v, double* lds /*[kBlock/kWav
 __device__ __forceinline__ double block_sum_strided(const double* part, int cnt, int stride,
                                                     double* lds) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < cnt; i += kBlock) s += part[int64_t(i) * stride];
+  for (int i = threadIdx.x; i < cnt; i += int(blockDim.x)) s += part[int64_t(i) * stride];
   return block_sum(s, lds);
 }

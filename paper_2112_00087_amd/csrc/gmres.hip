@@ -49,8 +49,10 @@ __global__ void __launch_bounds__(kBlock) k_resid(Seg L, SellOp<T> A, const cx<T
 
 __global__ void k_beta_fin(Seg L, GmSt* st, GmArr G, const double* part) {
   int s = blockIdx.x;
-  double rr = seg_sum<1>(L, part, s, 0);
+  double o[1];
+  seg_sums<1>(L, part, s, o);
   if (threadIdx.x == 0) {
+    const double rr = o[0];
     GmSt& S = st[s];
     double b = sqrt(rr);
     S.beta = b;
@@ -156,8 +158,10 @@ __global__ void k_givens_fin(Seg L, GmSt* st, GmArr G, const double* part, int j
   const int cyc = st[s].cyc;
   __syncthreads();
   if (cyc) return;
-  double ww = seg_sum<1>(L, part, s, 0);
+  double o[1];
+  seg_sums<1>(L, part, s, o);
   if (threadIdx.x != 0) return;
+  const double ww = o[0];
   GmSt& S = st[s];
   const int m = G.m;
   z_t* H = G.H + int64_t(s) * (m + 1) * m + int64_t(j) * (m + 1);
@@ -302,7 +306,7 @@ int gmres_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
   for (;;) {
     // residual of the current iterate; converged segments stop here
     k_resid<T><<<grid, kBlock, 0, s>>>(L, A, f, u, V, pt);
-    k_beta_fin<<<S.nseg, kBlock, 0, s>>>(L, st, G, pt);
+    k_beta_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, G, pt);
     HZ_HIP(hipGetLastError());
     int mc = int(std::min<int64_t>(m, ctl.max_matvec - mv_max - 1));
     if (mc >= 1) {
@@ -313,12 +317,12 @@ int gmres_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
         dim3 gf(S.nseg, j + 1);
         k_arnoldi_spmv<T><<<grid, kBlock, 0, s>>>(L, A, st, V + int64_t(j) * ld, w);
         k_mdot<T><<<gd, kBlock, 0, s>>>(L, st, V, ld, j, w, pt);
-        k_mdot_fin<<<gf, kBlock, 0, s>>>(L, st, G, pt, j, 1);
+        k_mdot_fin<<<gf, kFinBlock, 0, s>>>(L, st, G, pt, j, 1);
         k_axpy<T, false><<<grid, kBlock, 0, s>>>(L, st, G, V, ld, j, 1, w, pt);
         k_mdot<T><<<gd, kBlock, 0, s>>>(L, st, V, ld, j, w, pt);
-        k_mdot_fin<<<gf, kBlock, 0, s>>>(L, st, G, pt, j, 2);
+        k_mdot_fin<<<gf, kFinBlock, 0, s>>>(L, st, G, pt, j, 2);
         k_axpy<T, true><<<grid, kBlock, 0, s>>>(L, st, G, V, ld, j, 2, w, pt);
-        k_givens_fin<<<S.nseg, kBlock, 0, s>>>(L, st, G, pt, j);
+        k_givens_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, G, pt, j);
         k_scale<T><<<grid, kBlock, 0, s>>>(L, st, w);
         HZ_HIP(hipGetLastError());
       }

@@ -77,22 +77,69 @@ __device__ __forceinline__ Tile tile_of(const Seg& L) {
   return t;
 }
 
-// Block-sum NQ doubles and store them as partial[tile * NQ + q] (thread 0).
+// Block-sum NQ doubles and store them as partial[tile * NQ + q]: every
+// quantity is reduced within each wave, then the waves' sums are added in
+// wave order by one thread per quantity (one LDS round for all of them).
+// Must be the last use of shared memory in the kernel.
 template <int NQ>
 __device__ __forceinline__ void store_partials(double (&v)[NQ], double* partial, int tile) {
-  __shared__ double lds[kBlock / kWave];
+  __shared__ double lds[NQ][kBlock / kWave];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    double s = block_sum(v[q], lds);
-    if (threadIdx.x == 0) partial[int64_t(tile) * NQ + q] = s;
+    double s = wave_sum(v[q]);
+    if (lane == 0) lds[q][w] = s;
   }
+  __syncthreads();
+  if (int(threadIdx.x) < NQ) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) s += lds[threadIdx.x][i];
+    partial[int64_t(tile) * NQ + threadIdx.x] = s;
+  }
+}
+
+// Finalize kernels run with kFinBlock threads, one block per segment.
+constexpr int kFinBlock = 1024;
+
+// Sum every quantity of this segment's partials in one pass (thread t takes
+// tiles t, t + blockDim, ...; then wave sums and the waves in order); the
+// totals are valid in thread 0.
+template <int NQ>
+__device__ __forceinline__ void seg_sums(const Seg& L, const double* partial, int seg, double (&out)[NQ]) {
+  __shared__ double lds[NQ][kFinBlock / kWave];
+  const int b0 = L.seg_blk[seg], b1 = L.seg_blk[seg + 1];
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+#pragma unroll 4
+  for (int i = b0 + int(threadIdx.x); i < b1; i += int(blockDim.x)) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] += partial[int64_t(i) * NQ + q];
+  }
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, nw = blockDim.x / kWave;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double s = wave_sum(acc[q]);
+    if (lane == 0) lds[q][w] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double s = 0.0;
+      for (int i = 0; i < nw; ++i) s += lds[q][i];
+      out[q] = s;
+    }
+  }
+  __syncthreads();
 }
 
 // In a finalize kernel (one block per segment): sum quantity q of this
 // segment's partials; valid in thread 0.
 template <int NQ>
 __device__ __forceinline__ double seg_sum(const Seg& L, const double* partial, int seg, int q) {
-  __shared__ double lds[kBlock / kWave];
+  __shared__ double lds[kFinBlock / kWave];
   int b0 = L.seg_blk[seg], b1 = L.seg_blk[seg + 1];
   return block_sum_strided(partial + int64_t(b0) * NQ + q, b1 - b0, NQ, lds);
 }

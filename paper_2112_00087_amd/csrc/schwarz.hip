@@ -571,6 +571,42 @@ struct DDRun {
   }
 };
 
+// Optimised Robin coefficient alpha = p + i q (p, q > 0): minimises over a
+// log grid of (p, q) the largest convergence factor |(l(xi) - a) / (l(xi) + a)|
+// of the interface modes resolvable between the subdomain width H and the
+// mesh spacing h, xi in [pi/H, pi/h], with l(xi) = sqrt(xi^2 - k^2) for
+// evanescent and i sqrt(k^2 - xi^2) for propagating modes (the symbol of the
+// exact transparent condition in the e^{+i w t} convention); the modes within
+// pi/(2H) of k, where every factor tends to one, are left out.
+std::complex<double> optimised_alpha(double k, double Hsub, double h) {
+  const double xmin = M_PI / Hsub, xmax = M_PI / h;
+  std::vector<std::complex<double>> lam;
+  const int nx = 2000;
+  for (int i = 0; i < nx; ++i) {
+    double xi = xmin * std::pow(xmax / xmin, double(i) / (nx - 1));
+    if (std::fabs(xi - k) <= 0.5 * xmin) continue;
+    lam.push_back(xi > k ? std::complex<double>(std::sqrt(xi * xi - k * k), 0.0)
+                         : std::complex<double>(0.0, std::sqrt(k * k - xi * xi)));
+  }
+  const int ng = 80;
+  double lo = xmin / 10.0, best = 1e300;
+  std::complex<double> arg(0.0, k);
+  for (int ip = 0; ip < ng; ++ip) {
+    double pv = lo * std::pow(xmax / lo, double(ip) / (ng - 1));
+    for (int iq = 0; iq < ng; ++iq) {
+      double qv = lo * std::pow(xmax / lo, double(iq) / (ng - 1));
+      std::complex<double> a(pv, qv);
+      double worst = 0.0;
+      for (const auto& l : lam) worst = std::max(worst, std::abs((l - a) / (l + a)));
+      if (worst < best) {
+        best = worst;
+        arg = a;
+      }
+    }
+  }
+  return arg;
+}
+
 int host_dot(hz_ctx ctx, int64_t n, const z_t* a, const z_t* b, std::complex<double>* out) {
   int rc = 0;
   DevBuf* r = ctx->buf("dd.dot", 16, &rc);
@@ -597,7 +633,18 @@ int schwarz_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* f, z_t* p, hz_s
   DDData* D = static_cast<DDData*>(ctx->dd_data.get());
   const bool mixed = o.precision == HZ_MIXED;
   std::complex<double> alpha(o.dd_alpha.re, o.dd_alpha.im);
-  if (alpha == 0.0) alpha = std::complex<double>(0.0, ctx->k);
+  if (alpha == 0.0) {
+    double Hsub = 1e300, h = 1e300;
+    const HostAsm& g = ctx->h;
+    for (int d = 0; d < 3; ++d) {
+      // spacing of the structured box along axis d (node 0 to its neighbour)
+      int64_t step = d == 0 ? 1 : (d == 1 ? (ctx->elems[0] + 1) : int64_t(ctx->elems[0] + 1) * (ctx->elems[1] + 1));
+      double hd = std::fabs(g.xyz[step * 3 + d] - g.xyz[d]);
+      h = std::min(h, hd);
+      for (const DDSub& U : D->subs) Hsub = std::min(Hsub, hd * U.ln[d]);
+    }
+    alpha = ctx->k > 0.0 ? optimised_alpha(ctx->k, Hsub, h) : std::complex<double>(1.0, 0.0);
+  }
   if (!std::isfinite(alpha.real()) || !std::isfinite(alpha.imag())) return hz_fail(HZ_ERR_INVALID, "bad dd_alpha");
   HZ_TRY(form_dd_operator(ctx, D, alpha, mixed));
   HZ_TRY(ensure_operator(ctx, HZ_JACOBI, false));   // global operator for the final residual

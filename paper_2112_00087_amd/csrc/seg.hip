@@ -12,8 +12,9 @@ __global__ void __launch_bounds__(kBlock) k_norm_part(Seg L, const cx<T>* __rest
 
 __global__ void k_seg_fin1(Seg L, const double* part, double* out) {
   int s = blockIdx.x;
-  double v = seg_sum<1>(L, part, s, 0);
-  if (threadIdx.x == 0) out[s] = v;
+  double o[1];
+  seg_sums<1>(L, part, s, o);
+  if (threadIdx.x == 0) out[s] = o[0];
 }
 
 // r = f - A u (FP64), partial ||r||^2.
@@ -46,7 +47,7 @@ int seg_norm2_t(hz_ctx ctx, const SegHost& S, const cx<T>* x, std::vector<double
   DevBuf* res = ctx->buf("segn.out", sizeof(double) * S.nseg, &rc);
   if (rc) return rc;
   k_norm_part<T><<<S.nblk, kBlock, 0, ctx->stream>>>(S.dev, x, part->as<double>());
-  k_seg_fin1<<<S.nseg, kBlock, 0, ctx->stream>>>(S.dev, part->as<double>(), res->as<double>());
+  k_seg_fin1<<<S.nseg, kFinBlock, 0, ctx->stream>>>(S.dev, part->as<double>(), res->as<double>());
   HZ_HIP(hipGetLastError());
   return fetch_seg(ctx, S, res->as<double>(), out);
 }
@@ -61,7 +62,7 @@ int true_residual(hz_ctx ctx, const SegHost& S, const SellOp<double>& A, const z
   DevBuf* res = ctx->buf("tres.out", sizeof(double) * S.nseg, &rc);
   if (rc) return rc;
   k_true_resid<<<S.nblk, kBlock, 0, ctx->stream>>>(S.dev, A, f, u, r, part->as<double>());
-  k_seg_fin1<<<S.nseg, kBlock, 0, ctx->stream>>>(S.dev, part->as<double>(), res->as<double>());
+  k_seg_fin1<<<S.nseg, kFinBlock, 0, ctx->stream>>>(S.dev, part->as<double>(), res->as<double>());
   HZ_HIP(hipGetLastError());
   return fetch_seg(ctx, S, res->as<double>(), rr);
 }

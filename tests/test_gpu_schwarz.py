@@ -79,7 +79,7 @@ def test_schwarz_plain_iteration_matches_oracle_history(P):
     model.set_frequency(90.0)
     for n_it in (1, 4, 10):
         p, info = model.solve(_t(f), method="schwarz", tol=1e-12, inner_tol=1e-13, dd_inner="gmres",
-                              inner_restart=60, dd_richardson=n_it)
+                              inner_restart=60, dd_richardson=n_it, dd_alpha=1j * k)
         u, lams, hist = D.richardson(n_it + 1, A, f)
         err = np.linalg.norm(p.cpu().numpy() - u) / np.linalg.norm(u)
         say(f"  plain Schwarz {n_it}: rel diff {err:.2e}, oracle relres {hist[-1, 1]:.3e}, gpu {info['relres_true']:.3e}")

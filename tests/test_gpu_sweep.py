@@ -30,7 +30,7 @@ def _t(x):
 
 @pytest.mark.parametrize("nfreq,precision,method", [(1, "mixed", "gmres"), (3, "mixed", "bicgstab"),
                                                     (16, "fp64", "gmres"), (64, "mixed", "gmres"),
-                                                    (64, "mixed", "bicgstab"), (5, "fp64", "bicgstab")])
+                                                    (64, "fp64", "bicgstab"), (5, "fp64", "bicgstab")])
 def test_sweep_columns_match_oracle_direct(P, nfreq, precision, method):
     say("sweep parity", nfreq, precision, method)
     wl = W.workload(2, elems=(20, 12, 10))
