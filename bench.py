@@ -23,20 +23,14 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the complex128 product on this workload, from the
-# FETCH_SIZE / WRITE_SIZE passes recorded in profiles/ (calibrated against a
-# 1 GiB device copy); set to None whenever the kernel changes until re-measured.
-MEASURED_TRAFFIC = {"k_spmv<double>": 717.9e6}
+# HBM bytes per launch of the FP64 product on this workload, per storage form,
+# from the FETCH_SIZE / WRITE_SIZE passes recorded in profiles/ (calibrated
+# against a 1 GiB device copy); None until measured for the current kernel.
+MEASURED_TRAFFIC = {"split": None, "complex": None}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def spmv_bytes(n, nnz):
-    # values (16 B) + column index (4 B) per nonzero, row/slice pointers,
-    # x read once and y written once (16 B each)
-    return 20 * nnz + 4 * (n + 1) + 32 * n
 
 
 def cpu_baseline(wl, gpu_iters, iters):
@@ -59,9 +53,9 @@ def cpu_baseline(wl, gpu_iters, iters):
                       f"{per_iter * 1e3:.1f} ms/iteration), scaled to the GPU's {gpu_iters} iterations"}
 
 
-def sweep_leg(log_fn, precision="mixed", method="bicgstab"):
+def sweep_leg(log_fn, precisions=("fp64", "mixed"), method="bicgstab"):
     """Workload 2: 64 frequencies, 80x48x40.  T_A = 64 x (set_frequency + FP64
-    solve), T_B = one batched sweep; both use the same Krylov method."""
+    solve); T_B[precision] = one batched sweep; all use the same Krylov method."""
     import torch
     import workloads as W
     from paper_2112_00087_amd import Helmholtz
@@ -71,8 +65,9 @@ def sweep_leg(log_fn, precision="mixed", method="bicgstab"):
     freqs = wl["freqs"]
     F = f[:, None].repeat(1, freqs.size).contiguous()
     opts = dict(method=method, tol=1e-8, max_matvec=200000, restart=30)
-    # warm-up of both paths (autotuner, graph capture, allocations)
-    m.solve_sweep(freqs[:2], F[:, :2].contiguous(), precision=precision, **opts)
+    # warm-up of every path (autotuner, graph capture, allocations)
+    for prec in precisions:
+        m.solve_sweep(freqs[:2], F[:, :2].contiguous(), precision=prec, **opts)
     m.set_frequency(freqs[0])
     m.solve(f, **opts)
     torch.cuda.synchronize()
@@ -86,17 +81,19 @@ def sweep_leg(log_fn, precision="mixed", method="bicgstab"):
     torch.cuda.synchronize()
     T_A = time.perf_counter() - t
     log_fn(f"sweep A (64 x FP64 {method}): {T_A:.2f}s, converged {a_ok}/64")
-    t = time.perf_counter()
-    _, infos = m.solve_sweep(freqs, F, precision=precision, **opts)
-    torch.cuda.synchronize()
-    T_B = time.perf_counter() - t
-    b_ok = sum(i["status"] == 0 for i in infos)
-    worst = max(i["relres_true"] for i in infos)
-    log_fn(f"sweep B (batched {precision} {method}): {T_B:.2f}s, converged {b_ok}/64, worst relres {worst:.2e}")
+    out = {"workload": wl["name"], "method": method, "T_A_s": T_A, "converged_A": a_ok, "iters_A": a_iters}
+    for prec in precisions:
+        t = time.perf_counter()
+        _, infos = m.solve_sweep(freqs, F, precision=prec, **opts)
+        torch.cuda.synchronize()
+        T_B = time.perf_counter() - t
+        b_ok = sum(i["status"] == 0 for i in infos)
+        worst = max(i["relres_true"] for i in infos)
+        log_fn(f"sweep B (batched {prec} {method}): {T_B:.2f}s, converged {b_ok}/64, worst relres {worst:.2e}")
+        out[f"batched_{prec}"] = {"T_B_s": T_B, "speedup": T_A / T_B, "converged": b_ok, "worst_relres": worst,
+                                  "iters": [i["iters"] for i in infos]}
     m.close()
-    return {"workload": wl["name"], "method": method, "precision_B": precision, "T_A_s": T_A, "T_B_s": T_B,
-            "speedup": T_A / T_B, "converged_A": a_ok, "converged_B": b_ok, "worst_relres_B": worst,
-            "iters_A": a_iters, "iters_B": [i["iters"] for i in infos]}
+    return out
 
 
 def schwarz_leg(log_fn, max_matvec=300):
@@ -218,20 +215,30 @@ def main():
     log(f"timed: {dt:.4f} s/solve, {infos[-1]}")
 
     n, nnz = sizes["n_nodes"], sizes["nnz"]
-    ms = model.time_spmv(args.spmv_reps, "fp64")
-    byts = spmv_bytes(n, nnz)
+    # the product in the form the solver ran (split unless an absorption field
+    # makes every entry complex), then the complex128 form for reference
+    form = "split" if model.spmv_bytes("fp64", "solver") != model.spmv_bytes("fp64", "complex") else "complex"
+    ms = model.time_spmv(args.spmv_reps, "fp64", form)
+    byts = model.spmv_bytes("fp64", form)
     gbs = byts / (ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get("k_spmv<double>"),
-            "kernel": "k_spmv<double> (complex128 sliced-ELL product)",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get(form),
+            "kernel": f"k_spmv<double> ({form} form sliced-ELL product)",
             "avg_kernel_ms": ms, "algorithmic_bytes": byts}
-    log(f"spmv: {ms * 1e3:.1f} us, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
+    log(f"spmv ({form}): {ms * 1e3:.1f} us, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
 
     extra = {}
+    if form != "complex":
+        msc = model.time_spmv(args.spmv_reps, "fp64", "complex")
+        bc = model.spmv_bytes("fp64", "complex")
+        extra["spmv_complex128"] = {"ms": msc, "bytes": bc, "GBs": bc / (msc * 1e-3) / 1e9,
+                                    "frac": bc / (msc * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                    "traffic": MEASURED_TRAFFIC.get("complex")}
+        log(f"spmv (complex): {msc * 1e3:.1f} us, {extra['spmv_complex128']['GBs']:.0f} GB/s")
     if not args.no_extra and not args.spmv_only:
-        ms32 = model.time_spmv(args.spmv_reps, "mixed")
-        b32 = 12 * nnz + 4 * (n + 1) + 16 * n
-        extra["spmv_c64_GBs"] = b32 / (ms32 * 1e-3) / 1e9
+        ms32 = model.time_spmv(args.spmv_reps, "mixed", form)
+        b32 = model.spmv_bytes("mixed", form)
+        extra["spmv_fp32_GBs"] = b32 / (ms32 * 1e-3) / 1e9
         for label, o in (("gmres50", dict(method="gmres", restart=50)),
                          ("bicgstab_mixed", dict(method="bicgstab", precision="mixed")),
                          ("gmres50_mixed", dict(method="gmres", restart=50, precision="mixed"))):
@@ -267,7 +274,8 @@ def main():
                    "solver": "bicgstab, right Jacobi", "tol": 1e-8,
                    "iters": infos[-1]["iters"], "relres_true": infos[-1]["relres_true"]},
         "spmv_GBs": gbs,
-        "sweep_speedup": None if sweep is None else sweep["speedup"],
+        "sweep_speedup": None if sweep is None else {
+            k[len("batched_"):]: v["speedup"] for k, v in sweep.items() if k.startswith("batched_")},
         "sweep": sweep,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -251,15 +251,38 @@ int hz_solve_adjoint(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* p_dev
                      const hz_c128* g_dev, hz_c128* lambda_dev, double* dJ_dbeta,
                      double* dJ_deta_dev, hz_solve_info* info);
 
+/* Storage forms of the operator for the two calls below.  The complex form
+ * stores one complex value and one int32 column per entry.  The split form
+ * (used by the solvers whenever there is no absorption field) stores the
+ * real part of every entry, int16 column offsets from the row when they all
+ * fit (else int32 columns), and the imaginary parts of the few entries that
+ * can have one: those carrying a wall admittance term or lying in a wall
+ * node's column (the Jacobi scaling by a complex wall diagonal).  Both give
+ * the same product up to rounding order.  Environment variable HZ_SPLIT=0
+ * (read when the context is created) disables the split form. */
+enum { HZ_SPMV_SOLVER = 0, HZ_SPMV_COMPLEX = 1, HZ_SPMV_SPLIT = 2 };
+
 /* Measurement of the sparse product (paper Sec. 4: the product dominates
  * the solve time).  Runs y = A x of the current operator `reps` times
  * (1..100000) on the context's stream, bracketed by two HIP events recorded
  * on that stream, and returns the average duration of one product in
- * milliseconds.  precision HZ_FP64 times the complex128 product used by
- * hz_apply and the FP64 solvers; HZ_MIXED the complex64 product of the
- * mixed-precision inner solves.  x and y are internal buffers.  Host result;
- * synchronises the stream. */
-int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, double* avg_ms);
+ * milliseconds.  precision HZ_FP64 times the complex128 product of the FP64
+ * solvers; HZ_MIXED the complex64 product of the mixed-precision inner
+ * solves.  format: HZ_SPMV_SOLVER (the form the solvers use),
+ * HZ_SPMV_COMPLEX or HZ_SPMV_SPLIT (HZ_ERR_STATE if that form is not
+ * formed).  x and y are internal buffers.  Host result; synchronises the
+ * stream. */
+int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, int32_t format, double* avg_ms);
+
+/* Algorithmic bytes of one product of the given precision and form: every
+ * stored value, index and row pointer read once, x read once and y written
+ * once (n = n_nodes, nnz = CSR nonzeros, r = 8 for FP64 or 4 for FP32):
+ *   complex form  (2r + 4) nnz + 4 (n + 1) + 4 r n
+ *   split form    (r + idx) nnz + (r + 4) n_imag + 4 (n + 1) + 4 r n,
+ *                 idx = 2 (int16 offsets) or 4, n_imag = listed imaginary
+ *                 entries.
+ * Requires a frequency (HZ_ERR_STATE otherwise). */
+int hz_spmv_bytes(hz_ctx ctx, int32_t precision, int32_t format, int64_t* bytes);
 
 /* Sizes of the context: n_nodes, n_elems, stored nonzeros (CSR count),
  * and the device bytes the context holds. */

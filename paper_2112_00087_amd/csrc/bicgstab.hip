@@ -2,10 +2,11 @@
 // on the right-Jacobi operator, for every segment of a segmented system.
 //
 // One iteration of van der Vorst's method is five vector kernels (two of
-// them sparse products with fused inner-product epilogues) and four
+// them sparse products with fused inner-product epilogues) and three
 // one-block-per-segment finalize kernels that turn block partials into the
-// Krylov scalars.  The scalars never leave the device; the host only reads
-// the per-segment state every few iterations to decide whether to stop.
+// Krylov scalars (the early-exit test on ||s|| rides on the omega step).
+// The scalars never leave the device; the host only reads the per-segment
+// state every few iterations to decide whether to stop.
 // Every kernel first reads its segment's flags and returns if that segment
 // has converged, so extra queued iterations cost only empty launches.
 #include <chrono>
@@ -16,6 +17,7 @@ namespace {
 
 struct BiSt {
   z_t rho, rho_old, alpha, omega;
+  z_t beta;                       // (rho / rho_old) (alpha / omega) for the next p update
   double rr, ss, thr2, rhat2;
   int iter, done, early, reset;
   int nan, pad0;
@@ -62,6 +64,7 @@ __global__ void k_resid_fin(Seg L, BiSt* st, const double* part) {
     S.rr = rr;
     S.rho = z_t{rr, 0.0};
     S.rho_old = S.alpha = S.omega = z_t{1.0, 0.0};
+    S.beta = z_t{rr, 0.0};
     S.rhat2 = rr;
     S.early = 0;
     S.reset = 0;
@@ -82,9 +85,8 @@ __global__ void __launch_bounds__(kBlock) k_p(Seg L, const BiSt* st, BiV<T> V) {
     V.p[t.row] = r;
     return;
   }
-  z_t beta = cdiv(S.rho, S.rho_old) * cdiv(S.alpha, S.omega);
   z_t p = zd(V.p[t.row]) - S.omega * zd(V.v[t.row]);
-  V.p[t.row] = zt<T>(zd(r) + beta * p);
+  V.p[t.row] = zt<T>(zd(r) + S.beta * p);
 }
 
 // v = A p; partial rhat^H v.
@@ -118,52 +120,42 @@ __global__ void k_alpha_fin(Seg L, BiSt* st, const double* part) {
   }
 }
 
-// s = r - alpha v; partial ||s||^2.
+// s = r - alpha v.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_s(Seg L, const BiSt* st, BiV<T> V, double* part) {
+__global__ void __launch_bounds__(kBlock) k_s(Seg L, const BiSt* st, BiV<T> V) {
   Tile t = tile_of(L);
   const BiSt& S = st[t.seg];
   if (S.done) return;
   z_t s = zd(V.r[t.row]) - S.alpha * zd(V.v[t.row]);
-  cx<T> ss = zt<T>(s);
-  V.s[t.row] = ss;
-  double q[1] = {norm2(zd(ss))};
-  store_partials<1>(q, part, t.tile);
+  V.s[t.row] = zt<T>(s);
 }
 
-__global__ void k_s_fin(Seg L, BiSt* st, const double* part) {
-  int s = blockIdx.x;
-  if (st[s].done) return;
-  double o[1];
-  seg_sums<1>(L, part, s, o);
-  if (threadIdx.x == 0) {
-    const double ss = o[0];
-    st[s].ss = ss;
-    st[s].early = (ss <= st[s].thr2) ? 1 : 0;
-  }
-}
-
-// t = A s; partials t^H s, t^H t.
+// t = A s; partials t^H s, t^H t, s^H s.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_t(Seg L, SellOp<T> A, const BiSt* st, BiV<T> V, double* part) {
   Tile t = tile_of(L);
   const BiSt& S = st[t.seg];
-  if (S.done || S.early) return;
+  if (S.done) return;
   cx<T> y = sell_row(A, t.row, V.s);
   V.t[t.row] = y;
   z_t a = zd(y), b = zd(V.s[t.row]);
-  double q[3] = {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re, norm2(a)};
-  store_partials<3>(q, part, t.tile);
+  double q[4] = {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re, norm2(a), norm2(b)};
+  store_partials<4>(q, part, t.tile);
 }
 
+// omega = t^H s / t^H t, or the early exit when ||s|| already meets the target
+// (then x += alpha p completes the iteration).
 __global__ void k_omega_fin(Seg L, BiSt* st, const double* part) {
   int s = blockIdx.x;
-  if (st[s].done || st[s].early) return;
-  double o[3];
-  seg_sums<3>(L, part, s, o);
+  if (st[s].done) return;
+  double o[4];
+  seg_sums<4>(L, part, s, o);
   if (threadIdx.x == 0) {
-    const double re = o[0], im = o[1], tt = o[2];
-    st[s].omega = (tt > 0.0) ? z_t{re / tt, im / tt} : z_t{0.0, 0.0};
+    const double re = o[0], im = o[1], tt = o[2], ss = o[3];
+    BiSt& S = st[s];
+    S.ss = ss;
+    S.early = (ss <= S.thr2) ? 1 : 0;
+    S.omega = (tt > 0.0 && !S.early) ? z_t{re / tt, im / tt} : z_t{0.0, 0.0};
   }
 }
 
@@ -222,6 +214,7 @@ __global__ void k_rho_fin(Seg L, BiSt* st, const double* part) {
       S.rho_old = S.alpha = S.omega = z_t{1.0, 0.0};
       S.rhat2 = rr;
     }
+    S.beta = cdiv(S.rho, S.rho_old) * cdiv(S.alpha, S.omega);
   }
 }
 
@@ -253,7 +246,7 @@ int bicgstab_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* 
   }
   DevBuf* stb = ctx->buf(p + "st", sizeof(BiSt) * S.nseg, &rc);
   if (rc) return rc;
-  DevBuf* part = ctx->buf(p + "part", sizeof(double) * 3 * S.nblk, &rc);
+  DevBuf* part = ctx->buf(p + "part", sizeof(double) * 4 * S.nblk, &rc);
   if (rc) return rc;
   DevBuf* fnb = ctx->buf(p + "fn2", sizeof(double) * S.nseg, &rc);
   if (rc) return rc;
@@ -296,8 +289,7 @@ int bicgstab_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* 
     k_p<T><<<grid, kBlock, 0, s>>>(L, st, V);
     k_v<T><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     k_alpha_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
-    k_s<T><<<grid, kBlock, 0, s>>>(L, st, V, pt);
-    k_s_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
+    k_s<T><<<grid, kBlock, 0, s>>>(L, st, V);
     k_t<T><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     k_omega_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     k_xr<T><<<grid, kBlock, 0, s>>>(L, st, V, pt);

@@ -104,6 +104,7 @@ int hz_set_params(hz_ctx ctx, const hz_c128* beta, const double* eta) {
   ctx->have_freq = false;
   ctx->scaled = -1;
   ctx->have_A32 = false;
+  ctx->have_split = ctx->have_split32 = false;
   return HZ_OK;
   HZ_GUARD_END
 }
@@ -214,13 +215,29 @@ int hz_solve_adjoint(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* p_dev
   HZ_GUARD_END
 }
 
-int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, double* avg_ms) {
+namespace {
+// The product of the given form: the solvers' choice, or forced complex / split.
+int spmv_form(hz_ctx ctx, int32_t precision, int32_t format, bool* split) {
+  if (precision != HZ_FP64 && precision != HZ_MIXED) return hz_fail(HZ_ERR_INVALID, "bad precision");
+  if (format != HZ_SPMV_SOLVER && format != HZ_SPMV_COMPLEX && format != HZ_SPMV_SPLIT)
+    return hz_fail(HZ_ERR_INVALID, "bad format");
+  const bool mixed = precision == HZ_MIXED;
+  HZ_TRY(ensure_operator(ctx, ctx->scaled < 0 ? HZ_JACOBI : ctx->scaled, mixed));
+  const bool have = mixed ? ctx->have_split32 : ctx->have_split;
+  if (format == HZ_SPMV_SPLIT && !have)
+    return hz_fail(HZ_ERR_STATE, "split form not formed (absorption field present or HZ_SPLIT=0)");
+  *split = format == HZ_SPMV_SPLIT || (format == HZ_SPMV_SOLVER && have);
+  return HZ_OK;
+}
+}  // namespace
+
+int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, int32_t format, double* avg_ms) {
   HZ_GUARD_BEGIN
   HZ_TRY(check_ctx(ctx));
   if (!avg_ms || reps < 1 || reps > 100000) return hz_fail(HZ_ERR_INVALID, "bad arguments");
-  if (precision != HZ_FP64 && precision != HZ_MIXED) return hz_fail(HZ_ERR_INVALID, "bad precision");
+  bool split = false;
+  HZ_TRY(spmv_form(ctx, precision, format, &split));
   const bool mixed = precision == HZ_MIXED;
-  HZ_TRY(ensure_operator(ctx, ctx->scaled < 0 ? HZ_JACOBI : ctx->scaled, mixed));
   int rc = 0;
   const int64_t nr = ctx->sell.n_rows;
   const size_t es = mixed ? sizeof(c_t) : sizeof(z_t);
@@ -229,17 +246,18 @@ int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, double* avg_ms) {
   DevBuf* yb = ctx->buf("time.y", es * nr, &rc);
   if (rc) return rc;
   HZ_HIP(hipMemsetAsync(xb->p, 0, es * nr, ctx->stream));
+  const SellOp<double> A64 = split ? op_split<double>(ctx) : op_A_complex(ctx);
+  const SellOp<float> A32 = split ? op_split<float>(ctx) : op_A32_complex(ctx);
+  auto one = [&]() -> int {
+    if (mixed) return op_spmv<float>(ctx->stream, nr, nr, A32, xb->as<c_t>(), yb->as<c_t>());
+    return op_spmv<double>(ctx->stream, nr, nr, A64, xb->as<z_t>(), yb->as<z_t>());
+  };
   hipEvent_t e0, e1;
   HZ_HIP(hipEventCreate(&e0));
   HZ_HIP(hipEventCreate(&e1));
-  // one untimed product first
-  if (mixed) HZ_TRY(op_spmv<float>(ctx->stream, nr, nr, op_A32(ctx), xb->as<c_t>(), yb->as<c_t>()));
-  else HZ_TRY(op_spmv<double>(ctx->stream, nr, nr, op_A(ctx), xb->as<z_t>(), yb->as<z_t>()));
+  HZ_TRY(one());   // one untimed product first
   HZ_HIP(hipEventRecord(e0, ctx->stream));
-  for (int r = 0; r < reps; ++r) {
-    if (mixed) HZ_TRY(op_spmv<float>(ctx->stream, nr, nr, op_A32(ctx), xb->as<c_t>(), yb->as<c_t>()));
-    else HZ_TRY(op_spmv<double>(ctx->stream, nr, nr, op_A(ctx), xb->as<z_t>(), yb->as<z_t>()));
-  }
+  for (int r = 0; r < reps; ++r) HZ_TRY(one());
   HZ_HIP(hipEventRecord(e1, ctx->stream));
   HZ_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
@@ -247,6 +265,24 @@ int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, double* avg_ms) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *avg_ms = double(ms) / reps;
+  return HZ_OK;
+  HZ_GUARD_END
+}
+
+int hz_spmv_bytes(hz_ctx ctx, int32_t precision, int32_t format, int64_t* bytes) {
+  HZ_GUARD_BEGIN
+  HZ_TRY(check_ctx(ctx));
+  if (!bytes) return hz_fail(HZ_ERR_INVALID, "bytes is NULL");
+  bool split = false;
+  HZ_TRY(spmv_form(ctx, precision, format, &split));
+  const int64_t n = ctx->h.n, nnz = int64_t(ctx->h.col.size());
+  const int64_t real = precision == HZ_MIXED ? 4 : 8;   // bytes of one real part
+  if (!split) {
+    *bytes = (2 * real + 4) * nnz + 4 * (n + 1) + 4 * real * n;
+  } else {
+    const int64_t idx = ctx->split_dcol ? 2 : 4;
+    *bytes = (real + idx) * nnz + (real + 4) * ctx->n_imag + 4 * (n + 1) + 4 * real * n;
+  }
   return HZ_OK;
   HZ_GUARD_END
 }

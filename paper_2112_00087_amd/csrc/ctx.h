@@ -86,6 +86,16 @@ struct hz_ctx_s {
   DevBuf d_A, d_A32, d_d, d_dinv;    // A (maybe column-scaled), complex64 copy, diag, 1/diag
   bool have_A32 = false;
 
+  // split form of the operator (real parts of every stored entry, imaginary
+  // parts of the entries next to the absorbing walls); pattern built at
+  // upload, values formed with A when there is no absorption field
+  bool split_on = true;              // HZ_SPLIT=0 in the environment turns it off
+  bool split_dcol = false;           // every |col - row| fits int16
+  int64_t n_imag = 0;                // entries with a possibly nonzero imaginary part
+  DevBuf d_dcol, d_iptr, d_icol, d_ipos;
+  DevBuf d_R, d_R32, d_I, d_I32;
+  bool have_split = false, have_split32 = false;   // values match the current A / A32
+
   std::vector<std::complex<double>> beta;   // [6]
   bool have_eta = false;
   int params_version = 0;            // bumped by hz_set_params

@@ -1,6 +1,7 @@
 // Context lifecycle: device buffers, upload of the assembled operator parts
 // in sliced-ELL layout, error strings.
 #include <cstdarg>
+#include <cstdlib>
 #include <cstring>
 
 #include "ops.h"
@@ -132,11 +133,45 @@ int ctx_upload(hz_ctx ctx) {
       if (s.src[p] >= 0) bidx[p] = csr2b[s.src[p]];
     HZ_TRY(put(ctx, ctx->d_bidx, bidx.data(), bidx.size()));
   }
+  std::vector<int32_t> dpos(a.n);
+  for (int64_t i = 0; i < a.n; ++i)
+    dpos[i] = int32_t(s.ptr[i / kWave] + (a.diag[i] - a.rowptr[i]) * kWave + (i % kWave));
+  HZ_TRY(put(ctx, ctx->d_diag, dpos.data(), dpos.size()));
   {
-    std::vector<int32_t> dpos(a.n);
-    for (int64_t i = 0; i < a.n; ++i)
-      dpos[i] = int32_t(s.ptr[i / kWave] + (a.diag[i] - a.rowptr[i]) * kWave + (i % kWave));
-    HZ_TRY(put(ctx, ctx->d_diag, dpos.data(), dpos.size()));
+    // Split-form pattern.  Without an absorption field, entry (i, j) of the
+    // (column-scaled) operator is complex only if it carries a wall term or
+    // column j's diagonal does (then 1/diag_j is complex).
+    const char* env = std::getenv("HZ_SPLIT");
+    ctx->split_on = !(env && env[0] == '0');
+    std::vector<int32_t> csr2b(a.col.size(), -1);
+    for (size_t e = 0; e < a.bpos.size(); ++e) csr2b[a.bpos[e]] = int32_t(e);
+    std::vector<uint8_t> wall_col(a.n, 0);
+    for (int64_t j = 0; j < a.n; ++j) wall_col[j] = csr2b[a.diag[j]] >= 0;
+    std::vector<int32_t> iptr(nrows + 1, 0), icol, ipos;
+    std::vector<int16_t> dcol(s.n_pad, 0);
+    bool fits = true;
+    for (int64_t i = 0; i < nrows; ++i) {
+      if (i < a.n) {
+        const int64_t sl = i / kWave, l = i % kWave, w = (s.ptr[sl + 1] - s.ptr[sl]) / kWave;
+        for (int64_t k = 0; k < w; ++k) {
+          const int64_t p = s.ptr[sl] + k * kWave + l;
+          const int64_t d = int64_t(s.col[p]) - i;
+          if (d < -32768 || d > 32767) fits = false;
+          else dcol[p] = int16_t(d);
+          if (s.src[p] >= 0 && (csr2b[s.src[p]] >= 0 || wall_col[s.col[p]])) {
+            icol.push_back(s.col[p]);
+            ipos.push_back(int32_t(p));
+          }
+        }
+      }
+      iptr[i + 1] = int32_t(icol.size());
+    }
+    ctx->n_imag = int64_t(icol.size());
+    ctx->split_dcol = fits;
+    if (fits) HZ_TRY(put(ctx, ctx->d_dcol, dcol.data(), dcol.size()));
+    HZ_TRY(put(ctx, ctx->d_iptr, iptr.data(), iptr.size()));
+    HZ_TRY(put(ctx, ctx->d_icol, icol.data(), icol.size()));
+    HZ_TRY(put(ctx, ctx->d_ipos, ipos.data(), ipos.size()));
   }
   HZ_TRY(put(ctx, ctx->d_bmass, a.bmass.data(), a.bmass.size()));
   HZ_TRY(put(ctx, ctx->d_prow, a.prow.data(), a.prow.size()));

@@ -23,11 +23,26 @@ struct Seg {
   const int* seg_blk = nullptr;   // [nseg + 1]
 };
 
+// A sliced-ELL operator in one of two storage forms.
+//  complex form (val != NULL): one complex value per stored entry.
+//  split form (val == NULL): the real part of every stored entry (re) plus,
+//    per row, a short list of the entries whose imaginary part can be
+//    nonzero (iptr/icol/iim).  Without an absorption field only the entries
+//    that touch the absorbing walls are complex (the wall term and the
+//    Jacobi scaling of wall columns), so this form streams 8 (FP64) or 4
+//    (FP32) bytes per entry instead of 16 or 8.
+//  Column indices are int32 (col) or, when every |col - row| fits, int16
+//  offsets from the row (dcol).
 template <typename T>
 struct SellOp {
   const int* ptr = nullptr;       // [nrows / 64 + 1] slice offsets
   const int* col = nullptr;
   const cx<T>* val = nullptr;
+  const T* re = nullptr;          // split form
+  const int16_t* dcol = nullptr;  // split form: column - row (NULL: use col)
+  const int* iptr = nullptr;      // [nrows + 1] imaginary entries of each row
+  const int* icol = nullptr;
+  const T* iim = nullptr;
 };
 
 // Non-temporal loads for the streamed matrix data (read once per product):
@@ -43,6 +58,24 @@ __device__ __forceinline__ c_t ld_stream(const c_t* p) {
   return c_t{v.x, v.y};
 }
 __device__ __forceinline__ int ld_stream(const int* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ int ld_stream(const int16_t* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_stream(const float* p) { return __builtin_nontemporal_load(p); }
+
+// Real-part sweep of the split form: acc += re_k * x[col_k] over the row.
+template <typename T, typename I>
+__device__ __forceinline__ void split_real(const I* __restrict__ c, const T* __restrict__ v, int w, int64_t row,
+                                           const cx<T>* __restrict__ x, T& ar, T& ai) {
+#pragma unroll 3
+  for (int k = 0; k < w; ++k) {
+    int j = ld_stream(c + (k << 6));
+    if (sizeof(I) == 2) j += int(row);
+    T a = ld_stream(v + (k << 6));
+    cx<T> xv = x[j];
+    ar = fma(a, xv.re, ar);
+    ai = fma(a, xv.im, ai);
+  }
+}
 
 // y_row = sum_k A[row, col_k] x[col_k] over the row's sliced-ELL entries.
 template <typename T>
@@ -50,17 +83,30 @@ __device__ __forceinline__ cx<T> sell_row(const SellOp<T>& A, int64_t row, const
   int slice = int(row >> 6), lane = int(row & 63);
   int beg = A.ptr[slice];
   int w = (A.ptr[slice + 1] - beg) >> 6;
-  const int* __restrict__ c = A.col + beg + lane;
-  const cx<T>* __restrict__ v = A.val + beg + lane;
-  cx<T> acc = {T(0), T(0)};
+  if (A.val) {
+    const int* __restrict__ c = A.col + beg + lane;
+    const cx<T>* __restrict__ v = A.val + beg + lane;
+    cx<T> acc = {T(0), T(0)};
 #pragma unroll 3
-  for (int k = 0; k < w; ++k) {
-    int j = ld_stream(c + (k << 6));
-    cx<T> a = ld_stream(v + (k << 6));
-    cx<T> xv = x[j];
-    cfma(acc, a, xv);
+    for (int k = 0; k < w; ++k) {
+      int j = ld_stream(c + (k << 6));
+      cx<T> a = ld_stream(v + (k << 6));
+      cx<T> xv = x[j];
+      cfma(acc, a, xv);
+    }
+    return acc;
   }
-  return acc;
+  T ar = T(0), ai = T(0);
+  if (A.dcol) split_real(A.dcol + beg + lane, A.re + beg + lane, w, row, x, ar, ai);
+  else split_real(A.col + beg + lane, A.re + beg + lane, w, row, x, ar, ai);
+  const int q1 = A.iptr[row + 1];
+  for (int q = A.iptr[row]; q < q1; ++q) {
+    T b = A.iim[q];                 // i b x = -b x.im + i b x.re
+    cx<T> xv = x[A.icol[q]];
+    ar = fma(-b, xv.im, ar);
+    ai = fma(b, xv.re, ai);
+  }
+  return cx<T>{ar, ai};
 }
 
 // Block geometry of a segmented kernel: logical tile (XCD-contiguous), row, segment.

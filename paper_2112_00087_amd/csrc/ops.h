@@ -25,26 +25,43 @@ inline OpParts op_parts(hz_ctx ctx) {
   return P;
 }
 
-inline SellOp<double> op_A(hz_ctx ctx) {
+// The current operator in complex form.
+inline SellOp<double> op_A_complex(hz_ctx ctx) {
   SellOp<double> A;
   A.ptr = ctx->d_sptr.as<int>();
   A.col = ctx->d_scol.as<int>();
   A.val = ctx->d_A.as<z_t>();
   return A;
 }
-inline SellOp<float> op_A32(hz_ctx ctx) {
+inline SellOp<float> op_A32_complex(hz_ctx ctx) {
   SellOp<float> A;
   A.ptr = ctx->d_sptr.as<int>();
   A.col = ctx->d_scol.as<int>();
   A.val = ctx->d_A32.as<c_t>();
   return A;
 }
+// The same operator in split form (valid when ctx->have_split / have_split32).
+template <typename T>
+inline SellOp<T> op_split(hz_ctx ctx) {
+  SellOp<T> A;
+  A.ptr = ctx->d_sptr.as<int>();
+  A.col = ctx->d_scol.as<int>();
+  A.dcol = ctx->split_dcol ? ctx->d_dcol.as<int16_t>() : nullptr;
+  A.iptr = ctx->d_iptr.as<int>();
+  A.icol = ctx->d_icol.as<int>();
+  A.re = sizeof(T) == 8 ? static_cast<T*>(ctx->d_R.p) : static_cast<T*>(ctx->d_R32.p);
+  A.iim = sizeof(T) == 8 ? static_cast<T*>(ctx->d_I.p) : static_cast<T*>(ctx->d_I32.p);
+  return A;
+}
+// The operator the solvers use: the split form when it is formed.
+inline SellOp<double> op_A(hz_ctx ctx) { return ctx->have_split ? op_split<double>(ctx) : op_A_complex(ctx); }
+inline SellOp<float> op_A32(hz_ctx ctx) { return ctx->have_split32 ? op_split<float>(ctx) : op_A32_complex(ctx); }
 
 int op_set_frequency(hz_ctx ctx, const OpParts& P, double k, int scale, bool want32);
 // Forms A(k) (optionally column-scaled by 1/diag) on an explicit sliced-ELL
 // system; rows i >= n or with diag[i] < 0 are padding (d = 1).
 int op_form(hipStream_t s, int64_t n, int64_t nrows, int64_t npad, const int* col, const OpParts& P, double k,
-            int scale, z_t* A, c_t* A32, z_t* d, z_t* dinv);
+            int scale, z_t* A, c_t* A32, z_t* d, z_t* dinv, double* R = nullptr, float* R32 = nullptr);
 template <typename T>
 int op_spmv(hipStream_t s, int64_t nrows, int64_t nout, const SellOp<T>& A, const cx<T>* x, cx<T>* y);
 int op_mul(hipStream_t s, int64_t n, const z_t* a, const z_t* b, z_t* c);

@@ -32,33 +32,78 @@ __global__ void k_diag(int n, int64_t nrows, OpParts P, double k, z_t* __restric
 }
 
 // One pass over the stored entries: A (optionally with column j scaled by
-// dinv[j], i.e. the right-Jacobi operator A D^-1) and its complex64 copy.
+// dinv[j], i.e. the right-Jacobi operator A D^-1), its complex64 copy and the
+// real parts of the split form.
 __global__ void k_combine(int64_t npad, const int* __restrict__ col, OpParts P, double k,
                           const z_t* __restrict__ dinv, int scale, z_t* __restrict__ A,
-                          c_t* __restrict__ A32) {
+                          c_t* __restrict__ A32, double* __restrict__ R, float* __restrict__ R32) {
   int64_t stride = int64_t(gridDim.x) * kBlock;
   for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < npad; p += stride) {
     z_t a = entry_value(p, P, k);
     if (scale) a = a * dinv[col[p]];
     A[p] = a;
     if (A32) A32[p] = ccast<float>(a);
+    if (R) R[p] = a.re;
+    if (R32) R32[p] = float(a.re);
   }
 }
 
+// Imaginary parts of the split form's listed entries.
+__global__ void k_split_im(int64_t ni, const int* __restrict__ ipos, const z_t* __restrict__ A,
+                           double* __restrict__ I, float* __restrict__ I32) {
+  int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (q >= ni) return;
+  double v = A[ipos[q]].im;
+  I[q] = v;
+  if (I32) I32[q] = float(v);
+}
+
 int op_form(hipStream_t s, int64_t n, int64_t nrows, int64_t npad, const int* col, const OpParts& P, double k,
-            int scale, z_t* A, c_t* A32, z_t* d, z_t* dinv) {
+            int scale, z_t* A, c_t* A32, z_t* d, z_t* dinv, double* R, float* R32) {
   k_diag<<<ceil_div(nrows, kBlock), kBlock, 0, s>>>(int(n), nrows, P, k, d, dinv);
   HZ_HIP(hipGetLastError());
   int grid = int(std::min<int64_t>(ceil_div(npad, kBlock), 16384));
-  k_combine<<<grid, kBlock, 0, s>>>(npad, col, P, k, dinv, scale, A, A32);
+  k_combine<<<grid, kBlock, 0, s>>>(npad, col, P, k, dinv, scale, A, A32, R, R32);
   HZ_HIP(hipGetLastError());
   return HZ_OK;
 }
 
+namespace {
+int grow(hz_ctx ctx, DevBuf& b, size_t bytes) {
+  size_t before = b.bytes;
+  HZ_TRY(b.ensure(bytes));
+  ctx->dev_bytes += int64_t(b.bytes) - int64_t(before);
+  return HZ_OK;
+}
+}  // namespace
+
 int op_set_frequency(hz_ctx ctx, const OpParts& P, double k, int scale, bool want32) {
-  return op_form(ctx->stream, ctx->h.n, ctx->sell.n_rows, ctx->sell.n_pad, ctx->d_scol.as<int>(), P, k, scale,
+  const bool split = ctx->split_on && !ctx->have_eta;
+  const int64_t npad = ctx->sell.n_pad, ni = ctx->n_imag;
+  if (split) {
+    HZ_TRY(grow(ctx, ctx->d_R, sizeof(double) * npad));
+    HZ_TRY(grow(ctx, ctx->d_I, sizeof(double) * std::max<int64_t>(ni, 1)));
+    if (want32) {
+      HZ_TRY(grow(ctx, ctx->d_R32, sizeof(float) * npad));
+      HZ_TRY(grow(ctx, ctx->d_I32, sizeof(float) * std::max<int64_t>(ni, 1)));
+    }
+  }
+  ctx->have_split = ctx->have_split32 = false;
+  HZ_TRY(op_form(ctx->stream, ctx->h.n, ctx->sell.n_rows, npad, ctx->d_scol.as<int>(), P, k, scale,
                  ctx->d_A.as<z_t>(), want32 ? ctx->d_A32.as<c_t>() : nullptr, ctx->d_d.as<z_t>(),
-                 ctx->d_dinv.as<z_t>());
+                 ctx->d_dinv.as<z_t>(), split ? ctx->d_R.as<double>() : nullptr,
+                 split && want32 ? ctx->d_R32.as<float>() : nullptr));
+  if (split) {
+    if (ni > 0) {
+      k_split_im<<<ceil_div(ni, kBlock), kBlock, 0, ctx->stream>>>(
+          ni, ctx->d_ipos.as<int>(), ctx->d_A.as<z_t>(), ctx->d_I.as<double>(),
+          want32 ? ctx->d_I32.as<float>() : nullptr);
+      HZ_HIP(hipGetLastError());
+    }
+    ctx->have_split = true;
+    ctx->have_split32 = want32;
+  }
+  return HZ_OK;
 }
 
 // ---------------------------------------------------------------- products

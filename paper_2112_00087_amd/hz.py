@@ -26,6 +26,7 @@ HZ_JACOBI, HZ_NONE = 0, 1
 
 METHODS = {"gmres": HZ_GMRES, "bicgstab": HZ_BICGSTAB, "schwarz": HZ_SCHWARZ}
 PRECISIONS = {"fp64": HZ_FP64, "mixed": HZ_MIXED}
+SPMV_FORMS = {"solver": 0, "complex": 1, "split": 2}
 
 
 class hz_c128(C.Structure):
@@ -96,7 +97,8 @@ def lib():
                                      P(hz_solve_info)]),
         "hz_solve_adjoint": (C.c_int, [VP, P(hz_solve_opts), VP, VP, VP, P(C.c_double), VP,
                                        P(hz_solve_info)]),
-        "hz_time_spmv": (C.c_int, [VP, C.c_int32, C.c_int32, P(C.c_double)]),
+        "hz_time_spmv": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_int32, P(C.c_double)]),
+        "hz_spmv_bytes": (C.c_int, [VP, C.c_int32, C.c_int32, P(C.c_int64)]),
         "hz_sizes": (C.c_int, [VP, P(C.c_int64), P(C.c_int64), P(C.c_int64), P(C.c_int64)]),
         "hz_destroy": (None, [VP]),
         "hz_last_error": (C.c_char_p, []),
@@ -224,11 +226,19 @@ class Helmholtz:
         check(lib().hz_sizes(self.ctx, C.byref(a), C.byref(b), C.byref(c_), C.byref(d)))
         return dict(n_nodes=a.value, n_elems=b.value, nnz=c_.value, device_bytes=d.value)
 
-    def time_spmv(self, reps=100, precision="fp64"):
-        """Average duration (ms) of one sparse product, HIP events on the context stream."""
+    def time_spmv(self, reps=100, precision="fp64", form="solver"):
+        """Average duration (ms) of one sparse product of the given storage form
+        ("solver", "complex" or "split"), HIP events on the context stream."""
         ms = C.c_double()
-        check(lib().hz_time_spmv(self.ctx, int(reps), PRECISIONS[precision], C.byref(ms)), False)
+        check(lib().hz_time_spmv(self.ctx, int(reps), PRECISIONS[precision], SPMV_FORMS[form], C.byref(ms)),
+              False)
         return ms.value
+
+    def spmv_bytes(self, precision="fp64", form="solver"):
+        """Algorithmic bytes of one sparse product of the given form."""
+        b = C.c_int64()
+        check(lib().hz_spmv_bytes(self.ctx, PRECISIONS[precision], SPMV_FORMS[form], C.byref(b)), False)
+        return b.value
 
     # -------------------------------------------------------------- calls
     def set_params(self, beta=None, eta=None):

@@ -1,6 +1,7 @@
 """GPU parity of the core path against the oracle: operator formation, the
 sparse product, load, reductions, FP64 and mixed-precision solves, exact
 special cases, and error handling.  Calls go through the C ABI."""
+import os
 import sys
 
 import numpy as np
@@ -40,15 +41,31 @@ def _np(t):
 MESHES = [(1, 1, 1), (2, 2, 2), (4, 3, 2), (20, 12, 10), (33, 17, 9)]
 
 
+def _model_in_form(P, mesh, beta, eta, form):
+    """A context whose solvers use the given storage form: "split" (no
+    absorption field), "complex" (split form switched off by HZ_SPLIT=0), or
+    "eta" (absorption field: every entry complex, complex form)."""
+    old = os.environ.get("HZ_SPLIT")
+    os.environ["HZ_SPLIT"] = "0" if form == "complex" else "1"
+    try:
+        return _gpu_model(P, mesh, beta, eta)
+    finally:
+        if old is None:
+            del os.environ["HZ_SPLIT"]
+        else:
+            os.environ["HZ_SPLIT"] = old
+
+
+@pytest.mark.parametrize("form", ["eta", "split", "complex"])
 @pytest.mark.parametrize("elems", MESHES)
-def test_spmv_diag_load_parity(P, elems):
-    say("spmv parity", elems)
+def test_spmv_diag_load_parity(P, elems, form):
+    say("spmv parity", elems, form)
     wl = W.workload(1, elems=elems)
     mesh = wl["mesh"]
     rng = np.random.default_rng(7)
-    eta = rng.uniform(0, 0.02, mesh["n_elems"])
+    eta = rng.uniform(0, 0.02, mesh["n_elems"]) if form == "eta" else None
     S = H.System(mesh, wl["beta"], eta)
-    model = _gpu_model(P, mesh, wl["beta"], eta)
+    model = _model_in_form(P, mesh, wl["beta"], eta, form)
     x = rng.standard_normal(mesh["n_nodes"]) + 1j * rng.standard_normal(mesh["n_nodes"])
     for f in (0.0, 100.0, 250.0):
         k = W.wavenumber(f)
@@ -63,7 +80,8 @@ def test_spmv_diag_load_parity(P, elems):
         # points formed in a different (equally valid) order by library and oracle:
         # allow 1e-14 of the magnitudes, the same bound as the product above
         mag = (np.abs(S.asm["K"].diagonal()) + k * k * np.abs(S.asm["M"].diagonal())
-               + k * k * np.abs(S.Meta.diagonal()) + k * np.abs(S.Bbeta.diagonal()))
+               + (k * k * np.abs(S.Meta.diagonal()) if S.Meta is not None else 0.0)
+               + k * np.abs(S.Bbeta.diagonal()))
         assert np.all(np.abs(d - A.diagonal()) <= 1e-14 * mag)
     g = wl["g"] if np.any(wl["g"]) else rng.standard_normal(mesh["n_nodes"]) + 0j
     f = _np(model.load(_t(g)))
@@ -117,6 +135,37 @@ def test_solve_workload0(c0, method, precision):
     assert rel <= 1e-8
     assert abs(info["relres_true"] - rel) <= 1e-3 * rel + 1e-15
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_complex_form_solve_matches_oracle(P, c0, precision):
+    """The same solve with the split storage form switched off."""
+    wl = c0["wl"]
+    m = _model_in_form(P, wl["mesh"], wl["beta"], None, "complex")
+    m.set_frequency(wl["freqs"][0])
+    assert m.spmv_bytes("fp64", "solver") == m.spmv_bytes("fp64", "complex")
+    p, info = m.solve(_t(c0["f"]), method="bicgstab", precision=precision, tol=1e-8)
+    p = _np(p)
+    rel = H.relres(c0["A"], p, c0["f"])
+    err = np.linalg.norm(p - c0["x"]) / np.linalg.norm(c0["x"])
+    say(f"  complex form {precision}: info={info} relres={rel:.3e} relerr={err:.3e}")
+    assert info["status"] == 0 and rel <= 1e-8 and err <= 1e-6
+    m.close()
+
+
+def test_split_form_bytes(c0):
+    """The solvers run the split form when there is no absorption field; its
+    algorithmic bytes follow the documented formula."""
+    m = c0["model"]
+    n, nnz = m.sizes()["n_nodes"], m.sizes()["nnz"]
+    bs, bc = m.spmv_bytes("fp64", "split"), m.spmv_bytes("fp64", "complex")
+    assert bc == 20 * nnz + 4 * (n + 1) + 32 * n
+    assert m.spmv_bytes("fp64", "solver") == bs < bc
+    # every wall node's row is in the imaginary list; interior rows two layers
+    # in are not: n_imag lies between the wall entries and all entries
+    n_imag = (bs - 10 * nnz - 4 * (n + 1) - 32 * n) / 12
+    assert n_imag == int(n_imag) and 0 < n_imag < nnz
+    assert m.spmv_bytes("mixed", "split") == 6 * nnz + 8 * n_imag + 4 * (n + 1) + 16 * n
 
 
 def test_gpu_gmres_matches_oracle_iteration_count_roughly(c0):

@@ -71,15 +71,18 @@ def test_schwarz_trivial_partition_is_global_solve(P):
     model.close()
 
 
-def test_schwarz_plain_iteration_matches_oracle_history(P):
+@pytest.mark.parametrize("alpha_of_k", [lambda k: 1j * k, lambda k: 0.5 * k + 1.5j * k],
+                         ids=["ik", "general"])
+def test_schwarz_plain_iteration_matches_oracle_history(P, alpha_of_k):
     wl, mesh, et, k, A, f = _case((8, 6, 4), 90.0)
     parts = (2, 2, 1)
-    D = schwarz.Schwarz(mesh, parts, wl["beta"], None, k, f)
+    alpha = alpha_of_k(k)
+    D = schwarz.Schwarz(mesh, parts, wl["beta"], None, k, f, alpha=alpha)
     model = P.Helmholtz(mesh, wl["beta"], parts=parts)
     model.set_frequency(90.0)
     for n_it in (1, 4, 10):
         p, info = model.solve(_t(f), method="schwarz", tol=1e-12, inner_tol=1e-13, dd_inner="gmres",
-                              inner_restart=60, dd_richardson=n_it, dd_alpha=1j * k)
+                              inner_restart=60, dd_richardson=n_it, dd_alpha=alpha)
         u, lams, hist = D.richardson(n_it + 1, A, f)
         err = np.linalg.norm(p.cpu().numpy() - u) / np.linalg.norm(u)
         say(f"  plain Schwarz {n_it}: rel diff {err:.2e}, oracle relres {hist[-1, 1]:.3e}, gpu {info['relres_true']:.3e}")
