@@ -182,3 +182,116 @@ def bicgstab(A, f, tol=1e-8, max_matvec=20000, x0=None, precond="jacobi",
         # recursive residual says converged: the outer loop re-checks the true one
     rel = np.linalg.norm(f - A @ x) / nf
     return Result(x, 0 if rel <= tol else 1, iters, matvecs, rel, hist)
+
+
+def bicgstab_l(A, f, l=4, tol=1e-8, max_matvec=20000, x0=None, precond="jacobi",
+               on_cycle=None):
+    """BiCGStab(l) of Sleijpen and Fokkema (ETNA 1, 1993), the paper's
+    P-BiCGSTAB(8) family (Sec. 4, solver comparison table), on the
+    right-Jacobi operator B = A D^-1.
+
+    One cycle is l bi-conjugate gradient steps, each extending the chains
+    u_0..u_{j+1} and r_0..r_{j+1} with u_{j+1} = B u_j and r_{j+1} = B r_j
+    (2 products per step), followed by a minimal-residual step that picks
+    gamma minimising ||r_0 - sum_{j>=1} gamma_j r_j|| (modified Gram-Schmidt
+    on r_1..r_l, as in the original paper) and updates
+        x += sum_j gamma_j r_{j-1},  r_0 -= sum_j gamma_j r_j,
+        u_0 -= sum_j gamma_j u_j,    omega = gamma_l.
+    Shadow residual r~ = r_0 of the (re)start.  On breakdown (rho or
+    sigma zero) the method restarts from the true residual.  Convergence is
+    tested on the recursive residual after each cycle and confirmed with the
+    true residual.
+
+    on_cycle(r_list, gamma): optional hook called before each minimal-residual
+    update with the l+1 residual-chain vectors r_0..r_l (as formed by the
+    bi-conjugate gradient part) and the chosen gamma[1..l]."""
+    f = np.asarray(f, dtype=np.complex128)
+    n = f.size
+    dinv = _dinv(A, precond)
+
+    def B(z):
+        return A @ (dinv * z)
+
+    x = np.zeros(n, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128)
+    u_sol = x / dinv                      # iterate of B u = f
+    nf = np.linalg.norm(f)
+    if nf == 0.0:
+        return Result(np.zeros(n, dtype=np.complex128), 0, 0, 0, 0.0, [])
+    matvecs, cycles, hist = 0, 0, []
+    converged = False
+    while not converged and matvecs < max_matvec:
+        r = [f - B(u_sol)] + [None] * l
+        matvecs += 1
+        hist.append(np.linalg.norm(r[0]) / nf)
+        if hist[-1] <= tol:
+            converged = True
+            break
+        rt = r[0].copy()
+        uu = [np.zeros(n, dtype=np.complex128)] + [None] * l
+        rho0, alpha, omega = 1.0 + 0j, 0.0 + 0j, 1.0 + 0j
+        breakdown = False
+        while matvecs + 2 * l <= max_matvec:
+            rho0 = -omega * rho0
+            for j in range(l):
+                rho1 = np.vdot(rt, r[j])
+                if rho0 == 0 or rho1 == 0:
+                    breakdown = True
+                    break
+                beta = alpha * rho1 / rho0
+                rho0 = rho1
+                for i in range(j + 1):
+                    uu[i] = r[i] - beta * uu[i]
+                uu[j + 1] = B(uu[j])
+                sigma = np.vdot(rt, uu[j + 1])
+                if sigma == 0:
+                    breakdown = True
+                    break
+                alpha = rho0 / sigma
+                for i in range(j + 1):
+                    r[i] = r[i] - alpha * uu[i + 1]
+                r[j + 1] = B(r[j])
+                u_sol = u_sol + alpha * uu[0]
+                matvecs += 2
+            if breakdown:
+                break
+            # minimal-residual part: modified Gram-Schmidt on r_1..r_l
+            q = [None] + [r[j].copy() for j in range(1, l + 1)]
+            tau = np.zeros((l + 1, l + 1), dtype=np.complex128)
+            sig = np.zeros(l + 1)
+            gp = np.zeros(l + 1, dtype=np.complex128)
+            for j in range(1, l + 1):
+                for i in range(1, j):
+                    tau[i, j] = np.vdot(q[i], q[j]) / sig[i]
+                    q[j] = q[j] - tau[i, j] * q[i]
+                sig[j] = np.vdot(q[j], q[j]).real
+                if sig[j] == 0.0:
+                    breakdown = True
+                    break
+                gp[j] = np.vdot(q[j], r[0]) / sig[j]
+            if breakdown:
+                break
+            # back substitution: R gamma = gamma' with R unit upper triangular (tau)
+            g = np.zeros(l + 1, dtype=np.complex128)
+            for j in range(l, 0, -1):
+                g[j] = gp[j] - sum(tau[j, i] * g[i] for i in range(j + 1, l + 1))
+            if on_cycle is not None:
+                on_cycle([v.copy() for v in r], g[1:].copy())
+            omega = g[l]
+            u_sol = u_sol + sum(g[j] * r[j - 1] for j in range(1, l + 1))
+            r0 = r[0] - sum(g[j] * r[j] for j in range(1, l + 1))
+            uu[0] = uu[0] - sum(g[j] * uu[j] for j in range(1, l + 1))
+            r[0] = r0
+            cycles += 1
+            hist.append(np.linalg.norm(r[0]) / nf)
+            if hist[-1] <= tol:
+                break
+            if omega == 0:
+                breakdown = True
+                break
+        if matvecs + 2 * l > max_matvec and not (hist and hist[-1] <= tol):
+            break
+        # recursive residual converged or breakdown: the loop restarts from the
+        # true residual, which also confirms convergence
+    x = dinv * u_sol
+    rel = np.linalg.norm(f - A @ x) / nf
+    return Result(x, 0 if rel <= tol else 1, cycles, matvecs, rel, hist)

@@ -154,3 +154,78 @@ def test_bicgstab_restarts_from_true_residual_and_caps():
     assert r.status == 1 and r.matvecs <= 5
     r = krylov.gmres(A, f, m=5, tol=1e-8, max_matvec=3)
     assert r.status == 1 and r.matvecs <= 4
+
+
+def test_bicgstab_l1_equals_scipy_bicgstab_iterates():
+    """BiCGStab(1) is van der Vorst's BiCGStab: its iterate after k cycles is
+    SciPy's right-preconditioned BiCGStab iterate after k iterations (same
+    shadow residual r~ = r0 = f)."""
+    import scipy.sparse.linalg as spla
+    wl = W.workload(0)
+    S = H.System(wl["mesh"], wl["beta"])
+    A = S.operator(W.wavenumber(wl["freqs"][0])).tocsr()
+    f = S.load(wl["g"])
+    f = f / np.linalg.norm(f)
+    dinv = 1.0 / A.diagonal()
+    M = spla.LinearOperator(A.shape, matvec=lambda z: dinv * z, dtype=np.complex128)
+    its = []
+    spla.bicgstab(A, f, rtol=1e-300, atol=0.0, maxiter=8, M=M, callback=lambda xk: its.append(xk.copy()))
+    assert len(its) == 8
+    for k in (1, 2, 5, 8):
+        res = krylov.bicgstab_l(A, f, l=1, tol=1e-300, max_matvec=1 + 2 * k)
+        assert res.iters == k and res.matvecs == 1 + 2 * k
+        assert np.linalg.norm(res.x - its[k - 1]) <= 1e-9 * np.linalg.norm(its[k - 1]), k
+
+
+@pytest.mark.parametrize("n,l", [(8, 2), (8, 4), (7, 2), (9, 4), (8, 8)])
+def test_bicgstab_l_finite_termination(n, l):
+    """Without breakdown the bi-conjugate gradient part terminates after n
+    steps, so ceil(n / l) cycles solve an n x n system to rounding level."""
+    rng = np.random.default_rng(n * 10 + l)
+    G = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = sp.csr_matrix(G + G.T + 4 * n * np.eye(n))
+    f = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    cyc = -(-n // l)
+    res = krylov.bicgstab_l(A, f, l=l, tol=1e-300, max_matvec=1 + 2 * l * cyc)
+    x = np.linalg.solve(A.toarray(), f)
+    assert res.iters == cyc
+    assert np.linalg.norm(res.x - x) <= 1e-9 * np.linalg.norm(x)
+
+
+def test_bicgstab_l_chain_and_minimal_residual():
+    """Each cycle's residual chain satisfies r_j = B r_{j-1} (B = A D^-1), and
+    gamma minimises ||r_0 - sum_j gamma_j r_j|| (checked by least squares)."""
+    wl = W.workload(0)
+    S = H.System(wl["mesh"], wl["beta"])
+    A = S.operator(W.wavenumber(wl["freqs"][0])).tocsr()
+    f = S.load(wl["g"])
+    dinv = 1.0 / A.diagonal()
+    seen = []
+
+    def hook(r, g):
+        seen.append(1)
+        for j in range(1, len(r)):
+            Br = A @ (dinv * r[j - 1])
+            assert np.linalg.norm(r[j] - Br) <= 1e-9 * np.linalg.norm(Br)
+        R = np.stack(r[1:], axis=1)
+        gl, *_ = np.linalg.lstsq(R, r[0], rcond=None)
+        assert np.linalg.norm(g - gl) <= 1e-6 * np.linalg.norm(gl)
+        assert (np.linalg.norm(r[0] - R @ g)
+                <= (1 + 1e-10) * np.linalg.norm(r[0] - R @ gl) + 1e-300)
+
+    for l in (2, 4):
+        seen.clear()
+        krylov.bicgstab_l(A, f, l=l, tol=1e-300, max_matvec=1 + 2 * l * 5, on_cycle=hook)
+        assert len(seen) == 5
+
+
+@pytest.mark.parametrize("l", [1, 2, 4, 8])
+def test_bicgstab_l_converges_to_direct_solution(l):
+    wl = W.workload(0)
+    S = H.System(wl["mesh"], wl["beta"])
+    A = S.operator(W.wavenumber(wl["freqs"][0]))
+    f = S.load(wl["g"])
+    x = direct.SparseLU(A).solve(f)
+    res = krylov.bicgstab_l(A, f, l=l, tol=1e-8, max_matvec=20000)
+    assert res.status == 0 and res.relres <= 1e-8
+    assert np.linalg.norm(res.x - x) <= 1e-6 * np.linalg.norm(x)
