@@ -53,7 +53,7 @@ def cpu_baseline(wl, gpu_iters, iters):
                       f"{per_iter * 1e3:.1f} ms/iteration), scaled to the GPU's {gpu_iters} iterations"}
 
 
-def sweep_leg(log_fn, precisions=("fp64", "mixed"), method="bicgstab"):
+def sweep_leg(log_fn, precisions=("fp64", "mixed"), method="bicgstabl", ell=4):
     """Workload 2: 64 frequencies, 80x48x40.  T_A = 64 x (set_frequency + FP64
     solve); T_B[precision] = one batched sweep; all use the same Krylov method."""
     import torch
@@ -64,7 +64,7 @@ def sweep_leg(log_fn, precisions=("fp64", "mixed"), method="bicgstab"):
     f = m.load(torch.as_tensor(wl["g"], device="cuda"))
     freqs = wl["freqs"]
     F = f[:, None].repeat(1, freqs.size).contiguous()
-    opts = dict(method=method, tol=1e-8, max_matvec=200000, restart=30)
+    opts = dict(method=method, tol=1e-8, max_matvec=200000, restart=ell if method == "bicgstabl" else 30)
     # warm-up of every path (autotuner, graph capture, allocations)
     for prec in precisions:
         m.solve_sweep(freqs[:2], F[:, :2].contiguous(), precision=prec, **opts)
@@ -81,7 +81,8 @@ def sweep_leg(log_fn, precisions=("fp64", "mixed"), method="bicgstab"):
     torch.cuda.synchronize()
     T_A = time.perf_counter() - t
     log_fn(f"sweep A (64 x FP64 {method}): {T_A:.2f}s, converged {a_ok}/64")
-    out = {"workload": wl["name"], "method": method, "T_A_s": T_A, "converged_A": a_ok, "iters_A": a_iters}
+    out = {"workload": wl["name"], "method": method if method != "bicgstabl" else f"bicgstab({ell})",
+           "T_A_s": T_A, "converged_A": a_ok, "iters_A": a_iters}
     for prec in precisions:
         t = time.perf_counter()
         _, infos = m.solve_sweep(freqs, F, precision=prec, **opts)
@@ -165,6 +166,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (reference for the traffic counters)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 64-frequency sweep comparison")
+    ap.add_argument("--sweep-method", default="bicgstabl", choices=["bicgstabl", "bicgstab", "gmres"],
+                    help="Krylov method of both sides of the sweep comparison")
+    ap.add_argument("--sweep-l", type=int, default=4, help="l of BiCGStab(l) in the sweep comparison")
     ap.add_argument("--schwarz", action="store_true", help="also run the 24-subdomain Schwarz solve")
     ap.add_argument("--adjoint", action="store_true", help="also run the 16-frequency adjoint gradient")
     args = ap.parse_args()
@@ -240,6 +244,10 @@ def main():
         b32 = model.spmv_bytes("mixed", form)
         extra["spmv_fp32_GBs"] = b32 / (ms32 * 1e-3) / 1e9
         for label, o in (("gmres50", dict(method="gmres", restart=50)),
+                         ("bicgstabl2", dict(method="bicgstabl", restart=2)),
+                         ("bicgstabl4", dict(method="bicgstabl", restart=4)),
+                         ("bicgstabl8", dict(method="bicgstabl", restart=8)),
+                         ("bicgstabl4_mixed", dict(method="bicgstabl", restart=4, precision="mixed")),
                          ("bicgstab_mixed", dict(method="bicgstab", precision="mixed")),
                          ("gmres50_mixed", dict(method="gmres", restart=50, precision="mixed"))):
             model.set_frequency(freq)
@@ -254,7 +262,7 @@ def main():
 
     sweep = None
     if not args.no_sweep and not args.spmv_only:
-        sweep = sweep_leg(log)
+        sweep = sweep_leg(log, method=args.sweep_method, ell=args.sweep_l)
     if args.schwarz and not args.spmv_only:
         extra["schwarz"] = schwarz_leg(log)
     if args.adjoint and not args.spmv_only:

@@ -66,7 +66,7 @@ enum {
   HZ_ERR_STATE = -4       /* call order violated (e.g. no frequency set)  */
 };
 
-enum { HZ_GMRES = 0, HZ_BICGSTAB = 1, HZ_SCHWARZ = 2 };
+enum { HZ_GMRES = 0, HZ_BICGSTAB = 1, HZ_SCHWARZ = 2, HZ_BICGSTABL = 3 };
 enum { HZ_FP64 = 0, HZ_MIXED = 1 };
 enum { HZ_JACOBI = 0, HZ_NONE = 1 };
 
@@ -98,8 +98,13 @@ typedef struct {
 } hz_mesh;
 
 /* Solver options (host struct).
- *   method      HZ_GMRES, HZ_BICGSTAB or HZ_SCHWARZ
- *   restart     GMRES restart length m (1..128; Schwarz interface GMRES 1..1000)
+ *   method      HZ_GMRES, HZ_BICGSTAB, HZ_BICGSTABL or HZ_SCHWARZ.
+ *               HZ_BICGSTABL is BiCGStab(l) of Sleijpen and Fokkema (the
+ *               paper's P-BiCGSTAB(8) family, Sec. 4): l bi-conjugate
+ *               gradient steps and one l-dimensional minimal-residual step
+ *               per cycle (2 l products); l = 1 is BiCGStab.
+ *   restart     GMRES restart length m (1..128); l of BiCGStab(l) (1..8);
+ *               Schwarz interface GMRES restart (1..1000)
  *   max_matvec  cap on operator applications (>= 1)
  *   precision   HZ_FP64: complex128 throughout.  HZ_MIXED: complex64 inner
  *               Krylov solves on a complex64 copy of the operator, with the
@@ -109,7 +114,9 @@ typedef struct {
  *   tol         stop when ||f - A p||_2 / ||f||_2 <= tol (true residual,
  *               recomputed in FP64 at exit)
  *   inner_tol   relative tolerance of inner (mixed / subdomain) solves
- *   inner_restart  GMRES restart of the inner complex64 solves
+ *   inner_restart  GMRES restart of the inner complex64 solves; for the
+ *               Schwarz method with dd_inner HZ_BICGSTABL, l of the local
+ *               BiCGStab(l) (0: 4, at most 8)
  *   dd_alpha    Robin transmission coefficient alpha of the Schwarz method
  *               (interface term alpha M_G).  0 + 0i selects an optimised
  *               alpha = p + i q: the (p, q) on a log grid that minimises the
@@ -117,8 +124,8 @@ typedef struct {
  *               interface modes xi in [pi/H_sub, pi/h] (l = sqrt(xi^2 - k^2)
  *               or i sqrt(k^2 - xi^2)), leaving out xi within pi/(2 H_sub)
  *               of k; i k is the plain absorbing (Despres) choice
- *   dd_inner    Krylov method of the Schwarz subdomain solves (HZ_GMRES or
- *               HZ_BICGSTAB); for the Schwarz method inner_tol is the
+ *   dd_inner    Krylov method of the Schwarz subdomain solves (HZ_GMRES,
+ *               HZ_BICGSTAB or HZ_BICGSTABL); for the Schwarz method inner_tol is the
  *               subdomain solves' relative tolerance (0: 1e-10) and
  *               precision HZ_MIXED runs them in complex64 with FP64
  *               refinement; restart is the interface GMRES restart

@@ -66,7 +66,7 @@ __device__ __forceinline__ float ld_stream(const float* p) { return __builtin_no
 template <typename T, typename I>
 __device__ __forceinline__ void split_real(const I* __restrict__ c, const T* __restrict__ v, int w, int64_t row,
                                            const cx<T>* __restrict__ x, T& ar, T& ai) {
-#pragma unroll 3
+#pragma unroll 9
   for (int k = 0; k < w; ++k) {
     int j = ld_stream(c + (k << 6));
     if (sizeof(I) == 2) j += int(row);
@@ -87,7 +87,7 @@ __device__ __forceinline__ cx<T> sell_row(const SellOp<T>& A, int64_t row, const
     const int* __restrict__ c = A.col + beg + lane;
     const cx<T>* __restrict__ v = A.val + beg + lane;
     cx<T> acc = {T(0), T(0)};
-#pragma unroll 3
+#pragma unroll 6
     for (int k = 0; k < w; ++k) {
       int j = ld_stream(c + (k << 6));
       cx<T> a = ld_stream(v + (k << 6));
@@ -109,7 +109,9 @@ __device__ __forceinline__ cx<T> sell_row(const SellOp<T>& A, int64_t row, const
   return cx<T>{ar, ai};
 }
 
-// Block geometry of a segmented kernel: logical tile (XCD-contiguous), row, segment.
+// Block geometry of a segmented kernel: tile, row, segment.  Tiles follow the
+// dispatch order (workgroup b takes rows [256 b, 256 b + 256)); measured on
+// the 27-point products, this beats giving each XCD a contiguous row range.
 struct Tile {
   int tile;
   int seg;
@@ -117,7 +119,7 @@ struct Tile {
 };
 __device__ __forceinline__ Tile tile_of(const Seg& L) {
   Tile t;
-  t.tile = xcd_tile(blockIdx.x, gridDim.x);
+  t.tile = blockIdx.x;
   t.seg = L.blk_seg[t.tile];
   t.row = int64_t(t.tile) * kBlock + threadIdx.x;
   return t;

@@ -76,6 +76,7 @@ struct KrylovCtl {
   double tol = 1e-8;              // relative to ||f_seg||
   int max_matvec = 20000;
   int restart = 30;               // GMRES
+  int ell = 4;                    // BiCGStab(l)
 };
 struct KrylovOut {
   std::vector<int> iters, matvecs, status;
@@ -90,6 +91,17 @@ int bicgstab_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* 
 template <typename T>
 int gmres_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, cx<T>* u,
               const KrylovCtl& ctl, KrylovOut* out, const std::string& tag);
+template <typename T>
+int bicgstabl_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, cx<T>* u,
+                  const KrylovCtl& ctl, KrylovOut* out, const std::string& tag);
+// Dispatch on opts->method (HZ_GMRES, HZ_BICGSTAB or HZ_BICGSTABL).
+template <typename T>
+int krylov_run(hz_ctx ctx, int method, const SegHost& S, const SellOp<T>& A, const cx<T>* f, cx<T>* u,
+               const KrylovCtl& ctl, KrylovOut* out, const std::string& tag) {
+  if (method == HZ_BICGSTAB) return bicgstab_run<T>(ctx, S, A, f, u, ctl, out, tag);
+  if (method == HZ_BICGSTABL) return bicgstabl_run<T>(ctx, S, A, f, u, ctl, out, tag);
+  return gmres_run<T>(ctx, S, A, f, u, ctl, out, tag);
+}
 
 // ||f_seg - A u_seg||^2 per segment (FP64), written to host vector rr.
 int true_residual(hz_ctx ctx, const SegHost& S, const SellOp<double>& A, const z_t* f, const z_t* u,

@@ -113,8 +113,7 @@ int op_set_frequency(hz_ctx ctx, const OpParts& P, double k, int scale, bool wan
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_spmv(int64_t nout, SellOp<T> A, const cx<T>* __restrict__ x,
                                                  cx<T>* __restrict__ y) {
-  int tile = xcd_tile(blockIdx.x, gridDim.x);
-  int64_t row = int64_t(tile) * kBlock + threadIdx.x;
+  int64_t row = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   cx<T> v = sell_row(A, row, x);
   if (row < nout) y[row] = v;
 }

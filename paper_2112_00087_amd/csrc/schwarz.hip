@@ -538,12 +538,10 @@ struct DDRun {
       KrylovCtl c;
       c.tol = lo.tol;
       c.max_matvec = lo.max_matvec;
-      c.restart = lo.inner_restart > 0 ? lo.inner_restart : 30;
+      c.restart = lo.restart;
+      c.ell = lo.restart;
       KrylovOut ko;
-      if (lo.method == HZ_BICGSTAB)
-        HZ_TRY(bicgstab_run<double>(ctx, D->S, A64, rhs, u, c, &ko, "dd"));
-      else
-        HZ_TRY(gmres_run<double>(ctx, D->S, A64, rhs, u, c, &ko, "dd"));
+      HZ_TRY(krylov_run<double>(ctx, lo.method, D->S, A64, rhs, u, c, &ko, "dd"));
       int mx = 0;
       for (int m : ko.matvecs) mx = std::max(mx, m);
       local_mv += mx;
@@ -673,11 +671,13 @@ int schwarz_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* f, z_t* p, hz_s
   R.rhs = rhs;
   R.u = u;
   R.lo = o;
-  R.lo.method = o.dd_inner == HZ_BICGSTAB ? HZ_BICGSTAB : HZ_GMRES;
+  R.lo.method = o.dd_inner;
   R.lo.tol = o.inner_tol > 0 ? o.inner_tol : 1e-10;   // local solves
   R.lo.inner_tol = 1e-4;                              // complex64 stage of the refinement
   R.lo.max_matvec = 100000;
-  R.lo.restart = o.inner_restart > 0 ? o.inner_restart : 30;
+  // local GMRES restart, or l of local BiCGStab(l)
+  if (o.dd_inner == HZ_BICGSTABL) R.lo.restart = o.inner_restart > 0 ? o.inner_restart : 4;
+  else R.lo.restart = o.inner_restart > 0 ? o.inner_restart : 30;
   // f split into subdomain shares; global f norm
   k_dd_split<<<ceil_div(nr, kBlock), kBlock, 0, s>>>(nr, f, D->l2g.as<int>(), D->winv.as<double>(), fst);
   HZ_HIP(hipGetLastError());

@@ -100,6 +100,7 @@ int ir_run(hz_ctx ctx, const SegHost& S, const SellOp<double>& A64, const SellOp
   KrylovCtl ic;
   ic.tol = o.inner_tol > 0 ? o.inner_tol : 1e-4;
   ic.restart = o.inner_restart > 0 ? o.inner_restart : 30;
+  ic.ell = o.restart;                  // BiCGStab(l): l (validated 1..8)
   const int max_outer = 200;
   for (;;) {
     HZ_TRY(true_residual(ctx, S, A64, f, u, rb->as<z_t>(), &rr));
@@ -128,10 +129,7 @@ int ir_run(hz_ctx ctx, const SegHost& S, const SellOp<double>& A64, const SellOp
     HZ_HIP(hipGetLastError());
     ic.max_matvec = std::max<int64_t>(1, o.max_matvec - out->matvecs - out->inner_matvecs);
     KrylovOut ko;
-    if (o.method == HZ_BICGSTAB)
-      HZ_TRY(bicgstab_run<float>(ctx, S, A32, r32->as<c_t>(), d32->as<c_t>(), ic, &ko, tag + ".in"));
-    else
-      HZ_TRY(gmres_run<float>(ctx, S, A32, r32->as<c_t>(), d32->as<c_t>(), ic, &ko, tag + ".in"));
+    HZ_TRY(krylov_run<float>(ctx, o.method, S, A32, r32->as<c_t>(), d32->as<c_t>(), ic, &ko, tag + ".in"));
     int mx = 0;
     for (int i = 0; i < S.nseg; ++i) mx = std::max(mx, ko.matvecs[i]);
     out->inner_matvecs += mx;
@@ -176,11 +174,9 @@ int solve_single(hz_ctx ctx, const hz_solve_opts& o, const z_t* f, z_t* p, hz_so
     c.tol = o.tol;
     c.max_matvec = o.max_matvec;
     c.restart = o.restart;
+    c.ell = o.restart;
     KrylovOut ko;
-    if (o.method == HZ_BICGSTAB)
-      HZ_TRY(bicgstab_run<double>(ctx, *S, A, fz, uz, c, &ko, "main"));
-    else
-      HZ_TRY(gmres_run<double>(ctx, *S, A, fz, uz, c, &ko, "main"));
+    HZ_TRY(krylov_run<double>(ctx, o.method, *S, A, fz, uz, c, &ko, "main"));
     inf.iters = ko.iters[0];
     inf.matvecs = ko.matvecs[0];
     inf.relres_est = ko.relres_est[0];

@@ -1445,6 +1445,657 @@ int run_sweep_bicgstab(hz_ctx ctx, SweepData& D, int nf, const double* freqs, co
   return worst;
 }
 
+// ---------------------------------------------------------------- batched BiCGStab(l)
+// Each column runs its own BiCGStab(l) (the cycle of the single-system
+// solver: l bi-conjugate gradient steps, a Gram-matrix minimal-residual step)
+// on the correction equation B(k_c) y = R_c / scale_c, B = A D^-1.  When the
+// inner stopping test fires, or the column breaks down, the host runs that
+// column's refinement step: X += scale D^-1 y, R = F - A X in FP64, restart.
+// In FP64 storage the inner solve runs to the target, so the step only
+// confirms convergence; in complex64 storage it runs to inner_tol.
+constexpr int kSlMaxL = 8;
+
+struct SlCol {
+  double fn2, thr2, scale, ithr2, rr, beta, rhat2, pad0;
+  z_t rho0, alpha, omega, bet;
+  z_t gam[kSlMaxL + 1];
+  int done, idone, nan, iters, outer, restart_now, trunc, pad1;
+};
+
+template <typename T>
+struct SlVec {
+  cx<T>* y;      // inner iterate (scaled unknowns)
+  cx<T>* rt;
+  cx<T>* Z;      // D^-1 (chain vector): input of the products
+  cx<T>* r[kSlMaxL + 1];
+  cx<T>* u[kSlMaxL + 1];
+  const cx<T>* dT;
+};
+
+__device__ __forceinline__ bool sl_off(const SlCol& S) { return S.done || S.idone || S.nan; }
+__device__ __forceinline__ bool sl_pending(const SlCol& S) { return S.idone && !S.done && !S.nan; }
+
+// refinement, part 1: X += scale D^-1 y for columns whose inner solve ended
+template <typename T>
+__global__ void k_sl_addx(int64_t total, int s, const SlCol* __restrict__ st, SlVec<T> V, z_t* __restrict__ X) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= total) return;
+  const SlCol& S = st[e & (s - 1)];
+  if (!sl_pending(S) || S.scale == 0.0) return;
+  z_t d = ccast<double>(V.dT[e]) * ccast<double>(V.y[e]);
+  X[e] = z_t{fma(S.scale, d.re, X[e].re), fma(S.scale, d.im, X[e].im)};
+}
+
+// part 2 (block per column, after the FP64 residual): convergence, inner threshold
+__global__ void k_sl_true(int nblk, int s, SlCol* st, const double* __restrict__ part, double tol, double delta) {
+  __shared__ double lds[kBlock / kWave];
+  const int c = blockIdx.x;
+  const int pend = sl_pending(st[c]);
+  __syncthreads();
+  if (!pend) return;
+  const double rr = block_sum_strided(part + c, nblk, s, lds);
+  if (threadIdx.x != 0) return;
+  SlCol& S = st[c];
+  const double b = sqrt(rr);
+  S.beta = b;
+  S.nan = S.nan || !isfinite(rr);
+  S.done = (rr <= S.thr2) || S.fn2 == 0.0 || S.nan;
+  if (S.done) return;
+  S.outer += 1;
+  S.idone = 0;
+  S.restart_now = 1;
+  S.scale = b;
+  const double lim = 0.5 * tol * sqrt(S.fn2) / b;   // the target in the scaled system
+  const double it = delta > lim ? delta : lim;
+  S.ithr2 = it * it;
+}
+
+// part 3: r_0 = R / scale, rt = r_0, u_0 = y = 0 for restarting columns
+template <typename T>
+__global__ void k_sl_start(int64_t total, int s, const SlCol* __restrict__ st, const z_t* __restrict__ R,
+                           SlVec<T> V) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= total) return;
+  const SlCol& S = st[e & (s - 1)];
+  if (!S.restart_now) return;
+  const cx<T> r = ccast<T>((1.0 / S.scale) * R[e]);
+  const cx<T> z = {T(0), T(0)};
+  V.r[0][e] = r;
+  V.rt[e] = r;
+  V.u[0][e] = z;
+  V.y[e] = z;
+}
+
+__global__ void k_sl_start_fin(int s, SlCol* st) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= s) return;
+  SlCol& S = st[c];
+  if (!S.restart_now) return;
+  S.restart_now = 0;
+  S.rr = 1.0;                       // ||R / scale|| = 1
+  S.rhat2 = 1.0;
+  S.rho0 = z_t{1.0, 0.0};           // rt^H r_0
+  S.alpha = S.bet = z_t{0.0, 0.0};
+  S.omega = z_t{1.0, 0.0};
+  S.trunc = 0;
+}
+
+// partial a^H b per column (NQ = 2) or a^H b and ||b||^2 (NQ = 3), grid-stride
+template <typename T, int NQ>
+__global__ void __launch_bounds__(kBlock) k_sl_dots(int64_t total, int s, const SlCol* __restrict__ st,
+                                                    const cx<T>* __restrict__ a, const cx<T>* __restrict__ b,
+                                                    double* __restrict__ part) {
+  __shared__ double lds[4 * kWave];
+  const int c = threadIdx.x & (s - 1);
+  double q[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) q[i] = 0.0;
+  if (!sl_off(st[c])) {
+    for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
+      const z_t x = ccast<double>(a[e]), y = ccast<double>(b[e]);
+      q[0] = fma(x.re, y.re, fma(x.im, y.im, q[0]));
+      q[1] = fma(x.re, y.im, fma(-x.im, y.re, q[1]));
+      if (NQ == 3) q[2] += norm2(y);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const double t = col_reduce(q[i], s, lds);
+    if (int(threadIdx.x) < s) part[(int64_t(blockIdx.x) * NQ + i) * s + threadIdx.x] = t;
+  }
+}
+
+__device__ __forceinline__ double sl_sum(int G_, int s, int nq, const double* part, int c, int i, double* lds) {
+  return block_sum_strided(part + int64_t(i) * s + c, G_, nq * s, lds);
+}
+
+// u_i = r_i - beta u_i (i <= j); Z = D^-1 u_j
+template <typename T>
+__global__ void k_sl_u(int64_t total, int s, const SlCol* __restrict__ st, SlVec<T> V, int j) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= total) return;
+  const SlCol& S = st[e & (s - 1)];
+  if (sl_off(S)) return;
+  const z_t b = S.bet;
+  z_t uj = {0.0, 0.0};
+  for (int i = 0; i <= j; ++i) {
+    uj = ccast<double>(V.r[i][e]) - b * ccast<double>(V.u[i][e]);
+    V.u[i][e] = ccast<T>(uj);
+  }
+  V.Z[e] = ccast<T>(ccast<double>(V.dT[e]) * ccast<double>(ccast<T>(uj)));
+}
+
+// alpha = rho0 / rt^H u_{j+1}
+__global__ void k_sl_alpha(int G_, int s, SlCol* st, const double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  const int c = blockIdx.x;
+  const int off = sl_off(st[c]);
+  __syncthreads();
+  if (off) return;
+  const double re = sl_sum(G_, s, 2, part, c, 0, lds);
+  const double im = sl_sum(G_, s, 2, part, c, 1, lds);
+  if (threadIdx.x != 0) return;
+  SlCol& S = st[c];
+  const z_t sg = {re, im};
+  if (norm2(sg) == 0.0 || !isfinite(re) || !isfinite(im)) S.idone = 1;   // breakdown: refine and restart
+  else S.alpha = cdiv(S.rho0, sg);
+}
+
+// r_i -= alpha u_{i+1} (i <= j); y += alpha u_0; Z = D^-1 r_j
+template <typename T>
+__global__ void k_sl_r(int64_t total, int s, const SlCol* __restrict__ st, SlVec<T> V, int j) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= total) return;
+  const SlCol& S = st[e & (s - 1)];
+  if (sl_off(S)) return;
+  const z_t a = S.alpha;
+  cx<T> rj = {T(0), T(0)};
+  for (int i = 0; i <= j; ++i) {
+    rj = ccast<T>(ccast<double>(V.r[i][e]) - a * ccast<double>(V.u[i + 1][e]));
+    V.r[i][e] = rj;
+  }
+  V.y[e] = ccast<T>(ccast<double>(V.y[e]) + a * ccast<double>(V.u[0][e]));
+  V.Z[e] = ccast<T>(ccast<double>(V.dT[e]) * ccast<double>(rj));
+}
+
+// rho1 = rt^H r_{j+1}; beta = alpha rho1 / rho0; rho0 = rho1
+__global__ void k_sl_beta(int G_, int s, SlCol* st, const double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  const int c = blockIdx.x;
+  const int off = sl_off(st[c]);
+  __syncthreads();
+  if (off) return;
+  const double re = sl_sum(G_, s, 2, part, c, 0, lds);
+  const double im = sl_sum(G_, s, 2, part, c, 1, lds);
+  if (threadIdx.x != 0) return;
+  SlCol& S = st[c];
+  const z_t rho1 = {re, im};
+  if (norm2(S.rho0) == 0.0 || !isfinite(re) || !isfinite(im)) {
+    S.idone = 1;
+  } else {
+    S.bet = S.alpha * cdiv(rho1, S.rho0);
+    S.rho0 = rho1;
+  }
+}
+
+template <int LL> constexpr int sl_nq() { return 2 * (LL + LL * (LL + 1) / 2); }
+
+// partials of c_i = r_i^H r_0 and G_ij = r_i^H r_j (1 <= i <= j <= LL) per column
+template <typename T, int LL>
+__global__ void __launch_bounds__(kBlock) k_sl_gram(int64_t total, int s, const SlCol* __restrict__ st, SlVec<T> V,
+                                                    double* __restrict__ part) {
+  constexpr int NQ = sl_nq<LL>();
+  __shared__ double lds[4 * kWave];
+  const int c = threadIdx.x & (s - 1);
+  double q[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) q[i] = 0.0;
+  if (!sl_off(st[c])) {
+    for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
+      z_t r[LL + 1];
+#pragma unroll
+      for (int i = 0; i <= LL; ++i) r[i] = ccast<double>(V.r[i][e]);
+      int k = 0;
+#pragma unroll
+      for (int i = 1; i <= LL; ++i, k += 2) {
+        q[k] = fma(r[i].re, r[0].re, fma(r[i].im, r[0].im, q[k]));
+        q[k + 1] = fma(r[i].re, r[0].im, fma(-r[i].im, r[0].re, q[k + 1]));
+      }
+#pragma unroll
+      for (int i = 1; i <= LL; ++i)
+#pragma unroll
+        for (int jj = i; jj <= LL; ++jj, k += 2) {
+          q[k] = fma(r[i].re, r[jj].re, fma(r[i].im, r[jj].im, q[k]));
+          q[k + 1] = fma(r[i].re, r[jj].im, fma(-r[i].im, r[jj].re, q[k + 1]));
+        }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const double t = col_reduce(q[i], s, lds);
+    if (int(threadIdx.x) < s) part[(int64_t(blockIdx.x) * NQ + i) * s + threadIdx.x] = t;
+  }
+}
+
+// Cholesky solve of G gamma = c per column (truncated at a lost pivot)
+template <int LL>
+__global__ void k_sl_mr(int G_, int s, SlCol* st, const double* __restrict__ part) {
+  constexpr int NQ = sl_nq<LL>();
+  __shared__ double lds[kBlock / kWave];
+  __shared__ double tot[NQ];
+  const int c = blockIdx.x;
+  const int off = sl_off(st[c]);
+  __syncthreads();
+  if (off) return;
+  for (int i = 0; i < NQ; ++i) {
+    const double t = sl_sum(G_, s, NQ, part, c, i, lds);
+    if (threadIdx.x == 0) tot[i] = t;
+  }
+  if (threadIdx.x != 0) return;
+  SlCol& S = st[c];
+  z_t cv[LL], G[LL][LL];
+  int k = 0;
+  for (int i = 0; i < LL; ++i, k += 2) cv[i] = z_t{tot[k], tot[k + 1]};
+  for (int i = 0; i < LL; ++i)
+    for (int jj = i; jj < LL; ++jj, k += 2) {
+      G[i][jj] = z_t{tot[k], tot[k + 1]};
+      G[jj][i] = conj(G[i][jj]);
+    }
+  int m = LL;
+  for (int jj = 0; jj < LL; ++jj) {
+    double d = G[jj][jj].re;
+    for (int p = 0; p < jj; ++p) d -= norm2(G[jj][p]);
+    if (!(d > 1e-13 * G[jj][jj].re) || !isfinite(d)) {
+      m = jj;
+      break;
+    }
+    const double cd = sqrt(d);
+    G[jj][jj] = z_t{cd, 0.0};
+    for (int i = jj + 1; i < LL; ++i) {
+      z_t v = G[i][jj];
+      for (int p = 0; p < jj; ++p) v = v - G[i][p] * conj(G[jj][p]);
+      G[i][jj] = (1.0 / cd) * v;
+    }
+  }
+  z_t g[LL];
+  for (int i = 0; i < LL; ++i) g[i] = z_t{0.0, 0.0};
+  if (m == 0) {
+    S.idone = 1;
+    return;
+  }
+  z_t yv[LL];
+  for (int i = 0; i < m; ++i) {
+    z_t v = cv[i];
+    for (int p = 0; p < i; ++p) v = v - G[i][p] * yv[p];
+    yv[i] = (1.0 / G[i][i].re) * v;
+  }
+  for (int i = m - 1; i >= 0; --i) {
+    z_t v = yv[i];
+    for (int p = i + 1; p < m; ++p) v = v - conj(G[p][i]) * g[p];
+    g[i] = (1.0 / G[i][i].re) * v;
+  }
+  for (int i = 0; i < LL; ++i) S.gam[i + 1] = g[i];
+  S.omega = g[LL - 1];
+  S.trunc = m < LL;
+}
+
+// y += sum gamma_j r_{j-1}; r_0 -= sum gamma_j r_j; u_0 -= sum gamma_j u_j
+template <typename T, int LL>
+__global__ void k_sl_update(int64_t total, int s, const SlCol* __restrict__ st, SlVec<T> V) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= total) return;
+  const SlCol& S = st[e & (s - 1)];
+  if (sl_off(S)) return;
+  z_t y = ccast<double>(V.y[e]), r0 = ccast<double>(V.r[0][e]), u0 = ccast<double>(V.u[0][e]);
+  z_t rprev = r0;
+#pragma unroll
+  for (int jj = 1; jj <= LL; ++jj) {
+    const z_t g = S.gam[jj];
+    const z_t rj = ccast<double>(V.r[jj][e]);
+    y = y + g * rprev;
+    r0 = r0 - g * rj;
+    u0 = u0 - g * ccast<double>(V.u[jj][e]);
+    rprev = rj;
+  }
+  V.y[e] = ccast<T>(y);
+  V.r[0][e] = ccast<T>(r0);
+  V.u[0][e] = ccast<T>(u0);
+}
+
+// after the update: rho1 = rt^H r_0, ||r_0||^2; next cycle's beta, or done
+__global__ void k_sl_cycle(int G_, int s, SlCol* st, const double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  const int c = blockIdx.x;
+  const int off = sl_off(st[c]);
+  __syncthreads();
+  if (off) return;
+  const double re = sl_sum(G_, s, 3, part, c, 0, lds);
+  const double im = sl_sum(G_, s, 3, part, c, 1, lds);
+  const double rr = sl_sum(G_, s, 3, part, c, 2, lds);
+  if (threadIdx.x != 0) return;
+  SlCol& S = st[c];
+  S.iters += 1;
+  S.rr = rr;
+  const z_t rho1 = {re, im};
+  if (!isfinite(rr) || !isfinite(re) || !isfinite(im)) {
+    S.nan = 1;
+    return;
+  }
+  if (rr <= S.ithr2) {
+    S.idone = 1;
+    return;
+  }
+  const z_t rho0 = -1.0 * (S.omega * S.rho0);
+  if (S.trunc || norm2(rho0) == 0.0 || sqrt(norm2(rho1)) < 1e-300 * sqrt(S.rhat2 * rr)) {
+    S.idone = 1;               // refinement step and restart
+    return;
+  }
+  S.bet = S.alpha * cdiv(rho1, rho0);
+  S.rho0 = rho1;
+}
+
+__global__ void k_sl_init(int s, SlCol* st, const double* fn2, double tol) {
+  const int c = threadIdx.x;
+  if (c >= s) return;
+  st[c].fn2 = fn2[c];
+  st[c].thr2 = tol * tol * fn2[c];
+  st[c].idone = 1;                 // every column starts with a refinement step
+}
+
+// Buffers of one column width s.
+template <typename T>
+struct SlWidth {
+  int s = 0, Gr = 1, l = 4;
+  int64_t total = 0;
+  z_t *X = nullptr, *Fs = nullptr, *R = nullptr;
+  cx<T>* dT = nullptr;
+  double *kc = nullptr, *part = nullptr, *cn = nullptr;
+  SlCol* st = nullptr;
+  SlVec<T> V;
+  Variant vin, vres;
+};
+
+template <typename T>
+int sl_alloc(hz_ctx ctx, int64_t nrows, int s, int l, SlWidth<T>* W) {
+  int rc = 0;
+  const std::string p = std::string("swl.") + (sizeof(T) == 8 ? "z." : "c.") + std::to_string(s) + ".";
+  const int64_t total = nrows * s;
+  auto buf = [&](const std::string& nm, size_t bytes) -> void* {
+    DevBuf* b = ctx->buf(p + nm, bytes, &rc);
+    return rc ? nullptr : b->p;
+  };
+  W->s = s;
+  W->l = l;
+  W->total = total;
+  W->Gr = int(std::min<int64_t>(std::max<int64_t>(total / kBlock, 1), 1024));
+  const int64_t nblk_res = (nrows + kBlock / s - 1) / (kBlock / s);
+  W->X = static_cast<z_t*>(buf("X", sizeof(z_t) * total));
+  W->Fs = static_cast<z_t*>(buf("F", sizeof(z_t) * total));
+  W->R = static_cast<z_t*>(buf("R", sizeof(z_t) * total));
+  W->dT = static_cast<cx<T>*>(buf("dT", sizeof(cx<T>) * total));
+  W->kc = static_cast<double*>(buf("kc", sizeof(double) * 2 * s));
+  W->cn = static_cast<double*>(buf("cn", sizeof(double) * s));
+  const int64_t npart = std::max<int64_t>(int64_t(W->Gr) * sl_nq<kSlMaxL>(), nblk_res) * s;
+  W->part = static_cast<double*>(buf("part", sizeof(double) * npart));
+  W->st = static_cast<SlCol*>(buf("st", sizeof(SlCol) * s));
+  W->V = SlVec<T>{};
+  W->V.y = static_cast<cx<T>*>(buf("y", sizeof(cx<T>) * total));
+  W->V.rt = static_cast<cx<T>*>(buf("rt", sizeof(cx<T>) * total));
+  W->V.Z = static_cast<cx<T>*>(buf("Z", sizeof(cx<T>) * total));
+  for (int i = 0; i <= l; ++i) {
+    W->V.r[i] = static_cast<cx<T>*>(buf("r" + std::to_string(i), sizeof(cx<T>) * total));
+    W->V.u[i] = static_cast<cx<T>*>(buf("u" + std::to_string(i), sizeof(cx<T>) * total));
+  }
+  if (rc) return rc;
+  W->V.dT = W->dT;
+  W->vres.cpl = 1;
+  W->vres.bs = kBlock;
+  return HZ_OK;
+}
+
+template <typename T, int LL>
+int sl_enqueue_mr(hipStream_t q, SlWidth<T>& W) {
+  const int eb = ceil_div(W.total, kBlock);
+  k_sl_gram<T, LL><<<W.Gr, kBlock, 0, q>>>(W.total, W.s, W.st, W.V, W.part);
+  k_sl_mr<LL><<<W.s, kBlock, 0, q>>>(W.Gr, W.s, W.st, W.part);
+  k_sl_update<T, LL><<<eb, kBlock, 0, q>>>(W.total, W.s, W.st, W.V);
+  HZ_HIP(hipGetLastError());
+  return HZ_OK;
+}
+
+template <typename T>
+int run_sweep_bicgstabl(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const z_t* Fin, z_t* Pio,
+                        const hz_solve_opts& o, hz_solve_info* infos) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int l = o.restart;
+  // complex64 inner solves stop at inner_tol relative to their right-hand side
+  const double delta = sizeof(T) == 4 ? (o.inner_tol > 0 ? o.inner_tol : 1e-3) : 0.0;
+  const int chunk = std::max(1, 16 / l);      // cycles per graph launch (~32 products)
+  const int64_t nrows = D.nrows, n = ctx->h.n;
+  const RowOp<double> A64 = row_op<double>(D);
+  const RowOp<T> AT = row_op<T>(D);
+  int s = 1;
+  while (s < nf) s <<= 1;
+  SlWidth<T> W;
+  HZ_TRY(sl_alloc<T>(ctx, nrows, s, l, &W));
+  hipStream_t cs = ctx->stream;
+  std::vector<int> cols(nf);                   // current column j -> frequency index
+  for (int c = 0; c < nf; ++c) cols[c] = c;
+  auto upload_kc = [&](SlWidth<T>& w, hipStream_t q) -> int {
+    std::vector<double> kc(2 * w.s, 0.0);
+    for (size_t j = 0; j < cols.size(); ++j) {
+      double k = 2.0 * M_PI * freqs[cols[j]] / ctx->c;
+      kc[2 * j] = k;
+      kc[2 * j + 1] = k * k;
+    }
+    HZ_HIP(hipMemcpyAsync(w.kc, kc.data(), sizeof(double) * 2 * w.s, hipMemcpyHostToDevice, q));
+    HZ_HIP(hipStreamSynchronize(q));
+    return HZ_OK;
+  };
+  {
+    // set-up at the full width; the FP64 diagonal goes through R as scratch
+    HZ_TRY(upload_kc(W, cs));
+    k_in<<<ceil_div(W.total, kBlock), kBlock, 0, cs>>>(n, nrows, s, nf, Pio, Fin, W.X, W.Fs);
+    k_diag<T><<<ceil_div(W.total, kBlock), kBlock, 0, cs>>>(n, nrows, s, D.dpos.as<int>(), D.K64.as<double>(),
+                                                           D.M64.as<double>(), D.eta ? D.E64.as<double>() : nullptr,
+                                                           D.Bdiag.as<z_t>(), W.kc, W.R, W.dT);
+    k_colnorm<double><<<W.Gr, kBlock, 0, cs>>>(W.total, s, W.Fs, W.part);
+    k_colsum<<<s, kBlock, 0, cs>>>(W.Gr, s, W.part, W.cn);
+    HZ_HIP(hipMemsetAsync(W.st, 0, sizeof(SlCol) * s, cs));
+    k_sl_init<<<1, 64, 0, cs>>>(s, W.st, W.cn, o.tol);
+    HZ_HIP(hipGetLastError());
+    HZ_TRY(autotune<T>(ctx, cs, nrows, s, AT, W.kc, W.V.Z, W.V.u[1], &W.vin));
+  }
+  auto cycles_body = [&](hipStream_t q) -> int {
+    const int s_ = W.s, Gr = W.Gr, eb = ceil_div(W.total, kBlock);
+    const int64_t total = W.total;
+    for (int it = 0; it < chunk; ++it) {
+      for (int j = 0; j < l; ++j) {
+        k_sl_u<T><<<eb, kBlock, 0, q>>>(total, s_, W.st, W.V, j);
+        HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.Z, nullptr, W.V.u[j + 1], nullptr,
+                                      nullptr)));
+        k_sl_dots<T, 2><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V.rt, W.V.u[j + 1], W.part);
+        k_sl_alpha<<<s_, kBlock, 0, q>>>(Gr, s_, W.st, W.part);
+        k_sl_r<T><<<eb, kBlock, 0, q>>>(total, s_, W.st, W.V, j);
+        HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.Z, nullptr, W.V.r[j + 1], nullptr,
+                                      nullptr)));
+        if (j + 1 < l) {
+          k_sl_dots<T, 2><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V.rt, W.V.r[j + 1], W.part);
+          k_sl_beta<<<s_, kBlock, 0, q>>>(Gr, s_, W.st, W.part);
+        }
+      }
+      switch (l) {
+        case 1: HZ_TRY((sl_enqueue_mr<T, 1>(q, W))); break;
+        case 2: HZ_TRY((sl_enqueue_mr<T, 2>(q, W))); break;
+        case 3: HZ_TRY((sl_enqueue_mr<T, 3>(q, W))); break;
+        case 4: HZ_TRY((sl_enqueue_mr<T, 4>(q, W))); break;
+        case 5: HZ_TRY((sl_enqueue_mr<T, 5>(q, W))); break;
+        case 6: HZ_TRY((sl_enqueue_mr<T, 6>(q, W))); break;
+        case 7: HZ_TRY((sl_enqueue_mr<T, 7>(q, W))); break;
+        default: HZ_TRY((sl_enqueue_mr<T, 8>(q, W))); break;
+      }
+      k_sl_dots<T, 3><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V.rt, W.V.r[0], W.part);
+      k_sl_cycle<<<s_, kBlock, 0, q>>>(Gr, s_, W.st, W.part);
+    }
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+  };
+  auto outer = [&](hipStream_t q) -> int {
+    const int s_ = W.s;
+    const int64_t total = W.total;
+    const int eb = ceil_div(total, kBlock);
+    int nb = 0;
+    k_sl_addx<T><<<eb, kBlock, 0, q>>>(total, s_, W.st, W.V, W.X);
+    HZ_TRY((launch_spmm<double, true>(q, W.vres, nrows, s_, A64, W.kc, W.X, W.Fs, W.R, W.part, &nb)));
+    k_sl_true<<<s_, kBlock, 0, q>>>(nb, s_, W.st, W.part, o.tol, delta);
+    k_sl_start<T><<<eb, kBlock, 0, q>>>(total, s_, W.st, W.R, W.V);
+    k_sl_start_fin<<<1, 64, 0, q>>>(s_, W.st);
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+  };
+
+  std::unique_ptr<Graph> G(new Graph());
+  HZ_TRY(G->stream(cs));
+  HZ_TRY(G->capture(cycles_body));
+  hipStream_t q = G->gs;
+  void* hp = nullptr;
+  HZ_TRY(ctx_pinned(ctx, sizeof(SlCol) * 64, &hp));
+  SlCol* hs = static_cast<SlCol*>(hp);
+  std::vector<hz_solve_info> res(nf);
+  int worst = HZ_OK;
+  auto record = [&](int j, double secs) {
+    const SlCol& S = hs[j];
+    hz_solve_info inf = {};
+    const double fnv = std::sqrt(S.fn2);
+    inf.relres_true = fnv > 0 ? S.beta / fnv : 0.0;
+    inf.relres_est = inf.relres_true;
+    inf.iters = S.iters;
+    inf.matvecs = S.outer + 1;
+    inf.inner_matvecs = 2 * l * S.iters;
+    inf.seconds = secs;
+    inf.status = S.nan ? HZ_BREAKDOWN : (S.done && inf.relres_true <= o.tol * (1 + 1e-12) ? HZ_OK : HZ_NOT_CONVERGED);
+    if (!std::isfinite(inf.relres_true)) inf.status = HZ_BREAKDOWN;
+    res[cols[j]] = inf;
+  };
+  int rc = 0;
+  DevBuf* mapb = ctx->buf("swl.map", sizeof(int) * 128, &rc);
+  if (rc) return rc;
+  for (;;) {
+    HZ_HIP(hipMemcpyAsync(hs, W.st, sizeof(SlCol) * W.s, hipMemcpyDeviceToHost, q));
+    HZ_HIP(hipStreamSynchronize(q));
+    const int nreal = int(cols.size());
+    int active = 0;
+    bool pending = false;
+    int64_t mx = 0;
+    for (int j = 0; j < nreal; ++j) {
+      const SlCol& S = hs[j];
+      if (S.done || S.nan) continue;
+      ++active;
+      pending = pending || S.idone;
+      mx = std::max<int64_t>(mx, 2 * int64_t(l) * S.iters + S.outer + 1);
+    }
+    if (active == 0) break;
+    if (pending) {
+      HZ_TRY(outer(q));
+      continue;
+    }
+    if (mx + 2 * int64_t(l) * chunk + 1 > o.max_matvec) break;
+    if (active <= W.s / 2) {
+      // compaction: finished columns leave, the rest move to a narrower width
+      std::vector<int> keep, gone_j, gone_f;
+      for (int j = 0; j < nreal; ++j) {
+        if (hs[j].done || hs[j].nan) {
+          gone_j.push_back(j);
+          gone_f.push_back(cols[j]);
+        } else {
+          keep.push_back(j);
+        }
+      }
+      const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      for (int j : gone_j) record(j, secs);
+      if (!gone_j.empty()) {
+        std::vector<int> h2(gone_j);
+        h2.insert(h2.end(), gone_f.begin(), gone_f.end());
+        HZ_HIP(hipMemcpyAsync(mapb->p, h2.data(), sizeof(int) * h2.size(), hipMemcpyHostToDevice, q));
+        const int ng = int(gone_j.size());
+        k_out_cols<<<ceil_div(n * ng, kBlock), kBlock, 0, q>>>(n, W.s, nf, ng, mapb->as<int>(),
+                                                                mapb->as<int>() + ng, W.X, Pio);
+        HZ_HIP(hipGetLastError());
+        HZ_HIP(hipStreamSynchronize(q));
+      }
+      int s2 = 1;
+      while (s2 < int(keep.size())) s2 <<= 1;
+      SlWidth<T> W2;
+      HZ_TRY(sl_alloc<T>(ctx, nrows, s2, l, &W2));
+      std::vector<int> map(s2, -1);
+      for (size_t jn = 0; jn < keep.size(); ++jn) map[jn] = keep[jn];
+      HZ_HIP(hipMemcpyAsync(mapb->p, map.data(), sizeof(int) * s2, hipMemcpyHostToDevice, q));
+      const int gb = ceil_div(nrows * s2, kBlock);
+      const int* mp = mapb->as<int>();
+      k_gather_cols<z_t><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.X, W2.X);
+      k_gather_cols<z_t><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.Fs, W2.Fs);
+      k_gather_cols<cx<T>><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.dT, W2.dT);
+      k_gather_cols<cx<T>><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.V.y, W2.V.y);
+      k_gather_cols<cx<T>><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.V.rt, W2.V.rt);
+      for (int i = 0; i <= l; ++i) {
+        k_gather_cols<cx<T>><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.V.r[i], W2.V.r[i]);
+        k_gather_cols<cx<T>><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.V.u[i], W2.V.u[i]);
+      }
+      HZ_HIP(hipGetLastError());
+      std::vector<SlCol> ns(s2);
+      for (int jn = 0; jn < s2; ++jn) {
+        if (map[jn] >= 0) {
+          ns[jn] = hs[map[jn]];
+        } else {
+          ns[jn] = SlCol{};
+          ns[jn].done = 1;
+        }
+      }
+      std::vector<int> ncols;
+      for (int j : keep) ncols.push_back(cols[j]);
+      cols = ncols;
+      HZ_HIP(hipMemcpyAsync(W2.st, ns.data(), sizeof(SlCol) * s2, hipMemcpyHostToDevice, q));
+      HZ_TRY(upload_kc(W2, q));
+      HZ_TRY(autotune<T>(ctx, q, nrows, s2, AT, W2.kc, W2.V.Z, W2.V.u[1], &W2.vin));
+      W = W2;
+      // new graph ordered after the old stream; the old graph and stream go once idle
+      std::unique_ptr<Graph> G2(new Graph());
+      HZ_TRY(G2->stream(q));
+      HZ_TRY(G2->capture(cycles_body));
+      HZ_HIP(hipStreamSynchronize(q));
+      G = std::move(G2);
+      q = G->gs;
+      continue;
+    }
+    HZ_TRY(G->launch());
+  }
+  // remaining columns: copy out and record
+  HZ_HIP(hipMemcpyAsync(hs, W.st, sizeof(SlCol) * W.s, hipMemcpyDeviceToHost, q));
+  HZ_HIP(hipStreamSynchronize(q));
+  {
+    const int nreal = int(cols.size());
+    std::vector<int> h2(2 * nreal);
+    for (int j = 0; j < nreal; ++j) {
+      h2[j] = j;
+      h2[nreal + j] = cols[j];
+    }
+    if (nreal > 0) {
+      HZ_HIP(hipMemcpyAsync(mapb->p, h2.data(), sizeof(int) * h2.size(), hipMemcpyHostToDevice, q));
+      k_out_cols<<<ceil_div(n * nreal, kBlock), kBlock, 0, q>>>(n, W.s, nf, nreal, mapb->as<int>(),
+                                                                 mapb->as<int>() + nreal, W.X, Pio);
+      HZ_HIP(hipGetLastError());
+      HZ_HIP(hipStreamSynchronize(q));
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int j = 0; j < nreal; ++j) record(j, secs);
+  }
+  for (int f = 0; f < nf; ++f) {
+    worst = std::max(worst, res[f].status);
+    if (infos) infos[f] = res[f];
+  }
+  return worst;
+}
+
 }  // namespace
 
 int sweep_solve(hz_ctx ctx, int nfreq, const double* freqs, const z_t* F, z_t* P, const hz_solve_opts& o,
@@ -1462,6 +2113,9 @@ int sweep_solve(hz_ctx ctx, int nfreq, const double* freqs, const z_t* F, z_t* P
   if (o.method == HZ_BICGSTAB)
     return mixed ? run_sweep_bicgstab<float>(ctx, D, nfreq, freqs, F, P, o, infos)
                  : run_sweep_bicgstab<double>(ctx, D, nfreq, freqs, F, P, o, infos);
+  if (o.method == HZ_BICGSTABL)
+    return mixed ? run_sweep_bicgstabl<float>(ctx, D, nfreq, freqs, F, P, o, infos)
+                 : run_sweep_bicgstabl<double>(ctx, D, nfreq, freqs, F, P, o, infos);
   return mixed ? run_sweep_gmres<float>(ctx, D, nfreq, freqs, F, P, o, infos)
                : run_sweep_gmres<double>(ctx, D, nfreq, freqs, F, P, o, infos);
 }

@@ -51,11 +51,12 @@ def test_spmv_sampled_rows_full_size(c1):
     assert np.all(np.abs(y[rows] - yref) <= bound)
 
 
-def test_bicgstab_full_size_residual_by_oracle(c1):
+@pytest.mark.parametrize("method,l", [("bicgstab", 0), ("bicgstabl", 4)])
+def test_bicgstab_full_size_residual_by_oracle(c1, method, l):
     wl, model = c1
     f = model.load(torch.as_tensor(wl["g"], device="cuda"))
-    p, info = model.solve(f, method="bicgstab", tol=1e-8, max_matvec=100000)
-    say("full-size bicgstab", info)
+    p, info = model.solve(f, method=method, restart=l or 30, tol=1e-8, max_matvec=100000)
+    say(f"full-size {method}", info)
     assert info["status"] == 0
     p = p.cpu().numpy()
     fo = H.load_elementwise(wl["mesh"], wl["g"])

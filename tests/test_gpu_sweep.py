@@ -30,7 +30,9 @@ def _t(x):
 
 @pytest.mark.parametrize("nfreq,precision,method", [(1, "mixed", "gmres"), (3, "mixed", "bicgstab"),
                                                     (16, "fp64", "gmres"), (64, "mixed", "gmres"),
-                                                    (64, "fp64", "bicgstab"), (5, "fp64", "bicgstab")])
+                                                    (64, "fp64", "bicgstab"), (5, "fp64", "bicgstab"),
+                                                    (64, "fp64", "bicgstabl"), (7, "mixed", "bicgstabl"),
+                                                    (64, "mixed", "bicgstabl"), (2, "fp64", "bicgstabl")])
 def test_sweep_columns_match_oracle_direct(P, nfreq, precision, method):
     say("sweep parity", nfreq, precision, method)
     wl = W.workload(2, elems=(20, 12, 10))
@@ -41,8 +43,9 @@ def test_sweep_columns_match_oracle_direct(P, nfreq, precision, method):
     rng = np.random.default_rng(4)
     F = np.stack([f * (1 + 0.1 * rng.standard_normal()) for _ in range(nfreq)], axis=1)
     model = P.Helmholtz(mesh, wl["beta"])
-    Pg, infos = model.solve_sweep(freqs, _t(F), method=method, restart=60, tol=1e-10,
-                                  precision=precision, max_matvec=50000)
+    Pg, infos = model.solve_sweep(freqs, _t(F), method=method, restart=4 if method == "bicgstabl" else 60,
+                                  tol=1e-10, precision=precision, max_matvec=50000)
+    say("  iters", [i["iters"] for i in infos])
     Pg = Pg.cpu().numpy()
     for j, fr in enumerate(freqs):
         A = S.operator(W.wavenumber(fr))
