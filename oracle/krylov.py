@@ -295,3 +295,97 @@ def bicgstab_l(A, f, l=4, tol=1e-8, max_matvec=20000, x0=None, precond="jacobi",
     x = dinv * u_sol
     rel = np.linalg.norm(f - A @ x) / nf
     return Result(x, 0 if rel <= tol else 1, cycles, matvecs, rel, hist)
+
+
+def tfqmr(A, f, tol=1e-8, max_matvec=20000, x0=None, precond="jacobi", max_steps=None):
+    """Transpose-free QMR of Freund (SIAM J. Sci. Comput. 14, 1993), the
+    paper's P-tfQMR (Sec. 4, solver comparison table), on the right-Jacobi
+    operator B = A D^-1 (iterate u of B u = f, x = D^-1 u).
+
+    Half-steps m = 0, 1, 2, ...: on even m the CGS direction advances
+    (alpha = rho / r*^H v, u_next = u - alpha v); on every m the quasi-residual
+    w and the QMR direction d update and the smoothed iterate moves by
+    eta d, with theta = ||w|| / tau, c = 1 / sqrt(1 + theta^2), tau = tau theta c,
+    eta = c^2 alpha; on odd m the next CGS direction is built from
+    rho = r*^H w, beta = rho / rho_old.  Shadow vector r* = r0.  The
+    quasi-residual bound tau sqrt(m + 1) <= tol ||f|| stops the iteration,
+    which is confirmed (or restarted) with the true residual; a zero
+    r*^H v or rho restarts from the true residual as well.  max_steps caps
+    the half-steps (for comparing iterates)."""
+    f = np.asarray(f, dtype=np.complex128)
+    n = f.size
+    dinv = _dinv(A, precond)
+
+    def B(z):
+        return A @ (dinv * z)
+
+    x = np.zeros(n, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128)
+    u_sol = x / dinv
+    nf = np.linalg.norm(f)
+    if nf == 0.0:
+        return Result(np.zeros(n, dtype=np.complex128), 0, 0, 0, 0.0, [])
+    matvecs, steps, hist = 0, 0, []
+    converged = False
+    while not converged and matvecs < max_matvec:
+        r0 = f - B(u_sol)
+        matvecs += 1
+        hist.append(np.linalg.norm(r0) / nf)
+        if hist[-1] <= tol:
+            converged = True
+            break
+        rstar = r0.copy()
+        w = r0.copy()
+        u = r0.copy()
+        v = B(u)
+        matvecs += 1
+        uhat = v.copy()                       # B u
+        d = np.zeros(n, dtype=np.complex128)
+        theta, eta = 0.0, 0.0 + 0.0j
+        tau = np.linalg.norm(r0)
+        rho = np.vdot(rstar, r0)
+        alpha = 0.0 + 0.0j
+        u_next = None
+        m = 0
+        restart = False
+        while matvecs < max_matvec:
+            if m % 2 == 0:
+                sigma = np.vdot(rstar, v)
+                if sigma == 0:
+                    restart = True
+                    break
+                alpha = rho / sigma
+                u_next = u - alpha * v
+            w = w - alpha * uhat
+            d = u + (theta ** 2 / alpha) * eta * d
+            theta = np.linalg.norm(w) / tau
+            c = 1.0 / np.sqrt(1.0 + theta ** 2)
+            tau = tau * theta * c
+            eta = c * c * alpha
+            u_sol = u_sol + eta * d
+            steps += 1
+            if max_steps is not None and steps >= max_steps:
+                break
+            if tau * np.sqrt(m + 1) <= tol * nf:
+                break                         # the outer loop checks the true residual
+            if m % 2 == 1:
+                rho_new = np.vdot(rstar, w)
+                if rho == 0:
+                    restart = True
+                    break
+                beta = rho_new / rho
+                rho = rho_new
+                u = w + beta * u
+                v_part = beta * uhat + beta * beta * v
+                uhat = B(u)
+                matvecs += 1
+                v = v_part + uhat
+            else:
+                u = u_next
+                uhat = B(u)
+                matvecs += 1
+            m += 1
+        if (not restart and matvecs >= max_matvec) or (max_steps is not None and steps >= max_steps):
+            break
+    x = dinv * u_sol
+    rel = np.linalg.norm(f - A @ x) / nf
+    return Result(x, 0 if rel <= tol else 1, steps, matvecs, rel, hist)

@@ -229,3 +229,50 @@ def test_bicgstab_l_converges_to_direct_solution(l):
     res = krylov.bicgstab_l(A, f, l=l, tol=1e-8, max_matvec=20000)
     assert res.status == 0 and res.relres <= 1e-8
     assert np.linalg.norm(res.x - x) <= 1e-6 * np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_tfqmr_equals_scipy_tfqmr_iterates(precond):
+    """The oracle's transpose-free QMR follows Freund's recurrences: its
+    iterate after k half-steps is SciPy's unpreconditioned TFQMR iterate on
+    the same operator (A, or the column-scaled A D^-1 with x = D^-1 y)."""
+    import scipy.sparse.linalg as spla
+    wl = W.workload(0)
+    S = H.System(wl["mesh"], wl["beta"])
+    A = S.operator(W.wavenumber(wl["freqs"][0])).tocsr()
+    f = S.load(wl["g"])
+    f = f / np.linalg.norm(f)
+    dinv = 1.0 / A.diagonal() if precond == "jacobi" else np.ones(A.shape[0], dtype=complex)
+    Bm = (A @ sp.diags(dinv)).tocsr()
+    its = []
+    spla.tfqmr(Bm, f, rtol=1e-300, atol=0.0, maxiter=9, callback=lambda xk: its.append(xk.copy()))
+    assert len(its) == 9
+    for k in (1, 2, 3, 6, 9):
+        res = krylov.tfqmr(A, f, tol=1e-300, max_steps=k, precond=precond)
+        assert res.iters == k
+        ref = dinv * its[k - 1]
+        assert np.linalg.norm(res.x - ref) <= 1e-9 * np.linalg.norm(ref), k
+
+
+@pytest.mark.parametrize("n", [5, 8])
+def test_tfqmr_finite_termination(n):
+    """After 2n half-steps the underlying CGS residual vanishes, and so does
+    the quasi-residual: the iterate is the exact solution of an n x n system."""
+    rng = np.random.default_rng(n)
+    G = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = sp.csr_matrix(G + G.T + 4 * n * np.eye(n))
+    f = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    res = krylov.tfqmr(A, f, tol=1e-300, max_steps=2 * n)
+    x = np.linalg.solve(A.toarray(), f)
+    assert np.linalg.norm(res.x - x) <= 1e-9 * np.linalg.norm(x)
+
+
+def test_tfqmr_converges_to_direct_solution():
+    wl = W.workload(0)
+    S = H.System(wl["mesh"], wl["beta"])
+    A = S.operator(W.wavenumber(wl["freqs"][0]))
+    f = S.load(wl["g"])
+    x = direct.SparseLU(A).solve(f)
+    res = krylov.tfqmr(A, f, tol=1e-8, max_matvec=20000)
+    assert res.status == 0 and res.relres <= 1e-8
+    assert np.linalg.norm(res.x - x) <= 1e-6 * np.linalg.norm(x)
