@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the FP64 product on this workload, per storage form,
 # from the FETCH_SIZE / WRITE_SIZE passes recorded in profiles/ (calibrated
 # against a 1 GiB device copy); None until measured for the current kernel.
-MEASURED_TRAFFIC = {"split": None, "complex": None}
+MEASURED_TRAFFIC = {"split": 516.8e6, "complex": 827.0e6}
 
 
 def log(*a):
@@ -227,7 +227,7 @@ def main():
     gbs = byts / (ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": gbs / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get(form),
-            "kernel": f"k_spmv<double> ({form} form sliced-ELL product)",
+            "kernel": f"k_spmv<double, {1 if form == 'split' else 0}> ({form} form sliced-ELL product)",
             "avg_kernel_ms": ms, "algorithmic_bytes": byts}
     log(f"spmv ({form}): {ms * 1e3:.1f} us, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
 
@@ -247,7 +247,8 @@ def main():
                          ("bicgstabl2", dict(method="bicgstabl", restart=2)),
                          ("bicgstabl4", dict(method="bicgstabl", restart=4)),
                          ("bicgstabl8", dict(method="bicgstabl", restart=8)),
-                         ("bicgstabl4_mixed", dict(method="bicgstabl", restart=4, precision="mixed")),
+                         ("tfqmr", dict(method="tfqmr")),
+                         ("bicgstabl4_mixed", dict(method="bicgstabl", restart=4, precision="mixed", inner_tol=1e-2)),
                          ("bicgstab_mixed", dict(method="bicgstab", precision="mixed")),
                          ("gmres50_mixed", dict(method="gmres", restart=50, precision="mixed"))):
             model.set_frequency(freq)

@@ -66,7 +66,7 @@ enum {
   HZ_ERR_STATE = -4       /* call order violated (e.g. no frequency set)  */
 };
 
-enum { HZ_GMRES = 0, HZ_BICGSTAB = 1, HZ_SCHWARZ = 2, HZ_BICGSTABL = 3 };
+enum { HZ_GMRES = 0, HZ_BICGSTAB = 1, HZ_SCHWARZ = 2, HZ_BICGSTABL = 3, HZ_TFQMR = 4 };
 enum { HZ_FP64 = 0, HZ_MIXED = 1 };
 enum { HZ_JACOBI = 0, HZ_NONE = 1 };
 
@@ -98,7 +98,10 @@ typedef struct {
 } hz_mesh;
 
 /* Solver options (host struct).
- *   method      HZ_GMRES, HZ_BICGSTAB, HZ_BICGSTABL or HZ_SCHWARZ.
+ *   method      HZ_GMRES, HZ_BICGSTAB, HZ_BICGSTABL, HZ_TFQMR or HZ_SCHWARZ.
+ *               HZ_TFQMR is Freund's transpose-free QMR (the paper's P-tfQMR,
+ *               Sec. 4), stopped by its quasi-residual bound and confirmed
+ *               with the true residual.
  *               HZ_BICGSTABL is BiCGStab(l) of Sleijpen and Fokkema (the
  *               paper's P-BiCGSTAB(8) family, Sec. 4): l bi-conjugate
  *               gradient steps and one l-dimensional minimal-residual step
@@ -125,7 +128,7 @@ typedef struct {
  *               or i sqrt(k^2 - xi^2)), leaving out xi within pi/(2 H_sub)
  *               of k; i k is the plain absorbing (Despres) choice
  *   dd_inner    Krylov method of the Schwarz subdomain solves (HZ_GMRES,
- *               HZ_BICGSTAB or HZ_BICGSTABL); for the Schwarz method inner_tol is the
+ *               HZ_BICGSTAB, HZ_BICGSTABL or HZ_TFQMR); for the Schwarz method inner_tol is the
  *               subdomain solves' relative tolerance (0: 1e-10) and
  *               precision HZ_MIXED runs them in complex64 with FP64
  *               refinement; restart is the interface GMRES restart

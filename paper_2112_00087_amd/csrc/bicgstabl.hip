@@ -232,9 +232,10 @@ __global__ void __launch_bounds__(kBlock) k_bl_gram(Seg L, const BlSt* st, BlV<T
 }
 
 // Cholesky solve of G gamma = c (G Hermitian, LL x LL), truncated at the
-// first pivot that has lost all significant digits.
+// first pivot below piv times its diagonal entry (G is exact for the stored
+// vectors, so piv guards the FP64 Cholesky only).
 template <int LL>
-__global__ void k_bl_mr_fin(Seg L, BlSt* st, const double* part) {
+__global__ void k_bl_mr_fin(Seg L, BlSt* st, const double* part, double piv) {
   constexpr int NQ = gram_nq<LL>();
   __shared__ double tot[NQ];
   const int s = blockIdx.x;
@@ -257,7 +258,7 @@ __global__ void k_bl_mr_fin(Seg L, BlSt* st, const double* part) {
   for (int jj = 0; jj < LL && m == LL; ++jj) {
     double d = G[jj][jj].re;
     for (int p = 0; p < jj; ++p) d -= norm2(G[jj][p]);
-    if (!(d > 1e-13 * G[jj][jj].re) || !isfinite(d)) {
+    if (!(d > piv * G[jj][jj].re) || !isfinite(d)) {
       m = jj;
       break;
     }
@@ -286,6 +287,11 @@ __global__ void k_bl_mr_fin(Seg L, BlSt* st, const double* part) {
       g[i] = (1.0 / G[i][i].re) * v;
     }
   }
+  for (int i = 0; i < LL; ++i)
+    if (!isfinite(g[i].re) || !isfinite(g[i].im)) {
+      S.brk = 1;
+      return;
+    }
   for (int i = 0; i < LL; ++i) S.gam[i + 1] = g[i];
   S.omega = g[LL - 1];
   S.trunc = (m < LL) ? 1 : 0;
@@ -361,7 +367,7 @@ __global__ void k_bl_set_thr(int nseg, BlSt* st, const double* fn2, double tol) 
 template <typename T, int LL>
 int enqueue_mr(hipStream_t q, const SegHost& S, BlSt* st, const BlV<T>& V, double* pt) {
   k_bl_gram<T, LL><<<S.nblk, kBlock, 0, q>>>(S.dev, st, V, pt);
-  k_bl_mr_fin<LL><<<S.nseg, kFinBlock, 0, q>>>(S.dev, st, pt);
+  k_bl_mr_fin<LL><<<S.nseg, kFinBlock, 0, q>>>(S.dev, st, pt, 1e-13);
   k_bl_update<T, LL><<<S.nblk, kBlock, 0, q>>>(S.dev, st, V, pt);
   HZ_HIP(hipGetLastError());
   return HZ_OK;

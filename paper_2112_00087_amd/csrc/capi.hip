@@ -25,7 +25,7 @@ int adjoint_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* p, const z_t* g
 
 int validate_opts(const hz_solve_opts* o) {
   if (!o) return hz_fail(HZ_ERR_INVALID, "opts is NULL");
-  if (o->method < HZ_GMRES || o->method > HZ_BICGSTABL) return hz_fail(HZ_ERR_INVALID, "unknown method %d", o->method);
+  if (o->method < HZ_GMRES || o->method > HZ_TFQMR) return hz_fail(HZ_ERR_INVALID, "unknown method %d", o->method);
   if (o->precision != HZ_FP64 && o->precision != HZ_MIXED)
     return hz_fail(HZ_ERR_INVALID, "unknown precision %d", o->precision);
   if (o->precond != HZ_JACOBI && o->precond != HZ_NONE) return hz_fail(HZ_ERR_INVALID, "unknown precond %d", o->precond);
@@ -41,8 +41,8 @@ int validate_opts(const hz_solve_opts* o) {
   if (o->inner_restart < 0 || o->inner_restart > 128) return hz_fail(HZ_ERR_INVALID, "inner_restart not in 0..128");
   if (o->dd_richardson < 0) return hz_fail(HZ_ERR_INVALID, "dd_richardson must be >= 0");
   if (o->method == HZ_SCHWARZ && o->dd_inner != HZ_GMRES && o->dd_inner != HZ_BICGSTAB &&
-      o->dd_inner != HZ_BICGSTABL)
-    return hz_fail(HZ_ERR_INVALID, "dd_inner must be HZ_GMRES, HZ_BICGSTAB or HZ_BICGSTABL");
+      o->dd_inner != HZ_BICGSTABL && o->dd_inner != HZ_TFQMR)
+    return hz_fail(HZ_ERR_INVALID, "dd_inner must be HZ_GMRES, HZ_BICGSTAB, HZ_BICGSTABL or HZ_TFQMR");
   if (o->method == HZ_SCHWARZ && o->dd_inner == HZ_BICGSTABL && o->inner_restart > 8)
     return hz_fail(HZ_ERR_INVALID, "local BiCGStab(l): l = inner_restart %d not in 0..8", o->inner_restart);
   return HZ_OK;
@@ -200,7 +200,8 @@ int hz_solve_sweep(hz_ctx ctx, int32_t nfreq, const double* freqs_host, const hz
   HZ_TRY(validate_opts(opts));
   if (nfreq < 1 || nfreq > 64) return hz_fail(HZ_ERR_INVALID, "nfreq %d not in 1..64", nfreq);
   if (!freqs_host || !F_dev || !P_dev) return hz_fail(HZ_ERR_INVALID, "null argument");
-  if (opts->method == HZ_SCHWARZ) return hz_fail(HZ_ERR_INVALID, "the sweep runs GMRES, BiCGStab or BiCGStab(l)");
+  if (opts->method == HZ_SCHWARZ || opts->method == HZ_TFQMR)
+    return hz_fail(HZ_ERR_INVALID, "the sweep runs GMRES, BiCGStab or BiCGStab(l)");
   for (int j = 0; j < nfreq; ++j)
     if (!std::isfinite(freqs_host[j]) || freqs_host[j] < 0) return hz_fail(HZ_ERR_INVALID, "bad frequency");
   return sweep_solve(ctx, nfreq, freqs_host, reinterpret_cast<const z_t*>(F_dev), reinterpret_cast<z_t*>(P_dev),

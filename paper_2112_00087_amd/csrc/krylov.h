@@ -77,13 +77,17 @@ __device__ __forceinline__ void split_real(const I* __restrict__ c, const T* __r
   }
 }
 
-// y_row = sum_k A[row, col_k] x[col_k] over the row's sliced-ELL entries.
-template <typename T>
-__device__ __forceinline__ cx<T> sell_row(const SellOp<T>& A, int64_t row, const cx<T>* __restrict__ x) {
+// Storage forms of a SellOp (compile-time selector of sell_row_form).
+enum { kFormComplex = 0, kFormSplit = 1 };
+
+// y_row = sum_k A[row, col_k] x[col_k] over the row's sliced-ELL entries,
+// for an operator known to be in form F.
+template <int F, typename T>
+__device__ __forceinline__ cx<T> sell_row_form(const SellOp<T>& A, int64_t row, const cx<T>* __restrict__ x) {
   int slice = int(row >> 6), lane = int(row & 63);
   int beg = A.ptr[slice];
   int w = (A.ptr[slice + 1] - beg) >> 6;
-  if (A.val) {
+  if (F == kFormComplex) {
     const int* __restrict__ c = A.col + beg + lane;
     const cx<T>* __restrict__ v = A.val + beg + lane;
     cx<T> acc = {T(0), T(0)};
@@ -107,6 +111,12 @@ __device__ __forceinline__ cx<T> sell_row(const SellOp<T>& A, int64_t row, const
     ai = fma(b, xv.re, ai);
   }
   return cx<T>{ar, ai};
+}
+
+// The same for an operator of either form (a uniform branch on A.val).
+template <typename T>
+__device__ __forceinline__ cx<T> sell_row(const SellOp<T>& A, int64_t row, const cx<T>* __restrict__ x) {
+  return A.val ? sell_row_form<kFormComplex>(A, row, x) : sell_row_form<kFormSplit>(A, row, x);
 }
 
 // Block geometry of a segmented kernel: tile, row, segment.  Tiles follow the

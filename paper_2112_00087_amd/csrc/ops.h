@@ -94,12 +94,16 @@ int gmres_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
 template <typename T>
 int bicgstabl_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, cx<T>* u,
                   const KrylovCtl& ctl, KrylovOut* out, const std::string& tag);
-// Dispatch on opts->method (HZ_GMRES, HZ_BICGSTAB or HZ_BICGSTABL).
+template <typename T>
+int tfqmr_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, cx<T>* u,
+              const KrylovCtl& ctl, KrylovOut* out, const std::string& tag);
+// Dispatch on opts->method (HZ_GMRES, HZ_BICGSTAB, HZ_BICGSTABL or HZ_TFQMR).
 template <typename T>
 int krylov_run(hz_ctx ctx, int method, const SegHost& S, const SellOp<T>& A, const cx<T>* f, cx<T>* u,
                const KrylovCtl& ctl, KrylovOut* out, const std::string& tag) {
   if (method == HZ_BICGSTAB) return bicgstab_run<T>(ctx, S, A, f, u, ctl, out, tag);
   if (method == HZ_BICGSTABL) return bicgstabl_run<T>(ctx, S, A, f, u, ctl, out, tag);
+  if (method == HZ_TFQMR) return tfqmr_run<T>(ctx, S, A, f, u, ctl, out, tag);
   return gmres_run<T>(ctx, S, A, f, u, ctl, out, tag);
 }
 

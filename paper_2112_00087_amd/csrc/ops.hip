@@ -107,20 +107,19 @@ int op_set_frequency(hz_ctx ctx, const OpParts& P, double k, int scale, bool wan
 }
 
 // ---------------------------------------------------------------- products
-// y[row] = (A (s .* x))[row] for rows < nout (s = NULL: no column scaling
-// beyond what the stored values carry; used by the plain apply of a
-// column-scaled operator to undo the scaling).
-template <typename T>
+// y[row] = (A x)[row] for rows < nout; one kernel per storage form F.
+template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_spmv(int64_t nout, SellOp<T> A, const cx<T>* __restrict__ x,
                                                  cx<T>* __restrict__ y) {
   int64_t row = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  cx<T> v = sell_row(A, row, x);
+  cx<T> v = sell_row_form<F>(A, row, x);
   if (row < nout) y[row] = v;
 }
 
 template <typename T>
 int op_spmv(hipStream_t s, int64_t nrows, int64_t nout, const SellOp<T>& A, const cx<T>* x, cx<T>* y) {
-  k_spmv<T><<<int(nrows / kBlock), kBlock, 0, s>>>(nout, A, x, y);
+  if (A.val) k_spmv<T, kFormComplex><<<int(nrows / kBlock), kBlock, 0, s>>>(nout, A, x, y);
+  else k_spmv<T, kFormSplit><<<int(nrows / kBlock), kBlock, 0, s>>>(nout, A, x, y);
   HZ_HIP(hipGetLastError());
   return HZ_OK;
 }

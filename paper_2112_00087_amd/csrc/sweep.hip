@@ -70,13 +70,16 @@ __device__ __forceinline__ double col_reduce(double v, int s, double* lds /*[4*6
 // ---------------------------------------------------------------- product
 // Y[row, c] = (A(k_c) Z[:, c])[row]   or, with RESID, Y = F - A X and partial ||Y_c||^2.
 // L lanes per row, CPL columns per lane (s = L * CPL); block of blockDim.x threads.
-template <typename T, int L, int CPL, bool RESID>
+// XCD: block b takes row tile xcd_tile(b) (each XCD a contiguous range, so
+// the rows whose neighbours overlap share that XCD's L2) instead of tile b.
+template <typename T, int L, int CPL, bool RESID, bool XCD>
 __global__ void __launch_bounds__(512) k_spmm(int64_t nrows, int s, RowOp<T> A, const double* __restrict__ kc,
                                               const cx<T>* __restrict__ Z, const cx<T>* __restrict__ F,
                                               cx<T>* __restrict__ Y, double* __restrict__ part) {
   const int rpb = blockDim.x / L;
   const int ln = threadIdx.x % L;
-  int row = blockIdx.x * rpb + threadIdx.x / L;
+  const int tile = XCD ? xcd_tile(blockIdx.x, gridDim.x) : int(blockIdx.x);
+  int row = tile * rpb + threadIdx.x / L;
   if (L == kWave) row = __builtin_amdgcn_readfirstlane(row);
   double pn = 0.0;
   if (row < nrows) {
@@ -773,7 +776,7 @@ __global__ void k_out_cols(int64_t n, int s, int nf, int ncols, const int* __res
 
 // ---------------------------------------------------------------- dispatch of product variants
 struct Variant {
-  int cpl = 1, bs = 256;
+  int cpl = 1, bs = 256, xcd = 0;
 };
 
 template <typename T, bool RESID>
@@ -785,7 +788,8 @@ int launch_spmm(hipStream_t stream, const Variant& v, int64_t nrows, int s, cons
   if (nblk_out) *nblk_out = nblk;
 #define HZ_SPMM_CASE(LL, CC)                                                                               \
   if (L == LL && v.cpl == CC) {                                                                             \
-    k_spmm<T, LL, CC, RESID><<<nblk, v.bs, 0, stream>>>(nrows, s, A, st, Z, F, Y, part);                    \
+    if (v.xcd) k_spmm<T, LL, CC, RESID, true><<<nblk, v.bs, 0, stream>>>(nrows, s, A, st, Z, F, Y, part);   \
+    else k_spmm<T, LL, CC, RESID, false><<<nblk, v.bs, 0, stream>>>(nrows, s, A, st, Z, F, Y, part);        \
     HZ_HIP(hipGetLastError());                                                                              \
     return HZ_OK;                                                                                           \
   }
@@ -882,7 +886,7 @@ template <> RowOp<float> row_op<float>(const SweepData& D) {
 // ---------------------------------------------------------------- autotuner
 std::string tune_key(int64_t n, int64_t nnz, int s, int bytes) {
   std::ostringstream o;
-  o << "spmm n=" << n << " nnz=" << nnz << " s=" << s << " t=" << bytes;
+  o << "spmm2 n=" << n << " nnz=" << nnz << " s=" << s << " t=" << bytes;
   return o.str();
 }
 
@@ -912,17 +916,19 @@ int autotune(hz_ctx ctx, hipStream_t stream, int64_t nrows, int s, const RowOp<T
   if (ctx->tuned.empty()) load_tune_cache(ctx);
   auto it = ctx->tuned.find(key);
   if (it != ctx->tuned.end()) {
-    best->cpl = it->second / 1000;
+    best->xcd = it->second / 10000;
+    best->cpl = it->second / 1000 % 10;
     best->bs = it->second % 1000;
     return HZ_OK;
   }
   std::vector<Variant> cands;
-  for (int cpl : {1, 2})
-    for (int bs : {128, 256, 512}) {
-      if (cpl > s) continue;
-      if (bs < s / cpl) continue;
-      cands.push_back(Variant{cpl, bs});
-    }
+  for (int xcd : {0, 1})
+    for (int cpl : {1, 2})
+      for (int bs : {128, 256, 512}) {
+        if (cpl > s) continue;
+        if (bs < s / cpl) continue;
+        cands.push_back(Variant{cpl, bs, xcd});
+      }
   hipEvent_t e0, e1;
   HZ_HIP(hipEventCreate(&e0));
   HZ_HIP(hipEventCreate(&e1));
@@ -943,7 +949,7 @@ int autotune(hz_ctx ctx, hipStream_t stream, int64_t nrows, int s, const RowOp<T
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  int code = best->cpl * 1000 + best->bs;
+  int code = best->xcd * 10000 + best->cpl * 1000 + best->bs;
   ctx->tuned[key] = code;
   save_tune_entry(key, code);
   return HZ_OK;
@@ -1677,9 +1683,10 @@ __global__ void __launch_bounds__(kBlock) k_sl_gram(int64_t total, int s, const 
   }
 }
 
-// Cholesky solve of G gamma = c per column (truncated at a lost pivot)
+// Cholesky solve of G gamma = c per column (truncated at the first pivot
+// below piv times its diagonal entry)
 template <int LL>
-__global__ void k_sl_mr(int G_, int s, SlCol* st, const double* __restrict__ part) {
+__global__ void k_sl_mr(int G_, int s, SlCol* st, const double* __restrict__ part, double piv) {
   constexpr int NQ = sl_nq<LL>();
   __shared__ double lds[kBlock / kWave];
   __shared__ double tot[NQ];
@@ -1705,7 +1712,7 @@ __global__ void k_sl_mr(int G_, int s, SlCol* st, const double* __restrict__ par
   for (int jj = 0; jj < LL; ++jj) {
     double d = G[jj][jj].re;
     for (int p = 0; p < jj; ++p) d -= norm2(G[jj][p]);
-    if (!(d > 1e-13 * G[jj][jj].re) || !isfinite(d)) {
+    if (!(d > piv * G[jj][jj].re) || !isfinite(d)) {
       m = jj;
       break;
     }
@@ -1734,6 +1741,11 @@ __global__ void k_sl_mr(int G_, int s, SlCol* st, const double* __restrict__ par
     for (int p = i + 1; p < m; ++p) v = v - conj(G[p][i]) * g[p];
     g[i] = (1.0 / G[i][i].re) * v;
   }
+  for (int i = 0; i < LL; ++i)
+    if (!isfinite(g[i].re) || !isfinite(g[i].im)) {
+      S.idone = 1;
+      return;
+    }
   for (int i = 0; i < LL; ++i) S.gam[i + 1] = g[i];
   S.omega = g[LL - 1];
   S.trunc = m < LL;
@@ -1857,7 +1869,7 @@ template <typename T, int LL>
 int sl_enqueue_mr(hipStream_t q, SlWidth<T>& W) {
   const int eb = ceil_div(W.total, kBlock);
   k_sl_gram<T, LL><<<W.Gr, kBlock, 0, q>>>(W.total, W.s, W.st, W.V, W.part);
-  k_sl_mr<LL><<<W.s, kBlock, 0, q>>>(W.Gr, W.s, W.st, W.part);
+  k_sl_mr<LL><<<W.s, kBlock, 0, q>>>(W.Gr, W.s, W.st, W.part, 1e-13);
   k_sl_update<T, LL><<<eb, kBlock, 0, q>>>(W.total, W.s, W.st, W.V);
   HZ_HIP(hipGetLastError());
   return HZ_OK;

@@ -20,11 +20,11 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "hz.h")
 
 HZ_OK, HZ_NOT_CONVERGED, HZ_BREAKDOWN = 0, 1, 2
 HZ_ERR_INVALID, HZ_ERR_HIP, HZ_ERR_OOM, HZ_ERR_STATE = -1, -2, -3, -4
-HZ_GMRES, HZ_BICGSTAB, HZ_SCHWARZ, HZ_BICGSTABL = 0, 1, 2, 3
+HZ_GMRES, HZ_BICGSTAB, HZ_SCHWARZ, HZ_BICGSTABL, HZ_TFQMR = 0, 1, 2, 3, 4
 HZ_FP64, HZ_MIXED = 0, 1
 HZ_JACOBI, HZ_NONE = 0, 1
 
-METHODS = {"gmres": HZ_GMRES, "bicgstab": HZ_BICGSTAB, "schwarz": HZ_SCHWARZ, "bicgstabl": HZ_BICGSTABL}
+METHODS = {"gmres": HZ_GMRES, "bicgstab": HZ_BICGSTAB, "schwarz": HZ_SCHWARZ, "bicgstabl": HZ_BICGSTABL, "tfqmr": HZ_TFQMR}
 PRECISIONS = {"fp64": HZ_FP64, "mixed": HZ_MIXED}
 SPMV_FORMS = {"solver": 0, "complex": 1, "split": 2}
 

@@ -190,6 +190,23 @@ def test_bicgstab_l_workload0(c0, l, precision):
         assert 2 <= info["matvecs"] - 2 * l * info["iters"] <= 10
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_tfqmr_workload0(c0, precision):
+    say("tfqmr workload 0", precision)
+    m = c0["model"]
+    p, info = m.solve(_t(c0["f"]), method="tfqmr", precision=precision, tol=1e-8)
+    p = _np(p)
+    rel = H.relres(c0["A"], p, c0["f"])
+    err = np.linalg.norm(p - c0["x"]) / np.linalg.norm(c0["x"])
+    say(f"  info={info} oracle relres={rel:.3e} relerr={err:.3e}")
+    assert info["status"] == 0 and rel <= 1e-8 and err <= 1e-6
+    assert abs(info["relres_true"] - rel) <= 1e-3 * rel + 1e-15
+    if precision == "fp64":
+        ref = krylov.tfqmr(c0["A"], c0["f"], tol=1e-8)
+        say(f"  half-steps gpu {info['iters']} oracle {ref.iters}")
+        assert abs(info["iters"] - ref.iters) <= max(10, 0.2 * ref.iters)
+
+
 def test_bicgstab_l_rejects_bad_l(c0):
     import paper_2112_00087_amd as P
     for l in (0, 9):

@@ -51,7 +51,7 @@ def test_spmv_sampled_rows_full_size(c1):
     assert np.all(np.abs(y[rows] - yref) <= bound)
 
 
-@pytest.mark.parametrize("method,l", [("bicgstab", 0), ("bicgstabl", 4)])
+@pytest.mark.parametrize("method,l", [("bicgstab", 0), ("bicgstabl", 4), ("tfqmr", 0)])
 def test_bicgstab_full_size_residual_by_oracle(c1, method, l):
     wl, model = c1
     f = model.load(torch.as_tensor(wl["g"], device="cuda"))
