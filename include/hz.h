@@ -219,20 +219,25 @@ int hz_solve(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* f_dev,
 /* Frequency sweep: solves A(k_j) P[:, j] = F[:, j] for j < nfreq (1..64)
  * with all columns advanced together: one multi-vector sparse product per
  * Krylov step shares the real K, M (and M_eta) values across columns, and
- * each restart cycle of the inner solve is replayed from a captured HIP
- * graph.  The tile shape of the multi-vector product is chosen by a
- * built-in autotuner at first use for (n, nfreq, precision).
+ * each chunk of inner iterations is replayed from a captured HIP graph.
+ * The tile shape of the multi-vector product (columns per lane, block size,
+ * row-to-XCD mapping) is chosen by a built-in autotuner at first use for
+ * (n, nfreq, precision).
  *   freqs_host [nfreq] Hz
  *   F_dev, P_dev  [n_nodes][nfreq] row-major complex128 (column j of row i
  *          at i * nfreq + j); P is in: x0 (zero allowed), out: solutions
  *   infos  [nfreq] per-column results (may be NULL)
  * opts->method is HZ_GMRES (restarted GMRES(restart) advanced in lock-step,
- * every restart cycle one refinement step against the FP64 residual) or
- * HZ_BICGSTAB (one BiCGStab per column; each column's FP64 true residual
- * replaces its recursive one -- a reliable update -- when the latter has
- * dropped by the factor inner_tol (complex64, default 0.1) or reached the
- * target (FP64); converged columns leave the batch, which is compacted to
- * the next power-of-two width).  opts->precision HZ_MIXED: complex64 Krylov
+ * every restart cycle one refinement step against the FP64 residual), or
+ * HZ_BICGSTAB, HZ_BICGSTABL (l = restart) or HZ_TFQMR with independent
+ * per-column scalars: BiCGStab replaces a column's recursive residual by
+ * its FP64 true residual (a reliable update) when the former has dropped by
+ * the factor inner_tol (complex64, default 0.1) or reached the target
+ * (FP64); BiCGStab(l) and TFQMR end a column's inner solve at inner_tol
+ * (complex64, default 1e-3) or at the target (FP64) and run a refinement
+ * step X += correction, R = F - A X in FP64, restarting if needed.
+ * Converged columns leave the batch, which is compacted to the next
+ * power-of-two width.  opts->precision HZ_MIXED: complex64 Krylov
  * vectors and operator copy, FP64 residual / refinement / Gram-Schmidt
  * coefficients / Givens; HZ_FP64: complex128 throughout.  Columns converge
  * independently; the call returns when all have reached tol or one has used

@@ -200,8 +200,7 @@ int hz_solve_sweep(hz_ctx ctx, int32_t nfreq, const double* freqs_host, const hz
   HZ_TRY(validate_opts(opts));
   if (nfreq < 1 || nfreq > 64) return hz_fail(HZ_ERR_INVALID, "nfreq %d not in 1..64", nfreq);
   if (!freqs_host || !F_dev || !P_dev) return hz_fail(HZ_ERR_INVALID, "null argument");
-  if (opts->method == HZ_SCHWARZ || opts->method == HZ_TFQMR)
-    return hz_fail(HZ_ERR_INVALID, "the sweep runs GMRES, BiCGStab or BiCGStab(l)");
+  if (opts->method == HZ_SCHWARZ) return hz_fail(HZ_ERR_INVALID, "the sweep runs GMRES, BiCGStab, BiCGStab(l) or TFQMR");
   for (int j = 0; j < nfreq; ++j)
     if (!std::isfinite(freqs_host[j]) || freqs_host[j] < 0) return hz_fail(HZ_ERR_INVALID, "bad frequency");
   return sweep_solve(ctx, nfreq, freqs_host, reinterpret_cast<const z_t*>(F_dev), reinterpret_cast<z_t*>(P_dev),

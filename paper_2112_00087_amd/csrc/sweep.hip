@@ -2108,6 +2108,573 @@ int run_sweep_bicgstabl(hz_ctx ctx, SweepData& D, int nf, const double* freqs, c
   return worst;
 }
 
+// ---------------------------------------------------------------- batched transpose-free QMR
+// Each column runs Freund's TFQMR (the pair of half-steps of the
+// single-system solver) on the correction equation B(k_c) y = R_c / scale_c;
+// when its quasi-residual bound meets the inner target the column applies
+// its last update and the host runs the refinement step (X += scale D^-1 y,
+// R = F - A X in FP64): done, or restart.  A breakdown also ends the inner
+// solve with a refinement step.
+struct TsCol {
+  z_t alpha, rho, beta, eta;
+  double theta, tau, ithr, fn2, thr2, scale, beta_true, rr;
+  int done, idone, nan, m, iters, outer, restart_now, last;
+};
+
+template <typename T>
+struct TsVec {
+  cx<T>* y;      // inner iterate (scaled unknowns)
+  cx<T>* rs;     // shadow vector
+  cx<T>* w;
+  cx<T>* u;
+  cx<T>* un;
+  cx<T>* v;
+  cx<T>* vt;
+  cx<T>* uh;     // B u
+  cx<T>* d;
+  cx<T>* Z;      // D^-1 (product input)
+  const cx<T>* dT;
+};
+
+__device__ __forceinline__ bool ts_off(const TsCol& S) { return S.done || S.idone || S.nan; }
+__device__ __forceinline__ bool ts_pending(const TsCol& S) { return S.idone && !S.done && !S.nan; }
+// x-update of a half-step: always while active, once more right after the stop
+__device__ __forceinline__ bool ts_apply(const TsCol& S) { return !S.done && !S.nan && (!S.idone || S.last); }
+
+template <typename T>
+__global__ void k_ts_addx(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V, z_t* __restrict__ X) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= total) return;
+  const TsCol& S = st[e & (s - 1)];
+  if (!ts_pending(S) || S.scale == 0.0) return;
+  z_t d = ccast<double>(V.dT[e]) * ccast<double>(V.y[e]);
+  X[e] = z_t{fma(S.scale, d.re, X[e].re), fma(S.scale, d.im, X[e].im)};
+}
+
+__global__ void k_ts_true(int nblk, int s, TsCol* st, const double* __restrict__ part, double tol, double delta) {
+  __shared__ double lds[kBlock / kWave];
+  const int c = blockIdx.x;
+  const int pend = ts_pending(st[c]);
+  __syncthreads();
+  if (!pend) return;
+  const double rr = block_sum_strided(part + c, nblk, s, lds);
+  if (threadIdx.x != 0) return;
+  TsCol& S = st[c];
+  const double b = sqrt(rr);
+  S.beta_true = b;
+  S.nan = S.nan || !isfinite(rr);
+  S.done = (rr <= S.thr2) || S.fn2 == 0.0 || S.nan;
+  if (S.done) return;
+  S.outer += 1;
+  S.idone = 0;
+  S.last = 0;
+  S.restart_now = 1;
+  S.scale = b;
+  const double lim = 0.5 * tol * sqrt(S.fn2) / b;
+  S.ithr = delta > lim ? delta : lim;
+}
+
+// restart: r0 = R / scale; r* = w = u = r0; d = y = 0; Z = D^-1 u
+template <typename T>
+__global__ void k_ts_start(int64_t total, int s, const TsCol* __restrict__ st, const z_t* __restrict__ R,
+                           TsVec<T> V) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= total) return;
+  const TsCol& S = st[e & (s - 1)];
+  if (!S.restart_now) return;
+  const cx<T> r = ccast<T>((1.0 / S.scale) * R[e]);
+  const cx<T> z = {T(0), T(0)};
+  V.rs[e] = r;
+  V.w[e] = r;
+  V.u[e] = r;
+  V.d[e] = z;
+  V.y[e] = z;
+  V.Z[e] = ccast<T>(ccast<double>(V.dT[e]) * ccast<double>(r));
+}
+
+// after the restart product uh = B u: v = uh; partial r*^H v
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ts_v0(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V,
+                                                  double* __restrict__ part) {
+  __shared__ double lds[4 * kWave];
+  const int c = threadIdx.x & (s - 1);
+  double q[2] = {0.0, 0.0};
+  if (st[c].restart_now) {
+    for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
+      const cx<T> v = V.uh[e];
+      V.v[e] = v;
+      const z_t a = ccast<double>(V.rs[e]), b = ccast<double>(v);
+      q[0] = fma(a.re, b.re, fma(a.im, b.im, q[0]));
+      q[1] = fma(a.re, b.im, fma(-a.im, b.re, q[1]));
+    }
+  }
+  for (int i = 0; i < 2; ++i) {
+    const double t = col_reduce(q[i], s, lds);
+    if (int(threadIdx.x) < s) part[(int64_t(blockIdx.x) * 2 + i) * s + threadIdx.x] = t;
+  }
+}
+
+__global__ void k_ts_start_fin(int G_, int s, TsCol* st, const double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  const int c = blockIdx.x;
+  const int go = st[c].restart_now;
+  __syncthreads();
+  if (!go) return;
+  const double re = sl_sum(G_, s, 2, part, c, 0, lds);
+  const double im = sl_sum(G_, s, 2, part, c, 1, lds);
+  if (threadIdx.x != 0) return;
+  TsCol& S = st[c];
+  S.restart_now = 0;
+  S.rr = 1.0;
+  S.tau = 1.0;                      // ||R / scale||
+  S.theta = 0.0;
+  S.eta = z_t{0.0, 0.0};
+  S.rho = z_t{1.0, 0.0};            // r*^H r0
+  S.m = 0;
+  const z_t sg = {re, im};
+  if (norm2(sg) == 0.0 || !isfinite(re) || !isfinite(im)) S.nan = 1;
+  else S.alpha = cdiv(S.rho, sg);
+}
+
+__device__ __forceinline__ void ts_qmr(TsCol& S, double ww) {
+  S.theta = sqrt(ww) / S.tau;
+  const double c2 = 1.0 / (1.0 + S.theta * S.theta);
+  S.tau = S.tau * S.theta * sqrt(c2);
+  S.eta = c2 * S.alpha;
+  S.iters += 1;
+  if (!isfinite(ww)) {
+    S.nan = 1;
+    return;
+  }
+  if (S.tau * sqrt(double(S.m + 1)) <= S.ithr) {
+    S.idone = 1;
+    S.last = 1;
+  }
+  S.m += 1;
+}
+
+// even half-step, part 1: u' = u - alpha v; w -= alpha uh; d = u + g d; partial ||w||^2
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ts_even1(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V,
+                                                     double* __restrict__ part) {
+  __shared__ double lds[4 * kWave];
+  const int c = threadIdx.x & (s - 1);
+  const TsCol& S = st[c];
+  double ww = 0.0;
+  if (!ts_off(S)) {
+    const z_t a = S.alpha;
+    const z_t g = (S.theta * S.theta) * cdiv(S.eta, a);
+    for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
+      const z_t u = ccast<double>(V.u[e]);
+      V.un[e] = ccast<T>(u - a * ccast<double>(V.v[e]));
+      const cx<T> w = ccast<T>(ccast<double>(V.w[e]) - a * ccast<double>(V.uh[e]));
+      V.w[e] = w;
+      V.d[e] = ccast<T>(u + g * ccast<double>(V.d[e]));
+      ww += norm2(ccast<double>(w));
+    }
+  }
+  const double t = col_reduce(ww, s, lds);
+  if (int(threadIdx.x) < s) part[int64_t(blockIdx.x) * s + threadIdx.x] = t;
+}
+
+__global__ void k_ts_qmr_fin(int G_, int s, TsCol* st, const double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  const int c = blockIdx.x;
+  const int off = ts_off(st[c]), idn = st[c].idone;
+  __syncthreads();
+  if (off) {
+    if (threadIdx.x == 0 && idn) st[c].last = 0;
+    return;
+  }
+  const double ww = sl_sum(G_, s, 1, part, c, 0, lds);
+  if (threadIdx.x == 0) ts_qmr(st[c], ww);
+}
+
+// even half-step, part 2: y += eta d; then (still running) u = u', Z = D^-1 u'
+template <typename T>
+__global__ void k_ts_even2(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= total) return;
+  const TsCol& S = st[e & (s - 1)];
+  if (!ts_apply(S)) return;
+  V.y[e] = ccast<T>(ccast<double>(V.y[e]) + S.eta * ccast<double>(V.d[e]));
+  if (S.idone) return;
+  const cx<T> un = V.un[e];
+  V.u[e] = un;
+  V.Z[e] = ccast<T>(ccast<double>(V.dT[e]) * ccast<double>(un));
+}
+
+// odd half-step, part 1: w -= alpha uh; d = u + g d; partials ||w||^2, r*^H w
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ts_odd1(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V,
+                                                    double* __restrict__ part) {
+  __shared__ double lds[4 * kWave];
+  const int c = threadIdx.x & (s - 1);
+  const TsCol& S = st[c];
+  double q[3] = {0.0, 0.0, 0.0};
+  if (!ts_off(S)) {
+    const z_t a = S.alpha;
+    const z_t g = (S.theta * S.theta) * cdiv(S.eta, a);
+    for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
+      const cx<T> w = ccast<T>(ccast<double>(V.w[e]) - a * ccast<double>(V.uh[e]));
+      V.w[e] = w;
+      V.d[e] = ccast<T>(ccast<double>(V.u[e]) + g * ccast<double>(V.d[e]));
+      const z_t wv = ccast<double>(w), r = ccast<double>(V.rs[e]);
+      q[0] += norm2(wv);
+      q[1] = fma(r.re, wv.re, fma(r.im, wv.im, q[1]));
+      q[2] = fma(r.re, wv.im, fma(-r.im, wv.re, q[2]));
+    }
+  }
+  for (int i = 0; i < 3; ++i) {
+    const double t = col_reduce(q[i], s, lds);
+    if (int(threadIdx.x) < s) part[(int64_t(blockIdx.x) * 3 + i) * s + threadIdx.x] = t;
+  }
+}
+
+__global__ void k_ts_odd_fin(int G_, int s, TsCol* st, const double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  const int c = blockIdx.x;
+  const int off = ts_off(st[c]), idn = st[c].idone;
+  __syncthreads();
+  if (off) {
+    if (threadIdx.x == 0 && idn) st[c].last = 0;
+    return;
+  }
+  const double ww = sl_sum(G_, s, 3, part, c, 0, lds);
+  const double re = sl_sum(G_, s, 3, part, c, 1, lds);
+  const double im = sl_sum(G_, s, 3, part, c, 2, lds);
+  if (threadIdx.x != 0) return;
+  TsCol& S = st[c];
+  ts_qmr(S, ww);
+  const z_t rho1 = {re, im};
+  if (norm2(S.rho) == 0.0 || !isfinite(re) || !isfinite(im)) {
+    if (!S.idone) {
+      S.idone = 1;       // breakdown: refinement step and restart
+      S.last = 1;
+    }
+  } else {
+    S.beta = cdiv(rho1, S.rho);
+    S.rho = rho1;
+  }
+}
+
+// odd half-step, part 2: y += eta d; then u = w + beta u, vt = beta uh + beta^2 v, Z = D^-1 u
+template <typename T>
+__global__ void k_ts_odd2(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V) {
+  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= total) return;
+  const TsCol& S = st[e & (s - 1)];
+  if (!ts_apply(S)) return;
+  V.y[e] = ccast<T>(ccast<double>(V.y[e]) + S.eta * ccast<double>(V.d[e]));
+  if (S.idone) return;
+  const z_t b = S.beta;
+  const cx<T> u = ccast<T>(ccast<double>(V.w[e]) + b * ccast<double>(V.u[e]));
+  V.u[e] = u;
+  V.vt[e] = ccast<T>(b * ccast<double>(V.uh[e]) + (b * b) * ccast<double>(V.v[e]));
+  V.Z[e] = ccast<T>(ccast<double>(V.dT[e]) * ccast<double>(u));
+}
+
+// odd half-step, part 3 (after uh = B u): v = vt + uh; partial r*^H v
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ts_odd3(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V,
+                                                    double* __restrict__ part) {
+  __shared__ double lds[4 * kWave];
+  const int c = threadIdx.x & (s - 1);
+  double q[2] = {0.0, 0.0};
+  if (!ts_off(st[c])) {
+    for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
+      const cx<T> v = ccast<T>(ccast<double>(V.vt[e]) + ccast<double>(V.uh[e]));
+      V.v[e] = v;
+      const z_t a = ccast<double>(V.rs[e]), b = ccast<double>(v);
+      q[0] = fma(a.re, b.re, fma(a.im, b.im, q[0]));
+      q[1] = fma(a.re, b.im, fma(-a.im, b.re, q[1]));
+    }
+  }
+  for (int i = 0; i < 2; ++i) {
+    const double t = col_reduce(q[i], s, lds);
+    if (int(threadIdx.x) < s) part[(int64_t(blockIdx.x) * 2 + i) * s + threadIdx.x] = t;
+  }
+}
+
+__global__ void k_ts_alpha_fin(int G_, int s, TsCol* st, const double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  const int c = blockIdx.x;
+  const int off = ts_off(st[c]), idn = st[c].idone;
+  __syncthreads();
+  if (off) {
+    if (threadIdx.x == 0 && idn) st[c].last = 0;
+    return;
+  }
+  const double re = sl_sum(G_, s, 2, part, c, 0, lds);
+  const double im = sl_sum(G_, s, 2, part, c, 1, lds);
+  if (threadIdx.x != 0) return;
+  TsCol& S = st[c];
+  const z_t sg = {re, im};
+  if (norm2(sg) == 0.0 || !isfinite(re) || !isfinite(im)) S.idone = 1;   // refinement step and restart
+  else S.alpha = cdiv(S.rho, sg);
+}
+
+__global__ void k_ts_init(int s, TsCol* st, const double* fn2, double tol) {
+  const int c = threadIdx.x;
+  if (c >= s) return;
+  st[c].fn2 = fn2[c];
+  st[c].thr2 = tol * tol * fn2[c];
+  st[c].idone = 1;                 // every column starts with a refinement step
+}
+
+template <typename T>
+struct TsWidth {
+  int s = 0, Gr = 1;
+  int64_t total = 0;
+  z_t *X = nullptr, *Fs = nullptr, *R = nullptr;
+  cx<T>* dT = nullptr;
+  double *kc = nullptr, *part = nullptr, *cn = nullptr;
+  TsCol* st = nullptr;
+  TsVec<T> V;
+  Variant vin, vres;
+};
+
+template <typename T>
+int ts_alloc(hz_ctx ctx, int64_t nrows, int s, TsWidth<T>* W) {
+  int rc = 0;
+  const std::string p = std::string("swt.") + (sizeof(T) == 8 ? "z." : "c.") + std::to_string(s) + ".";
+  const int64_t total = nrows * s;
+  auto buf = [&](const std::string& nm, size_t bytes) -> void* {
+    DevBuf* b = ctx->buf(p + nm, bytes, &rc);
+    return rc ? nullptr : b->p;
+  };
+  W->s = s;
+  W->total = total;
+  W->Gr = int(std::min<int64_t>(std::max<int64_t>(total / kBlock, 1), 1024));
+  const int64_t nblk_res = (nrows + kBlock / s - 1) / (kBlock / s);
+  W->X = static_cast<z_t*>(buf("X", sizeof(z_t) * total));
+  W->Fs = static_cast<z_t*>(buf("F", sizeof(z_t) * total));
+  W->R = static_cast<z_t*>(buf("R", sizeof(z_t) * total));
+  W->dT = static_cast<cx<T>*>(buf("dT", sizeof(cx<T>) * total));
+  W->kc = static_cast<double*>(buf("kc", sizeof(double) * 2 * s));
+  W->cn = static_cast<double*>(buf("cn", sizeof(double) * s));
+  W->part = static_cast<double*>(buf("part", sizeof(double) * std::max<int64_t>(int64_t(W->Gr) * 3, nblk_res) * s));
+  W->st = static_cast<TsCol*>(buf("st", sizeof(TsCol) * s));
+  W->V = TsVec<T>{};
+  cx<T>** vv[10] = {&W->V.y, &W->V.rs, &W->V.w, &W->V.u, &W->V.un, &W->V.v, &W->V.vt, &W->V.uh, &W->V.d, &W->V.Z};
+  const char* names[10] = {"y", "rs", "w", "u", "un", "v", "vt", "uh", "d", "Z"};
+  for (int i = 0; i < 10; ++i) *vv[i] = static_cast<cx<T>*>(buf(names[i], sizeof(cx<T>) * total));
+  if (rc) return rc;
+  W->V.dT = W->dT;
+  W->vres.cpl = 1;
+  W->vres.bs = kBlock;
+  return HZ_OK;
+}
+
+template <typename T>
+int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const z_t* Fin, z_t* Pio,
+                    const hz_solve_opts& o, hz_solve_info* infos) {
+  auto t0 = std::chrono::steady_clock::now();
+  const double delta = sizeof(T) == 4 ? (o.inner_tol > 0 ? o.inner_tol : 1e-3) : 0.0;
+  const int chunk = 16;                         // pairs of half-steps per graph launch
+  const int64_t nrows = D.nrows, n = ctx->h.n;
+  const RowOp<double> A64 = row_op<double>(D);
+  const RowOp<T> AT = row_op<T>(D);
+  int s = 1;
+  while (s < nf) s <<= 1;
+  TsWidth<T> W;
+  HZ_TRY(ts_alloc<T>(ctx, nrows, s, &W));
+  hipStream_t cs = ctx->stream;
+  std::vector<int> cols(nf);
+  for (int c = 0; c < nf; ++c) cols[c] = c;
+  auto upload_kc = [&](TsWidth<T>& w, hipStream_t q) -> int {
+    std::vector<double> kc(2 * w.s, 0.0);
+    for (size_t j = 0; j < cols.size(); ++j) {
+      double k = 2.0 * M_PI * freqs[cols[j]] / ctx->c;
+      kc[2 * j] = k;
+      kc[2 * j + 1] = k * k;
+    }
+    HZ_HIP(hipMemcpyAsync(w.kc, kc.data(), sizeof(double) * 2 * w.s, hipMemcpyHostToDevice, q));
+    HZ_HIP(hipStreamSynchronize(q));
+    return HZ_OK;
+  };
+  HZ_TRY(upload_kc(W, cs));
+  k_in<<<ceil_div(W.total, kBlock), kBlock, 0, cs>>>(n, nrows, s, nf, Pio, Fin, W.X, W.Fs);
+  k_diag<T><<<ceil_div(W.total, kBlock), kBlock, 0, cs>>>(n, nrows, s, D.dpos.as<int>(), D.K64.as<double>(),
+                                                         D.M64.as<double>(), D.eta ? D.E64.as<double>() : nullptr,
+                                                         D.Bdiag.as<z_t>(), W.kc, W.R, W.dT);
+  k_colnorm<double><<<W.Gr, kBlock, 0, cs>>>(W.total, s, W.Fs, W.part);
+  k_colsum<<<s, kBlock, 0, cs>>>(W.Gr, s, W.part, W.cn);
+  HZ_HIP(hipMemsetAsync(W.st, 0, sizeof(TsCol) * s, cs));
+  k_ts_init<<<1, 64, 0, cs>>>(s, W.st, W.cn, o.tol);
+  HZ_HIP(hipGetLastError());
+  HZ_TRY(autotune<T>(ctx, cs, nrows, s, AT, W.kc, W.V.Z, W.V.uh, &W.vin));
+
+  auto pairs_body = [&](hipStream_t q) -> int {
+    const int s_ = W.s, Gr = W.Gr, eb = ceil_div(W.total, kBlock);
+    const int64_t total = W.total;
+    for (int it = 0; it < chunk; ++it) {
+      k_ts_even1<T><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V, W.part);
+      k_ts_qmr_fin<<<s_, kBlock, 0, q>>>(Gr, s_, W.st, W.part);
+      k_ts_even2<T><<<eb, kBlock, 0, q>>>(total, s_, W.st, W.V);
+      HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.Z, nullptr, W.V.uh, nullptr, nullptr)));
+      k_ts_odd1<T><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V, W.part);
+      k_ts_odd_fin<<<s_, kBlock, 0, q>>>(Gr, s_, W.st, W.part);
+      k_ts_odd2<T><<<eb, kBlock, 0, q>>>(total, s_, W.st, W.V);
+      HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.Z, nullptr, W.V.uh, nullptr, nullptr)));
+      k_ts_odd3<T><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V, W.part);
+      k_ts_alpha_fin<<<s_, kBlock, 0, q>>>(Gr, s_, W.st, W.part);
+    }
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+  };
+  auto outer = [&](hipStream_t q) -> int {
+    const int s_ = W.s;
+    const int64_t total = W.total;
+    const int eb = ceil_div(total, kBlock);
+    int nb = 0;
+    k_ts_addx<T><<<eb, kBlock, 0, q>>>(total, s_, W.st, W.V, W.X);
+    HZ_TRY((launch_spmm<double, true>(q, W.vres, nrows, s_, A64, W.kc, W.X, W.Fs, W.R, W.part, &nb)));
+    k_ts_true<<<s_, kBlock, 0, q>>>(nb, s_, W.st, W.part, o.tol, delta);
+    k_ts_start<T><<<eb, kBlock, 0, q>>>(total, s_, W.st, W.R, W.V);
+    HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.Z, nullptr, W.V.uh, nullptr, nullptr)));
+    k_ts_v0<T><<<W.Gr, kBlock, 0, q>>>(total, s_, W.st, W.V, W.part);
+    k_ts_start_fin<<<s_, kBlock, 0, q>>>(W.Gr, s_, W.st, W.part);
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+  };
+
+  std::unique_ptr<Graph> G(new Graph());
+  HZ_TRY(G->stream(cs));
+  HZ_TRY(G->capture(pairs_body));
+  hipStream_t q = G->gs;
+  void* hp = nullptr;
+  HZ_TRY(ctx_pinned(ctx, sizeof(TsCol) * 64, &hp));
+  TsCol* hs = static_cast<TsCol*>(hp);
+  std::vector<hz_solve_info> res(nf);
+  int worst = HZ_OK;
+  auto record = [&](int j, double secs) {
+    const TsCol& S = hs[j];
+    hz_solve_info inf = {};
+    const double fnv = std::sqrt(S.fn2);
+    inf.relres_true = fnv > 0 ? S.beta_true / fnv : 0.0;
+    inf.relres_est = inf.relres_true;
+    inf.iters = S.iters;
+    inf.matvecs = S.outer + 1;
+    inf.inner_matvecs = S.iters + S.outer;
+    inf.seconds = secs;
+    inf.status = S.nan ? HZ_BREAKDOWN : (S.done && inf.relres_true <= o.tol * (1 + 1e-12) ? HZ_OK : HZ_NOT_CONVERGED);
+    if (!std::isfinite(inf.relres_true)) inf.status = HZ_BREAKDOWN;
+    res[cols[j]] = inf;
+  };
+  int rc = 0;
+  DevBuf* mapb = ctx->buf("swt.map", sizeof(int) * 128, &rc);
+  if (rc) return rc;
+  for (;;) {
+    HZ_HIP(hipMemcpyAsync(hs, W.st, sizeof(TsCol) * W.s, hipMemcpyDeviceToHost, q));
+    HZ_HIP(hipStreamSynchronize(q));
+    const int nreal = int(cols.size());
+    int active = 0;
+    bool pending = false;
+    int64_t mx = 0;
+    for (int j = 0; j < nreal; ++j) {
+      const TsCol& S = hs[j];
+      if (S.done || S.nan) continue;
+      ++active;
+      pending = pending || S.idone;
+      mx = std::max<int64_t>(mx, int64_t(S.iters) + 2 * int64_t(S.outer) + 1);
+    }
+    if (active == 0) break;
+    if (pending) {
+      HZ_TRY(outer(q));
+      continue;
+    }
+    if (mx + 2 * chunk + 1 > o.max_matvec) break;
+    if (active <= W.s / 2) {
+      std::vector<int> keep, gone_j, gone_f;
+      for (int j = 0; j < nreal; ++j) {
+        if (hs[j].done || hs[j].nan) {
+          gone_j.push_back(j);
+          gone_f.push_back(cols[j]);
+        } else {
+          keep.push_back(j);
+        }
+      }
+      const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      for (int j : gone_j) record(j, secs);
+      if (!gone_j.empty()) {
+        std::vector<int> h2(gone_j);
+        h2.insert(h2.end(), gone_f.begin(), gone_f.end());
+        HZ_HIP(hipMemcpyAsync(mapb->p, h2.data(), sizeof(int) * h2.size(), hipMemcpyHostToDevice, q));
+        const int ng = int(gone_j.size());
+        k_out_cols<<<ceil_div(n * ng, kBlock), kBlock, 0, q>>>(n, W.s, nf, ng, mapb->as<int>(),
+                                                                mapb->as<int>() + ng, W.X, Pio);
+        HZ_HIP(hipGetLastError());
+        HZ_HIP(hipStreamSynchronize(q));
+      }
+      int s2 = 1;
+      while (s2 < int(keep.size())) s2 <<= 1;
+      TsWidth<T> W2;
+      HZ_TRY(ts_alloc<T>(ctx, nrows, s2, &W2));
+      std::vector<int> map(s2, -1);
+      for (size_t jn = 0; jn < keep.size(); ++jn) map[jn] = keep[jn];
+      HZ_HIP(hipMemcpyAsync(mapb->p, map.data(), sizeof(int) * s2, hipMemcpyHostToDevice, q));
+      const int gb = ceil_div(nrows * s2, kBlock);
+      const int* mp = mapb->as<int>();
+      k_gather_cols<z_t><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.X, W2.X);
+      k_gather_cols<z_t><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.Fs, W2.Fs);
+      k_gather_cols<cx<T>><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.dT, W2.dT);
+      cx<T>* from[10] = {W.V.y, W.V.rs, W.V.w, W.V.u, W.V.un, W.V.v, W.V.vt, W.V.uh, W.V.d, W.V.Z};
+      cx<T>* to[10] = {W2.V.y, W2.V.rs, W2.V.w, W2.V.u, W2.V.un, W2.V.v, W2.V.vt, W2.V.uh, W2.V.d, W2.V.Z};
+      for (int i = 0; i < 10; ++i) k_gather_cols<cx<T>><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, from[i], to[i]);
+      HZ_HIP(hipGetLastError());
+      std::vector<TsCol> ns(s2);
+      for (int jn = 0; jn < s2; ++jn) {
+        if (map[jn] >= 0) {
+          ns[jn] = hs[map[jn]];
+        } else {
+          ns[jn] = TsCol{};
+          ns[jn].done = 1;
+        }
+      }
+      std::vector<int> ncols;
+      for (int j : keep) ncols.push_back(cols[j]);
+      cols = ncols;
+      HZ_HIP(hipMemcpyAsync(W2.st, ns.data(), sizeof(TsCol) * s2, hipMemcpyHostToDevice, q));
+      HZ_TRY(upload_kc(W2, q));
+      HZ_TRY(autotune<T>(ctx, q, nrows, s2, AT, W2.kc, W2.V.Z, W2.V.vt, &W2.vin));
+      W = W2;
+      std::unique_ptr<Graph> G2(new Graph());
+      HZ_TRY(G2->stream(q));
+      HZ_TRY(G2->capture(pairs_body));
+      HZ_HIP(hipStreamSynchronize(q));
+      G = std::move(G2);
+      q = G->gs;
+      continue;
+    }
+    HZ_TRY(G->launch());
+  }
+  HZ_HIP(hipMemcpyAsync(hs, W.st, sizeof(TsCol) * W.s, hipMemcpyDeviceToHost, q));
+  HZ_HIP(hipStreamSynchronize(q));
+  {
+    const int nreal = int(cols.size());
+    std::vector<int> h2(2 * nreal);
+    for (int j = 0; j < nreal; ++j) {
+      h2[j] = j;
+      h2[nreal + j] = cols[j];
+    }
+    if (nreal > 0) {
+      HZ_HIP(hipMemcpyAsync(mapb->p, h2.data(), sizeof(int) * h2.size(), hipMemcpyHostToDevice, q));
+      k_out_cols<<<ceil_div(n * nreal, kBlock), kBlock, 0, q>>>(n, W.s, nf, nreal, mapb->as<int>(),
+                                                                 mapb->as<int>() + nreal, W.X, Pio);
+      HZ_HIP(hipGetLastError());
+      HZ_HIP(hipStreamSynchronize(q));
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int j = 0; j < nreal; ++j) record(j, secs);
+  }
+  for (int f = 0; f < nf; ++f) {
+    worst = std::max(worst, res[f].status);
+    if (infos) infos[f] = res[f];
+  }
+  return worst;
+}
+
 }  // namespace
 
 int sweep_solve(hz_ctx ctx, int nfreq, const double* freqs, const z_t* F, z_t* P, const hz_solve_opts& o,
@@ -2128,6 +2695,9 @@ int sweep_solve(hz_ctx ctx, int nfreq, const double* freqs, const z_t* F, z_t* P
   if (o.method == HZ_BICGSTABL)
     return mixed ? run_sweep_bicgstabl<float>(ctx, D, nfreq, freqs, F, P, o, infos)
                  : run_sweep_bicgstabl<double>(ctx, D, nfreq, freqs, F, P, o, infos);
+  if (o.method == HZ_TFQMR)
+    return mixed ? run_sweep_tfqmr<float>(ctx, D, nfreq, freqs, F, P, o, infos)
+                 : run_sweep_tfqmr<double>(ctx, D, nfreq, freqs, F, P, o, infos);
   return mixed ? run_sweep_gmres<float>(ctx, D, nfreq, freqs, F, P, o, infos)
                : run_sweep_gmres<double>(ctx, D, nfreq, freqs, F, P, o, infos);
 }

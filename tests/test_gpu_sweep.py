@@ -32,7 +32,9 @@ def _t(x):
                                                     (16, "fp64", "gmres"), (64, "mixed", "gmres"),
                                                     (64, "fp64", "bicgstab"), (5, "fp64", "bicgstab"),
                                                     (64, "fp64", "bicgstabl"), (7, "mixed", "bicgstabl"),
-                                                    (64, "mixed", "bicgstabl"), (2, "fp64", "bicgstabl")])
+                                                    (64, "mixed", "bicgstabl"), (2, "fp64", "bicgstabl"),
+                                                    (64, "fp64", "tfqmr"), (9, "mixed", "tfqmr"),
+                                                    (1, "fp64", "tfqmr")])
 def test_sweep_columns_match_oracle_direct(P, nfreq, precision, method):
     say("sweep parity", nfreq, precision, method)
     wl = W.workload(2, elems=(20, 12, 10))
