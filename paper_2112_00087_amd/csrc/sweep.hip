@@ -13,7 +13,9 @@
 // correction is added in FP64.  The cycle's kernel sequence is captured once
 // in a HIP graph and replayed.  The product's thread layout (columns per lane,
 // block size) is chosen by timing the candidates on first use.
+#include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdlib>
 #include <fstream>
 #include <sstream>
@@ -25,6 +27,12 @@ namespace {
 
 constexpr int NV = 8;   // basis vectors per multi-dot chunk
 
+// Rows of the sweep's operator are stored in a spatial brick order (section
+// "row-wise operator data"); every block of kHaloRows consecutive rows has
+// the list of columns its rows reference (its halo), and every entry the
+// position of its column in that list.
+constexpr int kHaloRows = 512;
+
 template <typename R>
 struct RowOp {
   const int* rowptr;
@@ -35,6 +43,11 @@ struct RowOp {
   const int* bptr;  // boundary entries of each row
   const int* bcol;
   const cx<R>* B;   // sum_w beta_w B0_w
+  const int* hptr = nullptr;       // [nblk + 1] halo of each block of kHaloRows rows
+  const int* hidx = nullptr;       // halo columns
+  const int16_t* lidx = nullptr;   // per entry: position of its column in the block's halo
+  const int16_t* blidx = nullptr;  // per boundary entry: the same
+  int hblocks = 0, hmax = 0;
 };
 
 struct SwCol {
@@ -138,24 +151,93 @@ __global__ void __launch_bounds__(512) k_spmm(int64_t nrows, int s, RowOp<T> A, 
   }
 }
 
+// The same product (no residual form) with the gathered rows staged in LDS:
+// block b computes rows [512 b, 512 b + 512); for each group of CG columns
+// it first copies its halo's CG columns of Z into LDS (consecutive threads
+// take consecutive columns of a halo row, so the copy is coalesced), then
+// every thread forms its row's CG outputs from LDS.  The gathers of a block
+// thus read each distinct row of Z once per column group instead of once per
+// nonzero.
+template <typename T, int CG>
+__global__ void __launch_bounds__(kHaloRows) k_spmm_lds(int64_t nrows, int s, RowOp<T> A,
+                                                        const double* __restrict__ kc, const cx<T>* __restrict__ Z,
+                                                        cx<T>* __restrict__ Y) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* xs = reinterpret_cast<cx<T>*>(smem_raw);
+  const int b = blockIdx.x;
+  const int h0 = A.hptr[b], hn = A.hptr[b + 1] - h0;
+  const int64_t row = int64_t(b) * kHaloRows + threadIdx.x;
+  const bool live = row < nrows;
+  int q0 = 0, q1 = 0, b0 = 0, b1 = 0;
+  if (live) {
+    q0 = A.rowptr[row];
+    q1 = A.rowptr[row + 1];
+    b0 = A.bptr[row];
+    b1 = A.bptr[row + 1];
+  }
+  for (int cg = 0; cg < s; cg += CG) {
+    for (int i = threadIdx.x; i < hn * CG; i += kHaloRows) {
+      const int64_t node = A.hidx[h0 + i / CG];
+      xs[i] = Z[node * s + cg + i % CG];
+    }
+    __syncthreads();
+    if (live) {
+      cx<T> aK[CG], aM[CG], aE[CG];
+#pragma unroll
+      for (int c = 0; c < CG; ++c) aK[c] = aM[c] = aE[c] = cx<T>{T(0), T(0)};
+      for (int q = q0; q < q1; ++q) {
+        const int li = A.lidx[q] * CG;
+        const T kv = A.K[q], mv = A.M[q];
+        const T ev = A.E ? A.E[q] : T(0);
+#pragma unroll
+        for (int c = 0; c < CG; ++c) {
+          const cx<T> z = xs[li + c];
+          aK[c].re = fma(kv, z.re, aK[c].re);
+          aK[c].im = fma(kv, z.im, aK[c].im);
+          aM[c].re = fma(mv, z.re, aM[c].re);
+          aM[c].im = fma(mv, z.im, aM[c].im);
+          aE[c].re = fma(ev, z.re, aE[c].re);
+          aE[c].im = fma(ev, z.im, aE[c].im);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CG; ++c) {
+        const int col = cg + c;
+        const T k = T(kc[2 * col]), k2 = T(kc[2 * col + 1]);
+        cx<T> y = {aK[c].re - k2 * aM[c].re - k2 * aE[c].im, aK[c].im - k2 * aM[c].im + k2 * aE[c].re};
+        cx<T> bz = {T(0), T(0)};
+        for (int q = b0; q < b1; ++q) cfma(bz, A.B[q], xs[A.blidx[q] * CG + c]);
+        y.re -= k * bz.im;
+        y.im += k * bz.re;
+        Y[row * s + col] = y;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- vector kernels over [nrows][s]
-__global__ void k_in(int64_t n, int64_t nrows, int s, int nf, const z_t* __restrict__ P, const z_t* __restrict__ F,
-                     z_t* __restrict__ X, z_t* __restrict__ Fs) {
+// X[row, c] = P[perm[row], c] (internal row order <- caller's node order)
+__global__ void k_in(int64_t n, int64_t nrows, int s, int nf, const int* __restrict__ perm,
+                     const z_t* __restrict__ P, const z_t* __restrict__ F, z_t* __restrict__ X,
+                     z_t* __restrict__ Fs) {
   int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (e >= nrows * s) return;
   int64_t row = e / s;
   int c = int(e % s);
   bool ok = row < n && c < nf;
-  X[e] = ok ? P[row * nf + c] : z_t{0.0, 0.0};
-  Fs[e] = ok ? F[row * nf + c] : z_t{0.0, 0.0};
+  const int64_t node = ok ? perm[row] : 0;
+  X[e] = ok ? P[node * nf + c] : z_t{0.0, 0.0};
+  Fs[e] = ok ? F[node * nf + c] : z_t{0.0, 0.0};
 }
 
-__global__ void k_out(int64_t n, int s, int nf, const z_t* __restrict__ X, z_t* __restrict__ P) {
+__global__ void k_out(int64_t n, int s, int nf, const int* __restrict__ perm, const z_t* __restrict__ X,
+                      z_t* __restrict__ P) {
   int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (e >= n * nf) return;
   int64_t row = e / nf;
   int c = int(e % nf);
-  P[e] = X[row * s + c];
+  P[int64_t(perm[row]) * nf + c] = X[row * s + c];
 }
 
 // dinv[row, c] = 1 / A(k_c)_{row,row}
@@ -764,24 +846,44 @@ __global__ void k_gather_cols(int64_t nrows, int s_old, int s_new, const int* __
   out[e] = c >= 0 ? in[row * s_old + c] : V{0, 0};
 }
 
-// P[row, orig] = X[row, c] for the listed (c, orig) pairs
-__global__ void k_out_cols(int64_t n, int s, int nf, int ncols, const int* __restrict__ cols,
-                           const int* __restrict__ orig, const z_t* __restrict__ X, z_t* __restrict__ P) {
+// P[perm[row], orig] = X[row, c] for the listed (c, orig) pairs
+__global__ void k_out_cols(int64_t n, int s, int nf, int ncols, const int* __restrict__ perm,
+                           const int* __restrict__ cols, const int* __restrict__ orig, const z_t* __restrict__ X,
+                           z_t* __restrict__ P) {
   int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (e >= n * ncols) return;
   int64_t row = e / ncols;
   int j = int(e % ncols);
-  P[row * nf + orig[j]] = X[row * s + cols[j]];
+  P[int64_t(perm[row]) * nf + orig[j]] = X[row * s + cols[j]];
 }
 
 // ---------------------------------------------------------------- dispatch of product variants
 struct Variant {
   int cpl = 1, bs = 256, xcd = 0;
+  int lds = 0;          // > 0: LDS-staged product with lds columns per group
 };
+
+// LDS bytes the staged product needs for a column group of cg columns.
+template <typename T>
+size_t lds_bytes(const RowOp<T>& A, int cg) { return size_t(A.hmax) * cg * sizeof(cx<T>); }
+constexpr size_t kLdsLimit = 64 * 1024;
 
 template <typename T, bool RESID>
 int launch_spmm(hipStream_t stream, const Variant& v, int64_t nrows, int s, const RowOp<T>& A, const double* st,
                 const cx<T>* Z, const cx<T>* F, cx<T>* Y, double* part, int* nblk_out) {
+  if (!RESID && v.lds > 0) {
+    const size_t sh = lds_bytes(A, v.lds);
+    if (A.hblocks <= 0 || s % v.lds || sh > kLdsLimit) return hz_fail(HZ_ERR_INVALID, "bad staged product variant");
+#define HZ_LDS_CASE(CC)                                                                                   \
+    if (v.lds == CC) {                                                                                      \
+      k_spmm_lds<T, CC><<<A.hblocks, kHaloRows, sh, stream>>>(nrows, s, A, st, Z, Y);                       \
+      HZ_HIP(hipGetLastError());                                                                            \
+      return HZ_OK;                                                                                         \
+    }
+    HZ_LDS_CASE(1) HZ_LDS_CASE(2) HZ_LDS_CASE(4) HZ_LDS_CASE(8)
+#undef HZ_LDS_CASE
+    return hz_fail(HZ_ERR_INVALID, "no staged product for %d columns per group", v.lds);
+  }
   const int L = s / v.cpl;
   const int rpb = v.bs / L;
   const int nblk = int((nrows + rpb - 1) / rpb);
@@ -807,6 +909,9 @@ int launch_spmm(hipStream_t stream, const Variant& v, int64_t nrows, int s, cons
 struct SweepData {
   int64_t nrows = 0;
   DevBuf rowptr, col, K64, M64, E64, K32, M32, E32, bptr, bcol, B64, B32, Bdiag, dpos;
+  DevBuf perm;                      // internal row -> node
+  DevBuf hptr, hidx, lidx, blidx;   // halos of the blocks of kHaloRows rows
+  int hblocks = 0, hmax = 0;
   bool eta = false;
 };
 
@@ -817,76 +922,193 @@ int upload(DevBuf& b, const std::vector<V>& h) {
   return HZ_OK;
 }
 
+// Spatial brick order of the nodes: bricks of about 8 x 8 x 8 node spacings
+// (brick index from the coordinates, z slowest), nodes inside a brick by
+// (z, y, x).  Consecutive rows then cover compact boxes of space, so a block
+// of 512 rows references about 2 x 512 distinct columns instead of the
+// ~27 x 512 of a row range in the natural order, which is what lets the
+// multi-vector product stage its gathered rows in LDS.
+std::vector<int> brick_order(const HostAsm& a) {
+  const int64_t n = a.n;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::min(lo[d], a.xyz[3 * i + d]);
+      hi[d] = std::max(hi[d], a.xyz[3 * i + d]);
+    }
+  double ext[3], vol = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = std::max(hi[d] - lo[d], 1e-300);
+    vol *= ext[d];
+  }
+  const double h = std::cbrt(vol / double(std::max<int64_t>(n, 1)));
+  int64_t nb[3];
+  double edge[3];
+  for (int d = 0; d < 3; ++d) {
+    nb[d] = std::max<int64_t>(1, int64_t(std::ceil(ext[d] / (8.0 * h) - 1e-9)));
+    edge[d] = ext[d] / double(nb[d]) * (1.0 + 1e-12);
+  }
+  std::vector<int64_t> key(n);
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t b[3];
+    for (int d = 0; d < 3; ++d)
+      b[d] = std::min<int64_t>(nb[d] - 1, int64_t((a.xyz[3 * i + d] - lo[d]) / edge[d]));
+    key[i] = (b[2] * nb[1] + b[1]) * nb[0] + b[0];
+  }
+  std::vector<int> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = int(i);
+  std::sort(order.begin(), order.end(), [&](int x, int y) {
+    if (key[x] != key[y]) return key[x] < key[y];
+    for (int d = 2; d >= 0; --d)
+      if (a.xyz[3 * x + d] != a.xyz[3 * y + d]) return a.xyz[3 * x + d] < a.xyz[3 * y + d];
+    return x < y;
+  });
+  return order;
+}
+
 int build_sweep_data(hz_ctx ctx, SweepData* D) {
   const HostAsm& a = ctx->h;
-  const int64_t n = a.n, nrows = ctx->sell.n_rows, nnz = int64_t(a.col.size());
+  const int64_t n = a.n, nrows = ctx->sell.n_rows;
   D->nrows = nrows;
-  std::vector<int> rowptr(nrows + 1), col(a.col.begin(), a.col.end());
-  for (int64_t i = 0; i <= nrows; ++i) rowptr[i] = int(a.rowptr[std::min(i, n)]);
+  const std::vector<int> perm = brick_order(a);
+  std::vector<int> iperm(n);
+  for (int64_t i = 0; i < n; ++i) iperm[perm[i]] = int(i);
+  // boundary entries of each node: (column, sum_w beta_w B0_w)
+  std::vector<std::vector<std::pair<int, z_t>>> bnd(n);
+  {
+    int64_t row = 0;
+    std::vector<int64_t> order(a.bpos.size());
+    for (size_t e = 0; e < order.size(); ++e) order[e] = int64_t(e);
+    std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return a.bpos[x] < a.bpos[y]; });
+    for (int64_t t = 0; t < int64_t(order.size()); ++t) {
+      const int64_t e = order[t], pos = a.bpos[e];
+      while (a.rowptr[row + 1] <= pos) ++row;
+      double re = 0.0, im = 0.0;
+      for (int w = 0; w < 6; ++w) {
+        re += ctx->beta[w].real() * a.bmass[e * a.ntags + w];
+        im += ctx->beta[w].imag() * a.bmass[e * a.ntags + w];
+      }
+      bnd[row].push_back({a.col[pos], z_t{re, im}});
+    }
+  }
+  // the operator in the internal order
+  const int64_t nnz = int64_t(a.col.size());
+  std::vector<int> rowptr(nrows + 1, 0), col(nnz), dpos(n), bptr(nrows + 1, 0), bcol;
+  std::vector<double> K(nnz), M(nnz), E(D->eta ? nnz : 0);
+  D->eta = ctx->have_eta && !a.Meta.empty();
+  if (D->eta) E.resize(nnz);
+  std::vector<z_t> B64, Bd(n, z_t{0.0, 0.0});
+  std::vector<c_t> B32;
+  int64_t q = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int node = perm[i];
+    for (int64_t p = a.rowptr[node]; p < a.rowptr[node + 1]; ++p, ++q) {
+      col[q] = iperm[a.col[p]];
+      K[q] = a.K[p];
+      M[q] = a.M[p];
+      if (D->eta) E[q] = a.Meta[p];
+      if (a.col[p] == node) dpos[i] = int(q);
+    }
+    rowptr[i + 1] = int(q);
+    for (const auto& b : bnd[node]) {
+      bcol.push_back(iperm[b.first]);
+      B64.push_back(b.second);
+      B32.push_back(c_t{float(b.second.re), float(b.second.im)});
+      if (b.first == node) Bd[i] = b.second;
+    }
+    bptr[i + 1] = int(bcol.size());
+  }
+  for (int64_t i = n; i < nrows; ++i) {
+    rowptr[i + 1] = rowptr[i];
+    bptr[i + 1] = bptr[i];
+  }
+  HZ_TRY(upload(D->perm, perm));
   HZ_TRY(upload(D->rowptr, rowptr));
   HZ_TRY(upload(D->col, col));
-  HZ_TRY(upload(D->K64, a.K));
-  HZ_TRY(upload(D->M64, a.M));
+  HZ_TRY(upload(D->K64, K));
+  HZ_TRY(upload(D->M64, M));
   std::vector<float> f(nnz);
-  for (int64_t q = 0; q < nnz; ++q) f[q] = float(a.K[q]);
+  for (int64_t p = 0; p < nnz; ++p) f[p] = float(K[p]);
   HZ_TRY(upload(D->K32, f));
-  for (int64_t q = 0; q < nnz; ++q) f[q] = float(a.M[q]);
+  for (int64_t p = 0; p < nnz; ++p) f[p] = float(M[p]);
   HZ_TRY(upload(D->M32, f));
-  D->eta = ctx->have_eta && !a.Meta.empty();
   if (D->eta) {
-    HZ_TRY(upload(D->E64, a.Meta));
-    for (int64_t q = 0; q < nnz; ++q) f[q] = float(a.Meta[q]);
+    HZ_TRY(upload(D->E64, E));
+    for (int64_t p = 0; p < nnz; ++p) f[p] = float(E[p]);
     HZ_TRY(upload(D->E32, f));
   }
-  // boundary entries grouped by row (CSR order)
-  std::vector<int64_t> order(a.bpos.size());
-  for (size_t e = 0; e < order.size(); ++e) order[e] = int64_t(e);
-  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return a.bpos[x] < a.bpos[y]; });
-  std::vector<int> bptr(nrows + 1, 0), bcol;
-  std::vector<z_t> B64;
-  std::vector<c_t> B32;
-  std::vector<z_t> Bd(n, z_t{0.0, 0.0});
-  int64_t row = 0;
-  for (int64_t t = 0; t < int64_t(order.size()); ++t) {
-    int64_t e = order[t], pos = a.bpos[e];
-    while (a.rowptr[row + 1] <= pos) ++row;
-    double re = 0.0, im = 0.0;
-    for (int w = 0; w < 6; ++w) {
-      re += ctx->beta[w].real() * a.bmass[e * a.ntags + w];
-      im += ctx->beta[w].imag() * a.bmass[e * a.ntags + w];
-    }
-    bptr[row + 1] += 1;
-    bcol.push_back(a.col[pos]);
-    B64.push_back(z_t{re, im});
-    B32.push_back(c_t{float(re), float(im)});
-    if (a.col[pos] == row) Bd[row] = z_t{re, im};
-  }
-  for (int64_t i = 0; i < nrows; ++i) bptr[i + 1] += bptr[i];
   HZ_TRY(upload(D->bptr, bptr));
   HZ_TRY(upload(D->bcol, bcol));
   HZ_TRY(upload(D->B64, B64));
   HZ_TRY(upload(D->B32, B32));
   HZ_TRY(upload(D->Bdiag, Bd));
-  std::vector<int> dpos(n);
-  for (int64_t i = 0; i < n; ++i) dpos[i] = int(a.diag[i]);
   HZ_TRY(upload(D->dpos, dpos));
+  // halos of the blocks of kHaloRows rows
+  const int64_t nblk = (nrows + kHaloRows - 1) / kHaloRows;
+  std::vector<int> hptr(nblk + 1, 0), hidx, cols;
+  std::vector<int16_t> lidx(nnz, 0), blidx(bcol.size(), 0);
+  int hmax = 0;
+  bool ok = true;
+  for (int64_t b = 0; b < nblk; ++b) {
+    const int64_t r0 = b * kHaloRows, r1 = std::min<int64_t>(n, r0 + kHaloRows);
+    cols.clear();
+    for (int64_t i = r0; i < r1; ++i) {
+      for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) cols.push_back(col[p]);
+      for (int p = bptr[i]; p < bptr[i + 1]; ++p) cols.push_back(bcol[p]);
+    }
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    if (cols.size() > 32767) ok = false;
+    hmax = std::max<int>(hmax, int(cols.size()));
+    for (int64_t i = r0; i < r1 && ok; ++i) {
+      for (int p = rowptr[i]; p < rowptr[i + 1]; ++p)
+        lidx[p] = int16_t(std::lower_bound(cols.begin(), cols.end(), col[p]) - cols.begin());
+      for (int p = bptr[i]; p < bptr[i + 1]; ++p)
+        blidx[p] = int16_t(std::lower_bound(cols.begin(), cols.end(), bcol[p]) - cols.begin());
+    }
+    hidx.insert(hidx.end(), cols.begin(), cols.end());
+    hptr[b + 1] = int(hidx.size());
+  }
+  D->hblocks = ok ? int(nblk) : 0;
+  D->hmax = ok ? hmax : 0;
+  if (ok) {
+    HZ_TRY(upload(D->hptr, hptr));
+    HZ_TRY(upload(D->hidx, hidx));
+    HZ_TRY(upload(D->lidx, lidx));
+    HZ_TRY(upload(D->blidx, blidx));
+  }
   return HZ_OK;
 }
 
 template <typename T> RowOp<T> row_op(const SweepData& D);
+template <typename T>
+void add_halo(const SweepData& D, RowOp<T>* A) {
+  A->hblocks = D.hblocks;
+  A->hmax = D.hmax;
+  if (D.hblocks) {
+    A->hptr = D.hptr.as<int>();
+    A->hidx = D.hidx.as<int>();
+    A->lidx = D.lidx.as<int16_t>();
+    A->blidx = D.blidx.as<int16_t>();
+  }
+}
 template <> RowOp<double> row_op<double>(const SweepData& D) {
-  return {D.rowptr.as<int>(), D.col.as<int>(), D.K64.as<double>(), D.M64.as<double>(),
-          D.eta ? D.E64.as<double>() : nullptr, D.bptr.as<int>(), D.bcol.as<int>(), D.B64.as<z_t>()};
+  RowOp<double> A = {D.rowptr.as<int>(), D.col.as<int>(), D.K64.as<double>(), D.M64.as<double>(),
+                     D.eta ? D.E64.as<double>() : nullptr, D.bptr.as<int>(), D.bcol.as<int>(), D.B64.as<z_t>()};
+  add_halo(D, &A);
+  return A;
 }
 template <> RowOp<float> row_op<float>(const SweepData& D) {
-  return {D.rowptr.as<int>(), D.col.as<int>(), D.K32.as<float>(), D.M32.as<float>(),
-          D.eta ? D.E32.as<float>() : nullptr, D.bptr.as<int>(), D.bcol.as<int>(), D.B32.as<c_t>()};
+  RowOp<float> A = {D.rowptr.as<int>(), D.col.as<int>(), D.K32.as<float>(), D.M32.as<float>(),
+                    D.eta ? D.E32.as<float>() : nullptr, D.bptr.as<int>(), D.bcol.as<int>(), D.B32.as<c_t>()};
+  add_halo(D, &A);
+  return A;
 }
 
 // ---------------------------------------------------------------- autotuner
 std::string tune_key(int64_t n, int64_t nnz, int s, int bytes) {
   std::ostringstream o;
-  o << "spmm2 n=" << n << " nnz=" << nnz << " s=" << s << " t=" << bytes;
+  o << "spmm3 n=" << n << " nnz=" << nnz << " s=" << s << " t=" << bytes;
   return o.str();
 }
 
@@ -914,21 +1136,28 @@ int autotune(hz_ctx ctx, hipStream_t stream, int64_t nrows, int s, const RowOp<T
              const cx<T>* Z, cx<T>* Y, Variant* best) {
   const std::string key = tune_key(ctx->h.n, int64_t(ctx->h.col.size()), s, int(sizeof(T)));
   if (ctx->tuned.empty()) load_tune_cache(ctx);
+  const char* force = std::getenv("HZ_SPMM_STAGED");   // "1": staged variants only, "0": none
   auto it = ctx->tuned.find(key);
-  if (it != ctx->tuned.end()) {
-    best->xcd = it->second / 10000;
+  if (it != ctx->tuned.end() && !force) {
+    best->lds = it->second / 100000;
+    best->xcd = it->second / 10000 % 10;
     best->cpl = it->second / 1000 % 10;
     best->bs = it->second % 1000;
     return HZ_OK;
   }
   std::vector<Variant> cands;
-  for (int xcd : {0, 1})
-    for (int cpl : {1, 2})
-      for (int bs : {128, 256, 512}) {
-        if (cpl > s) continue;
-        if (bs < s / cpl) continue;
-        cands.push_back(Variant{cpl, bs, xcd});
-      }
+  if (!(force && force[0] == '1'))
+    for (int xcd : {0, 1})
+      for (int cpl : {1, 2})
+        for (int bs : {128, 256, 512}) {
+          if (cpl > s) continue;
+          if (bs < s / cpl) continue;
+          cands.push_back(Variant{cpl, bs, xcd, 0});
+        }
+  if (!(force && force[0] == '0'))
+    for (int cg : {1, 2, 4, 8})
+      if (A.hblocks > 0 && cg <= s && lds_bytes(A, cg) <= kLdsLimit) cands.push_back(Variant{1, kHaloRows, 0, cg});
+  if (cands.empty()) cands.push_back(Variant{});
   hipEvent_t e0, e1;
   HZ_HIP(hipEventCreate(&e0));
   HZ_HIP(hipEventCreate(&e1));
@@ -949,7 +1178,7 @@ int autotune(hz_ctx ctx, hipStream_t stream, int64_t nrows, int s, const RowOp<T
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  int code = best->xcd * 10000 + best->cpl * 1000 + best->bs;
+  int code = best->lds * 100000 + best->xcd * 10000 + best->cpl * 1000 + best->bs;
   ctx->tuned[key] = code;
   save_tune_entry(key, code);
   return HZ_OK;
@@ -960,6 +1189,7 @@ template <typename T>
 struct Sweep {
   int s = 1, nf = 0, Gr = 1, nblk_res = 1;
   int64_t n = 0, nrows = 0, total = 0;
+  const int* perm = nullptr;      // internal row -> node
   z_t *X = nullptr, *Fs = nullptr, *R = nullptr, *d64 = nullptr;
   cx<T>* dT = nullptr;
   double *kc = nullptr, *part = nullptr, *cn = nullptr;
@@ -978,6 +1208,7 @@ int sweep_setup(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const z_t
   W->nf = nf;
   W->n = ctx->h.n;
   W->nrows = D.nrows;
+  W->perm = D.perm.as<int>();
   W->total = D.nrows * s;
   const int64_t total = W->total;
   auto buf = [&](const char* nm, size_t bytes) -> void* {
@@ -1004,7 +1235,7 @@ int sweep_setup(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const z_t
     kc[2 * c + 1] = k * k;
   }
   HZ_HIP(hipMemcpyAsync(W->kc, kc.data(), sizeof(double) * 2 * s, hipMemcpyHostToDevice, cs));
-  k_in<<<ceil_div(total, kBlock), kBlock, 0, cs>>>(W->n, W->nrows, s, nf, Pio, Fin, W->X, W->Fs);
+  k_in<<<ceil_div(total, kBlock), kBlock, 0, cs>>>(W->n, W->nrows, s, nf, D.perm.as<int>(), Pio, Fin, W->X, W->Fs);
   k_diag<T><<<ceil_div(total, kBlock), kBlock, 0, cs>>>(W->n, W->nrows, s, D.dpos.as<int>(), D.K64.as<double>(),
                                                        D.M64.as<double>(), D.eta ? D.E64.as<double>() : nullptr,
                                                        D.Bdiag.as<z_t>(), W->kc, W->d64, W->dT);
@@ -1064,7 +1295,7 @@ int sweep_report(Sweep<T>& W, hipStream_t q, z_t* Pio, const std::vector<double>
   int nb = 0;
   HZ_TRY((launch_spmm<double, true>(q, W.vres, W.nrows, W.s, W.A64, W.kc, W.X, W.Fs, W.R, W.part, &nb)));
   k_colsum<<<W.s, kBlock, 0, q>>>(nb, W.s, W.part, W.cn);
-  k_out<<<ceil_div(W.n * W.nf, kBlock), kBlock, 0, q>>>(W.n, W.s, W.nf, W.X, Pio);
+  k_out<<<ceil_div(W.n * W.nf, kBlock), kBlock, 0, q>>>(W.n, W.s, W.nf, W.perm, W.X, Pio);
   HZ_HIP(hipGetLastError());
   std::vector<double> rr(W.s);
   HZ_HIP(hipMemcpyAsync(rr.data(), W.cn, sizeof(double) * W.s, hipMemcpyDeviceToHost, q));
@@ -1259,7 +1490,7 @@ int run_sweep_bicgstab(hz_ctx ctx, SweepData& D, int nf, const double* freqs, co
   };
   // set-up at the full width
   HZ_TRY(upload_kc(W, cs));
-  k_in<<<ceil_div(W.total, kBlock), kBlock, 0, cs>>>(n, nrows, s, nf, Pio, Fin, W.X, W.Fs);
+  k_in<<<ceil_div(W.total, kBlock), kBlock, 0, cs>>>(n, nrows, s, nf, D.perm.as<int>(), Pio, Fin, W.X, W.Fs);
   k_diag<T><<<ceil_div(W.total, kBlock), kBlock, 0, cs>>>(n, nrows, s, D.dpos.as<int>(), D.K64.as<double>(),
                                                          D.M64.as<double>(), D.eta ? D.E64.as<double>() : nullptr,
                                                          D.Bdiag.as<z_t>(), W.kc, W.d64, W.dT);
@@ -1374,7 +1605,7 @@ int run_sweep_bicgstab(hz_ctx ctx, SweepData& D, int nf, const double* freqs, co
         h2.insert(h2.end(), gone_f.begin(), gone_f.end());
         HZ_HIP(hipMemcpyAsync(mapb->p, h2.data(), sizeof(int) * h2.size(), hipMemcpyHostToDevice, q));
         const int ng = int(gone_j.size());
-        k_out_cols<<<ceil_div(n * ng, kBlock), kBlock, 0, q>>>(n, W.s, nf, ng, mapb->as<int>(),
+        k_out_cols<<<ceil_div(n * ng, kBlock), kBlock, 0, q>>>(n, W.s, nf, ng, D.perm.as<int>(), mapb->as<int>(),
                                                                 mapb->as<int>() + ng, W.X, Pio);
         HZ_HIP(hipGetLastError());
         HZ_HIP(hipStreamSynchronize(q));
@@ -1435,7 +1666,7 @@ int run_sweep_bicgstab(hz_ctx ctx, SweepData& D, int nf, const double* freqs, co
     }
     if (nreal > 0) {
       HZ_HIP(hipMemcpyAsync(mapb->p, h2.data(), sizeof(int) * h2.size(), hipMemcpyHostToDevice, q));
-      k_out_cols<<<ceil_div(n * nreal, kBlock), kBlock, 0, q>>>(n, W.s, nf, nreal, mapb->as<int>(),
+      k_out_cols<<<ceil_div(n * nreal, kBlock), kBlock, 0, q>>>(n, W.s, nf, nreal, D.perm.as<int>(), mapb->as<int>(),
                                                                  mapb->as<int>() + nreal, W.X, Pio);
       HZ_HIP(hipGetLastError());
       HZ_HIP(hipStreamSynchronize(q));
@@ -1907,7 +2138,7 @@ int run_sweep_bicgstabl(hz_ctx ctx, SweepData& D, int nf, const double* freqs, c
   {
     // set-up at the full width; the FP64 diagonal goes through R as scratch
     HZ_TRY(upload_kc(W, cs));
-    k_in<<<ceil_div(W.total, kBlock), kBlock, 0, cs>>>(n, nrows, s, nf, Pio, Fin, W.X, W.Fs);
+    k_in<<<ceil_div(W.total, kBlock), kBlock, 0, cs>>>(n, nrows, s, nf, D.perm.as<int>(), Pio, Fin, W.X, W.Fs);
     k_diag<T><<<ceil_div(W.total, kBlock), kBlock, 0, cs>>>(n, nrows, s, D.dpos.as<int>(), D.K64.as<double>(),
                                                            D.M64.as<double>(), D.eta ? D.E64.as<double>() : nullptr,
                                                            D.Bdiag.as<z_t>(), W.kc, W.R, W.dT);
@@ -2030,7 +2261,7 @@ int run_sweep_bicgstabl(hz_ctx ctx, SweepData& D, int nf, const double* freqs, c
         h2.insert(h2.end(), gone_f.begin(), gone_f.end());
         HZ_HIP(hipMemcpyAsync(mapb->p, h2.data(), sizeof(int) * h2.size(), hipMemcpyHostToDevice, q));
         const int ng = int(gone_j.size());
-        k_out_cols<<<ceil_div(n * ng, kBlock), kBlock, 0, q>>>(n, W.s, nf, ng, mapb->as<int>(),
+        k_out_cols<<<ceil_div(n * ng, kBlock), kBlock, 0, q>>>(n, W.s, nf, ng, D.perm.as<int>(), mapb->as<int>(),
                                                                 mapb->as<int>() + ng, W.X, Pio);
         HZ_HIP(hipGetLastError());
         HZ_HIP(hipStreamSynchronize(q));
@@ -2093,7 +2324,7 @@ int run_sweep_bicgstabl(hz_ctx ctx, SweepData& D, int nf, const double* freqs, c
     }
     if (nreal > 0) {
       HZ_HIP(hipMemcpyAsync(mapb->p, h2.data(), sizeof(int) * h2.size(), hipMemcpyHostToDevice, q));
-      k_out_cols<<<ceil_div(n * nreal, kBlock), kBlock, 0, q>>>(n, W.s, nf, nreal, mapb->as<int>(),
+      k_out_cols<<<ceil_div(n * nreal, kBlock), kBlock, 0, q>>>(n, W.s, nf, nreal, D.perm.as<int>(), mapb->as<int>(),
                                                                  mapb->as<int>() + nreal, W.X, Pio);
       HZ_HIP(hipGetLastError());
       HZ_HIP(hipStreamSynchronize(q));
@@ -2494,7 +2725,7 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
     return HZ_OK;
   };
   HZ_TRY(upload_kc(W, cs));
-  k_in<<<ceil_div(W.total, kBlock), kBlock, 0, cs>>>(n, nrows, s, nf, Pio, Fin, W.X, W.Fs);
+  k_in<<<ceil_div(W.total, kBlock), kBlock, 0, cs>>>(n, nrows, s, nf, D.perm.as<int>(), Pio, Fin, W.X, W.Fs);
   k_diag<T><<<ceil_div(W.total, kBlock), kBlock, 0, cs>>>(n, nrows, s, D.dpos.as<int>(), D.K64.as<double>(),
                                                          D.M64.as<double>(), D.eta ? D.E64.as<double>() : nullptr,
                                                          D.Bdiag.as<z_t>(), W.kc, W.R, W.dT);
@@ -2602,7 +2833,7 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
         h2.insert(h2.end(), gone_f.begin(), gone_f.end());
         HZ_HIP(hipMemcpyAsync(mapb->p, h2.data(), sizeof(int) * h2.size(), hipMemcpyHostToDevice, q));
         const int ng = int(gone_j.size());
-        k_out_cols<<<ceil_div(n * ng, kBlock), kBlock, 0, q>>>(n, W.s, nf, ng, mapb->as<int>(),
+        k_out_cols<<<ceil_div(n * ng, kBlock), kBlock, 0, q>>>(n, W.s, nf, ng, D.perm.as<int>(), mapb->as<int>(),
                                                                 mapb->as<int>() + ng, W.X, Pio);
         HZ_HIP(hipGetLastError());
         HZ_HIP(hipStreamSynchronize(q));
@@ -2660,7 +2891,7 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
     }
     if (nreal > 0) {
       HZ_HIP(hipMemcpyAsync(mapb->p, h2.data(), sizeof(int) * h2.size(), hipMemcpyHostToDevice, q));
-      k_out_cols<<<ceil_div(n * nreal, kBlock), kBlock, 0, q>>>(n, W.s, nf, nreal, mapb->as<int>(),
+      k_out_cols<<<ceil_div(n * nreal, kBlock), kBlock, 0, q>>>(n, W.s, nf, nreal, D.perm.as<int>(), mapb->as<int>(),
                                                                  mapb->as<int>() + nreal, W.X, Pio);
       HZ_HIP(hipGetLastError());
       HZ_HIP(hipStreamSynchronize(q));

@@ -36,6 +36,19 @@ def _t(x):
                                                     (64, "fp64", "tfqmr"), (9, "mixed", "tfqmr"),
                                                     (1, "fp64", "tfqmr")])
 def test_sweep_columns_match_oracle_direct(P, nfreq, precision, method):
+    _sweep_parity(P, nfreq, precision, method)
+
+
+@pytest.mark.parametrize("nfreq,precision,method", [(64, "fp64", "tfqmr"), (16, "mixed", "bicgstabl"),
+                                                    (5, "fp64", "gmres"), (1, "fp64", "bicgstab")])
+def test_sweep_staged_product(P, nfreq, precision, method, monkeypatch):
+    """The same parity with the LDS-staged multi-vector product forced (the
+    autotuner otherwise picks whichever variant is fastest)."""
+    monkeypatch.setenv("HZ_SPMM_STAGED", "1")
+    _sweep_parity(P, nfreq, precision, method)
+
+
+def _sweep_parity(P, nfreq, precision, method):
     say("sweep parity", nfreq, precision, method)
     wl = W.workload(2, elems=(20, 12, 10))
     mesh = wl["mesh"]
