@@ -866,23 +866,46 @@ struct Variant {
 // LDS bytes the staged product needs for a column group of cg columns.
 template <typename T>
 size_t lds_bytes(const RowOp<T>& A, int cg) { return size_t(A.hmax) * cg * sizeof(cx<T>); }
-constexpr size_t kLdsLimit = 64 * 1024;
+
+// LDS a workgroup may allocate on the current device (160 KB on gfx950).
+size_t lds_limit() {
+  static size_t lim = 0;
+  if (!lim) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+      v = 64 * 1024;
+    lim = size_t(v);
+  }
+  return lim;
+}
+
+template <typename T, int CG>
+int launch_lds(hipStream_t stream, int64_t nrows, int s, const RowOp<T>& A, const double* kc, const cx<T>* Z,
+               cx<T>* Y) {
+  const size_t sh = lds_bytes(A, CG);
+  if (sh > 64 * 1024)
+    HZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmm_lds<T, CG>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(sh)));
+  k_spmm_lds<T, CG><<<A.hblocks, kHaloRows, sh, stream>>>(nrows, s, A, kc, Z, Y);
+  HZ_HIP(hipGetLastError());
+  return HZ_OK;
+}
 
 template <typename T, bool RESID>
 int launch_spmm(hipStream_t stream, const Variant& v, int64_t nrows, int s, const RowOp<T>& A, const double* st,
                 const cx<T>* Z, const cx<T>* F, cx<T>* Y, double* part, int* nblk_out) {
   if (!RESID && v.lds > 0) {
-    const size_t sh = lds_bytes(A, v.lds);
-    if (A.hblocks <= 0 || s % v.lds || sh > kLdsLimit) return hz_fail(HZ_ERR_INVALID, "bad staged product variant");
-#define HZ_LDS_CASE(CC)                                                                                   \
-    if (v.lds == CC) {                                                                                      \
-      k_spmm_lds<T, CC><<<A.hblocks, kHaloRows, sh, stream>>>(nrows, s, A, st, Z, Y);                       \
-      HZ_HIP(hipGetLastError());                                                                            \
-      return HZ_OK;                                                                                         \
+    if (A.hblocks <= 0 || s % v.lds || lds_bytes(A, v.lds) > lds_limit())
+      return hz_fail(HZ_ERR_INVALID, "bad staged product variant");
+    switch (v.lds) {
+      case 1: return launch_lds<T, 1>(stream, nrows, s, A, st, Z, Y);
+      case 2: return launch_lds<T, 2>(stream, nrows, s, A, st, Z, Y);
+      case 4: return launch_lds<T, 4>(stream, nrows, s, A, st, Z, Y);
+      case 8: return launch_lds<T, 8>(stream, nrows, s, A, st, Z, Y);
+      case 16: return launch_lds<T, 16>(stream, nrows, s, A, st, Z, Y);
+      default: return hz_fail(HZ_ERR_INVALID, "no staged product for %d columns per group", v.lds);
     }
-    HZ_LDS_CASE(1) HZ_LDS_CASE(2) HZ_LDS_CASE(4) HZ_LDS_CASE(8)
-#undef HZ_LDS_CASE
-    return hz_fail(HZ_ERR_INVALID, "no staged product for %d columns per group", v.lds);
   }
   const int L = s / v.cpl;
   const int rpb = v.bs / L;
@@ -1155,15 +1178,19 @@ int autotune(hz_ctx ctx, hipStream_t stream, int64_t nrows, int s, const RowOp<T
           cands.push_back(Variant{cpl, bs, xcd, 0});
         }
   if (!(force && force[0] == '0'))
-    for (int cg : {1, 2, 4, 8})
-      if (A.hblocks > 0 && cg <= s && lds_bytes(A, cg) <= kLdsLimit) cands.push_back(Variant{1, kHaloRows, 0, cg});
+    for (int cg : {1, 2, 4, 8, 16})
+      if (A.hblocks > 0 && cg <= s && lds_bytes(A, cg) <= lds_limit()) cands.push_back(Variant{1, kHaloRows, 0, cg});
   if (cands.empty()) cands.push_back(Variant{});
   hipEvent_t e0, e1;
   HZ_HIP(hipEventCreate(&e0));
   HZ_HIP(hipEventCreate(&e1));
   float best_ms = 1e30f;
   for (const Variant& v : cands) {
-    HZ_TRY((launch_spmm<T, false>(stream, v, nrows, s, A, st, Z, nullptr, Y, nullptr, nullptr)));
+    // a variant the device cannot launch (e.g. more LDS than it grants) is skipped
+    if (launch_spmm<T, false>(stream, v, nrows, s, A, st, Z, nullptr, Y, nullptr, nullptr) < 0) {
+      (void)hipGetLastError();
+      continue;
+    }
     HZ_HIP(hipEventRecord(e0, stream));
     for (int r = 0; r < 5; ++r)
       HZ_TRY((launch_spmm<T, false>(stream, v, nrows, s, A, st, Z, nullptr, Y, nullptr, nullptr)));
