@@ -13,14 +13,19 @@ the paper.  Readings taken here:
   them.
 * Each subdomain s carries its own Q1 matrices (elements and wall faces it
   owns) plus, on each interface face set G_st shared with a face neighbour
-  t, the Robin term T_st = alpha M_Gst (M_G: interface-face mass).  The
+  t, the Robin term T_st = alpha_st M_Gst (M_G: interface-face mass).  The
   default alpha = i k is the absorbing condition for normal incidence in
-  the sign convention of the wall admittance (beta = 1).
+  the sign convention of the wall admittance (beta = 1).  Two-sided
+  conditions (the optimised Schwarz methods of the cited works use a
+  different coefficient on each side of an interface): alpha_st = a_lo when
+  s is the lower-index side of G_st (its face on the high side of an axis),
+  a_hi when it is the higher-index side.
 * Local problem: (A~_s + sum_t T_st) u_s = f_s + sum_t R_st^T lam_st, with
   f_s = (R_s f) / multiplicity, so that sum_s R_s^T f_s = f.
-* Transmission: lam_st <- (T_st + T_ts) R_ts u_t - lam_ts.  At the fixed
-  point u_s = u_t on G_st and the assembled equations hold on interface
-  nodes, so the glued solution equals the global one.
+* Transmission: lam_st <- (T_st + T_ts) R_ts u_t - lam_ts, with
+  T_st + T_ts = (a_lo + a_hi) M_Gst.  At the fixed point u_s = u_t on G_st
+  and the assembled equations hold on interface nodes, so the glued
+  solution equals the global one for any coefficients.
 * One multiplier vector per ordered pair of face neighbours, on all nodes
   of G_st (edges and corners included), which handles cross points.
 * Glue: average of the duplicated interface values.
@@ -140,8 +145,15 @@ class Schwarz:
     """Subdomain operators, interface maps and the Schwarz iteration."""
 
     def __init__(self, mesh, parts, beta, eta, k, f, alpha=None):
+        """alpha: one coefficient for both sides (default i k), or a pair
+        (a_lo, a_hi) of two-sided coefficients."""
         self.mesh, self.parts, self.k = mesh, parts, k
-        self.alpha = 1j * k if alpha is None else complex(alpha)
+        if alpha is None:
+            alpha = 1j * k
+        if np.ndim(alpha) == 0:
+            self.a_lo = self.a_hi = complex(alpha)
+        else:
+            self.a_lo, self.a_hi = complex(alpha[0]), complex(alpha[1])
         self.subs = partition(mesh, parts)
         self.ns = len(self.subs)
         n = mesh["xyz"].shape[0]
@@ -172,7 +184,8 @@ class Schwarz:
                 if np.any(sel):
                     MG = fem.Pattern(bf[sel], nl).matrix(Fe[sel])
                     self.MG[(s, tag)] = MG
-                    A = A + self.alpha * MG
+                    # tag 6 + 2d + side: side 1 is the high face (s the lower-index side)
+                    A = A + (self.a_lo if (tag - 6) % 2 == 1 else self.a_hi) * MG
             A = sp.csr_matrix(A)
             self.A.append(A)
             self.lu.append(direct.SparseLU(A))
@@ -211,13 +224,13 @@ class Schwarz:
         return us
 
     def update(self, lams, us):
-        """lam_st <- 2 alpha M_G R_ts u_t - lam_ts."""
+        """lam_st <- (a_lo + a_hi) M_G R_ts u_t - lam_ts."""
         new = []
         for i, p in enumerate(self.pairs):
             j = self.index[(p["t"], p["s"])]
             # lam_ts is indexed by the same global nodes, in t's order of G_ts == G_st
             lam_ts = lams[j][np.searchsorted(self.pairs[j]["g"], p["g"])]
-            new.append(2.0 * self.alpha * (p["MG"] @ us[p["t"]][p["int"]]) - lam_ts)
+            new.append((self.a_lo + self.a_hi) * (p["MG"] @ us[p["t"]][p["int"]]) - lam_ts)
         return new
 
     def glue(self, us):

@@ -50,7 +50,8 @@ def test_trivial_partition_is_the_global_solve():
     assert np.linalg.norm(u - x) <= 1e-12 * np.linalg.norm(x)
 
 
-@pytest.mark.parametrize("parts,alpha", [((2, 1, 1), None), ((2, 2, 1), None), ((2, 2, 2), 0.7 + 2.0j)])
+@pytest.mark.parametrize("parts,alpha", [((2, 1, 1), None), ((2, 2, 1), None), ((2, 2, 2), 0.7 + 2.0j),
+                                         ((2, 2, 2), (0.7 + 2.0j, 3.1 + 0.4j)), ((3, 1, 2), (0.2 + 5.0j, 1.5 + 1.5j))])
 def test_interface_fixed_point_is_the_global_solution(parts, alpha):
     wl, mesh, et, k, A, f = _global((6, 4, 4), eta=True)
     D = schwarz.Schwarz(mesh, parts, wl["beta"], et, k, f, alpha=alpha)
@@ -60,12 +61,12 @@ def test_interface_fixed_point_is_the_global_solution(parts, alpha):
     u = D.glue(us)
     x = direct.SparseLU(A).solve(f)
     assert np.linalg.norm(u - x) <= 1e-10 * np.linalg.norm(x)
-    # duplicated interface values agree, and lam_st + lam_ts = 2 alpha M_G u_G
+    # duplicated interface values agree, and lam_st + lam_ts = (a_lo + a_hi) M_G u_G
     for i, p in enumerate(D.pairs):
         assert np.allclose(us[p["s"]][p["ins"]], us[p["t"]][p["int"]], rtol=1e-10, atol=1e-12 * abs(x).max())
         j = D.index[(p["t"], p["s"])]
         lhs = lam[i] + lam[j]
-        rhs = 2 * D.alpha * (p["MG"] @ us[p["s"]][p["ins"]])
+        rhs = (D.a_lo + D.a_hi) * (p["MG"] @ us[p["s"]][p["ins"]])
         assert np.linalg.norm(lhs - rhs) <= 1e-9 * np.linalg.norm(rhs)
 
 
