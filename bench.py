@@ -122,9 +122,17 @@ def schwarz_leg(log_fn, max_matvec=300):
     m = Helmholtz(wl["mesh"], wl["beta"], parts=wl["parts"])
     f = m.load(torch.as_tensor(wl["g"], device="cuda"))
     out = {"workload": wl["name"]}
-    runs = (("schwarz_bicgstabl4_fp64", dict(dd_inner="bicgstabl", inner_restart=4, precision="fp64")),
-            ("schwarz_bicgstabl4_mixed", dict(dd_inner="bicgstabl", inner_restart=4, precision="mixed")),
-            ("schwarz_bicgstab_fp64", dict(dd_inner="bicgstab", precision="fp64")))
+    # one-sided optimised coefficient for the comparison (the default is the two-sided pair)
+    from paper_2112_00087_amd import dd_alpha
+    nx, ny, nz = wl["mesh"]["elems"]
+    sp = [1.8 / nx, 1.2 / ny, 1.0 / nz]
+    H = min(sp[d] * (wl["mesh"]["elems"][d] // wl["parts"][d]) for d in range(3))
+    a1, _ = dd_alpha(W.wavenumber(wl["freqs"][0]), H, min(sp), sides=1)
+    out["alpha_one_sided"] = [a1.real, a1.imag]
+    loc = dict(dd_inner="bicgstabl", inner_restart=4)
+    runs = (("schwarz_two_sided_fp64", dict(loc, precision="fp64")),
+            ("schwarz_two_sided_mixed", dict(loc, precision="mixed")),
+            ("schwarz_one_sided_fp64", dict(loc, precision="fp64", dd_alpha=a1)))
     for label, o in runs:
         m.set_frequency(wl["freqs"][0])
         torch.cuda.synchronize()

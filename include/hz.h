@@ -120,13 +120,15 @@ typedef struct {
  *   inner_restart  GMRES restart of the inner complex64 solves; for the
  *               Schwarz method with dd_inner HZ_BICGSTABL, l of the local
  *               BiCGStab(l) (0: 4, at most 8)
- *   dd_alpha    Robin transmission coefficient alpha of the Schwarz method
- *               (interface term alpha M_G).  0 + 0i selects an optimised
- *               alpha = p + i q: the (p, q) on a log grid that minimises the
- *               largest convergence factor |(l - alpha)/(l + alpha)| over the
- *               interface modes xi in [pi/H_sub, pi/h] (l = sqrt(xi^2 - k^2)
- *               or i sqrt(k^2 - xi^2)), leaving out xi within pi/(2 H_sub)
- *               of k; i k is the plain absorbing (Despres) choice
+ *   dd_alpha    Robin transmission coefficients of the Schwarz method
+ *   dd_alpha2   (interface term alpha_st M_G; paper Sec. 4 uses optimised
+ *               two-sided conditions).  A subdomain uses dd_alpha on its
+ *               faces toward higher-index neighbours and dd_alpha2 on its
+ *               faces toward lower-index neighbours; dd_alpha2 = 0 means
+ *               dd_alpha on both sides (one-sided).  dd_alpha = 0 selects
+ *               the optimised two-sided pair of hz_dd_alpha for the
+ *               partition's smallest subdomain width and the mesh spacing;
+ *               i k on both sides is the plain absorbing (Despres) choice
  *   dd_inner    Krylov method of the Schwarz subdomain solves (HZ_GMRES,
  *               HZ_BICGSTAB, HZ_BICGSTABL or HZ_TFQMR); for the Schwarz method inner_tol is the
  *               subdomain solves' relative tolerance (0: 1e-10) and
@@ -147,6 +149,7 @@ typedef struct {
   hz_c128 dd_alpha;
   int32_t dd_inner;
   int32_t dd_richardson;
+  hz_c128 dd_alpha2;
 } hz_solve_opts;
 
 /* Filled by the solve entry points.
@@ -265,6 +268,17 @@ int hz_solve_sweep(hz_ctx ctx, int32_t nfreq, const double* freqs_host,
 int hz_solve_adjoint(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* p_dev,
                      const hz_c128* g_dev, hz_c128* lambda_dev, double* dJ_dbeta,
                      double* dJ_deta_dev, hz_solve_info* info);
+
+/* Optimised Robin coefficients for a Schwarz interface (host computation,
+ * no context, no GPU): the interface modes xi in [pi/H, pi/h] (H subdomain
+ * width, h mesh spacing, both > 0, H > h) have the transparent-condition
+ * symbol l(xi) = sqrt(xi^2 - k^2) or i sqrt(k^2 - xi^2); the modes within
+ * pi/(2H) of k are left out.  sides = 1: alpha[0] = alpha[1] = the p + i q
+ * (p, q > 0, log grid of 80 x 80) minimising max |(l - a)/(l + a)|.
+ * sides = 2: the pair p0 + i q, p1 + i q (q of the one-sided optimum)
+ * minimising max |(l - a0)(l - a1)/((l + a0)(l + a1))| (pattern search in
+ * log p0, log p1 from the one-sided optimum).  k > 0. */
+int hz_dd_alpha(double k, double H, double h, int32_t sides, hz_c128* alpha);
 
 /* Storage forms of the operator for the two calls below.  The complex form
  * stores one complex value and one int32 column per entry.  The split form

@@ -3,11 +3,14 @@
 #include <chrono>
 #include <new>
 
+#include <complex>
+
 #include "ops.h"
 #include "solve.h"
 
 const char* hz_last_error_str();
 int schwarz_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* f, z_t* p, hz_solve_info* info);
+void dd_optimised_alpha(double k, double Hsub, double h, int sides, std::complex<double>* out);
 int sweep_solve(hz_ctx ctx, int nfreq, const double* freqs, const z_t* F, z_t* P, const hz_solve_opts& o,
                 hz_solve_info* infos);
 int adjoint_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* p, const z_t* g, z_t* lam, double* dJ_dbeta,
@@ -270,6 +273,19 @@ int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, int32_t format, do
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *avg_ms = double(ms) / reps;
+  return HZ_OK;
+  HZ_GUARD_END
+}
+
+int hz_dd_alpha(double k, double H, double h, int32_t sides, hz_c128* alpha) {
+  HZ_GUARD_BEGIN
+  if (!alpha) return hz_fail(HZ_ERR_INVALID, "alpha is NULL");
+  if (!(k > 0.0) || !(h > 0.0) || !(H > h) || !std::isfinite(k) || !std::isfinite(H))
+    return hz_fail(HZ_ERR_INVALID, "need k > 0 and H > h > 0");
+  if (sides != 1 && sides != 2) return hz_fail(HZ_ERR_INVALID, "sides must be 1 or 2");
+  std::complex<double> a[2];
+  dd_optimised_alpha(k, H, h, sides, a);
+  for (int i = 0; i < 2; ++i) alpha[i] = hz_c128{a[i].real(), a[i].imag()};
   return HZ_OK;
   HZ_GUARD_END
 }

@@ -6,15 +6,17 @@
 // Structured partition of a box mesh into px x py x pz subdomains along
 // element planes (cut of axis d for part a at element (a n_d) / p_d).  Each
 // subdomain s has its own Q1 operator (its elements and wall faces) plus the
-// Robin term alpha M_G on every interface face set G_st:
-//     (A~_s + sum_t alpha M_Gst) u_s = f_s + sum_t R_st^T lam_st,
+// Robin term alpha_st M_G on every interface face set G_st:
+//     (A~_s + sum_t alpha_st M_Gst) u_s = f_s + sum_t R_st^T lam_st,
+// two-sided: alpha_st = a_lo when s is the lower-index side of G_st (its
+// face on the high side of an axis), a_hi when it is the higher-index side;
 // with f_s = (R_s f) / multiplicity.  All subdomain systems are stacked into
 // one block-diagonal sliced-ELL system whose blocks are the segments of the
 // segmented Krylov solvers: one batched solve advances every subdomain in
 // lock-step with its own Krylov scalars.  One multiplier vector lives on the
 // nodes of each ordered face-neighbour pair (cross points included) and is
 // updated by
-//     lam_st <- (T_st + T_ts) R_ts u_t - lam_ts = 2 alpha M_Gst R_ts u_t - lam_ts.
+//     lam_st <- (T_st + T_ts) R_ts u_t - lam_ts = (a_lo + a_hi) M_Gst R_ts u_t - lam_ts.
 // The fixed point of this map (the interface system (I - B) lam = c) is
 // solved by restarted GMRES in complex128 (or iterated plainly on request);
 // the glued solution (average of duplicated interface values) is then
@@ -66,8 +68,8 @@ struct DDData {
   int64_t nsrow = 0;
   DevBuf g2r_ptr, g2r_row;           // glue: stacked rows of every global node
   DevBuf l2g, winv;                  // stacked row -> global node, 1 / multiplicity
-  double alpha_k = -1.0;             // k and alpha the operator was formed for
-  std::complex<double> alpha_v;
+  double alpha_k = -1.0;             // k and coefficients the operator was formed for
+  std::complex<double> alpha_lo, alpha_hi;
 };
 
 template <typename V>
@@ -402,17 +404,21 @@ int build_dd(hz_ctx ctx, DDData* D) {
   return HZ_OK;
 }
 
-// Robin coefficient alpha enters as an interface "admittance" alpha / (i k):
-// the operator forming adds i k beta_tag M_tag for every boundary tag.
-int form_dd_operator(hz_ctx ctx, DDData* D, std::complex<double> alpha, bool want32) {
+// A Robin coefficient alpha enters as an interface "admittance" alpha / (i k):
+// the operator forming adds i k beta_tag M_tag for every boundary tag.  Tag
+// 6 + 2d + side is the interface face on the low (side 0) or high (side 1)
+// end of axis d: on a high face the subdomain is the lower-index side (a_lo).
+int form_dd_operator(hz_ctx ctx, DDData* D, std::complex<double> a_lo, std::complex<double> a_hi,
+                     bool want32) {
   const double k = ctx->k;
-  std::complex<double> bint = (k > 0.0) ? alpha / std::complex<double>(0.0, k) : 0.0;
+  const std::complex<double> ik(0.0, k);
+  const std::complex<double> b_lo = (k > 0.0) ? a_lo / ik : 0.0, b_hi = (k > 0.0) ? a_hi / ik : 0.0;
   const int64_t nbe = int64_t(D->bmass.size()) / NTAG;
   std::vector<z_t> Bb(std::max<int64_t>(nbe, 1), z_t{0.0, 0.0});
   for (int64_t e = 0; e < nbe; ++e) {
     std::complex<double> acc = 0.0;
     for (int w = 0; w < 6; ++w) acc += ctx->beta[w] * D->bmass[e * NTAG + w];
-    for (int w = 6; w < NTAG; ++w) acc += bint * D->bmass[e * NTAG + w];
+    for (int w = 6; w < NTAG; ++w) acc += ((w - 6) % 2 == 1 ? b_lo : b_hi) * D->bmass[e * NTAG + w];
     Bb[e] = z_t{acc.real(), acc.imag()};
   }
   HZ_TRY(up(ctx, D->Bb, Bb));
@@ -426,7 +432,8 @@ int form_dd_operator(hz_ctx ctx, DDData* D, std::complex<double> alpha, bool wan
   HZ_TRY(op_form(ctx->stream, D->nrows, D->nrows, D->npad, D->scol.as<int>(), P, k, 1, D->A.as<z_t>(),
                  want32 ? D->A32.as<c_t>() : nullptr, D->d.as<z_t>(), D->dinv.as<z_t>()));
   D->alpha_k = k;
-  D->alpha_v = alpha;
+  D->alpha_lo = a_lo;
+  D->alpha_hi = a_hi;
   return HZ_OK;
 }
 
@@ -456,7 +463,7 @@ __global__ void k_dd_unscale(int64_t nrows, const z_t* __restrict__ dinv, z_t* _
   if (r < nrows) u[r] = dinv[r] * u[r];
 }
 
-// y = s_lam * lam + s_sw * lam[sw] + s_t * 2 alpha M_G R_ts u
+// y = s_lam * lam + s_sw * lam[sw] + s_t * (a_lo + a_hi) M_G R_ts u
 __global__ void k_dd_update(int64_t nlam, const z_t* __restrict__ lam, const int* __restrict__ sw,
                             const int* __restrict__ mptr, const int* __restrict__ mcol, const double* __restrict__ mval,
                             const int* __restrict__ rowT, const z_t* __restrict__ u, z_t two_alpha, double s_lam,
@@ -555,12 +562,13 @@ struct DDRun {
   // y = (I - B) lam  (homogeneous), or c = B(0) with f when f != NULL
   int apply(const z_t* lam, z_t* y, const z_t* f_st) {
     HZ_TRY(local_solve(f_st, lam));
-    z_t ta = {2.0 * D->alpha_v.real(), 2.0 * D->alpha_v.imag()};
+    const std::complex<double> sum = D->alpha_lo + D->alpha_hi;   // T_st + T_ts
+    z_t ta = {sum.real(), sum.imag()};
     const int64_t nl = D->nlam;
-    if (f_st) {   // c = 2 alpha M_G R u(f)
+    if (f_st) {   // c = (a_lo + a_hi) M_G R u(f)
       k_dd_update<<<ceil_div(nl, kBlock), kBlock, 0, ctx->stream>>>(nl, y, D->sw.as<int>(), D->mptr.as<int>(),
           D->mcol.as<int>(), D->mval.as<double>(), D->rowT.as<int>(), u, ta, 0.0, 0.0, 1.0, y);
-    } else {      // (I - B) lam = lam + lam_sw - 2 alpha M_G R u(lam)
+    } else {      // (I - B) lam = lam + lam_sw - (a_lo + a_hi) M_G R u(lam)
       k_dd_update<<<ceil_div(nl, kBlock), kBlock, 0, ctx->stream>>>(nl, lam, D->sw.as<int>(), D->mptr.as<int>(),
           D->mcol.as<int>(), D->mval.as<double>(), D->rowT.as<int>(), u, ta, 1.0, 1.0, -1.0, y);
     }
@@ -569,14 +577,25 @@ struct DDRun {
   }
 };
 
-// Optimised Robin coefficient alpha = p + i q (p, q > 0): minimises over a
-// log grid of (p, q) the largest convergence factor |(l(xi) - a) / (l(xi) + a)|
-// of the interface modes resolvable between the subdomain width H and the
-// mesh spacing h, xi in [pi/H, pi/h], with l(xi) = sqrt(xi^2 - k^2) for
-// evanescent and i sqrt(k^2 - xi^2) for propagating modes (the symbol of the
-// exact transparent condition in the e^{+i w t} convention); the modes within
+}  // namespace
+
+// Optimised Robin coefficients (p + i q with p, q > 0) for the half-space
+// model of an interface: the interface modes xi resolvable between the
+// subdomain width H and the mesh spacing h, xi in [pi/H, pi/h], have the
+// transparent-condition symbol l(xi) = sqrt(xi^2 - k^2) (evanescent) or
+// i sqrt(k^2 - xi^2) (propagating, e^{+i w t} convention); the modes within
 // pi/(2H) of k, where every factor tends to one, are left out.
-std::complex<double> optimised_alpha(double k, double Hsub, double h) {
+//   one-sided: alpha minimises max |(l - alpha) / (l + alpha)| over a log
+//     grid of 80 x 80 (p, q);
+//   two-sided: (a_lo, a_hi) = (p_lo + i q, p_hi + i q) with q of the
+//     one-sided optimum; (p_lo, p_hi) minimise the factor of a double step,
+//     max |(l - a_lo)(l - a_hi) / ((l + a_lo)(l + a_hi))|, by a pattern search
+//     in log(p) started from the one-sided p split apart by factors 1 .. 16
+//     (the best start wins).  Keeping q keeps the local problems absorbing:
+//     the model's modes are all evanescent when k < pi/H, and a real pair
+//     (which the model would prefer) leaves the subdomains of a nearly
+//     lossless cavity without damping, which slows their inexact solves.
+void dd_optimised_alpha(double k, double Hsub, double h, int sides, std::complex<double>* out) {
   const double xmin = M_PI / Hsub, xmax = M_PI / h;
   std::vector<std::complex<double>> lam;
   const int nx = 2000;
@@ -602,8 +621,47 @@ std::complex<double> optimised_alpha(double k, double Hsub, double h) {
       }
     }
   }
-  return arg;
+  out[0] = out[1] = arg;
+  if (sides != 2 || lam.empty()) return;
+  const double q = arg.imag();
+  auto factor = [&](const double* v) {   // v = log p_lo, log p_hi
+    const std::complex<double> a1(std::exp(v[0]), q), a2(std::exp(v[1]), q);
+    double worst = 0.0;
+    for (const auto& l : lam) worst = std::max(worst, std::abs((l - a1) * (l - a2) / ((l + a1) * (l + a2))));
+    return worst;
+  };
+  double bestv[2] = {std::log(arg.real()), std::log(arg.real())};
+  double bestf = factor(bestv);
+  for (double split : {1.0, 2.0, 4.0, 8.0, 16.0}) {
+    double v[2] = {std::log(arg.real() / split), std::log(arg.real() * split)};
+    double fv = factor(v);
+    for (double step = std::log(2.0); step > 1e-3;) {
+      bool moved = false;
+      for (int c = 0; c < 2; ++c)
+        for (double sg : {1.0, -1.0}) {
+          double t[2] = {v[0], v[1]};
+          t[c] += sg * step;
+          const double ft = factor(t);
+          if (ft < fv) {
+            fv = ft;
+            v[0] = t[0];
+            v[1] = t[1];
+            moved = true;
+          }
+        }
+      if (!moved) step *= 0.5;
+    }
+    if (fv < bestf) {
+      bestf = fv;
+      bestv[0] = v[0];
+      bestv[1] = v[1];
+    }
+  }
+  out[0] = std::complex<double>(std::exp(bestv[0]), q);
+  out[1] = std::complex<double>(std::exp(bestv[1]), q);
 }
+
+namespace {
 
 int host_dot(hz_ctx ctx, int64_t n, const z_t* a, const z_t* b, std::complex<double>* out) {
   int rc = 0;
@@ -630,7 +688,7 @@ int schwarz_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* f, z_t* p, hz_s
   }
   DDData* D = static_cast<DDData*>(ctx->dd_data.get());
   const bool mixed = o.precision == HZ_MIXED;
-  std::complex<double> alpha(o.dd_alpha.re, o.dd_alpha.im);
+  std::complex<double> alpha(o.dd_alpha.re, o.dd_alpha.im), alpha2(o.dd_alpha2.re, o.dd_alpha2.im);
   if (alpha == 0.0) {
     double Hsub = 1e300, h = 1e300;
     const HostAsm& g = ctx->h;
@@ -641,10 +699,17 @@ int schwarz_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* f, z_t* p, hz_s
       h = std::min(h, hd);
       for (const DDSub& U : D->subs) Hsub = std::min(Hsub, hd * U.ln[d]);
     }
-    alpha = ctx->k > 0.0 ? optimised_alpha(ctx->k, Hsub, h) : std::complex<double>(1.0, 0.0);
+    std::complex<double> opt[2] = {1.0, 1.0};
+    if (ctx->k > 0.0) dd_optimised_alpha(ctx->k, Hsub, h, 2, opt);
+    alpha = opt[0];
+    alpha2 = opt[1];
+  } else if (alpha2 == 0.0) {
+    alpha2 = alpha;                    // one-sided
   }
-  if (!std::isfinite(alpha.real()) || !std::isfinite(alpha.imag())) return hz_fail(HZ_ERR_INVALID, "bad dd_alpha");
-  HZ_TRY(form_dd_operator(ctx, D, alpha, mixed));
+  if (!std::isfinite(alpha.real()) || !std::isfinite(alpha.imag()) || !std::isfinite(alpha2.real()) ||
+      !std::isfinite(alpha2.imag()))
+    return hz_fail(HZ_ERR_INVALID, "bad dd_alpha");
+  HZ_TRY(form_dd_operator(ctx, D, alpha, alpha2, mixed));
   HZ_TRY(ensure_operator(ctx, HZ_JACOBI, false));   // global operator for the final residual
   int rc = 0;
   const int64_t nr = D->nrows, nl = D->nlam, n = ctx->h.n;
@@ -716,7 +781,7 @@ int schwarz_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* f, z_t* p, hz_s
     const int rich = o.dd_richardson;            // > 0: plain Schwarz iterations
     if (rich > 0) {
       for (int it = 0; it < rich; ++it) {
-        // lam <- B lam + c = c + 2 alpha M R u(lam) - lam_sw   ==   c - ((I - B) lam - lam)
+        // lam <- B lam + c = c + (a_lo + a_hi) M R u(lam) - lam_sw   ==   c - ((I - B) lam - lam)
         HZ_TRY(R.apply(lam, w, nullptr));
         k_axpy_z<<<ceil_div(nl, kBlock), kBlock, 0, s>>>(nl, z_t{-1.0, 0.0}, w, lam);   // lam - (I-B) lam
         k_axpy_z<<<ceil_div(nl, kBlock), kBlock, 0, s>>>(nl, z_t{1.0, 0.0}, c, lam);

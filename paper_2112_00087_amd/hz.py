@@ -45,7 +45,7 @@ class hz_solve_opts(C.Structure):
     _fields_ = [("method", C.c_int32), ("restart", C.c_int32), ("max_matvec", C.c_int32),
                 ("precision", C.c_int32), ("precond", C.c_int32), ("inner_restart", C.c_int32),
                 ("tol", C.c_double), ("inner_tol", C.c_double), ("dd_alpha", hz_c128),
-                ("dd_inner", C.c_int32), ("dd_richardson", C.c_int32)]
+                ("dd_inner", C.c_int32), ("dd_richardson", C.c_int32), ("dd_alpha2", hz_c128)]
 
 
 class hz_solve_info(C.Structure):
@@ -99,6 +99,7 @@ def lib():
                                        P(hz_solve_info)]),
         "hz_time_spmv": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_int32, P(C.c_double)]),
         "hz_spmv_bytes": (C.c_int, [VP, C.c_int32, C.c_int32, P(C.c_int64)]),
+        "hz_dd_alpha": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int32, P(hz_c128)]),
         "hz_sizes": (C.c_int, [VP, P(C.c_int64), P(C.c_int64), P(C.c_int64), P(C.c_int64)]),
         "hz_destroy": (None, [VP]),
         "hz_last_error": (C.c_char_p, []),
@@ -122,7 +123,7 @@ def check(code, allow_positive=True):
 
 
 def make_opts(method="gmres", restart=30, max_matvec=20000, precision="fp64", precond="jacobi",
-              tol=1e-8, inner_tol=1e-4, inner_restart=30, dd_alpha=0j, dd_inner="gmres",
+              tol=1e-8, inner_tol=1e-4, inner_restart=30, dd_alpha=0j, dd_alpha2=0j, dd_inner="gmres",
               dd_richardson=0):
     o = hz_solve_opts()
     o.method = METHODS[method] if isinstance(method, str) else int(method)
@@ -134,9 +135,18 @@ def make_opts(method="gmres", restart=30, max_matvec=20000, precision="fp64", pr
     o.tol = tol
     o.inner_tol = inner_tol
     o.dd_alpha = hz_c128(complex(dd_alpha).real, complex(dd_alpha).imag)
+    o.dd_alpha2 = hz_c128(complex(dd_alpha2).real, complex(dd_alpha2).imag)
     o.dd_inner = METHODS[dd_inner] if isinstance(dd_inner, str) else int(dd_inner)
     o.dd_richardson = int(dd_richardson)
     return o
+
+
+def dd_alpha(k, H, h, sides=2):
+    """Optimised Robin coefficients (host computation, hz_dd_alpha): one
+    pair of complex numbers (equal for sides=1)."""
+    out = (hz_c128 * 2)()
+    check(lib().hz_dd_alpha(float(k), float(H), float(h), int(sides), out), False)
+    return complex(out[0].re, out[0].im), complex(out[1].re, out[1].im)
 
 
 def _np_ptr(a, ctype):

@@ -84,7 +84,35 @@ def test_null_context_and_options(L):
 
 
 def test_opts_struct_layout_matches_header():
-    # 6 int32, 2 double, hz_c128, 2 int32
-    assert C.sizeof(hz.hz_solve_opts) == 6 * 4 + 2 * 8 + 16 + 2 * 4
+    # 6 int32, 2 double, hz_c128, 2 int32, hz_c128
+    assert C.sizeof(hz.hz_solve_opts) == 6 * 4 + 2 * 8 + 16 + 2 * 4 + 16
+    assert hz.hz_solve_opts.dd_alpha2.offset == 64
     assert C.sizeof(hz.hz_solve_info) == 4 * 4 + 3 * 8
     assert hz.hz_mesh.xyz.offset == 16
+
+
+def _factor(lam, a0, a1):
+    return np.max(np.abs((lam - a0) * (lam - a1) / ((lam + a0) * (lam + a1))))
+
+
+def test_dd_alpha_optimiser_host_only():
+    """The coefficient optimiser runs on the host (no GPU).  Checked against
+    the convergence factor written out from its definition: the two-sided
+    pair does at least as well as the one-sided coefficient used on both
+    sides (whose double-step factor is the one-sided factor squared), and
+    both beat the plain absorbing choice i k."""
+    import paper_2112_00087_amd as P
+    k, H, h = 2.772, 0.4, 0.01
+    a1, b1 = P.dd_alpha(k, H, h, sides=1)
+    a2, b2 = P.dd_alpha(k, H, h, sides=2)
+    assert a1 == b1 and a1.real > 0 and a1.imag > 0
+    assert a2.real > 0 and a2.imag > 0 and b2.real > 0 and b2.imag > 0
+    xi = np.geomspace(np.pi / H, np.pi / h, 2000)
+    xi = xi[np.abs(xi - k) > 0.5 * np.pi / H]
+    lam = np.where(xi > k, np.sqrt(np.abs(xi ** 2 - k ** 2)) + 0j, 1j * np.sqrt(np.abs(k ** 2 - xi ** 2)))
+    one, two, plain = _factor(lam, a1, a1), _factor(lam, a2, b2), _factor(lam, 1j * k, 1j * k)
+    assert two <= one * (1 + 1e-12) and one < plain
+    with pytest.raises(P.HzError):
+        P.dd_alpha(k, 0.01, 0.4)
+    with pytest.raises(P.HzError):
+        P.dd_alpha(k, H, h, sides=3)

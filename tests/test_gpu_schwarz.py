@@ -71,8 +71,9 @@ def test_schwarz_trivial_partition_is_global_solve(P):
     model.close()
 
 
-@pytest.mark.parametrize("alpha_of_k", [lambda k: 1j * k, lambda k: 0.5 * k + 1.5j * k],
-                         ids=["ik", "general"])
+@pytest.mark.parametrize("alpha_of_k", [lambda k: 1j * k, lambda k: 0.5 * k + 1.5j * k,
+                                        lambda k: (0.5 * k + 1.5j * k, 3.0 * k + 0.2j * k)],
+                         ids=["ik", "general", "two-sided"])
 def test_schwarz_plain_iteration_matches_oracle_history(P, alpha_of_k):
     wl, mesh, et, k, A, f = _case((8, 6, 4), 90.0)
     parts = (2, 2, 1)
@@ -81,8 +82,9 @@ def test_schwarz_plain_iteration_matches_oracle_history(P, alpha_of_k):
     model = P.Helmholtz(mesh, wl["beta"], parts=parts)
     model.set_frequency(90.0)
     for n_it in (1, 4, 10):
+        a_lo, a_hi = alpha if isinstance(alpha, tuple) else (alpha, 0j)
         p, info = model.solve(_t(f), method="schwarz", tol=1e-12, inner_tol=1e-13, dd_inner="gmres",
-                              inner_restart=60, dd_richardson=n_it, dd_alpha=alpha)
+                              inner_restart=60, dd_richardson=n_it, dd_alpha=a_lo, dd_alpha2=a_hi)
         u, lams, hist = D.richardson(n_it + 1, A, f)
         err = np.linalg.norm(p.cpu().numpy() - u) / np.linalg.norm(u)
         say(f"  plain Schwarz {n_it}: rel diff {err:.2e}, oracle relres {hist[-1, 1]:.3e}, gpu {info['relres_true']:.3e}")
