@@ -69,6 +69,7 @@ enum {
 enum { HZ_GMRES = 0, HZ_BICGSTAB = 1, HZ_SCHWARZ = 2, HZ_BICGSTABL = 3, HZ_TFQMR = 4 };
 enum { HZ_FP64 = 0, HZ_MIXED = 1 };
 enum { HZ_JACOBI = 0, HZ_NONE = 1 };
+enum { HZ_ORDER_GIVEN = 0, HZ_ORDER_RCM = 1 };
 
 /* Mesh of trilinear hexahedra.  All arrays are host arrays read during
  * hz_assemble only.
@@ -84,7 +85,20 @@ enum { HZ_JACOBI = 0, HZ_NONE = 1 };
  *                            the Schwarz method (0 = not used); requires the
  *                            mesh to be a structured box with node id
  *                            i + (nx+1) (j + (ny+1) k) and elems[3] set
- *   elems[3]                 element counts of a structured box (or 0)    */
+ *   elems[3]                 element counts of a structured box (or 0)
+ *   order                    internal node numbering of the operator rows:
+ *                            HZ_ORDER_GIVEN keeps the mesh's numbering,
+ *                            HZ_ORDER_RCM renumbers by reverse Cuthill-McKee
+ *                            (a narrow band for unstructured meshes, whose
+ *                            node ids need not follow space)
+ *   sigma                    0, or a multiple of 64 (at most 2^20): rows are
+ *                            then sorted by length, longest first, within
+ *                            windows of sigma consecutive internal rows, so
+ *                            that each 64-row slice of the sliced-ELL storage
+ *                            holds rows of nearly equal length (SELL-C-sigma)
+ *   Every device vector of the API stays in the mesh's node numbering
+ *   whatever order and sigma are; the Schwarz method needs order
+ *   HZ_ORDER_GIVEN and sigma 0 (its partition uses the structured ids).   */
 typedef struct {
   int32_t n_nodes, n_elems, n_bfaces;
   const double* xyz;
@@ -95,6 +109,8 @@ typedef struct {
   double c, rho;
   int32_t elems[3];
   int32_t parts[3];
+  int32_t order;
+  int32_t sigma;
 } hz_mesh;
 
 /* Solver options (host struct).
@@ -131,7 +147,7 @@ typedef struct {
  *               i k on both sides is the plain absorbing (Despres) choice
  *   dd_inner    Krylov method of the Schwarz subdomain solves (HZ_GMRES,
  *               HZ_BICGSTAB, HZ_BICGSTABL or HZ_TFQMR); for the Schwarz method inner_tol is the
- *               subdomain solves' relative tolerance (0: 1e-10) and
+ *               subdomain solves' relative tolerance (0: 1e-12) and
  *               precision HZ_MIXED runs them in complex64 with FP64
  *               refinement; restart is the interface GMRES restart
  *   dd_richardson  0: interface GMRES; N > 0: exactly N plain Schwarz
@@ -317,6 +333,22 @@ int hz_spmv_bytes(hz_ctx ctx, int32_t precision, int32_t format, int64_t* bytes)
  * and the device bytes the context holds. */
 int hz_sizes(hz_ctx ctx, int64_t* n_nodes, int64_t* n_elems, int64_t* nnz,
              int64_t* device_bytes);
+
+/* Host-only (no GPU call): the internal numbering hz_assemble uses for this
+ * mesh's order and sigma fields.  Reads n_nodes, n_elems, hex, order and
+ * sigma; writes perm[n_nodes] (host), perm[p] = the mesh node of internal
+ * row p.  HZ_ERR_INVALID for bad fields or node ids. */
+int hz_node_order(const hz_mesh* mesh, int32_t* perm);
+
+/* Storage layout of the operator (host results; any pointer may be NULL):
+ *   perm       [n_nodes] host array: perm[p] = the mesh node stored as
+ *              internal row p (the identity for HZ_ORDER_GIVEN, sigma 0)
+ *   slots      stored entries of the sliced-ELL arrays, padding included
+ *              (each 64-row slice is as wide as its longest row)
+ *   bandwidth  max |p - q| over the stored entries (p, q) in the internal
+ *              numbering; int16 column offsets need it below 32768
+ *   n_imag     entries listed with an imaginary part in the split form   */
+int hz_layout(hz_ctx ctx, int32_t* perm, int64_t* slots, int64_t* bandwidth, int64_t* n_imag);
 
 /* Frees the context and its device memory (NULL is ignored). */
 void hz_destroy(hz_ctx ctx);

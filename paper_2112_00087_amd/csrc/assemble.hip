@@ -76,6 +76,55 @@ void assemble_rows(HostAsm& a, const double* eta, bool km) {
 
 }  // namespace
 
+int mesh_pattern(int64_t n, int64_t ne, const int32_t* hex, std::vector<int64_t>* n2e_ptr_out,
+                 std::vector<int32_t>* n2e_out, std::vector<int64_t>* rowptr_out, std::vector<int32_t>* col_out) {
+  // node -> element adjacency, ascending element id
+  std::vector<int64_t>& n2e_ptr = *n2e_ptr_out;
+  std::vector<int32_t>& n2e = *n2e_out;
+  n2e_ptr.assign(n + 1, 0);
+  for (int64_t q = 0; q < ne * 8; ++q) n2e_ptr[hex[q] + 1]++;
+  for (int64_t i = 0; i < n; ++i) n2e_ptr[i + 1] += n2e_ptr[i];
+  n2e.assign(n2e_ptr[n], 0);
+  {
+    std::vector<int64_t> fill(n2e_ptr.begin(), n2e_ptr.end() - 1);
+    for (int64_t e = 0; e < ne; ++e)
+      for (int l = 0; l < 8; ++l) n2e[fill[hex[e * 8 + l]]++] = int32_t(e);
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (n2e_ptr[i + 1] == n2e_ptr[i])
+      return hz_fail(HZ_ERR_INVALID, "hz_assemble: node %lld belongs to no element", (long long)i);
+
+  // CSR pattern: union of the nodes of the elements around each node
+  std::vector<int32_t> cnt(n);
+  auto row_nodes = [&](int64_t i, int32_t* buf) {
+    int c = 0;
+    for (int64_t t = n2e_ptr[i]; t < n2e_ptr[i + 1]; ++t)
+      for (int l = 0; l < 8; ++l) buf[c++] = hex[int64_t(n2e[t]) * 8 + l];
+    std::sort(buf, buf + c);
+    return int(std::unique(buf, buf + c) - buf);
+  };
+  int64_t maxdeg = 0;
+  for (int64_t i = 0; i < n; ++i) maxdeg = std::max(maxdeg, n2e_ptr[i + 1] - n2e_ptr[i]);
+  parallel_for(n, [&](int64_t r0, int64_t r1) {
+    std::vector<int32_t> buf(maxdeg * 8);
+    for (int64_t i = r0; i < r1; ++i) cnt[i] = row_nodes(i, buf.data());
+  });
+  std::vector<int64_t>& rowptr = *rowptr_out;
+  rowptr.assign(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) rowptr[i + 1] = rowptr[i] + cnt[i];
+  if (rowptr[n] >= (int64_t(1) << 31) - (n * 64))
+    return hz_fail(HZ_ERR_INVALID, "hz_assemble: %lld nonzeros exceed the int32 index range", (long long)rowptr[n]);
+  col_out->assign(rowptr[n], 0);
+  parallel_for(n, [&](int64_t r0, int64_t r1) {
+    std::vector<int32_t> buf(maxdeg * 8);
+    for (int64_t i = r0; i < r1; ++i) {
+      int c = row_nodes(i, buf.data());
+      std::copy(buf.data(), buf.data() + c, col_out->data() + rowptr[i]);
+    }
+  });
+  return HZ_OK;
+}
+
 int host_assemble_meta(HostAsm* a, const double* eta) {
   if (!eta) {
     a->Meta.clear();
@@ -88,7 +137,7 @@ int host_assemble_meta(HostAsm* a, const double* eta) {
   return HZ_OK;
 }
 
-int host_assemble(const hz_mesh* m, const double* eta, HostAsm* out, int ntags) {
+int host_assemble(const hz_mesh* m, const double* eta, HostAsm* out, int ntags, std::vector<int32_t>* perm) {
   HostAsm& a = *out;
   a.ntags = ntags;
   if (!m || !m->xyz || !m->hex || m->n_nodes <= 0 || m->n_elems <= 0 || m->n_bfaces < 0 ||
@@ -113,48 +162,20 @@ int host_assemble(const hz_mesh* m, const double* eta, HostAsm* out, int ntags) 
       if (t < 0 || t >= ntags) return hz_fail(HZ_ERR_INVALID, "hz_assemble: wall tag %d not in 0..%d", t, ntags - 1);
   }
 
-  // node -> element adjacency, ascending element id
-  a.n2e_ptr.assign(int64_t(a.n) + 1, 0);
-  for (int32_t v : a.hex) a.n2e_ptr[v + 1]++;
-  for (int64_t i = 0; i < a.n; ++i) a.n2e_ptr[i + 1] += a.n2e_ptr[i];
-  a.n2e.assign(a.n2e_ptr[a.n], 0);
-  {
-    std::vector<int64_t> fill(a.n2e_ptr.begin(), a.n2e_ptr.end() - 1);
-    for (int64_t e = 0; e < a.ne; ++e)
-      for (int l = 0; l < 8; ++l) a.n2e[fill[a.hex[e * 8 + l]]++] = int32_t(e);
+  HZ_TRY(mesh_pattern(a.n, a.ne, a.hex.data(), &a.n2e_ptr, &a.n2e, &a.rowptr, &a.col));
+  if (perm && (m->order == HZ_ORDER_RCM || m->sigma > 0)) {
+    // renumber the nodes (internal p = mesh node perm[p]) and rebuild the pattern
+    node_order(a.n, a.rowptr, a.col, m->order, m->sigma, perm);
+    std::vector<int32_t> iperm(a.n);
+    for (int64_t p = 0; p < a.n; ++p) iperm[(*perm)[p]] = int32_t(p);
+    for (int64_t p = 0; p < a.n; ++p)
+      for (int d = 0; d < 3; ++d) a.xyz[p * 3 + d] = m->xyz[int64_t((*perm)[p]) * 3 + d];
+    for (int32_t& v : a.hex) v = iperm[v];
+    for (int32_t& v : a.bface) v = iperm[v];
+    HZ_TRY(mesh_pattern(a.n, a.ne, a.hex.data(), &a.n2e_ptr, &a.n2e, &a.rowptr, &a.col));
+  } else if (perm) {
+    perm->clear();
   }
-  for (int64_t i = 0; i < a.n; ++i)
-    if (a.n2e_ptr[i + 1] == a.n2e_ptr[i])
-      return hz_fail(HZ_ERR_INVALID, "hz_assemble: node %lld belongs to no element", (long long)i);
-
-  // CSR pattern: union of the nodes of the elements around each node
-  std::vector<int32_t> cnt(a.n);
-  auto row_nodes = [&](int64_t i, int32_t* buf) {
-    int c = 0;
-    for (int64_t t = a.n2e_ptr[i]; t < a.n2e_ptr[i + 1]; ++t)
-      for (int l = 0; l < 8; ++l) buf[c++] = a.hex[int64_t(a.n2e[t]) * 8 + l];
-    std::sort(buf, buf + c);
-    return int(std::unique(buf, buf + c) - buf);
-  };
-  int64_t maxdeg = 0;
-  for (int64_t i = 0; i < a.n; ++i) maxdeg = std::max(maxdeg, a.n2e_ptr[i + 1] - a.n2e_ptr[i]);
-  parallel_for(a.n, [&](int64_t r0, int64_t r1) {
-    std::vector<int32_t> buf(maxdeg * 8);
-    for (int64_t i = r0; i < r1; ++i) cnt[i] = row_nodes(i, buf.data());
-  });
-  a.rowptr.assign(int64_t(a.n) + 1, 0);
-  for (int64_t i = 0; i < a.n; ++i) a.rowptr[i + 1] = a.rowptr[i] + cnt[i];
-  if (a.rowptr[a.n] >= (int64_t(1) << 31) - (int64_t(a.n) * 64))
-    return hz_fail(HZ_ERR_INVALID, "hz_assemble: %lld nonzeros exceed the int32 index range",
-                   (long long)a.rowptr[a.n]);
-  a.col.assign(a.rowptr[a.n], 0);
-  parallel_for(a.n, [&](int64_t r0, int64_t r1) {
-    std::vector<int32_t> buf(maxdeg * 8);
-    for (int64_t i = r0; i < r1; ++i) {
-      int c = row_nodes(i, buf.data());
-      std::copy(buf.data(), buf.data() + c, a.col.data() + a.rowptr[i]);
-    }
-  });
   a.diag.assign(a.n, -1);
   for (int64_t i = 0; i < a.n; ++i) a.diag[i] = find_col(a, int32_t(i), int32_t(i));
 

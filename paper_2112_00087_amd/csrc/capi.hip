@@ -69,11 +69,18 @@ int hz_assemble(const hz_mesh* mesh, const hz_c128* beta, const double* eta, voi
   *out = nullptr;
   if (!mesh || !beta) return hz_fail(HZ_ERR_INVALID, "mesh or beta is NULL");
   if (!(mesh->c > 0.0) || !std::isfinite(mesh->c)) return hz_fail(HZ_ERR_INVALID, "speed of sound must be > 0");
+  if (mesh->order != HZ_ORDER_GIVEN && mesh->order != HZ_ORDER_RCM)
+    return hz_fail(HZ_ERR_INVALID, "unknown node order %d", mesh->order);
+  if (mesh->sigma < 0 || mesh->sigma % kWave != 0 || mesh->sigma > (1 << 20))
+    return hz_fail(HZ_ERR_INVALID, "sigma %d is not a multiple of 64 in 0..2^20", mesh->sigma);
+  if ((mesh->order != HZ_ORDER_GIVEN || mesh->sigma > 0) &&
+      (mesh->parts[0] > 0 || mesh->parts[1] > 0 || mesh->parts[2] > 0))
+    return hz_fail(HZ_ERR_INVALID, "the Schwarz partition needs the mesh's own numbering (order 0, sigma 0)");
   for (int w = 0; w < 6; ++w)
     if (!std::isfinite(beta[w].re) || !std::isfinite(beta[w].im)) return hz_fail(HZ_ERR_INVALID, "beta not finite");
   std::unique_ptr<hz_ctx_s> ctx(new hz_ctx_s());
   // host-side validation and assembly first: bad input never touches the GPU
-  HZ_TRY(host_assemble(mesh, eta, &ctx->h));
+  HZ_TRY(host_assemble(mesh, eta, &ctx->h, 6, &ctx->perm));
   HZ_HIP(hipGetDevice(&ctx->device));
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   ctx->c = mesh->c;
@@ -143,7 +150,14 @@ int hz_apply(hz_ctx ctx, const hz_c128* x_dev, hz_c128* y_dev) {
   const z_t* x = reinterpret_cast<const z_t*>(x_dev);
   // a column-scaled operator A D^-1 is applied to D x
   HZ_TRY(pad_in(ctx, n, nr, x, ctx->scaled == HZ_JACOBI ? ctx->d_d.as<z_t>() : nullptr, t->as<z_t>()));
-  HZ_TRY(op_spmv<double>(ctx->stream, nr, n, op_A(ctx), t->as<z_t>(), reinterpret_cast<z_t*>(y_dev)));
+  if (ctx->perm.empty()) {
+    HZ_TRY(op_spmv<double>(ctx->stream, nr, n, op_A(ctx), t->as<z_t>(), reinterpret_cast<z_t*>(y_dev)));
+    return HZ_OK;
+  }
+  DevBuf* yt = ctx->buf("apply.y", sizeof(z_t) * nr, &rc);
+  if (rc) return rc;
+  HZ_TRY(op_spmv<double>(ctx->stream, nr, n, op_A(ctx), t->as<z_t>(), yt->as<z_t>()));
+  HZ_TRY(unpad_out(ctx, n, yt->as<z_t>(), nullptr, reinterpret_cast<z_t*>(y_dev)));
   return HZ_OK;
   HZ_GUARD_END
 }
@@ -153,7 +167,7 @@ int hz_get_diag(hz_ctx ctx, hz_c128* d_dev) {
   HZ_TRY(check_ctx(ctx));
   if (!d_dev) return hz_fail(HZ_ERR_INVALID, "null vector");
   if (!ctx->have_freq) return hz_fail(HZ_ERR_STATE, "no frequency set");
-  return op_copy(ctx->stream, ctx->h.n, ctx->d_d.as<z_t>(), reinterpret_cast<z_t*>(d_dev));
+  return unpad_out(ctx, ctx->h.n, ctx->d_d.as<z_t>(), nullptr, reinterpret_cast<z_t*>(d_dev));
   HZ_GUARD_END
 }
 
@@ -304,6 +318,45 @@ int hz_spmv_bytes(hz_ctx ctx, int32_t precision, int32_t format, int64_t* bytes)
     const int64_t idx = ctx->split_dcol ? 2 : 4;
     *bytes = (real + idx) * nnz + (real + 4) * ctx->n_imag + 4 * (n + 1) + 4 * real * n;
   }
+  return HZ_OK;
+  HZ_GUARD_END
+}
+
+int hz_node_order(const hz_mesh* mesh, int32_t* perm) {
+  HZ_GUARD_BEGIN
+  if (!mesh || !perm || !mesh->hex || mesh->n_nodes <= 0 || mesh->n_elems <= 0)
+    return hz_fail(HZ_ERR_INVALID, "null or empty mesh");
+  if (mesh->order != HZ_ORDER_GIVEN && mesh->order != HZ_ORDER_RCM)
+    return hz_fail(HZ_ERR_INVALID, "unknown node order %d", mesh->order);
+  if (mesh->sigma < 0 || mesh->sigma % kWave != 0 || mesh->sigma > (1 << 20))
+    return hz_fail(HZ_ERR_INVALID, "sigma %d is not a multiple of 64 in 0..2^20", mesh->sigma);
+  const int64_t n = mesh->n_nodes, ne = mesh->n_elems;
+  for (int64_t q = 0; q < ne * 8; ++q)
+    if (mesh->hex[q] < 0 || mesh->hex[q] >= n)
+      return hz_fail(HZ_ERR_INVALID, "element node %d out of range", mesh->hex[q]);
+  std::vector<int64_t> n2e_ptr, rowptr;
+  std::vector<int32_t> n2e, col, P;
+  HZ_TRY(mesh_pattern(n, ne, mesh->hex, &n2e_ptr, &n2e, &rowptr, &col));
+  node_order(n, rowptr, col, mesh->order, mesh->sigma, &P);
+  std::copy(P.begin(), P.end(), perm);
+  return HZ_OK;
+  HZ_GUARD_END
+}
+
+int hz_layout(hz_ctx ctx, int32_t* perm, int64_t* slots, int64_t* bandwidth, int64_t* n_imag) {
+  HZ_GUARD_BEGIN
+  if (!ctx) return hz_fail(HZ_ERR_INVALID, "ctx is NULL");
+  const HostAsm& a = ctx->h;
+  if (perm)
+    for (int64_t p = 0; p < a.n; ++p) perm[p] = ctx->perm.empty() ? int32_t(p) : ctx->perm[p];
+  if (slots) *slots = ctx->sell.n_pad;
+  if (bandwidth) {
+    int64_t bw = 0;
+    for (int64_t i = 0; i < a.n; ++i)
+      for (int64_t q = a.rowptr[i]; q < a.rowptr[i + 1]; ++q) bw = std::max<int64_t>(bw, std::abs(a.col[q] - i));
+    *bandwidth = bw;
+  }
+  if (n_imag) *n_imag = ctx->n_imag;
   return HZ_OK;
   HZ_GUARD_END
 }

@@ -47,7 +47,20 @@ struct HostAsm {
   std::vector<int32_t> n2e;
 };
 
-int host_assemble(const hz_mesh* mesh, const double* eta, HostAsm* out, int ntags = 6);
+// Validates and assembles a mesh.  With perm non-NULL the mesh's order and
+// sigma fields are honoured: the assembly is then in the internal numbering
+// and perm receives it (left empty for the mesh's own numbering).
+int host_assemble(const hz_mesh* mesh, const double* eta, HostAsm* out, int ntags = 6,
+                  std::vector<int32_t>* perm = nullptr);
+// CSR pattern of the node graph of a hexahedral mesh (row i: the sorted nodes
+// of the elements around node i) and the node -> element adjacency.
+int mesh_pattern(int64_t n, int64_t ne, const int32_t* hex, std::vector<int64_t>* n2e_ptr,
+                 std::vector<int32_t>* n2e, std::vector<int64_t>* rowptr, std::vector<int32_t>* col);
+// Internal node numbering for a pattern: position p holds node perm[p].
+// order HZ_ORDER_RCM: reverse Cuthill-McKee; sigma > 0: rows sorted by
+// length (longest first) within windows of sigma consecutive positions.
+void node_order(int64_t n, const std::vector<int64_t>& rowptr, const std::vector<int32_t>& col, int order,
+                int sigma, std::vector<int32_t>* perm);
 int host_assemble_meta(HostAsm* a, const double* eta);
 void build_sell(const HostAsm& a, int64_t nrows, SellHost* s);
 
@@ -65,8 +78,12 @@ struct hz_ctx_s {
   hipStream_t stream = nullptr;
   double c = 340.0, rho = 1.2;
   int32_t elems[3] = {0, 0, 0}, parts[3] = {0, 0, 0};
-  HostAsm h;
+  HostAsm h;                         // assembled in the internal node numbering
   SellHost sell;
+  // internal numbering: internal node p is the caller's node perm[p] (empty:
+  // the caller's numbering); vectors cross the C ABI in the caller's order
+  std::vector<int32_t> perm;
+  DevBuf d_perm;
   int64_t dev_bytes = 0;
 
   // device pattern + real values in SELL layout
@@ -120,5 +137,6 @@ struct hz_ctx_s {
 };
 
 int ctx_upload(hz_ctx ctx);
+inline const int* ctx_perm(hz_ctx ctx) { return ctx->perm.empty() ? nullptr : ctx->d_perm.as<int>(); }
 int ctx_upload_params(hz_ctx ctx);
 int ctx_pinned(hz_ctx ctx, size_t bytes, void** out);

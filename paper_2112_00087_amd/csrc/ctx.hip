@@ -174,14 +174,30 @@ int ctx_upload(hz_ctx ctx) {
     HZ_TRY(put(ctx, ctx->d_ipos, ipos.data(), ipos.size()));
   }
   HZ_TRY(put(ctx, ctx->d_bmass, a.bmass.data(), a.bmass.size()));
-  HZ_TRY(put(ctx, ctx->d_prow, a.prow.data(), a.prow.size()));
+  // The load and the gradient kernels work on caller-ordered vectors: their
+  // node ids go up in the mesh's own numbering.
+  const std::vector<int32_t>& P = ctx->perm;
+  auto to_mesh = [&](const std::vector<int32_t>& v) {
+    std::vector<int32_t> o(v);
+    if (!P.empty())
+      for (int32_t& x : o) x = P[x];
+    return o;
+  };
+  HZ_TRY(put(ctx, ctx->d_prow, to_mesh(a.prow).data(), a.prow.size()));
   HZ_TRY(put(ctx, ctx->d_pptr, a.pptr.data(), a.pptr.size()));
-  HZ_TRY(put(ctx, ctx->d_pcol, a.pcol.data(), a.pcol.size()));
+  HZ_TRY(put(ctx, ctx->d_pcol, to_mesh(a.pcol).data(), a.pcol.size()));
   HZ_TRY(put(ctx, ctx->d_pval, a.pval.data(), a.pval.size()));
-  HZ_TRY(put(ctx, ctx->d_xyz, a.xyz.data(), a.xyz.size()));
-  HZ_TRY(put(ctx, ctx->d_hex, a.hex.data(), a.hex.size()));
-  HZ_TRY(put(ctx, ctx->d_bface, a.bface.data(), a.bface.size()));
+  {
+    std::vector<double> xyz(a.xyz);
+    if (!P.empty())
+      for (int64_t p = 0; p < a.n; ++p)
+        for (int d = 0; d < 3; ++d) xyz[int64_t(P[p]) * 3 + d] = a.xyz[p * 3 + d];
+    HZ_TRY(put(ctx, ctx->d_xyz, xyz.data(), xyz.size()));
+  }
+  HZ_TRY(put(ctx, ctx->d_hex, to_mesh(a.hex).data(), a.hex.size()));
+  HZ_TRY(put(ctx, ctx->d_bface, to_mesh(a.bface).data(), a.bface.size()));
   HZ_TRY(put(ctx, ctx->d_btag, a.btag.data(), a.btag.size()));
+  if (!P.empty()) HZ_TRY(put(ctx, ctx->d_perm, P.data(), P.size()));
   size_t before = ctx->d_A.bytes + ctx->d_d.bytes + ctx->d_dinv.bytes;
   HZ_TRY(ctx->d_A.ensure(sizeof(z_t) * s.n_pad));
   HZ_TRY(ctx->d_d.ensure(sizeof(z_t) * nrows));

@@ -87,6 +87,7 @@ int check_structured(hz_ctx ctx) {
   const HostAsm& a = ctx->h;
   const int64_t nx = ctx->elems[0], ny = ctx->elems[1], nz = ctx->elems[2];
   if (nx < 1 || ny < 1 || nz < 1) return hz_fail(HZ_ERR_INVALID, "Schwarz needs mesh->elems of a structured box");
+  if (!ctx->perm.empty()) return hz_fail(HZ_ERR_INVALID, "Schwarz needs the mesh's own node numbering");
   if (int64_t(a.n) != (nx + 1) * (ny + 1) * (nz + 1) || int64_t(a.ne) != nx * ny * nz)
     return hz_fail(HZ_ERR_INVALID, "Schwarz: node/element counts do not match elems");
   for (int d = 0; d < 3; ++d)
@@ -737,7 +738,7 @@ int schwarz_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* f, z_t* p, hz_s
   R.u = u;
   R.lo = o;
   R.lo.method = o.dd_inner;
-  R.lo.tol = o.inner_tol > 0 ? o.inner_tol : 1e-10;   // local solves
+  R.lo.tol = o.inner_tol > 0 ? o.inner_tol : 1e-12;   // local solves
   R.lo.inner_tol = 1e-4;                              // complex64 stage of the refinement
   R.lo.max_matvec = 100000;
   // local GMRES restart, or l of local BiCGStab(l)

@@ -11,6 +11,8 @@ struct IrOut {
 };
 
 int ensure_operator(hz_ctx ctx, int precond, bool want32);
+// Caller-ordered vector -> padded internal vector (optionally scaled per
+// internal row), and back; both apply the context's node numbering.
 int pad_in(hz_ctx ctx, int64_t n, int64_t nrows, const z_t* x, const z_t* scale, z_t* y);
 int unpad_out(hz_ctx ctx, int64_t n, const z_t* u, const z_t* scale, z_t* p);
 int ir_run(hz_ctx ctx, const SegHost& S, const SellOp<double>& A64, const SellOp<float>& A32,

@@ -8,20 +8,25 @@
 
 namespace {
 
+// y[i] = s[i] x[perm[i]] for internal rows i < n (perm NULL: identity), 0 on padding
 __global__ void k_pad_in(int64_t n, int64_t nrows, const z_t* __restrict__ x, const z_t* __restrict__ s,
-                         z_t* __restrict__ y) {
+                         const int* __restrict__ perm, z_t* __restrict__ y) {
   int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= nrows) return;
   z_t v = {0.0, 0.0};
-  if (i < n) v = s ? s[i] * x[i] : x[i];
+  if (i < n) {
+    const z_t xv = x[perm ? int64_t(perm[i]) : i];
+    v = s ? s[i] * xv : xv;
+  }
   y[i] = v;
 }
 
+// p[perm[i]] = s[i] u[i] for internal rows i < n
 __global__ void k_unpad_out(int64_t n, const z_t* __restrict__ u, const z_t* __restrict__ s,
-                            z_t* __restrict__ p) {
+                            const int* __restrict__ perm, z_t* __restrict__ p) {
   int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= n) return;
-  p[i] = s ? s[i] * u[i] : u[i];
+  p[perm ? int64_t(perm[i]) : i] = s ? s[i] * u[i] : u[i];
 }
 
 // out = r / ||r_seg|| in complex64
@@ -45,14 +50,14 @@ __global__ void __launch_bounds__(kBlock) k_ir_add(Seg L, const c_t* __restrict_
 }  // namespace
 
 int pad_in(hz_ctx ctx, int64_t n, int64_t nrows, const z_t* x, const z_t* scale, z_t* y) {
-  k_pad_in<<<ceil_div(nrows, kBlock), kBlock, 0, ctx->stream>>>(n, nrows, x, scale, y);
+  k_pad_in<<<ceil_div(nrows, kBlock), kBlock, 0, ctx->stream>>>(n, nrows, x, scale, ctx_perm(ctx), y);
   HZ_HIP(hipGetLastError());
   return HZ_OK;
 }
 
 int unpad_out(hz_ctx ctx, int64_t n, const z_t* u, const z_t* scale, z_t* p) {
   if (n <= 0) return HZ_OK;
-  k_unpad_out<<<ceil_div(n, kBlock), kBlock, 0, ctx->stream>>>(n, u, scale, p);
+  k_unpad_out<<<ceil_div(n, kBlock), kBlock, 0, ctx->stream>>>(n, u, scale, ctx_perm(ctx), p);
   HZ_HIP(hipGetLastError());
   return HZ_OK;
 }

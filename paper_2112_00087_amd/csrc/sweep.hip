@@ -932,7 +932,7 @@ int launch_spmm(hipStream_t stream, const Variant& v, int64_t nrows, int s, cons
 struct SweepData {
   int64_t nrows = 0;
   DevBuf rowptr, col, K64, M64, E64, K32, M32, E32, bptr, bcol, B64, B32, Bdiag, dpos;
-  DevBuf perm;                      // internal row -> node
+  DevBuf perm;                      // sweep row -> the caller's node id
   DevBuf hptr, hidx, lidx, blidx;   // halos of the blocks of kHaloRows rows
   int hblocks = 0, hmax = 0;
   bool eta = false;
@@ -1045,7 +1045,13 @@ int build_sweep_data(hz_ctx ctx, SweepData* D) {
     rowptr[i + 1] = rowptr[i];
     bptr[i + 1] = bptr[i];
   }
-  HZ_TRY(upload(D->perm, perm));
+  {
+    // sweep row -> the caller's node id (through the context's numbering)
+    std::vector<int> to_mesh(perm);
+    if (!ctx->perm.empty())
+      for (int& v : to_mesh) v = ctx->perm[v];
+    HZ_TRY(upload(D->perm, to_mesh));
+  }
   HZ_TRY(upload(D->rowptr, rowptr));
   HZ_TRY(upload(D->col, col));
   HZ_TRY(upload(D->K64, K));

@@ -27,6 +27,7 @@ HZ_JACOBI, HZ_NONE = 0, 1
 METHODS = {"gmres": HZ_GMRES, "bicgstab": HZ_BICGSTAB, "schwarz": HZ_SCHWARZ, "bicgstabl": HZ_BICGSTABL, "tfqmr": HZ_TFQMR}
 PRECISIONS = {"fp64": HZ_FP64, "mixed": HZ_MIXED}
 SPMV_FORMS = {"solver": 0, "complex": 1, "split": 2}
+ORDERS = {"given": 0, "rcm": 1}
 
 
 class hz_c128(C.Structure):
@@ -38,7 +39,8 @@ class hz_mesh(C.Structure):
                 ("xyz", C.POINTER(C.c_double)), ("hex", C.POINTER(C.c_int32)),
                 ("bface", C.POINTER(C.c_int32)), ("bface_tag", C.POINTER(C.c_int32)),
                 ("bface_src", C.POINTER(C.c_uint8)), ("c", C.c_double), ("rho", C.c_double),
-                ("elems", C.c_int32 * 3), ("parts", C.c_int32 * 3)]
+                ("elems", C.c_int32 * 3), ("parts", C.c_int32 * 3), ("order", C.c_int32),
+                ("sigma", C.c_int32)]
 
 
 class hz_solve_opts(C.Structure):
@@ -100,6 +102,8 @@ def lib():
         "hz_time_spmv": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_int32, P(C.c_double)]),
         "hz_spmv_bytes": (C.c_int, [VP, C.c_int32, C.c_int32, P(C.c_int64)]),
         "hz_dd_alpha": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int32, P(hz_c128)]),
+        "hz_node_order": (C.c_int, [P(hz_mesh), P(C.c_int32)]),
+        "hz_layout": (C.c_int, [VP, P(C.c_int32), P(C.c_int64), P(C.c_int64), P(C.c_int64)]),
         "hz_sizes": (C.c_int, [VP, P(C.c_int64), P(C.c_int64), P(C.c_int64), P(C.c_int64)]),
         "hz_destroy": (None, [VP]),
         "hz_last_error": (C.c_char_p, []),
@@ -149,6 +153,21 @@ def dd_alpha(k, H, h, sides=2):
     return complex(out[0].re, out[0].im), complex(out[1].re, out[1].im)
 
 
+def node_order(mesh, order="rcm", sigma=0):
+    """Internal numbering hz_assemble would use (host computation,
+    hz_node_order): ``perm[p]`` = mesh node of internal row p."""
+    hexes = np.ascontiguousarray(mesh["hex"], dtype=np.int32)
+    m = hz_mesh()
+    m.n_nodes = int(np.asarray(mesh["xyz"]).shape[0])
+    m.n_elems = hexes.shape[0]
+    m.hex = _np_ptr(hexes, C.c_int32)
+    m.order = ORDERS[order] if isinstance(order, str) else int(order)
+    m.sigma = int(sigma)
+    perm = np.empty(m.n_nodes, dtype=np.int32)
+    check(lib().hz_node_order(C.byref(m), _np_ptr(perm, C.c_int32)), False)
+    return perm
+
+
 def _np_ptr(a, ctype):
     return a.ctypes.data_as(C.POINTER(ctype))
 
@@ -173,7 +192,10 @@ def _dev(t, dtype):
 class Helmholtz:
     """One assembled mesh on the GPU (wraps an ``hz_ctx``)."""
 
-    def __init__(self, mesh, beta, eta=None, c=340.0, rho=1.2, parts=None):
+    def __init__(self, mesh, beta, eta=None, c=340.0, rho=1.2, parts=None, order="given", sigma=0):
+        """``order`` "given" or "rcm" and ``sigma`` (0 or a multiple of 64)
+        choose the internal row numbering; vectors stay in the mesh's node
+        order either way."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Helmholtz needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -201,6 +223,8 @@ class Helmholtz:
         for d in range(3):
             m.elems[d] = int(el[d])
             m.parts[d] = int(pa[d])
+        m.order = ORDERS[order] if isinstance(order, str) else int(order)
+        m.sigma = int(sigma)
         self.n = m.n_nodes
         self.ne = m.n_elems
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -235,6 +259,14 @@ class Helmholtz:
         a, b, c_, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
         check(lib().hz_sizes(self.ctx, C.byref(a), C.byref(b), C.byref(c_), C.byref(d)))
         return dict(n_nodes=a.value, n_elems=b.value, nnz=c_.value, device_bytes=d.value)
+
+    def layout(self):
+        """Internal numbering (``perm[p]`` = mesh node of internal row p),
+        stored sliced-ELL slots, bandwidth and listed imaginary entries."""
+        perm = np.empty(self.n, dtype=np.int32)
+        sl, bw, ni = C.c_int64(), C.c_int64(), C.c_int64()
+        check(lib().hz_layout(self.ctx, _np_ptr(perm, C.c_int32), C.byref(sl), C.byref(bw), C.byref(ni)), False)
+        return dict(perm=perm, slots=sl.value, bandwidth=bw.value, n_imag=ni.value)
 
     def time_spmv(self, reps=100, precision="fp64", form="solver"):
         """Average duration (ms) of one sparse product of the given storage form

@@ -122,6 +122,132 @@ def box_mesh(nx, ny, nz, lengths=BOX, patch=PATCH):
     )
 
 
+# local vertex pairs of a tetrahedron's edges, in this order
+_TET_EDGES = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))
+
+
+def kuhn_hex_mesh(nx, ny, nz, lengths=BOX, patch=PATCH, jitter=0.1, seed=SEED, shuffle=True):
+    """Unstructured all-hexahedral mesh of the box (stand-in for the paper's
+    unstructured compartment mesh, Sec. 3.2).
+
+    The box is cut into ``nx x ny x nz`` cells, each cell into the 6 Kuhn
+    tetrahedra that share its main diagonal (conforming across cells), and
+    each tetrahedron into 4 hexahedra, one per corner, whose nodes are the
+    corner, the 3 edge midpoints, the 3 face centroids and the centroid next
+    to it (all faces planar).  Node valences then range from 4 to 24
+    elements, so matrix rows range from 15 to about 70 entries.
+
+    Grid vertices move by ``uniform(-jitter, jitter)`` cell widths along
+    every axis on which they are not on a wall (walls stay planar).  With
+    ``shuffle`` the nodes, elements and boundary faces are numbered in a
+    seeded random order, as an unstructured mesh generator may leave them.
+
+    Returns the same keys as :func:`box_mesh` (``elems`` is the cell grid;
+    the mesh is not a structured box).
+    """
+    Lx, Ly, Lz = lengths
+    h = np.array([Lx / nx, Ly / ny, Lz / nz])
+    rng = np.random.default_rng(seed)
+    nv = (nx + 1) * (ny + 1) * (nz + 1)
+    vid = np.arange(nv)
+    gi = np.stack([vid % (nx + 1), (vid // (nx + 1)) % (ny + 1), vid // ((nx + 1) * (ny + 1))], 1)
+    top = np.array([nx, ny, nz])
+    free = (gi > 0) & (gi < top)
+    vx = gi * h + np.where(free, rng.uniform(-jitter, jitter, size=(nv, 3)), 0.0) * h
+
+    # cells -> 6 Kuhn tetrahedra: corner bits x=1, y=2, z=4; path 0 -> 7
+    ci, cj, ck = [a.ravel() for a in np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")]
+    corner = np.stack([node_id(ci + (b & 1), cj + ((b >> 1) & 1), ck + ((b >> 2) & 1), nx, ny)
+                       for b in range(8)], 1)
+    tets = []
+    for p0, p1, _ in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        b1 = 1 << p0
+        b2 = b1 | (1 << p1)
+        tets.append(np.stack([corner[:, 0], corner[:, b1], corner[:, b2], corner[:, 7]], 1))
+    tet = np.concatenate(tets)
+    d = vx[tet[:, 1:]] - vx[tet[:, :1]]
+    vol = np.einsum("ij,ij->i", d[:, 0], np.cross(d[:, 1], d[:, 2]))
+    neg = vol < 0
+    tet[neg, 2], tet[neg, 3] = tet[neg, 3].copy(), tet[neg, 2].copy()
+    if not np.all(np.abs(vol) > 1e-3 * h.prod()):
+        raise ValueError("jitter too large: a tetrahedron degenerates")
+    nt = tet.shape[0]
+
+    # global ids of edge midpoints, face centroids and cell centroids
+    ekey = np.stack([np.sort(tet[:, list(e)], 1) for e in _TET_EDGES], 1)          # (nt,6,2)
+    ekey = ekey[..., 0].astype(np.int64) * nv + ekey[..., 1]
+    ue, einv = np.unique(ekey.ravel(), return_inverse=True)
+    eid = nv + einv.reshape(nt, 6)
+    fkey = np.stack([np.sort(np.delete(tet, o, axis=1), 1) for o in range(4)], 1)  # face opposite o
+    fkey = (fkey[..., 0].astype(np.int64) * nv + fkey[..., 1]) * nv + fkey[..., 2]
+    uf, finv, fcnt = np.unique(fkey.ravel(), return_inverse=True, return_counts=True)
+    fid = nv + ue.size + finv.reshape(nt, 4)
+    gid = nv + ue.size + uf.size + np.arange(nt)
+    n = nv + ue.size + uf.size + nt
+    xyz = np.empty((n, 3))
+    xyz[:nv] = vx
+    xyz[nv:nv + ue.size] = 0.5 * (vx[ue // nv] + vx[ue % nv])
+    fa, fb, fc = uf // (nv * nv), (uf // nv) % nv, uf % nv
+    xyz[nv + ue.size:nv + ue.size + uf.size] = (vx[fa] + vx[fb] + vx[fc]) / 3.0
+    xyz[nv + ue.size + uf.size:] = vx[tet].mean(1)
+
+    def mid(i, j):
+        return eid[:, _TET_EDGES.index((min(i, j), max(i, j)))]
+
+    def face(*v):
+        return fid[:, ({0, 1, 2, 3} - set(v)).pop()]
+
+    hexes = []
+    for i in range(4):
+        j, k, l = [v for v in range(4) if v != i]
+        if i % 2:
+            j, k = k, j          # keep the corner's axis triple right-handed
+        hexes.append(np.stack([tet[:, i], mid(i, j), mid(i, k), face(i, j, k),
+                               mid(i, l), face(i, j, l), face(i, k, l), gid], 1))
+    hexes = np.concatenate(hexes)
+    X = xyz[hexes]
+    jac = np.einsum("ij,ij->i", X[:, 1] - X[:, 0], np.cross(X[:, 2] - X[:, 0], X[:, 4] - X[:, 0]))
+    assert np.all(jac > 0), "hexahedron orientation"
+
+    # boundary: tetrahedron faces used once; 3 quads per triangle
+    once = np.nonzero(fcnt[finv] == 1)[0]
+    bt, bo = once // 4, once % 4
+    tri = np.array([[v for v in range(4) if v != o] for o in range(4)])[bo]   # local ids, ascending
+    eidx = np.full((4, 4), -1)
+    for q, (x, y) in enumerate(_TET_EDGES):
+        eidx[x, y] = eidx[y, x] = q
+    g3 = gi[tet[bt[:, None], tri]]                                            # (m,3,3) grid indices
+    tag = np.full(bt.size, -1)
+    for ax in range(3):
+        tag = np.where(np.all(g3[:, :, ax] == 0, 1), 2 * ax, tag)
+        tag = np.where(np.all(g3[:, :, ax] == top[ax], 1), 2 * ax + 1, tag)
+    assert np.all(tag >= 0)
+    quads, tags = [], []
+    for c in range(3):
+        a_, b_, c_ = tri[:, c], tri[:, (c + 1) % 3], tri[:, (c + 2) % 3]
+        quads.append(np.stack([tet[bt, a_], eid[bt, eidx[a_, b_]], eid[bt, eidx[a_, c_]], fid[bt, bo]], 1))
+        tags.append(tag)
+    bface = np.concatenate(quads)
+    btag = np.concatenate(tags).astype(np.int32)
+    cen = xyz[bface].mean(1)
+    src = ((btag == 5) & (cen[:, 0] >= patch[0][0]) & (cen[:, 0] <= patch[0][1]) &
+           (cen[:, 1] >= patch[1][0]) & (cen[:, 1] <= patch[1][1])).astype(np.uint8)
+
+    if shuffle:
+        pn = rng.permutation(n)           # old id -> new id
+        inv = np.empty(n, dtype=np.int64)
+        inv[pn] = np.arange(n)
+        xyz = xyz[inv]
+        hexes = pn[hexes][rng.permutation(hexes.shape[0])]
+        fo = rng.permutation(bface.shape[0])
+        bface, btag, src = pn[bface][fo], btag[fo], src[fo]
+    return dict(
+        xyz=np.ascontiguousarray(xyz), hex=hexes.astype(np.int32), bface=bface.astype(np.int32),
+        bface_tag=btag, bface_src=src, elems=(0, 0, 0), cells=(nx, ny, nz), h=tuple(h / 2.0),
+        lengths=tuple(lengths), n_nodes=n, n_elems=hexes.shape[0],
+    )
+
+
 def patch_nodes(mesh):
     """Sorted ids of the nodes of the source-patch quads (rim included)."""
     return np.unique(mesh["bface"][mesh["bface_src"] == 1].ravel())
