@@ -188,6 +188,59 @@ def adjoint_leg(log_fn):
     return out
 
 
+def unstructured_leg(log_fn, layouts=(("given", 0), ("rcm", 0), ("rcm", 256)), solves=True):
+    layouts = tuple(layouts)
+    """Workload 5 (unstructured hexahedra, random node ids): the sparse
+    product under each internal numbering (caller's order, reverse
+    Cuthill-McKee, RCM + length sort of the 64-row slices), and solves."""
+    import torch
+    import workloads as W
+    from paper_2112_00087_amd import Helmholtz
+    wl = W.workload(5)
+    freq = float(wl["freqs"][0])
+    out = {"workload": wl["name"], "n_nodes": int(wl["mesh"]["n_nodes"]), "n_elems": int(wl["mesh"]["n_elems"])}
+    g = torch.as_tensor(wl["g"], device="cuda")
+    for order, sigma in layouts:
+        t = time.perf_counter()
+        m = Helmholtz(wl["mesh"], wl["beta"], order=order, sigma=sigma)
+        t_asm = time.perf_counter() - t
+        m.set_frequency(freq)
+        lay = m.layout()
+        nnz = m.sizes()["nnz"]
+        r = {"assemble_s": t_asm, "nnz": nnz, "padding": lay["slots"] / nnz, "bandwidth": lay["bandwidth"],
+             "n_imag": lay["n_imag"]}
+        for prec, form in (("fp64", "solver"), ("fp64", "complex"), ("mixed", "solver")):
+            ms = m.time_spmv(100, prec, form)
+            b = m.spmv_bytes(prec, form)
+            r[f"spmv_{prec}_{form}"] = {"us": ms * 1e3, "GBs": b / (ms * 1e-3) / 1e9, "bytes": b}
+        f = m.load(g)
+        want_solves = solves
+        solves = (("bicgstab", dict(method="bicgstab")), ("tfqmr", dict(method="tfqmr")),
+                  ("bicgstabl4", dict(method="bicgstabl", restart=4)))
+        for label, o in solves if want_solves and (order, sigma) in (layouts[0], layouts[-1]) else ():
+            m.set_frequency(freq)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, inf = m.solve(f, tol=1e-8, max_matvec=60000, **o)
+            torch.cuda.synchronize()
+            r[label] = {"s": time.perf_counter() - t, "status": inf["status"], "iters": inf["iters"],
+                        "matvecs": inf["matvecs"], "relres_true": inf["relres_true"]}
+            log_fn(f"unstructured {order}/{sigma} {label}: {r[label]}")
+        key = f"{order}_sigma{sigma}"
+        out[key] = r
+        log_fn(f"unstructured {key}: {r}")
+        m.close()
+    return out
+
+
+def _layouts(spec):
+    out = []
+    for item in spec.split(","):
+        order, sigma = item.split(":")
+        out.append((order, int(sigma)))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +260,12 @@ def main():
     ap.add_argument("--sweep-l", type=int, default=8, help="l of BiCGStab(l) in the sweep comparison")
     ap.add_argument("--schwarz", action="store_true", help="also run the 24-subdomain Schwarz solve")
     ap.add_argument("--adjoint", action="store_true", help="also run the 16-frequency adjoint gradient")
+    ap.add_argument("--unstructured", action="store_true",
+                    help="also run the unstructured-mesh leg (product per row numbering, solves)")
+    ap.add_argument("--un-layouts", default="given:0,rcm:0,rcm:256",
+                    help="row numberings of the unstructured leg, order:sigma,...; solves run on the "
+                         "first and the last")
+    ap.add_argument("--un-spmv-only", action="store_true", help="unstructured leg without the solves")
     ap.add_argument("--legs-only", action="store_true",
                     help="skip the headline solve: run only the sweep (unless --no-sweep), Schwarz and adjoint "
                          "legs that are asked for and print them as one JSON line")
@@ -229,6 +288,8 @@ def main():
             legs["schwarz"] = schwarz_leg(log)
         if args.adjoint:
             legs["adjoint"] = adjoint_leg(log)
+        if args.unstructured:
+            legs["unstructured"] = unstructured_leg(log, _layouts(args.un_layouts), not args.un_spmv_only)
         print(json.dumps(legs), flush=True)
         return
     wl = W.workload(1)
@@ -318,6 +379,8 @@ def main():
         extra["schwarz"] = schwarz_leg(log)
     if args.adjoint and not args.spmv_only:
         extra["adjoint"] = adjoint_leg(log)
+    if args.unstructured and not args.spmv_only:
+        extra["unstructured"] = unstructured_leg(log, _layouts(args.un_layouts), not args.un_spmv_only)
 
     cpu = None
     if not args.no_cpu and not args.spmv_only:

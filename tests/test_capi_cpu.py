@@ -89,6 +89,9 @@ def test_opts_struct_layout_matches_header():
     assert hz.hz_solve_opts.dd_alpha2.offset == 64
     assert C.sizeof(hz.hz_solve_info) == 4 * 4 + 3 * 8
     assert hz.hz_mesh.xyz.offset == 16
+    # ..., elems[3], parts[3], order, sigma after c and rho
+    assert hz.hz_mesh.order.offset == hz.hz_mesh.parts.offset + 12
+    assert hz.hz_mesh.sigma.offset == hz.hz_mesh.order.offset + 4
 
 
 def _factor(lam, a0, a1):
@@ -116,3 +119,69 @@ def test_dd_alpha_optimiser_host_only():
         P.dd_alpha(k, 0.01, 0.4)
     with pytest.raises(P.HzError):
         P.dd_alpha(k, H, h, sides=3)
+
+
+def _graph(mesh):
+    import scipy.sparse as sp
+    ne, n = mesh["hex"].shape[0], mesh["xyz"].shape[0]
+    E = sp.csr_matrix((np.ones(ne * 8), (np.repeat(np.arange(ne), 8), mesh["hex"].ravel())), shape=(ne, n))
+    G = (E.T @ E).tocsr()
+    G.sort_indices()
+    return G
+
+
+def _bandwidth(G, perm):
+    ip = np.empty_like(perm)
+    ip[perm] = np.arange(perm.size)
+    c = G.tocoo()
+    return int(np.abs(ip[c.row] - ip[c.col]).max())
+
+
+def test_node_order_host_only():
+    """The internal numbering (host computation, no GPU): a permutation; the
+    reverse Cuthill-McKee band is as narrow as scipy's implementation of the
+    same method gives (an independent library routine) and far below the
+    random input numbering's; the length sort leaves every window of sigma
+    rows ordered by row length, longest first, holding the same nodes."""
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+    import paper_2112_00087_amd as P
+    mesh = W.kuhn_hex_mesh(6, 4, 4)
+    n = mesh["n_nodes"]
+    G = _graph(mesh)
+    rl = np.diff(G.indptr)
+    ident = P.node_order(mesh, "given", 0)
+    assert np.array_equal(ident, np.arange(n))
+    rcm = P.node_order(mesh, "rcm", 0)
+    assert np.array_equal(np.sort(rcm), np.arange(n))
+    ref = np.asarray(reverse_cuthill_mckee(G, symmetric_mode=True))
+    b_rcm, b_ref, b_in = _bandwidth(G, rcm), _bandwidth(G, ref), _bandwidth(G, ident)
+    assert b_rcm <= 1.15 * b_ref and b_rcm < b_in / 5, (b_rcm, b_ref, b_in)
+    for sigma in (64, 256):
+        srt = P.node_order(mesh, "rcm", sigma)
+        for w in range(0, n, sigma):
+            a, b = rcm[w:w + sigma], srt[w:w + sigma]
+            assert np.array_equal(np.sort(a), np.sort(b))
+            assert np.all(np.diff(rl[b]) <= 0)
+    # deterministic
+    assert np.array_equal(P.node_order(mesh, "rcm", 256), P.node_order(mesh, "rcm", 256))
+    # a structured box in lexicographic order stays a narrow band too
+    box = W.box_mesh(6, 5, 4)
+    Gb = _graph(box)
+    assert _bandwidth(Gb, P.node_order(box, "rcm", 0)) <= 2 * _bandwidth(Gb, np.arange(box["n_nodes"]))
+    with pytest.raises(P.HzError):
+        P.node_order(mesh, "rcm", 100)          # not a multiple of 64
+    with pytest.raises(P.HzError):
+        P.node_order(mesh, 7, 0)
+
+
+def test_assemble_rejects_reordered_schwarz_without_gpu(L):
+    out = C.c_void_p(1)
+    beta = hz._beta_array(np.zeros(6))
+    m, keep = _mesh_struct(W.box_mesh(2, 2, 2))
+    m.elems[:] = (2, 2, 2)
+    m.parts[:] = (2, 1, 1)
+    m.order = 1
+    assert L.hz_assemble(C.byref(m), beta, None, None, C.byref(out)) == hz.HZ_ERR_INVALID
+    assert "numbering" in hz.last_error()
+    m.order, m.sigma = 0, 96
+    assert L.hz_assemble(C.byref(m), beta, None, None, C.byref(out)) == hz.HZ_ERR_INVALID

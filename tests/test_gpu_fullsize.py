@@ -65,3 +65,49 @@ def test_bicgstab_full_size_residual_by_oracle(c1, method, l):
     say(f"  oracle relres {rel:.3e}")
     assert rel <= 1e-8
     assert abs(rel - info["relres_true"]) <= 1e-3 * rel
+
+
+@pytest.fixture(scope="module")
+def c5():
+    """Unstructured workload (48x32x32 Kuhn cells, 1,302,753 randomly numbered
+    nodes) in the row numbering the unstructured bench leg times."""
+    import paper_2112_00087_amd as P
+    assert torch.cuda.is_available()
+    wl = W.workload(5)
+    model = P.Helmholtz(wl["mesh"], wl["beta"], order="rcm", sigma=256)
+    model.set_frequency(wl["freqs"][0])
+    yield wl, model
+    model.close()
+
+
+def test_unstructured_spmv_sampled_rows_full_size(c5):
+    wl, model = c5
+    mesh = wl["mesh"]
+    n = mesh["n_nodes"]
+    rng = np.random.default_rng(23)
+    perm = model.layout()["perm"]
+    # random rows, the first and last internal rows, and the longest rows
+    rl = np.bincount(mesh["hex"].ravel(), minlength=n)
+    rows = np.unique(np.concatenate([rng.choice(n, 3000, replace=False), perm[:70], perm[-70:],
+                                     np.argsort(rl)[-50:]]))
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    y = model.apply(torch.as_tensor(x, device="cuda")).cpu().numpy()
+    R = H.rows_of_operator(mesh, W.wavenumber(wl["freqs"][0]), wl["beta"], None, rows)
+    yref = R @ x
+    bound = 1e-14 * (abs(R) @ np.ones(n)) * np.abs(x).max()
+    assert np.all(np.abs(y[rows] - yref) <= bound)
+
+
+def test_unstructured_full_size_residual_by_oracle(c5):
+    wl, model = c5
+    f = model.load(torch.as_tensor(wl["g"], device="cuda"))
+    p, info = model.solve(f, method="bicgstabl", restart=4, tol=1e-8, max_matvec=100000)
+    say("full-size unstructured bicgstab(4)", info)
+    assert info["status"] == 0
+    p = p.cpu().numpy()
+    fo = H.load_elementwise(wl["mesh"], wl["g"])
+    Ap = H.apply_elementwise(wl["mesh"], W.wavenumber(wl["freqs"][0]), wl["beta"], None, p)
+    rel = np.linalg.norm(fo - Ap) / np.linalg.norm(fo)
+    say(f"  oracle relres {rel:.3e}")
+    assert rel <= 1e-8
+    assert abs(rel - info["relres_true"]) <= 1e-3 * rel

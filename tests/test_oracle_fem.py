@@ -173,3 +173,54 @@ def test_p5_manufactured_plane_wave_second_order():
         errs.append(np.abs(p - pex).max())
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(np.abs(rates - 2.0) < 0.2), (errs, rates)
+
+
+# ---------------------------------------------------------------- unstructured
+@pytest.mark.parametrize("cells", [(3, 2, 2), (5, 4, 3)])
+def test_p6_unstructured_mesh_invariants(cells):
+    """Exact invariants of the assembly on the unstructured mesh (distorted,
+    non-affine hexahedra, random node ids): total mass = box volume, wall
+    masses = wall areas, constants in the kernel of K, and the patch test:
+    trilinear elements reproduce a linear field exactly, so K u vanishes on
+    every interior row for linear u."""
+    mesh = W.kuhn_hex_mesh(*cells)
+    asm = fem.assemble(mesh)
+    K, M = asm["K"], asm["M"]
+    n = mesh["n_nodes"]
+    Lx, Ly, Lz = W.BOX
+    assert abs(M.sum() - Lx * Ly * Lz) <= 1e-13
+    areas = [Ly * Lz, Ly * Lz, Lx * Lz, Lx * Lz, Lx * Ly, Lx * Ly]
+    for w in range(6):
+        assert abs(asm["B0"][w].sum() - areas[w]) <= 1e-13
+    assert abs(K - K.T).max() == 0.0 and abs(M - M.T).max() == 0.0
+    assert np.abs(K @ np.ones(n)).max() <= 1e-13
+    x = mesh["xyz"]
+    u = 0.3 * x[:, 0] - 1.2 * x[:, 1] + 0.7 * x[:, 2] + 0.1
+    r = K @ u
+    wall = np.unique(mesh["bface"].ravel())
+    inner = np.setdiff1d(np.arange(n), wall)
+    assert inner.size > 0
+    assert np.abs(r[inner]).max() <= 1e-13 * np.abs(r).max()
+
+
+def test_p6_unstructured_plane_wave_second_order():
+    """O(h^2) convergence to a plane wave with matching Robin data on
+    unstructured meshes refined by halving the Kuhn cells."""
+    d = np.array([1.0, 2.0, 2.0]) / 3.0
+    k = W.wavenumber(200.0)
+    beta = np.array([0.5, 0.4 + 0.1j, 0.3, 0.2 - 0.05j, 0.6, 0.45])
+    normals = [(-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
+    errs = []
+    for lev in range(3):
+        s = 2 ** lev
+        mesh = W.kuhn_hex_mesh(3 * s, 2 * s, 2 * s, jitter=0.0)
+        S = H.System(mesh, beta)
+        pex = np.exp(-1j * k * (mesh["xyz"] @ d))
+        f = np.zeros(mesh["n_nodes"], dtype=complex)
+        for w in range(6):
+            gw = 1j * k * (beta[w] - d @ np.array(normals[w], float)) * pex
+            f += S.asm["B0"][w] @ gw
+        p = direct.SparseLU(S.operator(k)).solve(f)
+        errs.append(np.abs(p - pex).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(rates - 2.0) < 0.3), (errs, rates)

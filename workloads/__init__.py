@@ -2,7 +2,8 @@
 
 This module is shared by the CPU oracle tests and by the GPU path.  It holds
 no finite-element, operator or solver arithmetic: only the node coordinates
-and connectivity of a structured box, the tagging of its boundary faces, and
+and connectivity of a structured box (or of an unstructured hexahedral mesh
+of the same box), the tagging of its boundary faces, and
 the seeded random draws (wall admittances, roof-patch forcing amplitudes,
 absorption field, receiver nodes) that stand in for the paper's car
 compartment and sun-roof data (paper Sec. 3.2, Helmholtz equation and the
@@ -19,6 +20,8 @@ Conventions
   lower-numbered axis fastest).
 * A roof quad belongs to the sun-roof source patch iff its centroid lies in
   ``[0.6, 1.2] x [0.3, 0.9]`` (a 0.6 m x 0.6 m opening centred on the roof).
+* Workload 5 is unstructured (:func:`kuhn_hex_mesh`, its own generator
+  seeded ``SEED + 1000 + cfg``); its node ids follow no spatial order.
 * Draw order for one workload, from ``numpy.random.default_rng(SEED + cfg)``:
   (1) wall admittances, per wall Re then Im (seeded-wall workloads only);
   (2) patch amplitudes, all Re then all Im, in ascending node id;
@@ -51,6 +54,9 @@ CONFIGS = {
     4: dict(name="adjoint-80x48x40-16f-50-200Hz", elems=(80, 48, 40),
             freqs=tuple(np.linspace(50.0, 200.0, 16)), walls="seeded", eta=True,
             receivers=16),
+    # unstructured: elems are the Kuhn cells (24 hexahedra each), nodes randomly numbered
+    5: dict(name="kuhn-48x32x32-250Hz", elems=(48, 32, 32), freqs=(250.0,),
+            walls="seeded", eta=False, receivers=0, mesh="kuhn"),
 }
 
 
@@ -258,7 +264,7 @@ def wavenumber(freq_hz, c=C_SOUND):
 
 
 def workload(cfg, elems=None):
-    """Seeded inputs for workload ``cfg`` (0..4); ``elems`` overrides the mesh
+    """Seeded inputs for workload ``cfg`` (0..5); ``elems`` overrides the mesh
     size (reduced parity cases) while keeping every other rule.
 
     Returns a dict: ``mesh``, ``beta`` (6,) complex128, ``g`` (n,) complex128
@@ -267,7 +273,10 @@ def workload(cfg, elems=None):
     """
     spec = CONFIGS[cfg]
     nx, ny, nz = elems if elems is not None else spec["elems"]
-    mesh = box_mesh(nx, ny, nz)
+    if spec.get("mesh") == "kuhn":
+        mesh = kuhn_hex_mesh(nx, ny, nz, seed=SEED + 1000 + cfg)
+    else:
+        mesh = box_mesh(nx, ny, nz)
     rng = np.random.default_rng(SEED + cfg)
     beta = np.zeros(6, dtype=np.complex128)
     if spec["walls"] == "floor":
