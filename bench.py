@@ -233,6 +233,17 @@ def unstructured_leg(log_fn, layouts=(("given", 0), ("rcm", 0), ("rcm", 256)), s
     return out
 
 
+def _calib_copy():
+    """A 1 GiB device fill and copy of known traffic (reference for the
+    hardware traffic counters)."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def _layouts(spec):
     out = []
     for item in spec.split(","):
@@ -281,6 +292,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     if args.legs_only:
+        if args.calib_copy:
+            _calib_copy()
         legs = {}
         if not args.no_sweep:
             legs["sweep"] = sweep_leg(log, method=args.sweep_method, ell=args.sweep_l)
@@ -307,11 +320,7 @@ def main():
         return model.solve(f, **opts)
 
     if args.calib_copy:
-        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        _calib_copy()
     if args.spmv_only:
         model.set_frequency(freq)
         args.steps = 0
