@@ -23,7 +23,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import direct
+from . import direct, fem
 from .helmholtz import System
 
 
@@ -44,11 +44,11 @@ def energy(mesh, beta, eta, freqs, g, receivers, c=340.0, system=None):
 def gradient(mesh, beta, eta, freqs, g, receivers, c=340.0):
     """Returns ``(J, dJ/dbeta (6,2) [Re, Im], dJ/deta (ne,), p list, lam list)``.
     ``eta=None`` is taken as the zero field (its gradient is still returned)."""
-    ne = mesh["hex"].shape[0]
+    hexes = fem.elements(mesh)
+    ne = hexes.shape[0]
     eta_v = np.zeros(ne) if eta is None else np.asarray(eta, dtype=np.float64)
     S = System(mesh, beta, eta_v)
     Me = S.asm["Me"]
-    hexes = mesh["hex"].astype(np.int64)
     f_load = S.load(g)
     J = 0.0
     dbeta = np.zeros((6, 2))

@@ -1,4 +1,5 @@
-"""Q1 (trilinear hexahedron) Galerkin matrices for the Helmholtz weak form.
+"""Q1 (trilinear hexahedron) and P1 (linear tetrahedron) Galerkin matrices
+for the Helmholtz weak form.
 
 Part of the CPU oracle (test infrastructure only).
 
@@ -16,6 +17,12 @@ with ``phi`` the trilinear shape functions.  Integrals use 2x2x2 (cells) and
 Local node ``a`` of a hexahedron sits at reference corner
 ``(2*bit0(a)-1, 2*bit1(a)-1, 2*bit2(a)-1)``; of a quad at
 ``(2*bit0(a)-1, 2*bit1(a)-1)``.
+
+A tetrahedral mesh (key ``tet``, 4 nodes per element, triangles as boundary
+faces) uses P1 elements: the shape functions are the barycentric
+coordinates, whose gradients are constant, so every integral is a closed
+form (no quadrature): ``K_ab = V grad(l_a).grad(l_b)``,
+``M_ab = V (1 + delta_ab) / 20``, face ``F_ab = A (1 + delta_ab) / 12``.
 """
 from __future__ import annotations
 
@@ -93,6 +100,49 @@ def quad_mass(X):
     return 0.5 * (Fe + Fe.transpose(0, 2, 1))
 
 
+def tet_matrices(X):
+    """Element stiffness and mass matrices of linear tetrahedra (closed forms).
+
+    ``X`` (ne,4,3) vertex coordinates.  With ``D`` the edge matrix (columns
+    ``x_a - x_0``, a = 1..3), the barycentric gradients of vertices 1..3 are
+    the rows of ``D^-1`` and that of vertex 0 is minus their sum; the volume
+    is ``|det D| / 6``.  Returns ``Ke``, ``Me`` (ne,4,4), exactly symmetric."""
+    X = np.asarray(X, dtype=np.float64)
+    D = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=2)   # columns
+    vol = np.abs(np.linalg.det(D)) / 6.0
+    Dinv = np.linalg.inv(D)
+    G = np.concatenate([-Dinv.sum(axis=1, keepdims=True), Dinv], axis=1)             # (ne,4,3)
+    Ke = np.einsum("eai,ebi->eab", G, G) * vol[:, None, None]
+    Me = (np.ones((4, 4)) + np.eye(4))[None] * (vol / 20.0)[:, None, None]
+    Ke = 0.5 * (Ke + Ke.transpose(0, 2, 1))
+    return Ke, Me
+
+
+def tri_mass(X):
+    """Boundary-face mass ``int_face phi_a phi_b`` of linear triangles:
+    ``A (1 + delta_ab) / 12`` with ``A`` the area.  ``X`` (nf,3,3)."""
+    X = np.asarray(X, dtype=np.float64)
+    area = 0.5 * np.linalg.norm(np.cross(X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]), axis=1)
+    return (np.ones((3, 3)) + np.eye(3))[None] * (area / 12.0)[:, None, None]
+
+
+def elements(mesh):
+    """Element connectivity (int64) of a hexahedral (``hex``) or tetrahedral
+    (``tet``) mesh."""
+    conn = mesh["tet"] if "tet" in mesh else mesh["hex"]
+    return np.asarray(conn, dtype=np.int64)
+
+
+def element_matrices(X):
+    """``Ke``, ``Me`` of Q1 hexahedra (8 nodes) or P1 tetrahedra (4 nodes)."""
+    return tet_matrices(X) if X.shape[1] == 4 else hex_matrices(X)
+
+
+def face_mass(X):
+    """Boundary-face mass of bilinear quads (4 nodes) or linear triangles (3)."""
+    return tri_mass(X) if X.shape[1] == 3 else quad_mass(X)
+
+
 class Pattern:
     """COO -> CSR summation in a fixed order.
 
@@ -128,20 +178,20 @@ class Pattern:
 
 
 def assemble(mesh, with_element_mass=False):
-    """Assemble the real matrices of the box (or any Q1 hex) mesh.
+    """Assemble the real matrices of a hexahedral (Q1) or tetrahedral (P1) mesh.
 
     Returns a dict of scipy CSR matrices over the full cell pattern:
     ``K``, ``M``, ``B0`` (list of 6, wall w = tag w), ``Mpatch`` (faces with
-    the source flag), and, on request, the element mass array ``Me`` (ne,8,8)
-    used for the absorption field."""
+    the source flag), and, on request, the element mass array ``Me``
+    (ne,8,8) or (ne,4,4) used for the absorption field."""
     xyz = mesh["xyz"]
-    hexes = mesh["hex"].astype(np.int64)
+    conn = elements(mesh)
     n = xyz.shape[0]
-    Ke, Me = hex_matrices(xyz[hexes])
-    pat = Pattern(hexes, n)
+    Ke, Me = element_matrices(xyz[conn])
+    pat = Pattern(conn, n)
     out = dict(K=pat.matrix(Ke), M=pat.matrix(Me), pattern=pat)
     bf = mesh["bface"].astype(np.int64)
-    Fe = quad_mass(xyz[bf])
+    Fe = face_mass(xyz[bf])
     out["B0"] = []
     for w in range(6):
         sel = mesh["bface_tag"] == w
@@ -161,5 +211,5 @@ def _face_matrix(faces, Fe, n):
 
 def element_weighted_mass(mesh, Me, weights):
     """``sum_e w_e M_e`` assembled on the cell pattern (w = absorption field)."""
-    pat = Pattern(mesh["hex"], mesh["xyz"].shape[0])
+    pat = Pattern(elements(mesh), mesh["xyz"].shape[0])
     return pat.matrix(Me * np.asarray(weights, dtype=np.float64)[:, None, None])

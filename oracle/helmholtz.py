@@ -70,14 +70,14 @@ def apply_elementwise(mesh, k, beta, eta, x, chunk=200_000):
     """Matrix-free ``y = A(k) x`` summed element by element (no CSR), used to
     check residuals at sizes where building the CSR on the CPU is slow."""
     xyz = mesh["xyz"]
-    hexes = mesh["hex"].astype(np.int64)
+    hexes = fem.elements(mesh)
     n = xyz.shape[0]
     x = np.asarray(x, dtype=np.complex128)
     yr = np.zeros(n)
     yi = np.zeros(n)
     for s in range(0, hexes.shape[0], chunk):
         h = hexes[s:s + chunk]
-        Ke, Me = fem.hex_matrices(xyz[h])
+        Ke, Me = fem.element_matrices(xyz[h])
         Ae = Ke.astype(np.complex128) - (k * k) * Me
         if eta is not None:
             Ae = Ae + (1j * k * k) * np.asarray(eta[s:s + chunk])[:, None, None] * Me
@@ -88,7 +88,7 @@ def apply_elementwise(mesh, k, beta, eta, x, chunk=200_000):
     tag = mesh["bface_tag"]
     for s in range(0, bf.shape[0], chunk):
         q = bf[s:s + chunk]
-        Fe = fem.quad_mass(xyz[q]).astype(np.complex128)
+        Fe = fem.face_mass(xyz[q]).astype(np.complex128)
         Fe *= (1j * k * np.asarray(beta, dtype=np.complex128)[tag[s:s + chunk]])[:, None, None]
         ye = np.einsum("eab,eb->ea", Fe, x[q])
         yr += np.bincount(q.ravel(), weights=ye.real.ravel(), minlength=n)
@@ -101,7 +101,7 @@ def load_elementwise(mesh, g):
     xyz = mesh["xyz"]
     bf = mesh["bface"][mesh["bface_src"] == 1].astype(np.int64)
     n = xyz.shape[0]
-    Fe = fem.quad_mass(xyz[bf])
+    Fe = fem.face_mass(xyz[bf])
     ye = np.einsum("eab,eb->ea", Fe, np.asarray(g, dtype=np.complex128)[bf])
     return (np.bincount(bf.ravel(), weights=ye.real.ravel(), minlength=n)
             + 1j * np.bincount(bf.ravel(), weights=ye.imag.ravel(), minlength=n))
@@ -115,23 +115,25 @@ def rows_of_operator(mesh, k, beta, eta, rows):
     n = xyz.shape[0]
     pos = -np.ones(n, dtype=np.int64)
     pos[rows] = np.arange(rows.size)
-    hexes = mesh["hex"].astype(np.int64)
+    hexes = fem.elements(mesh)
     esel = np.flatnonzero((pos[hexes] >= 0).any(axis=1))
     h = hexes[esel]
-    Ke, Me = fem.hex_matrices(xyz[h])
+    npe = h.shape[1]
+    Ke, Me = fem.element_matrices(xyz[h])
     Ae = Ke.astype(np.complex128) - (k * k) * Me
     if eta is not None:
         Ae = Ae + (1j * k * k) * np.asarray(eta)[esel][:, None, None] * Me
-    r = np.repeat(h, 8, axis=1).ravel()
-    c = np.tile(h, (1, 8)).ravel()
+    r = np.repeat(h, npe, axis=1).ravel()
+    c = np.tile(h, (1, npe)).ravel()
     v = Ae.reshape(-1)
     bf = mesh["bface"].astype(np.int64)
     fsel = np.flatnonzero((pos[bf] >= 0).any(axis=1))
     q = bf[fsel]
-    Fe = fem.quad_mass(xyz[q]).astype(np.complex128)
+    npf = q.shape[1]
+    Fe = fem.face_mass(xyz[q]).astype(np.complex128)
     Fe *= (1j * k * np.asarray(beta)[mesh["bface_tag"][fsel]])[:, None, None]
-    r = np.concatenate([r, np.repeat(q, 4, axis=1).ravel()])
-    c = np.concatenate([c, np.tile(q, (1, 4)).ravel()])
+    r = np.concatenate([r, np.repeat(q, npf, axis=1).ravel()])
+    c = np.concatenate([c, np.tile(q, (1, npf)).ravel()])
     v = np.concatenate([v, Fe.reshape(-1)])
     keep = pos[r] >= 0
     return sp.csr_matrix((v[keep], (pos[r[keep]], c[keep])), shape=(rows.size, n))

@@ -64,3 +64,31 @@ def test_p12_gradient_directional_workload0_size():
     for i in rng.choice(eta.size, 4, replace=False):
         fd = _fd(J_eta, eta, i)
         assert abs(fd - de[i]) <= 1e-5 * np.abs(de).max()
+
+
+def test_p12_gradient_vs_central_fd_tetrahedra():
+    """The same pin on an unstructured tetrahedral (P1) mesh."""
+    mesh = W.kuhn_tet_mesh(3, 2, 2)
+    wl = W.workload(4, elems=(4, 3, 2))
+    beta = wl["beta"]
+    rng = np.random.default_rng(9)
+    eta = rng.uniform(0, 0.02, mesh["n_elems"])
+    rec = rng.choice(mesh["n_nodes"], size=5, replace=False)
+    g = np.zeros(mesh["n_nodes"], dtype=complex)
+    pn = W.patch_nodes(mesh)
+    g[pn] = rng.standard_normal(pn.size) + 1j * rng.standard_normal(pn.size)
+    freqs = np.array([80.0, 170.0])
+    J, db, de, _, _ = adjoint.gradient(mesh, beta, eta, freqs, g, rec)
+
+    def J_beta(v):
+        return adjoint.energy(mesh, v[0::2] + 1j * v[1::2], eta, freqs, g, rec)[0]
+
+    bv = np.stack([beta.real, beta.imag], axis=1).ravel()
+    fd_b = np.array([_fd(J_beta, bv, i) for i in range(12)])
+    assert np.linalg.norm(fd_b - db.ravel()) <= 1e-6 * np.linalg.norm(db)
+
+    def J_eta(v):
+        return adjoint.energy(mesh, beta, v, freqs, g, rec)[0]
+
+    fd_e = np.array([_fd(J_eta, eta, i) for i in range(eta.size)])
+    assert np.linalg.norm(fd_e - de) <= 1e-6 * np.linalg.norm(de)

@@ -224,3 +224,126 @@ def test_p6_unstructured_plane_wave_second_order():
         errs.append(np.abs(p - pex).max())
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(np.abs(rates - 2.0) < 0.3), (errs, rates)
+
+
+# ---------------------------------------------------------------- P1 tetrahedra
+def _duffy_integral(X, f):
+    """int_T f over the tetrahedron with vertices X (4,3), by the collapsed-cube
+    (Duffy) map and 4-point Gauss-Legendre per axis: exact for polynomial f of
+    degree <= 4.  Independent of the barycentric-gradient closed forms."""
+    g, w = np.polynomial.legendre.leggauss(4)
+    g, w = 0.5 * (g + 1.0), 0.5 * w
+    tot = 0.0
+    for a, wa in zip(g, w):
+        for b, wb in zip(g, w):
+            for c, wc in zip(g, w):
+                # (a, b, c) in the unit cube -> barycentric (l1, l2, l3)
+                l1 = a
+                l2 = (1 - a) * b
+                l3 = (1 - a) * (1 - b) * c
+                jac = (1 - a) ** 2 * (1 - b)
+                x = X[0] + l1 * (X[1] - X[0]) + l2 * (X[2] - X[0]) + l3 * (X[3] - X[0])
+                tot += wa * wb * wc * jac * f(x)
+    return tot * abs(np.linalg.det(np.stack([X[1] - X[0], X[2] - X[0], X[3] - X[0]], 1)))
+
+
+def test_p7_tet_element_matrices_by_quadrature():
+    """On random tetrahedra: u^T M v = int u v and u^T K v = int grad u . grad v
+    for random linear u, v, the integrals taken by Duffy quadrature."""
+    rng = np.random.default_rng(17)
+    for _ in range(5):
+        X = rng.standard_normal((4, 3))
+        Ke, Me = fem.tet_matrices(X[None])
+        for _ in range(3):
+            a, b = rng.standard_normal(3), rng.standard_normal(3)
+            a0, b0 = rng.standard_normal(2)
+            u, v = X @ a + a0, X @ b + b0           # nodal values of linear functions
+            m = _duffy_integral(X, lambda x: (x @ a + a0) * (x @ b + b0))
+            k = _duffy_integral(X, lambda x: a @ b)
+            assert abs(u @ Me[0] @ v - m) <= 1e-13 * max(1.0, abs(m))
+            assert abs(u @ Ke[0] @ v - k) <= 1e-12 * max(1.0, abs(k))
+    # a boundary triangle: u^T F v = int u v over the face, by a 2-D collapsed map
+    X = rng.standard_normal((3, 3))
+    F = fem.tri_mass(X[None])[0]
+    a, b = rng.standard_normal(3), rng.standard_normal(3)
+    g, w = np.polynomial.legendre.leggauss(4)
+    g, w = 0.5 * (g + 1.0), 0.5 * w
+    area2 = np.linalg.norm(np.cross(X[1] - X[0], X[2] - X[0]))
+    ref = sum(wa * wb * (1 - s) * ((X[0] + s * (X[1] - X[0]) + (1 - s) * t * (X[2] - X[0])) @ a)
+              * ((X[0] + s * (X[1] - X[0]) + (1 - s) * t * (X[2] - X[0])) @ b)
+              for s, wa in zip(g, w) for t, wb in zip(g, w)) * area2
+    assert abs((X @ a) @ F @ (X @ b) - ref) <= 1e-13 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("cells", [(9, 6, 5), (9, 4, 5)])
+def test_p7_kuhn_p1_stiffness_is_seven_point_stencil(cells):
+    """On the un-jittered Kuhn triangulation of a box of h_x x h_y x h_z cells
+    the P1 stiffness of an interior node is the 7-point finite-difference
+    stencil scaled by the cell volume (the diagonal couplings of the Kuhn
+    tetrahedra cancel), and its mass row sums to the cell volume."""
+    nx, ny, nz = cells
+    m = W.kuhn_tet_mesh(nx, ny, nz, jitter=0.0, shuffle=False)
+    asm = fem.assemble(m)
+    K, M = asm["K"].tocsr(), asm["M"].tocsr()
+    hx, hy, hz = m["h"]
+    V = hx * hy * hz
+    for (i, j, k) in ((1, 1, 1), (nx // 2, ny // 2, nz // 2), (nx - 2, ny - 2, nz - 2)):
+        r = W.node_id(i, j, k, nx, ny)
+        ref = {r: 2 * V * (1 / hx ** 2 + 1 / hy ** 2 + 1 / hz ** 2)}
+        for d, hd in zip(((1, 0, 0), (0, 1, 0), (0, 0, 1)), (hx, hy, hz)):
+            for sgn in (1, -1):
+                ref[W.node_id(i + sgn * d[0], j + sgn * d[1], k + sgn * d[2], nx, ny)] = -V / hd ** 2
+        row = K.getrow(r)
+        got = {c: v for c, v in zip(row.indices, row.data) if abs(v) > 1e-13 * ref[r]}
+        assert set(got) == set(ref)
+        for c in ref:
+            assert abs(got[c] - ref[c]) <= 1e-13 * ref[r]
+        assert abs(M.getrow(r).sum() - V) <= 1e-15
+
+
+@pytest.mark.parametrize("cells", [(3, 2, 2), (5, 4, 3)])
+def test_p7_tet_mesh_invariants(cells):
+    """Volume, wall areas, constants in the kernel of K, exact linear patch
+    test, bitwise symmetry on the jittered, randomly numbered tet mesh."""
+    mesh = W.kuhn_tet_mesh(*cells)
+    asm = fem.assemble(mesh)
+    K, M = asm["K"], asm["M"]
+    n = mesh["n_nodes"]
+    Lx, Ly, Lz = W.BOX
+    assert abs(M.sum() - Lx * Ly * Lz) <= 1e-13
+    areas = [Ly * Lz, Ly * Lz, Lx * Lz, Lx * Lz, Lx * Ly, Lx * Ly]
+    for w in range(6):
+        assert abs(asm["B0"][w].sum() - areas[w]) <= 1e-13
+    assert abs(K - K.T).max() == 0.0 and abs(M - M.T).max() == 0.0
+    assert np.abs(K @ np.ones(n)).max() <= 1e-13
+    x = mesh["xyz"]
+    u = 0.3 * x[:, 0] - 1.2 * x[:, 1] + 0.7 * x[:, 2] + 0.1
+    r = K @ u
+    inner = np.setdiff1d(np.arange(n), np.unique(mesh["bface"].ravel()))
+    assert inner.size > 0
+    assert np.abs(r[inner]).max() <= 1e-13 * np.abs(r).max()
+
+
+def test_p7_tet_plane_wave_second_order():
+    """O(h^2) convergence in the L2 (mass) norm to a plane wave with matching
+    Robin data on Kuhn tetrahedral meshes refined by halving the cells (the
+    coarsest level, k h = 0.7, is still pre-asymptotic: rates rise to 2)."""
+    d = np.array([1.0, 2.0, 2.0]) / 3.0
+    k = W.wavenumber(200.0)
+    beta = np.array([0.5, 0.4 + 0.1j, 0.3, 0.2 - 0.05j, 0.6, 0.45])
+    normals = [(-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
+    errs = []
+    for lev in range(3):
+        s = 2 ** lev
+        mesh = W.kuhn_tet_mesh(9 * s, 6 * s, 5 * s, jitter=0.0)
+        S = H.System(mesh, beta)
+        pex = np.exp(-1j * k * (mesh["xyz"] @ d))
+        f = np.zeros(mesh["n_nodes"], dtype=complex)
+        for w in range(6):
+            gw = 1j * k * (beta[w] - d @ np.array(normals[w], float)) * pex
+            f += S.asm["B0"][w] @ gw
+        p = direct.SparseLU(S.operator(k)).solve(f)
+        e = p - pex
+        errs.append(np.sqrt(np.real(np.vdot(e, S.asm["M"] @ e))))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates[0] < rates[1] and abs(rates[1] - 2.0) < 0.15, (errs, rates)

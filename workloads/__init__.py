@@ -20,8 +20,10 @@ Conventions
   lower-numbered axis fastest).
 * A roof quad belongs to the sun-roof source patch iff its centroid lies in
   ``[0.6, 1.2] x [0.3, 0.9]`` (a 0.6 m x 0.6 m opening centred on the roof).
-* Workload 5 is unstructured (:func:`kuhn_hex_mesh`, its own generator
-  seeded ``SEED + 1000 + cfg``); its node ids follow no spatial order.
+* Workloads 5 and 6 are unstructured (:func:`kuhn_hex_mesh`,
+  :func:`kuhn_tet_mesh`; generators seeded ``SEED + 1000 + cfg``); their node
+  ids follow no spatial order.  Workload 6 holds tetrahedra (key ``tet``,
+  triangles in ``bface``).
 * Draw order for one workload, from ``numpy.random.default_rng(SEED + cfg)``:
   (1) wall admittances, per wall Re then Im (seeded-wall workloads only);
   (2) patch amplitudes, all Re then all Im, in ascending node id;
@@ -57,6 +59,9 @@ CONFIGS = {
     # unstructured: elems are the Kuhn cells (24 hexahedra each), nodes randomly numbered
     5: dict(name="kuhn-48x32x32-250Hz", elems=(48, 32, 32), freqs=(250.0,),
             walls="seeded", eta=False, receivers=0, mesh="kuhn"),
+    # unstructured tetrahedra: the Kuhn tetrahedra of the cells themselves (P1)
+    6: dict(name="kuhn-tet-144x96x96-250Hz", elems=(144, 96, 96), freqs=(250.0,),
+            walls="seeded", eta=False, receivers=0, mesh="kuhn-tet"),
 }
 
 
@@ -132,35 +137,17 @@ def box_mesh(nx, ny, nz, lengths=BOX, patch=PATCH):
 _TET_EDGES = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))
 
 
-def kuhn_hex_mesh(nx, ny, nz, lengths=BOX, patch=PATCH, jitter=0.1, seed=SEED, shuffle=True):
-    """Unstructured all-hexahedral mesh of the box (stand-in for the paper's
-    unstructured compartment mesh, Sec. 3.2).
-
-    The box is cut into ``nx x ny x nz`` cells, each cell into the 6 Kuhn
-    tetrahedra that share its main diagonal (conforming across cells), and
-    each tetrahedron into 4 hexahedra, one per corner, whose nodes are the
-    corner, the 3 edge midpoints, the 3 face centroids and the centroid next
-    to it (all faces planar).  Node valences then range from 4 to 24
-    elements, so matrix rows range from 15 to about 70 entries.
-
-    Grid vertices move by ``uniform(-jitter, jitter)`` cell widths along
-    every axis on which they are not on a wall (walls stay planar).  With
-    ``shuffle`` the nodes, elements and boundary faces are numbered in a
-    seeded random order, as an unstructured mesh generator may leave them.
-
-    Returns the same keys as :func:`box_mesh` (``elems`` is the cell grid;
-    the mesh is not a structured box).
-    """
+def _kuhn_tets(nx, ny, nz, lengths, jitter, rng):
+    """Jittered grid vertices and the positively oriented Kuhn tetrahedra of
+    its cells (6 per cell around the main diagonal, conforming)."""
     Lx, Ly, Lz = lengths
     h = np.array([Lx / nx, Ly / ny, Lz / nz])
-    rng = np.random.default_rng(seed)
     nv = (nx + 1) * (ny + 1) * (nz + 1)
     vid = np.arange(nv)
     gi = np.stack([vid % (nx + 1), (vid // (nx + 1)) % (ny + 1), vid // ((nx + 1) * (ny + 1))], 1)
     top = np.array([nx, ny, nz])
     free = (gi > 0) & (gi < top)
     vx = gi * h + np.where(free, rng.uniform(-jitter, jitter, size=(nv, 3)), 0.0) * h
-
     # cells -> 6 Kuhn tetrahedra: corner bits x=1, y=2, z=4; path 0 -> 7
     ci, cj, ck = [a.ravel() for a in np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")]
     corner = np.stack([node_id(ci + (b & 1), cj + ((b >> 1) & 1), ck + ((b >> 2) & 1), nx, ny)
@@ -177,6 +164,88 @@ def kuhn_hex_mesh(nx, ny, nz, lengths=BOX, patch=PATCH, jitter=0.1, seed=SEED, s
     tet[neg, 2], tet[neg, 3] = tet[neg, 3].copy(), tet[neg, 2].copy()
     if not np.all(np.abs(vol) > 1e-3 * h.prod()):
         raise ValueError("jitter too large: a tetrahedron degenerates")
+    return vx, gi, top, tet, h
+
+
+def _wall_tags(gi, top, tri):
+    """Wall id of boundary triangles given by their grid-vertex ids."""
+    g3 = gi[tri]
+    tag = np.full(tri.shape[0], -1)
+    for ax in range(3):
+        tag = np.where(np.all(g3[:, :, ax] == 0, 1), 2 * ax, tag)
+        tag = np.where(np.all(g3[:, :, ax] == top[ax], 1), 2 * ax + 1, tag)
+    assert np.all(tag >= 0)
+    return tag.astype(np.int32)
+
+
+def _faces_once(tet, nv):
+    """(tetrahedron, opposite local vertex) of the faces used by one
+    tetrahedron only (the boundary), plus per-tetrahedron face keys."""
+    fkey = np.stack([np.sort(np.delete(tet, o, axis=1), 1) for o in range(4)], 1)  # face opposite o
+    fkey = (fkey[..., 0].astype(np.int64) * nv + fkey[..., 1]) * nv + fkey[..., 2]
+    uf, finv, fcnt = np.unique(fkey.ravel(), return_inverse=True, return_counts=True)
+    once = np.nonzero(fcnt[finv] == 1)[0]
+    return once // 4, once % 4, uf, finv.reshape(tet.shape[0], 4)
+
+
+def _patch_flags(btag, cen, patch):
+    return ((btag == 5) & (cen[:, 0] >= patch[0][0]) & (cen[:, 0] <= patch[0][1]) &
+            (cen[:, 1] >= patch[1][0]) & (cen[:, 1] <= patch[1][1])).astype(np.uint8)
+
+
+def kuhn_tet_mesh(nx, ny, nz, lengths=BOX, patch=PATCH, jitter=0.1, seed=SEED, shuffle=True):
+    """Unstructured tetrahedral mesh of the box: the jittered Kuhn
+    tetrahedra of ``nx x ny x nz`` cells (see :func:`kuhn_hex_mesh`),
+    boundary triangles tagged by wall, nodes, elements and faces in a seeded
+    random order with ``shuffle``.  Returns ``xyz``, ``tet`` (ne,4) int32,
+    ``bface`` (nb,3) triangles and the tags of :func:`box_mesh`."""
+    rng = np.random.default_rng(seed)
+    vx, gi, top, tet, h = _kuhn_tets(nx, ny, nz, lengths, jitter, rng)
+    nv = vx.shape[0]
+    bt, bo, _, _ = _faces_once(tet, nv)
+    tri = np.stack([tet[bt, v] for v in range(4)], 1)
+    keep = np.arange(4)[None, :] != bo[:, None]
+    tri = tri[keep].reshape(-1, 3)
+    btag = _wall_tags(gi, top, tri)
+    src = _patch_flags(btag, vx[tri].mean(1), patch)
+    xyz = vx
+    if shuffle:
+        pn = rng.permutation(nv)
+        inv = np.empty(nv, dtype=np.int64)
+        inv[pn] = np.arange(nv)
+        xyz = vx[inv]
+        tet = pn[tet][rng.permutation(tet.shape[0])]
+        fo = rng.permutation(tri.shape[0])
+        tri, btag, src = pn[tri][fo], btag[fo], src[fo]
+    return dict(
+        xyz=np.ascontiguousarray(xyz), tet=tet.astype(np.int32), bface=tri.astype(np.int32),
+        bface_tag=btag, bface_src=src, elems=(0, 0, 0), cells=(nx, ny, nz), h=tuple(h),
+        lengths=tuple(lengths), n_nodes=nv, n_elems=tet.shape[0],
+    )
+
+
+def kuhn_hex_mesh(nx, ny, nz, lengths=BOX, patch=PATCH, jitter=0.1, seed=SEED, shuffle=True):
+    """Unstructured all-hexahedral mesh of the box (stand-in for the paper's
+    unstructured compartment mesh, Sec. 3.2).
+
+    The box is cut into ``nx x ny x nz`` cells, each cell into the 6 Kuhn
+    tetrahedra that share its main diagonal (conforming across cells), and
+    each tetrahedron into 4 hexahedra, one per corner, whose nodes are the
+    corner, the 3 edge midpoints, the 3 face centroids and the centroid next
+    to it (all faces planar).  Node valences then range from 4 to 24
+    elements, so matrix rows range from 12 to 75 entries.
+
+    Grid vertices move by ``uniform(-jitter, jitter)`` cell widths along
+    every axis on which they are not on a wall (walls stay planar).  With
+    ``shuffle`` the nodes, elements and boundary faces are numbered in a
+    seeded random order, as an unstructured mesh generator may leave them.
+
+    Returns the same keys as :func:`box_mesh` (``elems`` is the cell grid;
+    the mesh is not a structured box).
+    """
+    rng = np.random.default_rng(seed)
+    vx, gi, top, tet, h = _kuhn_tets(nx, ny, nz, lengths, jitter, rng)
+    nv = vx.shape[0]
     nt = tet.shape[0]
 
     # global ids of edge midpoints, face centroids and cell centroids
@@ -184,10 +253,8 @@ def kuhn_hex_mesh(nx, ny, nz, lengths=BOX, patch=PATCH, jitter=0.1, seed=SEED, s
     ekey = ekey[..., 0].astype(np.int64) * nv + ekey[..., 1]
     ue, einv = np.unique(ekey.ravel(), return_inverse=True)
     eid = nv + einv.reshape(nt, 6)
-    fkey = np.stack([np.sort(np.delete(tet, o, axis=1), 1) for o in range(4)], 1)  # face opposite o
-    fkey = (fkey[..., 0].astype(np.int64) * nv + fkey[..., 1]) * nv + fkey[..., 2]
-    uf, finv, fcnt = np.unique(fkey.ravel(), return_inverse=True, return_counts=True)
-    fid = nv + ue.size + finv.reshape(nt, 4)
+    bt, bo, uf, finv = _faces_once(tet, nv)
+    fid = nv + ue.size + finv
     gid = nv + ue.size + uf.size + np.arange(nt)
     n = nv + ue.size + uf.size + nt
     xyz = np.empty((n, 3))
@@ -216,18 +283,11 @@ def kuhn_hex_mesh(nx, ny, nz, lengths=BOX, patch=PATCH, jitter=0.1, seed=SEED, s
     assert np.all(jac > 0), "hexahedron orientation"
 
     # boundary: tetrahedron faces used once; 3 quads per triangle
-    once = np.nonzero(fcnt[finv] == 1)[0]
-    bt, bo = once // 4, once % 4
     tri = np.array([[v for v in range(4) if v != o] for o in range(4)])[bo]   # local ids, ascending
     eidx = np.full((4, 4), -1)
     for q, (x, y) in enumerate(_TET_EDGES):
         eidx[x, y] = eidx[y, x] = q
-    g3 = gi[tet[bt[:, None], tri]]                                            # (m,3,3) grid indices
-    tag = np.full(bt.size, -1)
-    for ax in range(3):
-        tag = np.where(np.all(g3[:, :, ax] == 0, 1), 2 * ax, tag)
-        tag = np.where(np.all(g3[:, :, ax] == top[ax], 1), 2 * ax + 1, tag)
-    assert np.all(tag >= 0)
+    tag = _wall_tags(gi, top, tet[bt[:, None], tri])
     quads, tags = [], []
     for c in range(3):
         a_, b_, c_ = tri[:, c], tri[:, (c + 1) % 3], tri[:, (c + 2) % 3]
@@ -235,9 +295,7 @@ def kuhn_hex_mesh(nx, ny, nz, lengths=BOX, patch=PATCH, jitter=0.1, seed=SEED, s
         tags.append(tag)
     bface = np.concatenate(quads)
     btag = np.concatenate(tags).astype(np.int32)
-    cen = xyz[bface].mean(1)
-    src = ((btag == 5) & (cen[:, 0] >= patch[0][0]) & (cen[:, 0] <= patch[0][1]) &
-           (cen[:, 1] >= patch[1][0]) & (cen[:, 1] <= patch[1][1])).astype(np.uint8)
+    src = _patch_flags(btag, xyz[bface].mean(1), patch)
 
     if shuffle:
         pn = rng.permutation(n)           # old id -> new id
@@ -264,7 +322,7 @@ def wavenumber(freq_hz, c=C_SOUND):
 
 
 def workload(cfg, elems=None):
-    """Seeded inputs for workload ``cfg`` (0..5); ``elems`` overrides the mesh
+    """Seeded inputs for workload ``cfg`` (0..6); ``elems`` overrides the mesh
     size (reduced parity cases) while keeping every other rule.
 
     Returns a dict: ``mesh``, ``beta`` (6,) complex128, ``g`` (n,) complex128
@@ -275,6 +333,8 @@ def workload(cfg, elems=None):
     nx, ny, nz = elems if elems is not None else spec["elems"]
     if spec.get("mesh") == "kuhn":
         mesh = kuhn_hex_mesh(nx, ny, nz, seed=SEED + 1000 + cfg)
+    elif spec.get("mesh") == "kuhn-tet":
+        mesh = kuhn_tet_mesh(nx, ny, nz, seed=SEED + 1000 + cfg)
     else:
         mesh = box_mesh(nx, ny, nz)
     rng = np.random.default_rng(SEED + cfg)
