@@ -188,15 +188,16 @@ def adjoint_leg(log_fn):
     return out
 
 
-def unstructured_leg(log_fn, layouts=(("given", 0), ("rcm", 0), ("rcm", 256)), solves=True):
+def unstructured_leg(log_fn, layouts=(("given", 0), ("rcm", 0), ("rcm", 256)), solves=True, cfg=5):
     layouts = tuple(layouts)
-    """Workload 5 (unstructured hexahedra, random node ids): the sparse
-    product under each internal numbering (caller's order, reverse
-    Cuthill-McKee, RCM + length sort of the 64-row slices), and solves."""
+    """Workload 5 (unstructured hexahedra) or 6 (unstructured P1
+    tetrahedra), random node ids: the sparse product under each internal
+    numbering (caller's order, reverse Cuthill-McKee, RCM + length sort of
+    the 64-row slices), and solves."""
     import torch
     import workloads as W
     from paper_2112_00087_amd import Helmholtz
-    wl = W.workload(5)
+    wl = W.workload(cfg)
     freq = float(wl["freqs"][0])
     out = {"workload": wl["name"], "n_nodes": int(wl["mesh"]["n_nodes"]), "n_elems": int(wl["mesh"]["n_elems"])}
     g = torch.as_tensor(wl["g"], device="cuda")
@@ -225,10 +226,10 @@ def unstructured_leg(log_fn, layouts=(("given", 0), ("rcm", 0), ("rcm", 256)), s
             torch.cuda.synchronize()
             r[label] = {"s": time.perf_counter() - t, "status": inf["status"], "iters": inf["iters"],
                         "matvecs": inf["matvecs"], "relres_true": inf["relres_true"]}
-            log_fn(f"unstructured {order}/{sigma} {label}: {r[label]}")
+            log_fn(f"{wl['name']} {order}/{sigma} {label}: {r[label]}")
         key = f"{order}_sigma{sigma}"
         out[key] = r
-        log_fn(f"unstructured {key}: {r}")
+        log_fn(f"{wl['name']} {key}: {r}")
         m.close()
     return out
 
@@ -242,6 +243,14 @@ def _calib_copy():
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
+
+
+def _unstructured_legs(args):
+    return {W_NAMES.get(int(c), c): unstructured_leg(log, _layouts(args.un_layouts), not args.un_spmv_only, int(c))
+            for c in args.un_workloads.split(",")}
+
+
+W_NAMES = {5: "hexahedra", 6: "tetrahedra"}
 
 
 def _layouts(spec):
@@ -277,6 +286,7 @@ def main():
                     help="row numberings of the unstructured leg, order:sigma,...; solves run on the "
                          "first and the last")
     ap.add_argument("--un-spmv-only", action="store_true", help="unstructured leg without the solves")
+    ap.add_argument("--un-workloads", default="5,6", help="unstructured workloads: 5 hexahedra, 6 tetrahedra")
     ap.add_argument("--legs-only", action="store_true",
                     help="skip the headline solve: run only the sweep (unless --no-sweep), Schwarz and adjoint "
                          "legs that are asked for and print them as one JSON line")
@@ -302,7 +312,7 @@ def main():
         if args.adjoint:
             legs["adjoint"] = adjoint_leg(log)
         if args.unstructured:
-            legs["unstructured"] = unstructured_leg(log, _layouts(args.un_layouts), not args.un_spmv_only)
+            legs["unstructured"] = _unstructured_legs(args)
         print(json.dumps(legs), flush=True)
         return
     wl = W.workload(1)
@@ -389,7 +399,7 @@ def main():
     if args.adjoint and not args.spmv_only:
         extra["adjoint"] = adjoint_leg(log)
     if args.unstructured and not args.spmv_only:
-        extra["unstructured"] = unstructured_leg(log, _layouts(args.un_layouts), not args.un_spmv_only)
+        extra["unstructured"] = _unstructured_legs(args)
 
     cpu = None
     if not args.no_cpu and not args.spmv_only:

@@ -70,14 +70,17 @@ enum { HZ_GMRES = 0, HZ_BICGSTAB = 1, HZ_SCHWARZ = 2, HZ_BICGSTABL = 3, HZ_TFQMR
 enum { HZ_FP64 = 0, HZ_MIXED = 1 };
 enum { HZ_JACOBI = 0, HZ_NONE = 1 };
 enum { HZ_ORDER_GIVEN = 0, HZ_ORDER_RCM = 1 };
+enum { HZ_HEX8 = 0, HZ_TET4 = 1 };
 
-/* Mesh of trilinear hexahedra.  All arrays are host arrays read during
- * hz_assemble only.
+/* Mesh of trilinear hexahedra (Q1) or linear tetrahedra (P1).  All arrays
+ * are host arrays read during hz_assemble only.
  *   xyz       [n_nodes][3]   node coordinates (m)
- *   hex       [n_elems][8]   element nodes in tensor order: local node
- *                            a + 2 b + 4 c sits at reference corner
- *                            (2a-1, 2b-1, 2c-1)
- *   bface     [n_bfaces][4]  boundary quads, tensor order a + 2 b
+ *   hex       [n_elems][8]   element nodes; hexahedra in tensor order:
+ *                            local node a + 2 b + 4 c sits at reference
+ *                            corner (2a-1, 2b-1, 2c-1).  [n_elems][4] for
+ *                            tetrahedra (any vertex order)
+ *   bface     [n_bfaces][4]  boundary quads, tensor order a + 2 b;
+ *                            [n_bfaces][3] triangles for tetrahedra
  *   bface_tag [n_bfaces]     wall id 0..5 (x-, x+, y-, y+, z-, z+)
  *   bface_src [n_bfaces]     1 = the face carries the source (Neumann) datum
  *   c, rho                   speed of sound (m/s); rho is stored only
@@ -96,9 +99,13 @@ enum { HZ_ORDER_GIVEN = 0, HZ_ORDER_RCM = 1 };
  *                            windows of sigma consecutive internal rows, so
  *                            that each 64-row slice of the sliced-ELL storage
  *                            holds rows of nearly equal length (SELL-C-sigma)
+ *   elem_type                HZ_HEX8 (Q1, 2x2x2 Gauss) or HZ_TET4 (P1,
+ *                            closed-form integrals; paper Sec. 3.2 solves on
+ *                            an unstructured mesh)
  *   Every device vector of the API stays in the mesh's node numbering
  *   whatever order and sigma are; the Schwarz method needs order
- *   HZ_ORDER_GIVEN and sigma 0 (its partition uses the structured ids).   */
+ *   HZ_ORDER_GIVEN and sigma 0 (its partition uses the structured ids) and
+ *   hexahedra.                                                             */
 typedef struct {
   int32_t n_nodes, n_elems, n_bfaces;
   const double* xyz;
@@ -111,6 +118,7 @@ typedef struct {
   int32_t parts[3];
   int32_t order;
   int32_t sigma;
+  int32_t elem_type;
 } hz_mesh;
 
 /* Solver options (host struct).
@@ -335,8 +343,8 @@ int hz_sizes(hz_ctx ctx, int64_t* n_nodes, int64_t* n_elems, int64_t* nnz,
              int64_t* device_bytes);
 
 /* Host-only (no GPU call): the internal numbering hz_assemble uses for this
- * mesh's order and sigma fields.  Reads n_nodes, n_elems, hex, order and
- * sigma; writes perm[n_nodes] (host), perm[p] = the mesh node of internal
+ * mesh's order and sigma fields.  Reads n_nodes, n_elems, hex, elem_type,
+ * order and sigma; writes perm[n_nodes] (host), perm[p] = the mesh node of internal
  * row p.  HZ_ERR_INVALID for bad fields or node ids. */
 int hz_node_order(const hz_mesh* mesh, int32_t* perm);
 

@@ -6,6 +6,7 @@
 // A^H lambda = g.  A is complex symmetric, so A^H = conj(A) and
 // lambda = conj(A^-1 conj(g)): the adjoint reuses the forward solver.
 #include "ops.h"
+#include "p1.h"
 #include "q1.h"
 #include "solve.h"
 
@@ -18,26 +19,41 @@ __global__ void k_conj(int64_t n, const z_t* __restrict__ a, z_t* __restrict__ b
   if (i < n) b[i] = conj(a[i]);
 }
 
+// M_e of a Q1 hexahedron (NPE 8) or P1 tetrahedron (NPE 4).
+template <int NPE>
+__device__ __forceinline__ void elem_mass(const double X[NPE][3], double Me[NPE][NPE]);
+template <>
+__device__ __forceinline__ void elem_mass<8>(const double X[8][3], double Me[8][8]) { q1::hex_mass(X, Me); }
+template <>
+__device__ __forceinline__ void elem_mass<4>(const double X[4][3], double Me[4][4]) { p1::tet_mass(X, Me); }
+template <int NPF>
+__device__ __forceinline__ void face_mass(const double X[NPF][3], double Fe[NPF][NPF]);
+template <>
+__device__ __forceinline__ void face_mass<4>(const double X[4][3], double Fe[4][4]) { q1::quad_mass(X, Fe); }
+template <>
+__device__ __forceinline__ void face_mass<3>(const double X[3][3], double Fe[3][3]) { p1::tri_mass(X, Fe); }
+
 // dJ/deta_e += 2 k^2 Im(lambda_e^H M_e p_e), M_e formed from the node coordinates.
+template <int NPE>
 __global__ void __launch_bounds__(kBlock) k_grad_eta(int ne, const int* __restrict__ hex, const double* __restrict__ xyz,
                                                      const z_t* __restrict__ p, const z_t* __restrict__ lam,
                                                      double k2x2, double* __restrict__ dJ) {
   int e = blockIdx.x * kBlock + threadIdx.x;
   if (e >= ne) return;
-  double X[8][3];
-  int v[8];
-  for (int a = 0; a < 8; ++a) {
-    v[a] = hex[int64_t(e) * 8 + a];
+  double X[NPE][3];
+  int v[NPE];
+  for (int a = 0; a < NPE; ++a) {
+    v[a] = hex[int64_t(e) * NPE + a];
     for (int d = 0; d < 3; ++d) X[a][d] = xyz[int64_t(v[a]) * 3 + d];
   }
-  double Me[8][8];
-  q1::hex_mass(X, Me);
-  z_t pe[8];
-  for (int a = 0; a < 8; ++a) pe[a] = p[v[a]];
+  double Me[NPE][NPE];
+  elem_mass<NPE>(X, Me);
+  z_t pe[NPE];
+  for (int a = 0; a < NPE; ++a) pe[a] = p[v[a]];
   double im = 0.0;
-  for (int a = 0; a < 8; ++a) {
+  for (int a = 0; a < NPE; ++a) {
     z_t q = {0.0, 0.0};
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < NPE; ++b) {
       q.re = fma(Me[a][b], pe[b].re, q.re);
       q.im = fma(Me[a][b], pe[b].im, q.im);
     }
@@ -48,6 +64,7 @@ __global__ void __launch_bounds__(kBlock) k_grad_eta(int ne, const int* __restri
 }
 
 // partials of lambda^H B0_w p per wall (12 doubles per block)
+template <int NPF>
 __global__ void __launch_bounds__(kBlock) k_grad_beta(int nb, const int* __restrict__ bface, const int* __restrict__ btag,
                                                       const double* __restrict__ xyz, const z_t* __restrict__ p,
                                                       const z_t* __restrict__ lam, double* __restrict__ part) {
@@ -55,18 +72,18 @@ __global__ void __launch_bounds__(kBlock) k_grad_beta(int nb, const int* __restr
   double q[12];
   for (int i = 0; i < 12; ++i) q[i] = 0.0;
   if (f < nb) {
-    double X[4][3];
-    int v[4];
-    for (int a = 0; a < 4; ++a) {
-      v[a] = bface[int64_t(f) * 4 + a];
+    double X[NPF][3];
+    int v[NPF];
+    for (int a = 0; a < NPF; ++a) {
+      v[a] = bface[int64_t(f) * NPF + a];
       for (int d = 0; d < 3; ++d) X[a][d] = xyz[int64_t(v[a]) * 3 + d];
     }
-    double Fe[4][4];
-    q1::quad_mass(X, Fe);
+    double Fe[NPF][NPF];
+    face_mass<NPF>(X, Fe);
     z_t acc = {0.0, 0.0};
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < NPF; ++a) {
       z_t s = {0.0, 0.0};
-      for (int b = 0; b < 4; ++b) {
+      for (int b = 0; b < NPF; ++b) {
         z_t pb = p[v[b]];
         s.re = fma(Fe[a][b], pb.re, s.re);
         s.im = fma(Fe[a][b], pb.im, s.im);
@@ -112,8 +129,12 @@ int adjoint_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* p, const z_t* g
   HZ_HIP(hipGetLastError());
   const double k = ctx->k;
   if (dJ_deta) {
-    k_grad_eta<<<ceil_div(ctx->h.ne, kBlock), kBlock, 0, ctx->stream>>>(
-        ctx->h.ne, ctx->d_hex.as<int>(), ctx->d_xyz.as<double>(), p, lam, 2.0 * k * k, dJ_deta);
+    if (ctx->h.npe == 4)
+      k_grad_eta<4><<<ceil_div(ctx->h.ne, kBlock), kBlock, 0, ctx->stream>>>(
+          ctx->h.ne, ctx->d_hex.as<int>(), ctx->d_xyz.as<double>(), p, lam, 2.0 * k * k, dJ_deta);
+    else
+      k_grad_eta<8><<<ceil_div(ctx->h.ne, kBlock), kBlock, 0, ctx->stream>>>(
+          ctx->h.ne, ctx->d_hex.as<int>(), ctx->d_xyz.as<double>(), p, lam, 2.0 * k * k, dJ_deta);
     HZ_HIP(hipGetLastError());
   }
   if (dJ_dbeta && ctx->h.nb > 0) {
@@ -122,8 +143,12 @@ int adjoint_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* p, const z_t* g
     if (rc) return rc;
     DevBuf* res = ctx->buf("adj.res", sizeof(double) * 12, &rc);
     if (rc) return rc;
-    k_grad_beta<<<nblk, kBlock, 0, ctx->stream>>>(ctx->h.nb, ctx->d_bface.as<int>(), ctx->d_btag.as<int>(),
-                                                  ctx->d_xyz.as<double>(), p, lam, part->as<double>());
+    if (ctx->h.npf == 3)
+      k_grad_beta<3><<<nblk, kBlock, 0, ctx->stream>>>(ctx->h.nb, ctx->d_bface.as<int>(), ctx->d_btag.as<int>(),
+                                                       ctx->d_xyz.as<double>(), p, lam, part->as<double>());
+    else
+      k_grad_beta<4><<<nblk, kBlock, 0, ctx->stream>>>(ctx->h.nb, ctx->d_bface.as<int>(), ctx->d_btag.as<int>(),
+                                                       ctx->d_xyz.as<double>(), p, lam, part->as<double>());
     k_grad_beta_fin<<<1, kBlock, 0, ctx->stream>>>(nblk, part->as<double>(), res->as<double>());
     HZ_HIP(hipGetLastError());
     double h[12];

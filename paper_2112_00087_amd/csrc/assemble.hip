@@ -12,6 +12,7 @@
 #include <unordered_map>
 
 #include "ctx.h"
+#include "p1.h"
 #include "q1.h"
 
 namespace {
@@ -42,9 +43,9 @@ inline int64_t find_col(const HostAsm& a, int32_t row, int32_t col) {
   return p - a.col.data();
 }
 
-void gather_hex(const HostAsm& a, int32_t e, double X[8][3]) {
-  for (int l = 0; l < 8; ++l) {
-    int32_t v = a.hex[int64_t(e) * 8 + l];
+void gather_elem(const HostAsm& a, int32_t e, double X[8][3]) {
+  for (int l = 0; l < a.npe; ++l) {
+    int32_t v = a.hex[int64_t(e) * a.npe + l];
     for (int d = 0; d < 3; ++d) X[l][d] = a.xyz[int64_t(v) * 3 + d];
   }
 }
@@ -59,13 +60,20 @@ void assemble_rows(HostAsm& a, const double* eta, bool km) {
       for (int64_t t = a.n2e_ptr[i]; t < a.n2e_ptr[i + 1]; ++t) {
         int32_t e = a.n2e[t];
         int loc = -1;
-        for (int l = 0; l < 8; ++l)
-          if (a.hex[int64_t(e) * 8 + l] == int32_t(i)) { loc = l; break; }
+        for (int l = 0; l < a.npe; ++l)
+          if (a.hex[int64_t(e) * a.npe + l] == int32_t(i)) { loc = l; break; }
         double X[8][3], Kr[8], Mr[8];
-        gather_hex(a, e, X);
-        q1::hex_rows(X, loc, Kr, Mr);
-        for (int b = 0; b < 8; ++b) {
-          int64_t pos = find_col(a, int32_t(i), a.hex[int64_t(e) * 8 + b]);
+        gather_elem(a, e, X);
+        if (a.npe == 8) {
+          q1::hex_rows(X, loc, Kr, Mr);
+        } else {
+          double T[4][3];
+          for (int l = 0; l < 4; ++l)
+            for (int d = 0; d < 3; ++d) T[l][d] = X[l][d];
+          p1::tet_rows(T, loc, Kr, Mr);
+        }
+        for (int b = 0; b < a.npe; ++b) {
+          int64_t pos = find_col(a, int32_t(i), a.hex[int64_t(e) * a.npe + b]);
           if (km) { a.K[pos] += Kr[b]; a.M[pos] += Mr[b]; }
           if (eta) a.Meta[pos] += eta[e] * Mr[b];
         }
@@ -76,19 +84,19 @@ void assemble_rows(HostAsm& a, const double* eta, bool km) {
 
 }  // namespace
 
-int mesh_pattern(int64_t n, int64_t ne, const int32_t* hex, std::vector<int64_t>* n2e_ptr_out,
+int mesh_pattern(int64_t n, int64_t ne, int npe, const int32_t* hex, std::vector<int64_t>* n2e_ptr_out,
                  std::vector<int32_t>* n2e_out, std::vector<int64_t>* rowptr_out, std::vector<int32_t>* col_out) {
   // node -> element adjacency, ascending element id
   std::vector<int64_t>& n2e_ptr = *n2e_ptr_out;
   std::vector<int32_t>& n2e = *n2e_out;
   n2e_ptr.assign(n + 1, 0);
-  for (int64_t q = 0; q < ne * 8; ++q) n2e_ptr[hex[q] + 1]++;
+  for (int64_t q = 0; q < ne * npe; ++q) n2e_ptr[hex[q] + 1]++;
   for (int64_t i = 0; i < n; ++i) n2e_ptr[i + 1] += n2e_ptr[i];
   n2e.assign(n2e_ptr[n], 0);
   {
     std::vector<int64_t> fill(n2e_ptr.begin(), n2e_ptr.end() - 1);
     for (int64_t e = 0; e < ne; ++e)
-      for (int l = 0; l < 8; ++l) n2e[fill[hex[e * 8 + l]]++] = int32_t(e);
+      for (int l = 0; l < npe; ++l) n2e[fill[hex[e * npe + l]]++] = int32_t(e);
   }
   for (int64_t i = 0; i < n; ++i)
     if (n2e_ptr[i + 1] == n2e_ptr[i])
@@ -99,14 +107,14 @@ int mesh_pattern(int64_t n, int64_t ne, const int32_t* hex, std::vector<int64_t>
   auto row_nodes = [&](int64_t i, int32_t* buf) {
     int c = 0;
     for (int64_t t = n2e_ptr[i]; t < n2e_ptr[i + 1]; ++t)
-      for (int l = 0; l < 8; ++l) buf[c++] = hex[int64_t(n2e[t]) * 8 + l];
+      for (int l = 0; l < npe; ++l) buf[c++] = hex[int64_t(n2e[t]) * npe + l];
     std::sort(buf, buf + c);
     return int(std::unique(buf, buf + c) - buf);
   };
   int64_t maxdeg = 0;
   for (int64_t i = 0; i < n; ++i) maxdeg = std::max(maxdeg, n2e_ptr[i + 1] - n2e_ptr[i]);
   parallel_for(n, [&](int64_t r0, int64_t r1) {
-    std::vector<int32_t> buf(maxdeg * 8);
+    std::vector<int32_t> buf(maxdeg * npe);
     for (int64_t i = r0; i < r1; ++i) cnt[i] = row_nodes(i, buf.data());
   });
   std::vector<int64_t>& rowptr = *rowptr_out;
@@ -116,7 +124,7 @@ int mesh_pattern(int64_t n, int64_t ne, const int32_t* hex, std::vector<int64_t>
     return hz_fail(HZ_ERR_INVALID, "hz_assemble: %lld nonzeros exceed the int32 index range", (long long)rowptr[n]);
   col_out->assign(rowptr[n], 0);
   parallel_for(n, [&](int64_t r0, int64_t r1) {
-    std::vector<int32_t> buf(maxdeg * 8);
+    std::vector<int32_t> buf(maxdeg * npe);
     for (int64_t i = r0; i < r1; ++i) {
       int c = row_nodes(i, buf.data());
       std::copy(buf.data(), buf.data() + c, col_out->data() + rowptr[i]);
@@ -143,17 +151,21 @@ int host_assemble(const hz_mesh* m, const double* eta, HostAsm* out, int ntags, 
   if (!m || !m->xyz || !m->hex || m->n_nodes <= 0 || m->n_elems <= 0 || m->n_bfaces < 0 ||
       (m->n_bfaces > 0 && (!m->bface || !m->bface_tag || !m->bface_src)))
     return hz_fail(HZ_ERR_INVALID, "hz_assemble: null or empty mesh arrays");
+  if (m->elem_type != HZ_HEX8 && m->elem_type != HZ_TET4)
+    return hz_fail(HZ_ERR_INVALID, "hz_assemble: unknown element type %d", m->elem_type);
+  a.npe = m->elem_type == HZ_TET4 ? 4 : 8;
+  a.npf = m->elem_type == HZ_TET4 ? 3 : 4;
   a.n = m->n_nodes;
   a.ne = m->n_elems;
   a.nb = m->n_bfaces;
   a.xyz.assign(m->xyz, m->xyz + int64_t(a.n) * 3);
-  a.hex.assign(m->hex, m->hex + int64_t(a.ne) * 8);
+  a.hex.assign(m->hex, m->hex + int64_t(a.ne) * a.npe);
   for (double v : a.xyz)
     if (!std::isfinite(v)) return hz_fail(HZ_ERR_INVALID, "hz_assemble: non-finite coordinate");
   for (int32_t v : a.hex)
     if (v < 0 || v >= a.n) return hz_fail(HZ_ERR_INVALID, "hz_assemble: element node %d out of range", v);
   if (a.nb > 0) {
-    a.bface.assign(m->bface, m->bface + int64_t(a.nb) * 4);
+    a.bface.assign(m->bface, m->bface + int64_t(a.nb) * a.npf);
     a.btag.assign(m->bface_tag, m->bface_tag + a.nb);
     a.bsrc.assign(m->bface_src, m->bface_src + a.nb);
     for (int32_t v : a.bface)
@@ -162,7 +174,7 @@ int host_assemble(const hz_mesh* m, const double* eta, HostAsm* out, int ntags, 
       if (t < 0 || t >= ntags) return hz_fail(HZ_ERR_INVALID, "hz_assemble: wall tag %d not in 0..%d", t, ntags - 1);
   }
 
-  HZ_TRY(mesh_pattern(a.n, a.ne, a.hex.data(), &a.n2e_ptr, &a.n2e, &a.rowptr, &a.col));
+  HZ_TRY(mesh_pattern(a.n, a.ne, a.npe, a.hex.data(), &a.n2e_ptr, &a.n2e, &a.rowptr, &a.col));
   if (perm && (m->order == HZ_ORDER_RCM || m->sigma > 0)) {
     // renumber the nodes (internal p = mesh node perm[p]) and rebuild the pattern
     node_order(a.n, a.rowptr, a.col, m->order, m->sigma, perm);
@@ -172,7 +184,7 @@ int host_assemble(const hz_mesh* m, const double* eta, HostAsm* out, int ntags, 
       for (int d = 0; d < 3; ++d) a.xyz[p * 3 + d] = m->xyz[int64_t((*perm)[p]) * 3 + d];
     for (int32_t& v : a.hex) v = iperm[v];
     for (int32_t& v : a.bface) v = iperm[v];
-    HZ_TRY(mesh_pattern(a.n, a.ne, a.hex.data(), &a.n2e_ptr, &a.n2e, &a.rowptr, &a.col));
+    HZ_TRY(mesh_pattern(a.n, a.ne, a.npe, a.hex.data(), &a.n2e_ptr, &a.n2e, &a.rowptr, &a.col));
   } else if (perm) {
     perm->clear();
   }
@@ -199,13 +211,23 @@ int host_assemble(const hz_mesh* m, const double* eta, HostAsm* out, int ntags, 
   a.bmass.clear();
   std::map<int64_t, double> patch;   // (row * n + col) -> value
   for (int64_t f = 0; f < a.nb; ++f) {
+    const int nf = a.npf;
     double X[4][3], Fe[4][4];
-    for (int l = 0; l < 4; ++l)
-      for (int d = 0; d < 3; ++d) X[l][d] = a.xyz[int64_t(a.bface[f * 4 + l]) * 3 + d];
-    q1::quad_mass(X, Fe);
-    for (int l = 0; l < 4; ++l)
-      for (int o = 0; o < 4; ++o) {
-        int32_t r = a.bface[f * 4 + l], c = a.bface[f * 4 + o];
+    for (int l = 0; l < nf; ++l)
+      for (int d = 0; d < 3; ++d) X[l][d] = a.xyz[int64_t(a.bface[f * nf + l]) * 3 + d];
+    if (nf == 4) {
+      q1::quad_mass(X, Fe);
+    } else {
+      double T[3][3], F3[3][3];
+      for (int l = 0; l < 3; ++l)
+        for (int d = 0; d < 3; ++d) T[l][d] = X[l][d];
+      p1::tri_mass(T, F3);
+      for (int l = 0; l < 3; ++l)
+        for (int o = 0; o < 3; ++o) Fe[l][o] = F3[l][o];
+    }
+    for (int l = 0; l < nf; ++l)
+      for (int o = 0; o < nf; ++o) {
+        int32_t r = a.bface[f * nf + l], c = a.bface[f * nf + o];
         int64_t pos = find_col(a, r, c);
         if (pos < 0) return hz_fail(HZ_ERR_INVALID, "hz_assemble: boundary face %lld is not an element face", (long long)f);
         auto it = slot.find(pos);

@@ -330,13 +330,16 @@ int hz_node_order(const hz_mesh* mesh, int32_t* perm) {
     return hz_fail(HZ_ERR_INVALID, "unknown node order %d", mesh->order);
   if (mesh->sigma < 0 || mesh->sigma % kWave != 0 || mesh->sigma > (1 << 20))
     return hz_fail(HZ_ERR_INVALID, "sigma %d is not a multiple of 64 in 0..2^20", mesh->sigma);
+  if (mesh->elem_type != HZ_HEX8 && mesh->elem_type != HZ_TET4)
+    return hz_fail(HZ_ERR_INVALID, "unknown element type %d", mesh->elem_type);
+  const int npe = mesh->elem_type == HZ_TET4 ? 4 : 8;
   const int64_t n = mesh->n_nodes, ne = mesh->n_elems;
-  for (int64_t q = 0; q < ne * 8; ++q)
+  for (int64_t q = 0; q < ne * npe; ++q)
     if (mesh->hex[q] < 0 || mesh->hex[q] >= n)
       return hz_fail(HZ_ERR_INVALID, "element node %d out of range", mesh->hex[q]);
   std::vector<int64_t> n2e_ptr, rowptr;
   std::vector<int32_t> n2e, col, P;
-  HZ_TRY(mesh_pattern(n, ne, mesh->hex, &n2e_ptr, &n2e, &rowptr, &col));
+  HZ_TRY(mesh_pattern(n, ne, npe, mesh->hex, &n2e_ptr, &n2e, &rowptr, &col));
   node_order(n, rowptr, col, mesh->order, mesh->sigma, &P);
   std::copy(P.begin(), P.end(), perm);
   return HZ_OK;

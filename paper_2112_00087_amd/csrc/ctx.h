@@ -26,6 +26,7 @@ struct SellHost {
 // Host-side assembly products (CSR with sorted columns).
 struct HostAsm {
   int32_t n = 0, ne = 0, nb = 0;
+  int32_t npe = 8, npf = 4;          // nodes per element / boundary face (8, 4: Q1; 4, 3: P1)
   int32_t ntags = 6;                 // boundary tags: 6 walls (+ 6 interface directions)
   std::vector<int64_t> rowptr;
   std::vector<int32_t> col;
@@ -38,7 +39,7 @@ struct HostAsm {
   std::vector<int32_t> prow;
   std::vector<int32_t> pptr, pcol;
   std::vector<double> pval;
-  // mesh copy
+  // mesh copy (hex: npe nodes per element, bface: npf per face)
   std::vector<double> xyz;
   std::vector<int32_t> hex, bface, btag;
   std::vector<uint8_t> bsrc;
@@ -52,9 +53,10 @@ struct HostAsm {
 // and perm receives it (left empty for the mesh's own numbering).
 int host_assemble(const hz_mesh* mesh, const double* eta, HostAsm* out, int ntags = 6,
                   std::vector<int32_t>* perm = nullptr);
-// CSR pattern of the node graph of a hexahedral mesh (row i: the sorted nodes
-// of the elements around node i) and the node -> element adjacency.
-int mesh_pattern(int64_t n, int64_t ne, const int32_t* hex, std::vector<int64_t>* n2e_ptr,
+// CSR pattern of the node graph of a mesh with npe nodes per element (row i:
+// the sorted nodes of the elements around node i) and the node -> element
+// adjacency.
+int mesh_pattern(int64_t n, int64_t ne, int npe, const int32_t* hex, std::vector<int64_t>* n2e_ptr,
                  std::vector<int32_t>* n2e, std::vector<int64_t>* rowptr, std::vector<int32_t>* col);
 // Internal node numbering for a pattern: position p holds node perm[p].
 // order HZ_ORDER_RCM: reverse Cuthill-McKee; sigma > 0: rows sorted by

@@ -88,6 +88,7 @@ int check_structured(hz_ctx ctx) {
   const int64_t nx = ctx->elems[0], ny = ctx->elems[1], nz = ctx->elems[2];
   if (nx < 1 || ny < 1 || nz < 1) return hz_fail(HZ_ERR_INVALID, "Schwarz needs mesh->elems of a structured box");
   if (!ctx->perm.empty()) return hz_fail(HZ_ERR_INVALID, "Schwarz needs the mesh's own node numbering");
+  if (a.npe != 8) return hz_fail(HZ_ERR_INVALID, "Schwarz needs a hexahedral mesh");
   if (int64_t(a.n) != (nx + 1) * (ny + 1) * (nz + 1) || int64_t(a.ne) != nx * ny * nz)
     return hz_fail(HZ_ERR_INVALID, "Schwarz: node/element counts do not match elems");
   for (int d = 0; d < 3; ++d)

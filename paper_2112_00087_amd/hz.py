@@ -28,6 +28,15 @@ METHODS = {"gmres": HZ_GMRES, "bicgstab": HZ_BICGSTAB, "schwarz": HZ_SCHWARZ, "b
 PRECISIONS = {"fp64": HZ_FP64, "mixed": HZ_MIXED}
 SPMV_FORMS = {"solver": 0, "complex": 1, "split": 2}
 ORDERS = {"given": 0, "rcm": 1}
+HZ_HEX8, HZ_TET4 = 0, 1
+
+
+def _connectivity(mesh):
+    """Element array and element type of a mesh dict: ``tet`` (4 nodes per
+    element) or ``hex`` (8)."""
+    if "tet" in mesh:
+        return np.ascontiguousarray(mesh["tet"], dtype=np.int32), HZ_TET4
+    return np.ascontiguousarray(mesh["hex"], dtype=np.int32), HZ_HEX8
 
 
 class hz_c128(C.Structure):
@@ -40,7 +49,7 @@ class hz_mesh(C.Structure):
                 ("bface", C.POINTER(C.c_int32)), ("bface_tag", C.POINTER(C.c_int32)),
                 ("bface_src", C.POINTER(C.c_uint8)), ("c", C.c_double), ("rho", C.c_double),
                 ("elems", C.c_int32 * 3), ("parts", C.c_int32 * 3), ("order", C.c_int32),
-                ("sigma", C.c_int32)]
+                ("sigma", C.c_int32), ("elem_type", C.c_int32)]
 
 
 class hz_solve_opts(C.Structure):
@@ -156,11 +165,12 @@ def dd_alpha(k, H, h, sides=2):
 def node_order(mesh, order="rcm", sigma=0):
     """Internal numbering hz_assemble would use (host computation,
     hz_node_order): ``perm[p]`` = mesh node of internal row p."""
-    hexes = np.ascontiguousarray(mesh["hex"], dtype=np.int32)
+    hexes, et = _connectivity(mesh)
     m = hz_mesh()
     m.n_nodes = int(np.asarray(mesh["xyz"]).shape[0])
     m.n_elems = hexes.shape[0]
     m.hex = _np_ptr(hexes, C.c_int32)
+    m.elem_type = et
     m.order = ORDERS[order] if isinstance(order, str) else int(order)
     m.sigma = int(sigma)
     perm = np.empty(m.n_nodes, dtype=np.int32)
@@ -200,9 +210,10 @@ class Helmholtz:
         if not torch.cuda.is_available():
             raise RuntimeError("Helmholtz needs a ROCm GPU (torch.cuda.is_available() is False)")
         L = lib()
+        conn, et = _connectivity(mesh)
         self._keep = dict(
             xyz=np.ascontiguousarray(mesh["xyz"], dtype=np.float64),
-            hex=np.ascontiguousarray(mesh["hex"], dtype=np.int32),
+            hex=conn,
             bface=np.ascontiguousarray(mesh["bface"], dtype=np.int32),
             tag=np.ascontiguousarray(mesh["bface_tag"], dtype=np.int32),
             src=np.ascontiguousarray(mesh["bface_src"], dtype=np.uint8),
@@ -225,6 +236,7 @@ class Helmholtz:
             m.parts[d] = int(pa[d])
         m.order = ORDERS[order] if isinstance(order, str) else int(order)
         m.sigma = int(sigma)
+        m.elem_type = et
         self.n = m.n_nodes
         self.ne = m.n_elems
         self.device = torch.device("cuda", torch.cuda.current_device())

@@ -92,6 +92,7 @@ def test_opts_struct_layout_matches_header():
     # ..., elems[3], parts[3], order, sigma after c and rho
     assert hz.hz_mesh.order.offset == hz.hz_mesh.parts.offset + 12
     assert hz.hz_mesh.sigma.offset == hz.hz_mesh.order.offset + 4
+    assert hz.hz_mesh.elem_type.offset == hz.hz_mesh.sigma.offset + 4
 
 
 def _factor(lam, a0, a1):
@@ -123,8 +124,9 @@ def test_dd_alpha_optimiser_host_only():
 
 def _graph(mesh):
     import scipy.sparse as sp
-    ne, n = mesh["hex"].shape[0], mesh["xyz"].shape[0]
-    E = sp.csr_matrix((np.ones(ne * 8), (np.repeat(np.arange(ne), 8), mesh["hex"].ravel())), shape=(ne, n))
+    conn = mesh["tet"] if "tet" in mesh else mesh["hex"]
+    ne, n, npe = conn.shape[0], mesh["xyz"].shape[0], conn.shape[1]
+    E = sp.csr_matrix((np.ones(ne * npe), (np.repeat(np.arange(ne), npe), conn.ravel())), shape=(ne, n))
     G = (E.T @ E).tocsr()
     G.sort_indices()
     return G
@@ -137,7 +139,8 @@ def _bandwidth(G, perm):
     return int(np.abs(ip[c.row] - ip[c.col]).max())
 
 
-def test_node_order_host_only():
+@pytest.mark.parametrize("kind", ["hex", "tet"])
+def test_node_order_host_only(kind):
     """The internal numbering (host computation, no GPU): a permutation; the
     reverse Cuthill-McKee band is as narrow as scipy's implementation of the
     same method gives (an independent library routine) and far below the
@@ -145,7 +148,7 @@ def test_node_order_host_only():
     rows ordered by row length, longest first, holding the same nodes."""
     from scipy.sparse.csgraph import reverse_cuthill_mckee
     import paper_2112_00087_amd as P
-    mesh = W.kuhn_hex_mesh(6, 4, 4)
+    mesh = W.kuhn_hex_mesh(6, 4, 4) if kind == "hex" else W.kuhn_tet_mesh(12, 8, 8)
     n = mesh["n_nodes"]
     G = _graph(mesh)
     rl = np.diff(G.indptr)
@@ -185,3 +188,23 @@ def test_assemble_rejects_reordered_schwarz_without_gpu(L):
     assert "numbering" in hz.last_error()
     m.order, m.sigma = 0, 96
     assert L.hz_assemble(C.byref(m), beta, None, None, C.byref(out)) == hz.HZ_ERR_INVALID
+
+
+def test_assemble_rejects_bad_element_type_without_gpu(L):
+    out = C.c_void_p(1)
+    beta = hz._beta_array(np.zeros(6))
+    m, keep = _mesh_struct(W.box_mesh(2, 2, 2))
+    m.elem_type = 2
+    assert L.hz_assemble(C.byref(m), beta, None, None, C.byref(out)) == hz.HZ_ERR_INVALID
+    assert "element type" in hz.last_error()
+    # tetrahedra with a node id out of range (4 ids per element are read)
+    t = W.kuhn_tet_mesh(2, 2, 1)
+    conn = np.ascontiguousarray(t["tet"], np.int32)
+    conn[-1, 3] = t["n_nodes"]
+    m2 = hz.hz_mesh()
+    m2.n_nodes, m2.n_elems = t["n_nodes"], conn.shape[0]
+    m2.hex = conn.ctypes.data_as(C.POINTER(C.c_int32))
+    m2.elem_type = hz.HZ_TET4
+    perm = np.empty(t["n_nodes"], np.int32)
+    assert L.hz_node_order(C.byref(m2), perm.ctypes.data_as(C.POINTER(C.c_int32))) == hz.HZ_ERR_INVALID
+    assert "out of range" in hz.last_error()

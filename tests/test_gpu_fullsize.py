@@ -67,13 +67,15 @@ def test_bicgstab_full_size_residual_by_oracle(c1, method, l):
     assert abs(rel - info["relres_true"]) <= 1e-3 * rel
 
 
-@pytest.fixture(scope="module")
-def c5():
-    """Unstructured workload (48x32x32 Kuhn cells, 1,302,753 randomly numbered
-    nodes) in the row numbering the unstructured bench leg times."""
+@pytest.fixture(scope="module", params=[5, 6])
+def c5(request):
+    """Unstructured workloads (48x32x32 Kuhn cells split into 1,179,648
+    hexahedra, 1,302,753 nodes; 144x96x96 cells of 7,962,624 P1 tetrahedra,
+    1,364,305 nodes; random node numbering) in the row numbering the
+    unstructured bench leg times."""
     import paper_2112_00087_amd as P
     assert torch.cuda.is_available()
-    wl = W.workload(5)
+    wl = W.workload(request.param)
     model = P.Helmholtz(wl["mesh"], wl["beta"], order="rcm", sigma=256)
     model.set_frequency(wl["freqs"][0])
     yield wl, model
@@ -87,7 +89,7 @@ def test_unstructured_spmv_sampled_rows_full_size(c5):
     rng = np.random.default_rng(23)
     perm = model.layout()["perm"]
     # random rows, the first and last internal rows, and the longest rows
-    rl = np.bincount(mesh["hex"].ravel(), minlength=n)
+    rl = np.bincount((mesh["tet"] if "tet" in mesh else mesh["hex"]).ravel(), minlength=n)
     rows = np.unique(np.concatenate([rng.choice(n, 3000, replace=False), perm[:70], perm[-70:],
                                      np.argsort(rl)[-50:]]))
     x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
@@ -102,7 +104,7 @@ def test_unstructured_full_size_residual_by_oracle(c5):
     wl, model = c5
     f = model.load(torch.as_tensor(wl["g"], device="cuda"))
     p, info = model.solve(f, method="bicgstabl", restart=4, tol=1e-8, max_matvec=100000)
-    say("full-size unstructured bicgstab(4)", info)
+    say("full-size unstructured bicgstab(4)", wl["name"], info)
     assert info["status"] == 0
     p = p.cpu().numpy()
     fo = H.load_elementwise(wl["mesh"], wl["g"])

@@ -1,6 +1,7 @@
 """GPU path on unstructured meshes (randomly numbered hexahedra from split
-Kuhn tetrahedra) under each internal row numbering: the caller's, reverse
-Cuthill-McKee, and either with the length sort of the sliced-ELL rows.
+Kuhn tetrahedra, and the Kuhn tetrahedra themselves as P1 elements) under
+each internal row numbering: the caller's, reverse Cuthill-McKee, and either
+with the length sort of the sliced-ELL rows.
 Vectors cross the C ABI in the mesh's numbering, so every result is compared
 with the oracle element by element in that numbering."""
 import sys
@@ -15,6 +16,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 ORDERS = [("given", 0), ("rcm", 0), ("rcm", 256), ("given", 1024)]
+WL = {"hex": 5, "tet": 6}
 
 
 def say(*a):
@@ -37,14 +39,17 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-# (16, 12, 10): 50k nodes, so the caller's random numbering has column
-# offsets beyond int16 and the split form falls back to int32 columns
+# (16, 12, 10) hexahedral and (40, 30, 30) tetrahedral cells: 50k and 39k
+# nodes, so the caller's random numbering has column offsets beyond int16 and
+# the split form falls back to int32 columns
 @pytest.mark.parametrize("order,sigma", ORDERS)
-@pytest.mark.parametrize("cells,with_eta", [((2, 2, 1), False), ((5, 4, 3), True), ((10, 8, 6), False),
-                                            ((16, 12, 10), False)])
-def test_unstructured_spmv_diag_load_parity(P, cells, with_eta, order, sigma):
-    say("unstructured spmv parity", cells, with_eta, order, sigma)
-    wl = W.workload(5, elems=cells)
+@pytest.mark.parametrize("kind,cells,with_eta", [("hex", (2, 2, 1), False), ("hex", (5, 4, 3), True),
+                                                 ("hex", (10, 8, 6), False), ("hex", (16, 12, 10), False),
+                                                 ("tet", (4, 3, 3), False), ("tet", (12, 8, 8), True),
+                                                 ("tet", (40, 30, 30), False)])
+def test_unstructured_spmv_diag_load_parity(P, kind, cells, with_eta, order, sigma):
+    say("unstructured spmv parity", kind, cells, with_eta, order, sigma)
+    wl = W.workload(WL[kind], elems=cells)
     mesh = wl["mesh"]
     rng = np.random.default_rng(11)
     eta = rng.uniform(0, 0.02, mesh["n_elems"]) if with_eta else None
@@ -100,14 +105,15 @@ def test_unstructured_layout(P):
     assert out[("given", 1024)][0] < 0.5 * out[("given", 0)][0]
 
 
-@pytest.fixture(scope="module")
-def u1(P):
-    wl = W.workload(5, elems=(10, 8, 6))
+@pytest.fixture(scope="module", params=["hex", "tet"])
+def u1(P, request):
+    cells = (10, 8, 6) if request.param == "hex" else (30, 20, 20)
+    wl = W.workload(WL[request.param], elems=cells)
     S = H.System(wl["mesh"], wl["beta"])
     A = S.operator(W.wavenumber(wl["freqs"][0]))
     f = S.load(wl["g"])
     x = direct.SparseLU(A).solve(f)
-    return dict(wl=wl, A=A, f=f, x=x)
+    return dict(wl=wl, A=A, f=f, x=x, kind=request.param)
 
 
 @pytest.mark.parametrize("order,sigma", [("given", 0), ("rcm", 256)])
@@ -115,7 +121,7 @@ def u1(P):
                                                       ("gmres", "fp64", 50), ("bicgstabl", "fp64", 4),
                                                       ("tfqmr", "mixed", 0)])
 def test_unstructured_solve_matches_oracle(P, u1, order, sigma, method, precision, restart):
-    say("unstructured solve", order, sigma, method, precision)
+    say("unstructured solve", u1["kind"], order, sigma, method, precision)
     wl = u1["wl"]
     m = P.Helmholtz(wl["mesh"], wl["beta"], order=order, sigma=sigma)
     m.set_frequency(wl["freqs"][0])
@@ -132,10 +138,11 @@ def test_unstructured_solve_matches_oracle(P, u1, order, sigma, method, precisio
     m.close()
 
 
+@pytest.mark.parametrize("kind", ["hex", "tet"])
 @pytest.mark.parametrize("method,precision", [("tfqmr", "fp64"), ("bicgstabl", "fp64"), ("gmres", "mixed")])
-def test_unstructured_sweep_matches_oracle(P, method, precision):
-    say("unstructured sweep", method, precision)
-    wl = W.workload(5, elems=(6, 4, 4))
+def test_unstructured_sweep_matches_oracle(P, kind, method, precision):
+    say("unstructured sweep", kind, method, precision)
+    wl = W.workload(WL[kind], elems=(6, 4, 4) if kind == "hex" else (12, 8, 8))
     mesh = wl["mesh"]
     freqs = np.array([40.0, 120.0, 200.0, 260.0, 300.0])
     S = H.System(mesh, wl["beta"])
@@ -156,11 +163,12 @@ def test_unstructured_sweep_matches_oracle(P, method, precision):
     model.close()
 
 
-def test_unstructured_adjoint_gradient_matches_oracle(P):
+@pytest.mark.parametrize("kind", ["hex", "tet"])
+def test_unstructured_adjoint_gradient_matches_oracle(P, kind):
     """Adjoint gradient with an absorption field under the reordered
     numbering: element- and wall-indexed results stay in the mesh's order."""
-    say("unstructured adjoint")
-    wl = W.workload(5, elems=(4, 3, 3))
+    say("unstructured adjoint", kind)
+    wl = W.workload(WL[kind], elems=(4, 3, 3) if kind == "hex" else (8, 6, 6))
     mesh = wl["mesh"]
     rng = np.random.default_rng(5)
     eta = rng.uniform(0.0, 0.02, mesh["n_elems"])
@@ -190,3 +198,30 @@ def test_unstructured_adjoint_gradient_matches_oracle(P):
     assert np.linalg.norm(db - dbo) <= 1e-6 * np.linalg.norm(dbo)
     assert np.linalg.norm(de - deo) <= 1e-6 * np.linalg.norm(deo)
     model.close()
+
+
+def test_tet_layout(P):
+    """Tetrahedral rows (P1 Kuhn: 15 entries inside, fewer on the walls):
+    RCM narrows the random numbering's band and the sorted slices pad less."""
+    wl = W.workload(6, elems=(24, 16, 16))
+    mesh = wl["mesh"]
+    out = {}
+    for order, sigma in (("given", 0), ("rcm", 0), ("rcm", 256)):
+        m = P.Helmholtz(mesh, wl["beta"], order=order, sigma=sigma)
+        lay = m.layout()
+        assert np.array_equal(lay["perm"], P.node_order(mesh, order, sigma))
+        out[(order, sigma)] = (lay["slots"] / m.sizes()["nnz"], lay["bandwidth"])
+        m.close()
+    say("  padding, bandwidth:", out)
+    assert out[("rcm", 0)][1] < out[("given", 0)][1] / 10
+    assert out[("rcm", 256)][0] < out[("given", 0)][0]
+
+
+def test_schwarz_rejects_tetrahedra(P):
+    wl = W.workload(6, elems=(4, 3, 3))
+    m = P.Helmholtz(wl["mesh"], wl["beta"])
+    m.set_frequency(100.0)
+    f = m.load(_t(wl["g"]))
+    with pytest.raises(P.HzError):
+        m.solve(f, method="schwarz")
+    m.close()
