@@ -39,10 +39,10 @@ template <typename T> __device__ __forceinline__ z_t zd(cx<T> a) { return ccast<
 template <typename T> __device__ __forceinline__ cx<T> zt(z_t a) { return ccast<T>(a); }
 
 // r = f - A u; restart: rhat = r, p = v = 0.  Partial ||r||^2.
-template <typename T>
+template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_resid(Seg L, SellOp<T> A, BiV<T> V, double* part) {
   Tile t = tile_of(L);
-  z_t y = zd(sell_row(A, t.row, V.u));
+  z_t y = zd(sell_row_form<F>(A, t.row, V.u));
   z_t r = zd(V.f[t.row]) - y;
   cx<T> rs = zt<T>(r);
   V.r[t.row] = rs;
@@ -89,12 +89,13 @@ __global__ void __launch_bounds__(kBlock) k_p(Seg L, const BiSt* st, BiV<T> V) {
   V.p[t.row] = zt<T>(zd(r) + S.beta * p);
 }
 
-// v = A p; partial rhat^H v.
-template <typename T>
+// v = A p; partial rhat^H v.  Instantiated per storage form F of A (one
+// form per kernel keeps the register count, hence the occupancy, of that form).
+template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_v(Seg L, SellOp<T> A, const BiSt* st, BiV<T> V, double* part) {
   Tile t = tile_of(L);
   if (st[t.seg].done) return;
-  cx<T> y = sell_row(A, t.row, V.p);
+  cx<T> y = sell_row_form<F>(A, t.row, V.p);
   V.v[t.row] = y;
   z_t a = zd(V.rhat[t.row]), b = zd(y);
   double q[2] = {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
@@ -130,13 +131,13 @@ __global__ void __launch_bounds__(kBlock) k_s(Seg L, const BiSt* st, BiV<T> V) {
   V.s[t.row] = zt<T>(s);
 }
 
-// t = A s; partials t^H s, t^H t, s^H s.
-template <typename T>
+// t = A s; partials t^H s, t^H t, s^H s (per storage form F, as k_v).
+template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_t(Seg L, SellOp<T> A, const BiSt* st, BiV<T> V, double* part) {
   Tile t = tile_of(L);
   const BiSt& S = st[t.seg];
   if (S.done) return;
-  cx<T> y = sell_row(A, t.row, V.s);
+  cx<T> y = sell_row_form<F>(A, t.row, V.s);
   V.t[t.row] = y;
   z_t a = zd(y), b = zd(V.s[t.row]);
   double q[4] = {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re, norm2(a), norm2(b)};
@@ -279,7 +280,8 @@ int bicgstab_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* 
     return HZ_OK;
   };
   auto enqueue_resid = [&]() -> int {
-    k_resid<T><<<grid, kBlock, 0, s>>>(L, A, V, pt);
+    if (A.val) k_resid<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, V, pt);
+    else k_resid<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, V, pt);
     k_resid_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     HZ_HIP(hipGetLastError());
     ++resid_calls;
@@ -287,10 +289,12 @@ int bicgstab_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* 
   };
   auto enqueue_iter = [&]() -> int {
     k_p<T><<<grid, kBlock, 0, s>>>(L, st, V);
-    k_v<T><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    if (A.val) k_v<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    else k_v<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     k_alpha_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     k_s<T><<<grid, kBlock, 0, s>>>(L, st, V);
-    k_t<T><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    if (A.val) k_t<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    else k_t<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     k_omega_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     k_xr<T><<<grid, kBlock, 0, s>>>(L, st, V, pt);
     k_rho_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);

@@ -91,11 +91,11 @@ __global__ void k_bl_mark(int nseg, BlSt* st, int all) {
 }
 
 // r_0 = f - B x, rt = r_0, u_0 = 0; partial ||r_0||^2.
-template <typename T>
+template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_bl_resid(Seg L, SellOp<T> A, const BlSt* st, BlV<T> V, double* part) {
   Tile t = tile_of(L);
   if (!st[t.seg].restart) return;
-  z_t r = zd(V.f[t.row]) - zd(sell_row(A, t.row, V.x));
+  z_t r = zd(V.f[t.row]) - zd(sell_row_form<F>(A, t.row, V.x));
   cx<T> rs = zt<T>(r);
   V.r[0][t.row] = rs;
   V.rt[t.row] = rs;
@@ -139,13 +139,13 @@ __global__ void __launch_bounds__(kBlock) k_bl_u(Seg L, const BlSt* st, BlV<T> V
 }
 
 // y_{j+1} = B y_j for the chain y (u or r); partial rt^H y_{j+1}.
-template <typename T>
+template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_bl_prod(Seg L, SellOp<T> A, const BlSt* st, const cx<T>* __restrict__ yj,
                                                     cx<T>* __restrict__ yj1, const cx<T>* __restrict__ rt,
                                                     double* part) {
   Tile t = tile_of(L);
   if (bl_off(st[t.seg])) return;
-  cx<T> y = sell_row(A, t.row, yj);
+  cx<T> y = sell_row_form<F>(A, t.row, yj);
   yj1[t.row] = y;
   double q[2] = {0.0, 0.0};
   acc_dot(q, zd(rt[t.row]), zd(y));
@@ -431,7 +431,8 @@ int bicgstabl_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>*
   };
   auto enqueue_resid = [&](int all) -> int {
     k_bl_mark<<<ceil_div(S.nseg, kBlock), kBlock, 0, s>>>(S.nseg, st, all);
-    k_bl_resid<T><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    if (A.val) k_bl_resid<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    else k_bl_resid<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     k_bl_resid_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     HZ_HIP(hipGetLastError());
     ++resid_calls;
@@ -440,10 +441,12 @@ int bicgstabl_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>*
   auto enqueue_cycle = [&]() -> int {
     for (int j = 0; j < l; ++j) {
       k_bl_u<T><<<grid, kBlock, 0, s>>>(L, st, V, j);
-      k_bl_prod<T><<<grid, kBlock, 0, s>>>(L, A, st, V.u[j], V.u[j + 1], V.rt, pt);
+      if (A.val) k_bl_prod<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V.u[j], V.u[j + 1], V.rt, pt);
+      else k_bl_prod<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V.u[j], V.u[j + 1], V.rt, pt);
       k_bl_alpha_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
       k_bl_r<T><<<grid, kBlock, 0, s>>>(L, st, V, j);
-      k_bl_prod<T><<<grid, kBlock, 0, s>>>(L, A, st, V.r[j], V.r[j + 1], V.rt, pt);
+      if (A.val) k_bl_prod<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V.r[j], V.r[j + 1], V.rt, pt);
+      else k_bl_prod<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V.r[j], V.r[j + 1], V.rt, pt);
       if (j + 1 < l) k_bl_beta_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     }
     switch (l) {

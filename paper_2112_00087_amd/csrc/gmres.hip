@@ -35,12 +35,12 @@ struct GmArr {         // per-segment small arrays (FP64)
 template <typename T> __device__ __forceinline__ z_t zd(cx<T> a) { return ccast<double>(a); }
 
 // V0 = f - A u; partial ||V0||^2
-template <typename T>
+template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_resid(Seg L, SellOp<T> A, const cx<T>* __restrict__ f,
                                                   const cx<T>* __restrict__ u, cx<T>* __restrict__ V0,
                                                   double* part) {
   Tile t = tile_of(L);
-  z_t r = zd(f[t.row]) - zd(sell_row(A, t.row, u));
+  z_t r = zd(f[t.row]) - zd(sell_row_form<F>(A, t.row, u));
   cx<T> rs = ccast<T>(r);
   V0[t.row] = rs;
   double q[1] = {norm2(zd(rs))};
@@ -79,12 +79,12 @@ __global__ void __launch_bounds__(kBlock) k_scale(Seg L, const GmSt* st, cx<T>* 
 }
 
 // w = A V_j
-template <typename T>
+template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_arnoldi_spmv(Seg L, SellOp<T> A, const GmSt* st,
                                                          const cx<T>* __restrict__ Vj, cx<T>* __restrict__ w) {
   Tile t = tile_of(L);
   if (st[t.seg].cyc) return;
-  w[t.row] = sell_row(A, t.row, Vj);
+  w[t.row] = sell_row_form<F>(A, t.row, Vj);
 }
 
 // partial h_i = V_i^H w for i in chunk blockIdx.y (i <= j)
@@ -305,7 +305,8 @@ int gmres_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
   const int grid = S.nblk;
   for (;;) {
     // residual of the current iterate; converged segments stop here
-    k_resid<T><<<grid, kBlock, 0, s>>>(L, A, f, u, V, pt);
+    if (A.val) k_resid<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, f, u, V, pt);
+    else k_resid<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, f, u, V, pt);
     k_beta_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, G, pt);
     HZ_HIP(hipGetLastError());
     int mc = int(std::min<int64_t>(m, ctl.max_matvec - mv_max - 1));
@@ -315,7 +316,8 @@ int gmres_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
         cx<T>* w = V + int64_t(j + 1) * ld;
         dim3 gd(grid, ceil_div(j + 1, NV));
         dim3 gf(S.nseg, j + 1);
-        k_arnoldi_spmv<T><<<grid, kBlock, 0, s>>>(L, A, st, V + int64_t(j) * ld, w);
+        if (A.val) k_arnoldi_spmv<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V + int64_t(j) * ld, w);
+        else k_arnoldi_spmv<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V + int64_t(j) * ld, w);
         k_mdot<T><<<gd, kBlock, 0, s>>>(L, st, V, ld, j, w, pt);
         k_mdot_fin<<<gf, kFinBlock, 0, s>>>(L, st, G, pt, j, 1);
         k_axpy<T, false><<<grid, kBlock, 0, s>>>(L, st, G, V, ld, j, 1, w, pt);

@@ -17,12 +17,13 @@ __global__ void k_seg_fin1(Seg L, const double* part, double* out) {
   if (threadIdx.x == 0) out[s] = o[0];
 }
 
-// r = f - A u (FP64), partial ||r||^2.
+// r = f - A u (FP64), partial ||r||^2; per storage form F of A.
+template <int F>
 __global__ void __launch_bounds__(kBlock) k_true_resid(Seg L, SellOp<double> A, const z_t* __restrict__ f,
                                                        const z_t* __restrict__ u, z_t* __restrict__ r,
                                                        double* part) {
   Tile t = tile_of(L);
-  z_t v = f[t.row] - sell_row(A, t.row, u);
+  z_t v = f[t.row] - sell_row_form<F>(A, t.row, u);
   if (r) r[t.row] = v;
   double q[1] = {norm2(v)};
   store_partials<1>(q, part, t.tile);
@@ -61,7 +62,8 @@ int true_residual(hz_ctx ctx, const SegHost& S, const SellOp<double>& A, const z
   if (rc) return rc;
   DevBuf* res = ctx->buf("tres.out", sizeof(double) * S.nseg, &rc);
   if (rc) return rc;
-  k_true_resid<<<S.nblk, kBlock, 0, ctx->stream>>>(S.dev, A, f, u, r, part->as<double>());
+  if (A.val) k_true_resid<kFormComplex><<<S.nblk, kBlock, 0, ctx->stream>>>(S.dev, A, f, u, r, part->as<double>());
+  else k_true_resid<kFormSplit><<<S.nblk, kBlock, 0, ctx->stream>>>(S.dev, A, f, u, r, part->as<double>());
   k_seg_fin1<<<S.nseg, kFinBlock, 0, ctx->stream>>>(S.dev, part->as<double>(), res->as<double>());
   HZ_HIP(hipGetLastError());
   return fetch_seg(ctx, S, res->as<double>(), rr);

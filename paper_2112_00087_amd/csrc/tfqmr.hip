@@ -76,11 +76,11 @@ __global__ void k_tq_mark(int nseg, TqSt* st, int all) {
 }
 
 // r0 = f - B x; r* = w = u = r0; d = 0; partial ||r0||^2
-template <typename T>
+template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_tq_resid(Seg L, SellOp<T> A, const TqSt* st, TqV<T> V, double* part) {
   Tile t = tile_of(L);
   if (!st[t.seg].restart) return;
-  const cx<T> r = zt<T>(zd(V.f[t.row]) - zd(sell_row(A, t.row, V.x)));
+  const cx<T> r = zt<T>(zd(V.f[t.row]) - zd(sell_row_form<F>(A, t.row, V.x)));
   V.rs[t.row] = r;
   V.w[t.row] = r;
   V.u[t.row] = r;
@@ -114,13 +114,13 @@ __global__ void k_tq_resid_fin(Seg L, TqSt* st, const double* part) {
 }
 
 // v = uhat = B u for restarting segments; partial r*^H v
-template <typename T>
+template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_tq_resid_prod(Seg L, SellOp<T> A, const TqSt* st, TqV<T> V,
                                                           double* part) {
   Tile t = tile_of(L);
   const TqSt& S = st[t.seg];
   if (!S.restart || S.done) return;
-  const cx<T> y = sell_row(A, t.row, V.u);
+  const cx<T> y = sell_row_form<F>(A, t.row, V.u);
   V.v[t.row] = y;
   V.uh[t.row] = y;
   double q[2] = {0.0, 0.0};
@@ -182,14 +182,14 @@ __global__ void k_tq_qmr_fin(Seg L, TqSt* st, const double* part) {
 }
 
 // x += eta d; then (unless stopping) uhat = B u', u = u'
-template <typename T>
+template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_tq_even2(Seg L, SellOp<T> A, const TqSt* st, TqV<T> V) {
   Tile t = tile_of(L);
   const TqSt& S = st[t.seg];
   if (S.brk || S.nan || (S.done && !S.last)) return;
   V.x[t.row] = zt<T>(zd(V.x[t.row]) + S.eta * zd(V.d[t.row]));
   if (S.done) return;
-  V.uh[t.row] = sell_row(A, t.row, V.un);
+  V.uh[t.row] = sell_row_form<F>(A, t.row, V.un);
   V.u[t.row] = V.un[t.row];
 }
 
@@ -249,11 +249,11 @@ __global__ void __launch_bounds__(kBlock) k_tq_odd2(Seg L, const TqSt* st, TqV<T
 }
 
 // uhat = B u; v = vt + uhat; partial r*^H v
-template <typename T>
+template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_tq_odd3(Seg L, SellOp<T> A, const TqSt* st, TqV<T> V, double* part) {
   Tile t = tile_of(L);
   if (tq_off(st[t.seg])) return;
-  const cx<T> y = sell_row(A, t.row, V.u);
+  const cx<T> y = sell_row_form<F>(A, t.row, V.u);
   V.uh[t.row] = y;
   const cx<T> v = zt<T>(zd(V.vt[t.row]) + zd(y));
   V.v[t.row] = v;
@@ -323,9 +323,11 @@ int tfqmr_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
   };
   auto enqueue_restart = [&](int all) -> int {
     k_tq_mark<<<ceil_div(S.nseg, kBlock), kBlock, 0, s>>>(S.nseg, st, all);
-    k_tq_resid<T><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    if (A.val) k_tq_resid<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    else k_tq_resid<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     k_tq_resid_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
-    k_tq_resid_prod<T><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    if (A.val) k_tq_resid_prod<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    else k_tq_resid_prod<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     k_tq_alpha_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt, 1);
     HZ_HIP(hipGetLastError());
     ++restarts;
@@ -334,11 +336,13 @@ int tfqmr_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
   auto enqueue_pair = [&]() -> int {
     k_tq_even1<T><<<grid, kBlock, 0, s>>>(L, st, V, pt);
     k_tq_qmr_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
-    k_tq_even2<T><<<grid, kBlock, 0, s>>>(L, A, st, V);
+    if (A.val) k_tq_even2<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V);
+    else k_tq_even2<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V);
     k_tq_odd1<T><<<grid, kBlock, 0, s>>>(L, st, V, pt);
     k_tq_odd_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     k_tq_odd2<T><<<grid, kBlock, 0, s>>>(L, st, V);
-    k_tq_odd3<T><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    if (A.val) k_tq_odd3<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    else k_tq_odd3<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     k_tq_alpha_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt, 0);
     HZ_HIP(hipGetLastError());
     ++pairs;
