@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(kBlock) k_p(Seg L, const BiSt* st, BiV<T> V) {
 // v = A p; partial rhat^H v.  Instantiated per storage form F of A (one
 // form per kernel keeps the register count, hence the occupancy, of that form).
 template <typename T, int F>
-__global__ void __launch_bounds__(kBlock) k_v(Seg L, SellOp<T> A, const BiSt* st, BiV<T> V, double* part) {
+__global__ void HZ_PRODUCT_BOUNDS k_v(Seg L, SellOp<T> A, const BiSt* st, BiV<T> V, double* part) {
   Tile t = tile_of(L);
   if (st[t.seg].done) return;
   cx<T> y = sell_row_form<F>(A, t.row, V.p);
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(kBlock) k_s(Seg L, const BiSt* st, BiV<T> V) {
 
 // t = A s; partials t^H s, t^H t, s^H s (per storage form F, as k_v).
 template <typename T, int F>
-__global__ void __launch_bounds__(kBlock) k_t(Seg L, SellOp<T> A, const BiSt* st, BiV<T> V, double* part) {
+__global__ void HZ_PRODUCT_BOUNDS k_t(Seg L, SellOp<T> A, const BiSt* st, BiV<T> V, double* part) {
   Tile t = tile_of(L);
   const BiSt& S = st[t.seg];
   if (S.done) return;

@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(kBlock) k_bl_u(Seg L, const BlSt* st, BlV<T> V
 
 // y_{j+1} = B y_j for the chain y (u or r); partial rt^H y_{j+1}.
 template <typename T, int F>
-__global__ void __launch_bounds__(kBlock) k_bl_prod(Seg L, SellOp<T> A, const BlSt* st, const cx<T>* __restrict__ yj,
+__global__ void HZ_PRODUCT_BOUNDS k_bl_prod(Seg L, SellOp<T> A, const BlSt* st, const cx<T>* __restrict__ yj,
                                                     cx<T>* __restrict__ yj1, const cx<T>* __restrict__ rt,
                                                     double* part) {
   Tile t = tile_of(L);

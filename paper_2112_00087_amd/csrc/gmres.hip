@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(kBlock) k_scale(Seg L, const GmSt* st, cx<T>* 
 
 // w = A V_j
 template <typename T, int F>
-__global__ void __launch_bounds__(kBlock) k_arnoldi_spmv(Seg L, SellOp<T> A, const GmSt* st,
+__global__ void HZ_PRODUCT_BOUNDS k_arnoldi_spmv(Seg L, SellOp<T> A, const GmSt* st,
                                                          const cx<T>* __restrict__ Vj, cx<T>* __restrict__ w) {
   Tile t = tile_of(L);
   if (st[t.seg].cyc) return;

@@ -80,6 +80,13 @@ __device__ __forceinline__ void split_real(const I* __restrict__ c, const T* __r
 // Storage forms of a SellOp (compile-time selector of sell_row_form).
 enum { kFormComplex = 0, kFormSplit = 1 };
 
+// Launch bounds of the solver kernels that carry a sparse product (T: the
+// vector type).  Capping the FP64 kernels at 6 waves per SIMD lets the
+// compiler give the product loop more registers (measured: 88 VGPRs, 5 waves,
+// 250.5 us per BiCGStab iteration on the 160x96x80 cavity, against 76 VGPRs,
+// 6 waves, 258.5 us uncapped); the complex64 kernels ran slower capped.
+#define HZ_PRODUCT_BOUNDS __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, sizeof(T) == 8 ? 6 : 8)))
+
 // y_row = sum_k A[row, col_k] x[col_k] over the row's sliced-ELL entries,
 // for an operator known to be in form F.
 template <int F, typename T>

@@ -115,7 +115,7 @@ __global__ void k_tq_resid_fin(Seg L, TqSt* st, const double* part) {
 
 // v = uhat = B u for restarting segments; partial r*^H v
 template <typename T, int F>
-__global__ void __launch_bounds__(kBlock) k_tq_resid_prod(Seg L, SellOp<T> A, const TqSt* st, TqV<T> V,
+__global__ void HZ_PRODUCT_BOUNDS k_tq_resid_prod(Seg L, SellOp<T> A, const TqSt* st, TqV<T> V,
                                                           double* part) {
   Tile t = tile_of(L);
   const TqSt& S = st[t.seg];
@@ -183,7 +183,7 @@ __global__ void k_tq_qmr_fin(Seg L, TqSt* st, const double* part) {
 
 // x += eta d; then (unless stopping) uhat = B u', u = u'
 template <typename T, int F>
-__global__ void __launch_bounds__(kBlock) k_tq_even2(Seg L, SellOp<T> A, const TqSt* st, TqV<T> V) {
+__global__ void HZ_PRODUCT_BOUNDS k_tq_even2(Seg L, SellOp<T> A, const TqSt* st, TqV<T> V) {
   Tile t = tile_of(L);
   const TqSt& S = st[t.seg];
   if (S.brk || S.nan || (S.done && !S.last)) return;
@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(kBlock) k_tq_odd2(Seg L, const TqSt* st, TqV<T
 
 // uhat = B u; v = vt + uhat; partial r*^H v
 template <typename T, int F>
-__global__ void __launch_bounds__(kBlock) k_tq_odd3(Seg L, SellOp<T> A, const TqSt* st, TqV<T> V, double* part) {
+__global__ void HZ_PRODUCT_BOUNDS k_tq_odd3(Seg L, SellOp<T> A, const TqSt* st, TqV<T> V, double* part) {
   Tile t = tile_of(L);
   if (tq_off(st[t.seg])) return;
   const cx<T> y = sell_row_form<F>(A, t.row, V.u);
