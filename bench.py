@@ -77,9 +77,17 @@ def sweep_leg(log_fn, precisions=("fp64", "mixed"), method="tfqmr", ell=8):
     F = f[:, None].repeat(1, freqs.size).contiguous()
     opts = dict(method=method, tol=1e-8, max_matvec=200000, restart=ell if method == "bicgstabl" else 30)
     label = {"bicgstabl": f"bicgstab({ell})"}.get(method, method)
-    # warm-up of every path (autotuner, graph capture, allocations)
+    # warm-up of every path the timed sweeps take (the product autotuner runs
+    # once per column count a context meets, compaction included; graph
+    # capture; allocations): one untimed pass of each batched sweep
+    def mixed_opts(o):
+        # complex64 inner solves to 1e-5: of the inner tolerances 1e-2 .. 1e-7
+        # the only one with every TFQMR column converged, and the fastest;
+        # the cap bounds a column that stalls
+        return dict(o, max_matvec=20000, inner_tol=1e-5)
+
     for prec in precisions:
-        m.solve_sweep(freqs[:2], F[:, :2].contiguous(), precision=prec, **opts)
+        m.solve_sweep(freqs, F, precision=prec, **(mixed_opts(opts) if prec == "mixed" else opts))
         log_fn(f"  sweep warm-up {prec} done")
     m.set_frequency(freqs[0])
     m.solve(f, **opts)
@@ -100,10 +108,7 @@ def sweep_leg(log_fn, precisions=("fp64", "mixed"), method="tfqmr", ell=8):
            "T_A_s": T_A, "converged_A": a_ok, "iters_A": a_iters}
     for prec in precisions:
         t = time.perf_counter()
-        # the complex64 recurrences stall on the hard columns: cap their work;
-        # inner tolerance 1e-4 converged most columns in the least time of
-        # 1e-2 .. 1e-5 (TFQMR: 51, 57, 60, 58 of 64)
-        o = dict(opts, max_matvec=20000, inner_tol=1e-4) if prec == "mixed" else opts
+        o = mixed_opts(opts) if prec == "mixed" else opts
         _, infos = m.solve_sweep(freqs, F, precision=prec, **o)
         torch.cuda.synchronize()
         T_B = time.perf_counter() - t

@@ -85,6 +85,16 @@ __device__ __forceinline__ double col_reduce(double v, int s, double* lds /*[4*6
 // L lanes per row, CPL columns per lane (s = L * CPL); block of blockDim.x threads.
 // XCD: block b takes row tile xcd_tile(b) (each XCD a contiguous range, so
 // the rows whose neighbours overlap share that XCD's L2) instead of tile b.
+// In complex64 the stiffness part is applied in difference form,
+// (K z)_i = sum_j K_ij (z_j - z_i), which holds because every row of K sums
+// to zero (constants are in its kernel).  For the smooth fields that dominate
+// a Krylov solve, sum_j K_ij z_j is a small difference of terms of size
+// |K_ii| |z|: accumulated directly in FP32 it loses about log10(1 / (k h)^2)
+// digits (2 to 4 here), the difference form keeps the rounding relative to
+// the result.  The FP64 products keep the direct form.
+template <typename T>
+constexpr bool kDiffK = sizeof(T) == 4;
+
 template <typename T, int L, int CPL, bool RESID, bool XCD>
 __global__ void __launch_bounds__(512) k_spmm(int64_t nrows, int s, RowOp<T> A, const double* __restrict__ kc,
                                               const cx<T>* __restrict__ Z, const cx<T>* __restrict__ F,
@@ -96,9 +106,12 @@ __global__ void __launch_bounds__(512) k_spmm(int64_t nrows, int s, RowOp<T> A, 
   if (L == kWave) row = __builtin_amdgcn_readfirstlane(row);
   double pn = 0.0;
   if (row < nrows) {
-    cx<T> aK[CPL], aM[CPL], aE[CPL];
+    cx<T> aK[CPL], aM[CPL], aE[CPL], zi[CPL];
 #pragma unroll
-    for (int q = 0; q < CPL; ++q) aK[q] = aM[q] = aE[q] = cx<T>{T(0), T(0)};
+    for (int q = 0; q < CPL; ++q) {
+      aK[q] = aM[q] = aE[q] = cx<T>{T(0), T(0)};
+      zi[q] = kDiffK<T> ? Z[int64_t(row) * s + ln + L * q] : cx<T>{T(0), T(0)};
+    }
     const int q0 = A.rowptr[row], q1 = A.rowptr[row + 1];
     for (int q = q0; q < q1; ++q) {
       const int64_t j = A.col[q];
@@ -107,8 +120,8 @@ __global__ void __launch_bounds__(512) k_spmm(int64_t nrows, int s, RowOp<T> A, 
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) {
         cx<T> z = Z[j * s + ln + L * cc];
-        aK[cc].re = fma(kv, z.re, aK[cc].re);
-        aK[cc].im = fma(kv, z.im, aK[cc].im);
+        aK[cc].re = fma(kv, z.re - zi[cc].re, aK[cc].re);   // K z = sum_j K_ij (z_j - z_i)
+        aK[cc].im = fma(kv, z.im - zi[cc].im, aK[cc].im);
         aM[cc].re = fma(mv, z.re, aM[cc].re);
         aM[cc].im = fma(mv, z.im, aM[cc].im);
         aE[cc].re = fma(ev, z.re, aE[cc].re);
@@ -182,9 +195,12 @@ __global__ void __launch_bounds__(kHaloRows) k_spmm_lds(int64_t nrows, int s, Ro
     }
     __syncthreads();
     if (live) {
-      cx<T> aK[CG], aM[CG], aE[CG];
+      cx<T> aK[CG], aM[CG], aE[CG], zi[CG];
 #pragma unroll
-      for (int c = 0; c < CG; ++c) aK[c] = aM[c] = aE[c] = cx<T>{T(0), T(0)};
+      for (int c = 0; c < CG; ++c) {
+        aK[c] = aM[c] = aE[c] = cx<T>{T(0), T(0)};
+        zi[c] = kDiffK<T> ? Z[row * s + cg + c] : cx<T>{T(0), T(0)};
+      }
       for (int q = q0; q < q1; ++q) {
         const int li = A.lidx[q] * CG;
         const T kv = A.K[q], mv = A.M[q];
@@ -192,8 +208,8 @@ __global__ void __launch_bounds__(kHaloRows) k_spmm_lds(int64_t nrows, int s, Ro
 #pragma unroll
         for (int c = 0; c < CG; ++c) {
           const cx<T> z = xs[li + c];
-          aK[c].re = fma(kv, z.re, aK[c].re);
-          aK[c].im = fma(kv, z.im, aK[c].im);
+          aK[c].re = fma(kv, z.re - zi[c].re, aK[c].re);
+          aK[c].im = fma(kv, z.im - zi[c].im, aK[c].im);
           aM[c].re = fma(mv, z.re, aM[c].re);
           aM[c].im = fma(mv, z.im, aM[c].im);
           aE[c].re = fma(ev, z.re, aE[c].re);
