@@ -2406,11 +2406,11 @@ struct TsVec {
   cx<T>* y;      // inner iterate (scaled unknowns)
   cx<T>* rs;     // shadow vector
   cx<T>* w;
-  cx<T>* u;
-  cx<T>* un;
+  cx<T>* u;      // u at the start of a pair of half-steps
+  cx<T>* un;     // u after the even half-step
   cx<T>* v;
-  cx<T>* vt;
-  cx<T>* uh;     // B u
+  cx<T>* uhe;    // B un (product of the even half-step)
+  cx<T>* uh;     // B u (product of the odd half-step, or of a restart)
   cx<T>* d;
   cx<T>* Z;      // D^-1 (product input)
   const cx<T>* dT;
@@ -2533,7 +2533,13 @@ __device__ __forceinline__ void ts_qmr(TsCol& S, double ww) {
   S.m += 1;
 }
 
-// even half-step, part 1: u' = u - alpha v; w -= alpha uh; d = u + g d; partial ||w||^2
+// Buffers of a pair of half-steps: u holds u at the start of the pair, the
+// even half-step writes un (never copied back: the odd half-step reads it and
+// writes the next u into u), the even product writes uhe and the odd (or
+// restart) product writes uh, so the odd half-step's v needs no staging.
+// even half-step, part 1: un = u - alpha v; w -= alpha uh; d = u + g d;
+// Z = D^-1 un (the even product's input; unused if the column stops);
+// partial ||w||^2
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ts_even1(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V,
                                                      double* __restrict__ part) {
@@ -2546,7 +2552,9 @@ __global__ void __launch_bounds__(kBlock) k_ts_even1(int64_t total, int s, const
     const z_t g = (S.theta * S.theta) * cdiv(S.eta, a);
     for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
       const z_t u = ccast<double>(V.u[e]);
-      V.un[e] = ccast<T>(u - a * ccast<double>(V.v[e]));
+      const cx<T> un = ccast<T>(u - a * ccast<double>(V.v[e]));
+      V.un[e] = un;
+      V.Z[e] = ccast<T>(ccast<double>(V.dT[e]) * ccast<double>(un));
       const cx<T> w = ccast<T>(ccast<double>(V.w[e]) - a * ccast<double>(V.uh[e]));
       V.w[e] = w;
       V.d[e] = ccast<T>(u + g * ccast<double>(V.d[e]));
@@ -2570,7 +2578,7 @@ __global__ void k_ts_qmr_fin(int G_, int s, TsCol* st, const double* __restrict_
   if (threadIdx.x == 0) ts_qmr(st[c], ww);
 }
 
-// even half-step, part 2: y += eta d; then (still running) u = u', Z = D^-1 u'
+// even half-step, part 2: y += eta d
 template <typename T>
 __global__ void k_ts_even2(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V) {
   int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
@@ -2578,13 +2586,9 @@ __global__ void k_ts_even2(int64_t total, int s, const TsCol* __restrict__ st, T
   const TsCol& S = st[e & (s - 1)];
   if (!ts_apply(S)) return;
   V.y[e] = ccast<T>(ccast<double>(V.y[e]) + S.eta * ccast<double>(V.d[e]));
-  if (S.idone) return;
-  const cx<T> un = V.un[e];
-  V.u[e] = un;
-  V.Z[e] = ccast<T>(ccast<double>(V.dT[e]) * ccast<double>(un));
 }
 
-// odd half-step, part 1: w -= alpha uh; d = u + g d; partials ||w||^2, r*^H w
+// odd half-step, part 1: w -= alpha uhe; d = un + g d; partials ||w||^2, r*^H w
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ts_odd1(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V,
                                                     double* __restrict__ part) {
@@ -2596,9 +2600,9 @@ __global__ void __launch_bounds__(kBlock) k_ts_odd1(int64_t total, int s, const 
     const z_t a = S.alpha;
     const z_t g = (S.theta * S.theta) * cdiv(S.eta, a);
     for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
-      const cx<T> w = ccast<T>(ccast<double>(V.w[e]) - a * ccast<double>(V.uh[e]));
+      const cx<T> w = ccast<T>(ccast<double>(V.w[e]) - a * ccast<double>(V.uhe[e]));
       V.w[e] = w;
-      V.d[e] = ccast<T>(ccast<double>(V.u[e]) + g * ccast<double>(V.d[e]));
+      V.d[e] = ccast<T>(ccast<double>(V.un[e]) + g * ccast<double>(V.d[e]));
       const z_t wv = ccast<double>(w), r = ccast<double>(V.rs[e]);
       q[0] += norm2(wv);
       q[1] = fma(r.re, wv.re, fma(r.im, wv.im, q[1]));
@@ -2638,7 +2642,7 @@ __global__ void k_ts_odd_fin(int G_, int s, TsCol* st, const double* __restrict_
   }
 }
 
-// odd half-step, part 2: y += eta d; then u = w + beta u, vt = beta uh + beta^2 v, Z = D^-1 u
+// odd half-step, part 2: y += eta d; then u = w + beta un, Z = D^-1 u
 template <typename T>
 __global__ void k_ts_odd2(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V) {
   int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
@@ -2648,13 +2652,12 @@ __global__ void k_ts_odd2(int64_t total, int s, const TsCol* __restrict__ st, Ts
   V.y[e] = ccast<T>(ccast<double>(V.y[e]) + S.eta * ccast<double>(V.d[e]));
   if (S.idone) return;
   const z_t b = S.beta;
-  const cx<T> u = ccast<T>(ccast<double>(V.w[e]) + b * ccast<double>(V.u[e]));
+  const cx<T> u = ccast<T>(ccast<double>(V.w[e]) + b * ccast<double>(V.un[e]));
   V.u[e] = u;
-  V.vt[e] = ccast<T>(b * ccast<double>(V.uh[e]) + (b * b) * ccast<double>(V.v[e]));
   V.Z[e] = ccast<T>(ccast<double>(V.dT[e]) * ccast<double>(u));
 }
 
-// odd half-step, part 3 (after uh = B u): v = vt + uh; partial r*^H v
+// odd half-step, part 3 (after uh = B u): v = uh + beta uhe + beta^2 v; partial r*^H v
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ts_odd3(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V,
                                                     double* __restrict__ part) {
@@ -2662,8 +2665,10 @@ __global__ void __launch_bounds__(kBlock) k_ts_odd3(int64_t total, int s, const 
   const int c = threadIdx.x & (s - 1);
   double q[2] = {0.0, 0.0};
   if (!ts_off(st[c])) {
+    const z_t bt = st[c].beta;
+    const z_t bt2 = bt * bt;
     for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
-      const cx<T> v = ccast<T>(ccast<double>(V.vt[e]) + ccast<double>(V.uh[e]));
+      const cx<T> v = ccast<T>(ccast<double>(V.uh[e]) + (bt * ccast<double>(V.uhe[e]) + bt2 * ccast<double>(V.v[e])));
       V.v[e] = v;
       const z_t a = ccast<double>(V.rs[e]), b = ccast<double>(v);
       q[0] = fma(a.re, b.re, fma(a.im, b.im, q[0]));
@@ -2736,8 +2741,8 @@ int ts_alloc(hz_ctx ctx, int64_t nrows, int s, TsWidth<T>* W) {
   W->part = static_cast<double*>(buf("part", sizeof(double) * std::max<int64_t>(int64_t(W->Gr) * 3, nblk_res) * s));
   W->st = static_cast<TsCol*>(buf("st", sizeof(TsCol) * s));
   W->V = TsVec<T>{};
-  cx<T>** vv[10] = {&W->V.y, &W->V.rs, &W->V.w, &W->V.u, &W->V.un, &W->V.v, &W->V.vt, &W->V.uh, &W->V.d, &W->V.Z};
-  const char* names[10] = {"y", "rs", "w", "u", "un", "v", "vt", "uh", "d", "Z"};
+  cx<T>** vv[10] = {&W->V.y, &W->V.rs, &W->V.w, &W->V.u, &W->V.un, &W->V.v, &W->V.uhe, &W->V.uh, &W->V.d, &W->V.Z};
+  const char* names[10] = {"y", "rs", "w", "u", "un", "v", "uhe", "uh", "d", "Z"};
   for (int i = 0; i < 10; ++i) *vv[i] = static_cast<cx<T>*>(buf(names[i], sizeof(cx<T>) * total));
   if (rc) return rc;
   W->V.dT = W->dT;
@@ -2792,7 +2797,7 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
       k_ts_even1<T><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V, W.part);
       k_ts_qmr_fin<<<s_, kBlock, 0, q>>>(Gr, s_, W.st, W.part);
       k_ts_even2<T><<<eb, kBlock, 0, q>>>(total, s_, W.st, W.V);
-      HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.Z, nullptr, W.V.uh, nullptr, nullptr)));
+      HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.Z, nullptr, W.V.uhe, nullptr, nullptr)));
       k_ts_odd1<T><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V, W.part);
       k_ts_odd_fin<<<s_, kBlock, 0, q>>>(Gr, s_, W.st, W.part);
       k_ts_odd2<T><<<eb, kBlock, 0, q>>>(total, s_, W.st, W.V);
@@ -2899,8 +2904,8 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
       k_gather_cols<z_t><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.X, W2.X);
       k_gather_cols<z_t><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.Fs, W2.Fs);
       k_gather_cols<cx<T>><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.dT, W2.dT);
-      cx<T>* from[10] = {W.V.y, W.V.rs, W.V.w, W.V.u, W.V.un, W.V.v, W.V.vt, W.V.uh, W.V.d, W.V.Z};
-      cx<T>* to[10] = {W2.V.y, W2.V.rs, W2.V.w, W2.V.u, W2.V.un, W2.V.v, W2.V.vt, W2.V.uh, W2.V.d, W2.V.Z};
+      cx<T>* from[10] = {W.V.y, W.V.rs, W.V.w, W.V.u, W.V.un, W.V.v, W.V.uhe, W.V.uh, W.V.d, W.V.Z};
+      cx<T>* to[10] = {W2.V.y, W2.V.rs, W2.V.w, W2.V.u, W2.V.un, W2.V.v, W2.V.uhe, W2.V.uh, W2.V.d, W2.V.Z};
       for (int i = 0; i < 10; ++i) k_gather_cols<cx<T>><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, from[i], to[i]);
       HZ_HIP(hipGetLastError());
       std::vector<TsCol> ns(s2);
@@ -2917,7 +2922,8 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
       cols = ncols;
       HZ_HIP(hipMemcpyAsync(W2.st, ns.data(), sizeof(TsCol) * s2, hipMemcpyHostToDevice, q));
       HZ_TRY(upload_kc(W2, q));
-      HZ_TRY(autotune<T>(ctx, q, nrows, s2, AT, W2.kc, W2.V.Z, W2.V.vt, &W2.vin));
+      // uhe is dead between pairs: scratch output of the tuning runs
+      HZ_TRY(autotune<T>(ctx, q, nrows, s2, AT, W2.kc, W2.V.Z, W2.V.uhe, &W2.vin));
       W = W2;
       std::unique_ptr<Graph> G2(new Graph());
       HZ_TRY(G2->stream(q));
