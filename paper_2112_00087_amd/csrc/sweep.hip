@@ -2578,17 +2578,9 @@ __global__ void k_ts_qmr_fin(int G_, int s, TsCol* st, const double* __restrict_
   if (threadIdx.x == 0) ts_qmr(st[c], ww);
 }
 
-// even half-step, part 2: y += eta d
-template <typename T>
-__global__ void k_ts_even2(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V) {
-  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (e >= total) return;
-  const TsCol& S = st[e & (s - 1)];
-  if (!ts_apply(S)) return;
-  V.y[e] = ccast<T>(ccast<double>(V.y[e]) + S.eta * ccast<double>(V.d[e]));
-}
-
-// odd half-step, part 1: w -= alpha uhe; d = un + g d; partials ||w||^2, r*^H w
+// odd half-step, part 1, with the even half-step's x-update folded in:
+// y += eta d (while the even half-step applies; eta, d of that half-step),
+// then (column running) w -= alpha uhe; d = un + g d; partials ||w||^2, r*^H w
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ts_odd1(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V,
                                                     double* __restrict__ part) {
@@ -2596,13 +2588,18 @@ __global__ void __launch_bounds__(kBlock) k_ts_odd1(int64_t total, int s, const 
   const int c = threadIdx.x & (s - 1);
   const TsCol& S = st[c];
   double q[3] = {0.0, 0.0, 0.0};
-  if (!ts_off(S)) {
+  const bool run = !ts_off(S);
+  if (ts_apply(S)) {
+    const z_t eta = S.eta;
     const z_t a = S.alpha;
-    const z_t g = (S.theta * S.theta) * cdiv(S.eta, a);
+    const z_t g = run ? (S.theta * S.theta) * cdiv(S.eta, a) : z_t{0.0, 0.0};
     for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
+      const z_t dv = ccast<double>(V.d[e]);
+      V.y[e] = ccast<T>(ccast<double>(V.y[e]) + eta * dv);
+      if (!run) continue;
       const cx<T> w = ccast<T>(ccast<double>(V.w[e]) - a * ccast<double>(V.uhe[e]));
       V.w[e] = w;
-      V.d[e] = ccast<T>(ccast<double>(V.un[e]) + g * ccast<double>(V.d[e]));
+      V.d[e] = ccast<T>(ccast<double>(V.un[e]) + g * dv);
       const z_t wv = ccast<double>(w), r = ccast<double>(V.rs[e]);
       q[0] += norm2(wv);
       q[1] = fma(r.re, wv.re, fma(r.im, wv.im, q[1]));
@@ -2796,7 +2793,6 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
     for (int it = 0; it < chunk; ++it) {
       k_ts_even1<T><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V, W.part);
       k_ts_qmr_fin<<<s_, kBlock, 0, q>>>(Gr, s_, W.st, W.part);
-      k_ts_even2<T><<<eb, kBlock, 0, q>>>(total, s_, W.st, W.V);
       HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.Z, nullptr, W.V.uhe, nullptr, nullptr)));
       k_ts_odd1<T><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V, W.part);
       k_ts_odd_fin<<<s_, kBlock, 0, q>>>(Gr, s_, W.st, W.part);
