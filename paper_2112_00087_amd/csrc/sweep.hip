@@ -113,10 +113,7 @@ __global__ void __launch_bounds__(512) k_spmm(int64_t nrows, int s, RowOp<T> A, 
       zi[q] = kDiffK<T> ? Z[int64_t(row) * s + ln + L * q] : cx<T>{T(0), T(0)};
     }
     const int q0 = A.rowptr[row], q1 = A.rowptr[row + 1];
-    for (int q = q0; q < q1; ++q) {
-      const int64_t j = A.col[q];
-      const T kv = A.K[q], mv = A.M[q];
-      const T ev = A.E ? A.E[q] : T(0);
+    auto term = [&](int64_t j, T kv, T mv, T ev) {
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) {
         cx<T> z = Z[j * s + ln + L * cc];
@@ -127,6 +124,28 @@ __global__ void __launch_bounds__(512) k_spmm(int64_t nrows, int s, RowOp<T> A, 
         aE[cc].re = fma(ev, z.re, aE[cc].re);
         aE[cc].im = fma(ev, z.im, aE[cc].im);
       }
+    };
+    if constexpr (L >= 8) {
+      // The L lanes of a row load its entries cooperatively, L at a time
+      // (lane ln takes entry qc + ln), and broadcast them within the row's
+      // lanes: the gathers of consecutive entries no longer wait on a
+      // dependent index load each.
+      for (int qc = q0; qc < q1; qc += L) {
+        const int qq = qc + ln;
+        int jl = row;
+        T kl = T(0), ml = T(0), el = T(0);
+        if (qq < q1) {
+          jl = A.col[qq];
+          kl = A.K[qq];
+          ml = A.M[qq];
+          if (A.E) el = A.E[qq];
+        }
+        const int cnt = min(L, q1 - qc);
+        for (int t = 0; t < cnt; ++t)
+          term(__shfl(jl, t, L), __shfl(kl, t, L), __shfl(ml, t, L), A.E ? __shfl(el, t, L) : T(0));
+      }
+    } else {
+      for (int q = q0; q < q1; ++q) term(A.col[q], A.K[q], A.M[q], A.E ? A.E[q] : T(0));
     }
     const int b0 = A.bptr[row], b1 = A.bptr[row + 1];
 #pragma unroll
