@@ -369,6 +369,18 @@ def main():
             "kernel": f"k_spmv<double, {1 if form == 'split' else 0}> ({form} form sliced-ELL product)",
             "avg_kernel_ms": ms, "algorithmic_bytes": byts}
     log(f"spmv ({form}): {ms * 1e3:.1f} us, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
+    solve_roof = None
+    if args.steps > 0:
+        # whole-solve roofline: per BiCGStab iteration two products plus 16
+        # complex128 vector passes (k_p 4, k_v 1 beyond its product, k_s 3,
+        # k_t 1, k_xr 7), over the iterations the timed solve took
+        it = infos[-1]["iters"]
+        per_it = 2 * byts + 16 * 16 * n
+        solve_roof = {"bytes_per_iteration": per_it, "iterations": it,
+                      "achieved": per_it * it / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": per_it * it / dt / 1e9 / HBM_PEAK_GBS}
+        log(f"solve roofline: {per_it / 1e6:.0f} MB per iteration, {solve_roof['achieved']:.0f} GB/s "
+            f"({100 * solve_roof['frac']:.1f}% of HBM peak)")
 
     extra = {}
     if form != "complex":
@@ -430,6 +442,7 @@ def main():
             k[len("batched_"):]: v["speedup"] for k, v in sweep.items() if k.startswith("batched_")},
         "sweep": sweep,
         "roofline": roof,
+        "solve_roofline": solve_roof,
         "cpu_baseline": cpu,
         "extra": extra,
     }
