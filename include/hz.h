@@ -311,9 +311,14 @@ int hz_dd_alpha(double k, double H, double h, int32_t sides, hz_c128* alpha);
  * fit (else int32 columns), and the imaginary parts of the few entries that
  * can have one: those carrying a wall admittance term or lying in a wall
  * node's column (the Jacobi scaling by a complex wall diagonal).  Both give
- * the same product up to rounding order.  Environment variable HZ_SPLIT=0
- * (read when the context is created) disables the split form. */
-enum { HZ_SPMV_SOLVER = 0, HZ_SPMV_COMPLEX = 1, HZ_SPMV_SPLIT = 2 };
+ * the same product up to rounding order.  On a structured box in its own
+ * numbering (elems set, order HZ_ORDER_GIVEN, sigma 0) the split values are
+ * also stored in stencil form (HZ_SPMV_STENCIL, the solvers' choice there):
+ * 27 slots per row at the fixed neighbour offsets of the box, a missing
+ * neighbour's slot 0, no column indices.  Environment variables HZ_SPLIT=0
+ * and HZ_STENCIL=0 (read when the context is created) disable the split
+ * and the stencil forms. */
+enum { HZ_SPMV_SOLVER = 0, HZ_SPMV_COMPLEX = 1, HZ_SPMV_SPLIT = 2, HZ_SPMV_STENCIL = 3 };
 
 /* Measurement of the sparse product (paper Sec. 4: the product dominates
  * the solve time).  Runs y = A x of the current operator `reps` times
@@ -322,8 +327,8 @@ enum { HZ_SPMV_SOLVER = 0, HZ_SPMV_COMPLEX = 1, HZ_SPMV_SPLIT = 2 };
  * milliseconds.  precision HZ_FP64 times the complex128 product of the FP64
  * solvers; HZ_MIXED the complex64 product of the mixed-precision inner
  * solves.  format: HZ_SPMV_SOLVER (the form the solvers use),
- * HZ_SPMV_COMPLEX or HZ_SPMV_SPLIT (HZ_ERR_STATE if that form is not
- * formed).  x and y are internal buffers.  Host result; synchronises the
+ * HZ_SPMV_COMPLEX, HZ_SPMV_SPLIT or HZ_SPMV_STENCIL (HZ_ERR_STATE if that
+ * form is not formed).  x and y are internal buffers.  Host result; synchronises the
  * stream. */
 int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, int32_t format, double* avg_ms);
 
@@ -334,6 +339,9 @@ int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, int32_t format, do
  *   split form    (r + idx) nnz + (r + 4) n_imag + 4 (n + 1) + 4 r n,
  *                 idx = 2 (int16 offsets) or 4, n_imag = listed imaginary
  *                 entries.
+ *   stencil form  r nnz + (r + 4) n_imag + 4 (n + 1) + 4 r n (missing
+ *                 neighbours' zero slots, 27 n - nnz of them, are storage,
+ *                 not algorithmic bytes).
  * Requires a frequency (HZ_ERR_STATE otherwise). */
 int hz_spmv_bytes(hz_ctx ctx, int32_t precision, int32_t format, int64_t* bytes);
 

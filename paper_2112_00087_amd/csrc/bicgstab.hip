@@ -281,6 +281,7 @@ int bicgstab_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* 
   };
   auto enqueue_resid = [&]() -> int {
     if (A.val) k_resid<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, V, pt);
+    else if (A.st) k_resid<T, kFormStencil><<<grid, kBlock, 0, s>>>(L, A, V, pt);
     else k_resid<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, V, pt);
     k_resid_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     HZ_HIP(hipGetLastError());
@@ -290,10 +291,12 @@ int bicgstab_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* 
   auto enqueue_iter = [&]() -> int {
     k_p<T><<<grid, kBlock, 0, s>>>(L, st, V);
     if (A.val) k_v<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    else if (A.st) k_v<T, kFormStencil><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     else k_v<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     k_alpha_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     k_s<T><<<grid, kBlock, 0, s>>>(L, st, V);
     if (A.val) k_t<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    else if (A.st) k_t<T, kFormStencil><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     else k_t<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     k_omega_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     k_xr<T><<<grid, kBlock, 0, s>>>(L, st, V, pt);

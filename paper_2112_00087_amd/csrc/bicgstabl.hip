@@ -432,6 +432,7 @@ int bicgstabl_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>*
   auto enqueue_resid = [&](int all) -> int {
     k_bl_mark<<<ceil_div(S.nseg, kBlock), kBlock, 0, s>>>(S.nseg, st, all);
     if (A.val) k_bl_resid<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    else if (A.st) k_bl_resid<T, kFormStencil><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     else k_bl_resid<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     k_bl_resid_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     HZ_HIP(hipGetLastError());
@@ -442,10 +443,12 @@ int bicgstabl_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>*
     for (int j = 0; j < l; ++j) {
       k_bl_u<T><<<grid, kBlock, 0, s>>>(L, st, V, j);
       if (A.val) k_bl_prod<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V.u[j], V.u[j + 1], V.rt, pt);
+      else if (A.st) k_bl_prod<T, kFormStencil><<<grid, kBlock, 0, s>>>(L, A, st, V.u[j], V.u[j + 1], V.rt, pt);
       else k_bl_prod<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V.u[j], V.u[j + 1], V.rt, pt);
       k_bl_alpha_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
       k_bl_r<T><<<grid, kBlock, 0, s>>>(L, st, V, j);
       if (A.val) k_bl_prod<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V.r[j], V.r[j + 1], V.rt, pt);
+      else if (A.st) k_bl_prod<T, kFormStencil><<<grid, kBlock, 0, s>>>(L, A, st, V.r[j], V.r[j + 1], V.rt, pt);
       else k_bl_prod<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V.r[j], V.r[j + 1], V.rt, pt);
       if (j + 1 < l) k_bl_beta_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     }

@@ -120,6 +120,7 @@ int hz_set_params(hz_ctx ctx, const hz_c128* beta, const double* eta) {
   ctx->scaled = -1;
   ctx->have_A32 = false;
   ctx->have_split = ctx->have_split32 = false;
+  ctx->have_stencil = ctx->have_stencil32 = false;
   return HZ_OK;
   HZ_GUARD_END
 }
@@ -238,17 +239,25 @@ int hz_solve_adjoint(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* p_dev
 }
 
 namespace {
-// The product of the given form: the solvers' choice, or forced complex / split.
-int spmv_form(hz_ctx ctx, int32_t precision, int32_t format, bool* split) {
+enum { kKindComplex = 0, kKindSplit = 1, kKindStencil = 2 };
+// The product of the given form: the solvers' choice, or a forced form.
+int spmv_form(hz_ctx ctx, int32_t precision, int32_t format, int* kind) {
   if (precision != HZ_FP64 && precision != HZ_MIXED) return hz_fail(HZ_ERR_INVALID, "bad precision");
-  if (format != HZ_SPMV_SOLVER && format != HZ_SPMV_COMPLEX && format != HZ_SPMV_SPLIT)
+  if (format != HZ_SPMV_SOLVER && format != HZ_SPMV_COMPLEX && format != HZ_SPMV_SPLIT &&
+      format != HZ_SPMV_STENCIL)
     return hz_fail(HZ_ERR_INVALID, "bad format");
   const bool mixed = precision == HZ_MIXED;
   HZ_TRY(ensure_operator(ctx, ctx->scaled < 0 ? HZ_JACOBI : ctx->scaled, mixed));
-  const bool have = mixed ? ctx->have_split32 : ctx->have_split;
-  if (format == HZ_SPMV_SPLIT && !have)
+  const bool split = mixed ? ctx->have_split32 : ctx->have_split;
+  const bool stencil = mixed ? ctx->have_stencil32 : ctx->have_stencil;
+  if (format == HZ_SPMV_SPLIT && !split)
     return hz_fail(HZ_ERR_STATE, "split form not formed (absorption field present or HZ_SPLIT=0)");
-  *split = format == HZ_SPMV_SPLIT || (format == HZ_SPMV_SOLVER && have);
+  if (format == HZ_SPMV_STENCIL && !stencil)
+    return hz_fail(HZ_ERR_STATE, "stencil form not formed (not a box in its own numbering, or HZ_STENCIL=0)");
+  if (format == HZ_SPMV_COMPLEX) *kind = kKindComplex;
+  else if (format == HZ_SPMV_SPLIT) *kind = kKindSplit;
+  else if (format == HZ_SPMV_STENCIL || stencil) *kind = kKindStencil;
+  else *kind = split ? kKindSplit : kKindComplex;
   return HZ_OK;
 }
 }  // namespace
@@ -257,8 +266,8 @@ int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, int32_t format, do
   HZ_GUARD_BEGIN
   HZ_TRY(check_ctx(ctx));
   if (!avg_ms || reps < 1 || reps > 100000) return hz_fail(HZ_ERR_INVALID, "bad arguments");
-  bool split = false;
-  HZ_TRY(spmv_form(ctx, precision, format, &split));
+  int kind = 0;
+  HZ_TRY(spmv_form(ctx, precision, format, &kind));
   const bool mixed = precision == HZ_MIXED;
   int rc = 0;
   const int64_t nr = ctx->sell.n_rows;
@@ -268,8 +277,10 @@ int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, int32_t format, do
   DevBuf* yb = ctx->buf("time.y", es * nr, &rc);
   if (rc) return rc;
   HZ_HIP(hipMemsetAsync(xb->p, 0, es * nr, ctx->stream));
-  const SellOp<double> A64 = split ? op_split<double>(ctx) : op_A_complex(ctx);
-  const SellOp<float> A32 = split ? op_split<float>(ctx) : op_A32_complex(ctx);
+  const SellOp<double> A64 = kind == kKindStencil ? op_stencil<double>(ctx)
+                             : kind == kKindSplit  ? op_split<double>(ctx) : op_A_complex(ctx);
+  const SellOp<float> A32 = kind == kKindStencil ? op_stencil<float>(ctx)
+                            : kind == kKindSplit  ? op_split<float>(ctx) : op_A32_complex(ctx);
   auto one = [&]() -> int {
     if (mixed) return op_spmv<float>(ctx->stream, nr, nr, A32, xb->as<c_t>(), yb->as<c_t>());
     return op_spmv<double>(ctx->stream, nr, nr, A64, xb->as<z_t>(), yb->as<z_t>());
@@ -308,12 +319,14 @@ int hz_spmv_bytes(hz_ctx ctx, int32_t precision, int32_t format, int64_t* bytes)
   HZ_GUARD_BEGIN
   HZ_TRY(check_ctx(ctx));
   if (!bytes) return hz_fail(HZ_ERR_INVALID, "bytes is NULL");
-  bool split = false;
-  HZ_TRY(spmv_form(ctx, precision, format, &split));
+  int kind = 0;
+  HZ_TRY(spmv_form(ctx, precision, format, &kind));
   const int64_t n = ctx->h.n, nnz = int64_t(ctx->h.col.size());
   const int64_t real = precision == HZ_MIXED ? 4 : 8;   // bytes of one real part
-  if (!split) {
+  if (kind == kKindComplex) {
     *bytes = (2 * real + 4) * nnz + 4 * (n + 1) + 4 * real * n;
+  } else if (kind == kKindStencil) {
+    *bytes = real * nnz + (real + 4) * ctx->n_imag + 4 * (n + 1) + 4 * real * n;
   } else {
     const int64_t idx = ctx->split_dcol ? 2 : 4;
     *bytes = (real + idx) * nnz + (real + 4) * ctx->n_imag + 4 * (n + 1) + 4 * real * n;

@@ -115,6 +115,14 @@ struct hz_ctx_s {
   DevBuf d_R, d_R32, d_I, d_I32;
   bool have_split = false, have_split32 = false;   // values match the current A / A32
 
+  // stencil form of the split values (structured boxes in their own node
+  // numbering; HZ_STENCIL=0 in the environment turns it off): per slot the
+  // sliced-ELL position it copies, or -1 for a missing neighbour
+  bool stencil_ok = false;
+  StencilOffsets soff = {};
+  DevBuf d_ssrc, d_S, d_S32;
+  bool have_stencil = false, have_stencil32 = false;
+
   std::vector<std::complex<double>> beta;   // [6]
   bool have_eta = false;
   int params_version = 0;            // bumped by hz_set_params

@@ -1,5 +1,6 @@
 // Context lifecycle: device buffers, upload of the assembled operator parts
 // in sliced-ELL layout, error strings.
+#include <algorithm>
 #include <cstdarg>
 #include <cstdlib>
 #include <cstring>
@@ -172,6 +173,39 @@ int ctx_upload(hz_ctx ctx) {
     HZ_TRY(put(ctx, ctx->d_iptr, iptr.data(), iptr.size()));
     HZ_TRY(put(ctx, ctx->d_icol, icol.data(), icol.size()));
     HZ_TRY(put(ctx, ctx->d_ipos, ipos.data(), ipos.size()));
+  }
+  {
+    // Stencil form: a box in its own numbering stores the split values in 27
+    // slots per row at the fixed neighbour offsets, without column indices.
+    const char* env = std::getenv("HZ_STENCIL");
+    const int64_t nx = ctx->elems[0], ny = ctx->elems[1], nz = ctx->elems[2];
+    ctx->stencil_ok = false;
+    if (!(env && env[0] == '0') && ctx->split_on && ctx->perm.empty() && a.npe == 8 && nx > 0 && ny > 0 &&
+        nz > 0 && int64_t(a.n) == (nx + 1) * (ny + 1) * (nz + 1)) {
+      StencilOffsets off;
+      int t = 0;
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) off.o[t++] = int(dx + (nx + 1) * (dy + (ny + 1) * dz));
+      std::vector<int32_t> src(int64_t(kStencil) * nrows, -1);
+      bool ok = true;
+      for (int64_t i = 0; i < a.n && ok; ++i)
+        for (int64_t q = a.rowptr[i]; q < a.rowptr[i + 1]; ++q) {
+          const int64_t d = int64_t(a.col[q]) - i;
+          const int* k = std::lower_bound(off.o, off.o + kStencil, int(d));
+          if (k == off.o + kStencil || *k != d) {
+            ok = false;
+            break;
+          }
+          src[(i / kWave) * kStencil * kWave + (k - off.o) * kWave + i % kWave] =
+              int32_t(s.ptr[i / kWave] + (q - a.rowptr[i]) * kWave + i % kWave);
+        }
+      if (ok) {
+        HZ_TRY(put(ctx, ctx->d_ssrc, src.data(), src.size()));
+        ctx->soff = off;
+        ctx->stencil_ok = true;
+      }
+    }
   }
   HZ_TRY(put(ctx, ctx->d_bmass, a.bmass.data(), a.bmass.size()));
   // The load and the gradient kernels work on caller-ordered vectors: their

@@ -306,6 +306,7 @@ int gmres_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
   for (;;) {
     // residual of the current iterate; converged segments stop here
     if (A.val) k_resid<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, f, u, V, pt);
+    else if (A.st) k_resid<T, kFormStencil><<<grid, kBlock, 0, s>>>(L, A, f, u, V, pt);
     else k_resid<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, f, u, V, pt);
     k_beta_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, G, pt);
     HZ_HIP(hipGetLastError());
@@ -317,6 +318,7 @@ int gmres_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
         dim3 gd(grid, ceil_div(j + 1, NV));
         dim3 gf(S.nseg, j + 1);
         if (A.val) k_arnoldi_spmv<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V + int64_t(j) * ld, w);
+        else if (A.st) k_arnoldi_spmv<T, kFormStencil><<<grid, kBlock, 0, s>>>(L, A, st, V + int64_t(j) * ld, w);
         else k_arnoldi_spmv<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V + int64_t(j) * ld, w);
         k_mdot<T><<<gd, kBlock, 0, s>>>(L, st, V, ld, j, w, pt);
         k_mdot_fin<<<gf, kFinBlock, 0, s>>>(L, st, G, pt, j, 1);

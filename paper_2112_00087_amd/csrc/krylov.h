@@ -33,6 +33,16 @@ struct Seg {
 //    (FP32) bytes per entry instead of 16 or 8.
 //  Column indices are int32 (col) or, when every |col - row| fits, int16
 //  offsets from the row (dcol).
+//  stencil form (st != NULL, structured boxes): the split form's real parts
+//    stored with implied columns: slot k of every row is the neighbour at
+//    offset soff[k] (the 27 neighbours of a node of the box, ascending), a
+//    missing neighbour holds 0; 64-row slices of 27 slots, slot k of lane l
+//    at 27 * 64 * slice + 64 k + l.  No index is streamed; the imaginary
+//    entries are the split form's row lists.
+constexpr int kStencil = 27;
+struct StencilOffsets {
+  int o[kStencil];
+};
 template <typename T>
 struct SellOp {
   const int* ptr = nullptr;       // [nrows / 64 + 1] slice offsets
@@ -43,6 +53,9 @@ struct SellOp {
   const int* iptr = nullptr;      // [nrows + 1] imaginary entries of each row
   const int* icol = nullptr;
   const T* iim = nullptr;
+  const T* st = nullptr;          // stencil form
+  int64_t nrows = 0;              // stencil form: rows of the vectors (gathers are clamped to them)
+  StencilOffsets soff = {};
 };
 
 // Non-temporal loads for the streamed matrix data (read once per product):
@@ -78,7 +91,7 @@ __device__ __forceinline__ void split_real(const I* __restrict__ c, const T* __r
 }
 
 // Storage forms of a SellOp (compile-time selector of sell_row_form).
-enum { kFormComplex = 0, kFormSplit = 1 };
+enum { kFormComplex = 0, kFormSplit = 1, kFormStencil = 2 };
 
 // Launch bounds of the solver kernels that carry a sparse product (T: the
 // vector type).  Capping the FP64 kernels at 6 waves per SIMD lets the
@@ -91,10 +104,10 @@ enum { kFormComplex = 0, kFormSplit = 1 };
 // for an operator known to be in form F.
 template <int F, typename T>
 __device__ __forceinline__ cx<T> sell_row_form(const SellOp<T>& A, int64_t row, const cx<T>* __restrict__ x) {
-  int slice = int(row >> 6), lane = int(row & 63);
-  int beg = A.ptr[slice];
-  int w = (A.ptr[slice + 1] - beg) >> 6;
-  if (F == kFormComplex) {
+  const int slice = int(row >> 6), lane = int(row & 63);
+  if constexpr (F == kFormComplex) {
+    const int beg = A.ptr[slice];
+    const int w = (A.ptr[slice + 1] - beg) >> 6;
     const int* __restrict__ c = A.col + beg + lane;
     const cx<T>* __restrict__ v = A.val + beg + lane;
     cx<T> acc = {T(0), T(0)};
@@ -108,8 +121,26 @@ __device__ __forceinline__ cx<T> sell_row_form(const SellOp<T>& A, int64_t row, 
     return acc;
   }
   T ar = T(0), ai = T(0);
-  if (A.dcol) split_real(A.dcol + beg + lane, A.re + beg + lane, w, row, x, ar, ai);
-  else split_real(A.col + beg + lane, A.re + beg + lane, w, row, x, ar, ai);
+  if constexpr (F == kFormStencil) {
+    // slot k: neighbour row + soff[k]; a missing neighbour's slot is 0, its
+    // gather is clamped into the vector (any row; it is multiplied by 0)
+    const T* __restrict__ v = A.st + int64_t(slice) * (kStencil * 64) + lane;
+    const int64_t last = A.nrows - 1;
+#pragma unroll 9
+    for (int k = 0; k < kStencil; ++k) {
+      int64_t j = row + A.soff.o[k];
+      j = j < 0 ? 0 : (j > last ? last : j);
+      const T a = ld_stream(v + (k << 6));
+      const cx<T> xv = x[j];
+      ar = fma(a, xv.re, ar);
+      ai = fma(a, xv.im, ai);
+    }
+  } else {
+    const int beg = A.ptr[slice];
+    const int w = (A.ptr[slice + 1] - beg) >> 6;
+    if (A.dcol) split_real(A.dcol + beg + lane, A.re + beg + lane, w, row, x, ar, ai);
+    else split_real(A.col + beg + lane, A.re + beg + lane, w, row, x, ar, ai);
+  }
   const int q1 = A.iptr[row + 1];
   for (int q = A.iptr[row]; q < q1; ++q) {
     T b = A.iim[q];                 // i b x = -b x.im + i b x.re
@@ -120,11 +151,6 @@ __device__ __forceinline__ cx<T> sell_row_form(const SellOp<T>& A, int64_t row, 
   return cx<T>{ar, ai};
 }
 
-// The same for an operator of either form (a uniform branch on A.val).
-template <typename T>
-__device__ __forceinline__ cx<T> sell_row(const SellOp<T>& A, int64_t row, const cx<T>* __restrict__ x) {
-  return A.val ? sell_row_form<kFormComplex>(A, row, x) : sell_row_form<kFormSplit>(A, row, x);
-}
 
 // Block geometry of a segmented kernel: tile, row, segment.  Tiles follow the
 // dispatch order (workgroup b takes rows [256 b, 256 b + 256)); measured on

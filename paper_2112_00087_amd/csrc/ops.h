@@ -53,9 +53,23 @@ inline SellOp<T> op_split(hz_ctx ctx) {
   A.iim = sizeof(T) == 8 ? static_cast<T*>(ctx->d_I.p) : static_cast<T*>(ctx->d_I32.p);
   return A;
 }
-// The operator the solvers use: the split form when it is formed.
-inline SellOp<double> op_A(hz_ctx ctx) { return ctx->have_split ? op_split<double>(ctx) : op_A_complex(ctx); }
-inline SellOp<float> op_A32(hz_ctx ctx) { return ctx->have_split32 ? op_split<float>(ctx) : op_A32_complex(ctx); }
+// The same in stencil form (valid when ctx->have_stencil / have_stencil32).
+template <typename T>
+inline SellOp<T> op_stencil(hz_ctx ctx) {
+  SellOp<T> A = op_split<T>(ctx);   // imaginary lists
+  A.st = sizeof(T) == 8 ? static_cast<T*>(ctx->d_S.p) : static_cast<T*>(ctx->d_S32.p);
+  A.nrows = ctx->sell.n_rows;
+  A.soff = ctx->soff;
+  return A;
+}
+// The operator the solvers use: the stencil form, else the split form, when formed.
+inline SellOp<double> op_A(hz_ctx ctx) {
+  return ctx->have_stencil ? op_stencil<double>(ctx) : ctx->have_split ? op_split<double>(ctx) : op_A_complex(ctx);
+}
+inline SellOp<float> op_A32(hz_ctx ctx) {
+  return ctx->have_stencil32 ? op_stencil<float>(ctx)
+                             : ctx->have_split32 ? op_split<float>(ctx) : op_A32_complex(ctx);
+}
 
 int op_set_frequency(hz_ctx ctx, const OpParts& P, double k, int scale, bool want32);
 // Forms A(k) (optionally column-scaled by 1/diag) on an explicit sliced-ELL

@@ -48,6 +48,17 @@ __global__ void k_combine(int64_t npad, const int* __restrict__ col, OpParts P, 
   }
 }
 
+// Stencil-form values: slot q copies the split value of sliced-ELL position
+// src[q] (0 for a missing neighbour).
+__global__ void k_stencil_fill(int64_t nslot, const int* __restrict__ src, const double* __restrict__ R,
+                               const float* __restrict__ R32, double* __restrict__ S, float* __restrict__ S32) {
+  int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (q >= nslot) return;
+  const int p = src[q];
+  S[q] = p >= 0 ? R[p] : 0.0;
+  if (S32) S32[q] = p >= 0 ? R32[p] : 0.0f;
+}
+
 // Imaginary parts of the split form's listed entries.
 __global__ void k_split_im(int64_t ni, const int* __restrict__ ipos, const z_t* __restrict__ A,
                            double* __restrict__ I, float* __restrict__ I32) {
@@ -89,6 +100,7 @@ int op_set_frequency(hz_ctx ctx, const OpParts& P, double k, int scale, bool wan
     }
   }
   ctx->have_split = ctx->have_split32 = false;
+  ctx->have_stencil = ctx->have_stencil32 = false;
   HZ_TRY(op_form(ctx->stream, ctx->h.n, ctx->sell.n_rows, npad, ctx->d_scol.as<int>(), P, k, scale,
                  ctx->d_A.as<z_t>(), want32 ? ctx->d_A32.as<c_t>() : nullptr, ctx->d_d.as<z_t>(),
                  ctx->d_dinv.as<z_t>(), split ? ctx->d_R.as<double>() : nullptr,
@@ -102,6 +114,17 @@ int op_set_frequency(hz_ctx ctx, const OpParts& P, double k, int scale, bool wan
     }
     ctx->have_split = true;
     ctx->have_split32 = want32;
+    if (ctx->stencil_ok) {
+      const int64_t nslot = int64_t(kStencil) * ctx->sell.n_rows;
+      HZ_TRY(grow(ctx, ctx->d_S, sizeof(double) * nslot));
+      if (want32) HZ_TRY(grow(ctx, ctx->d_S32, sizeof(float) * nslot));
+      k_stencil_fill<<<ceil_div(nslot, kBlock), kBlock, 0, ctx->stream>>>(
+          nslot, ctx->d_ssrc.as<int>(), ctx->d_R.as<double>(), want32 ? ctx->d_R32.as<float>() : nullptr,
+          ctx->d_S.as<double>(), want32 ? ctx->d_S32.as<float>() : nullptr);
+      HZ_HIP(hipGetLastError());
+      ctx->have_stencil = true;
+      ctx->have_stencil32 = want32;
+    }
   }
   return HZ_OK;
 }
@@ -119,6 +142,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int64_t nout, SellOp<T> A, cons
 template <typename T>
 int op_spmv(hipStream_t s, int64_t nrows, int64_t nout, const SellOp<T>& A, const cx<T>* x, cx<T>* y) {
   if (A.val) k_spmv<T, kFormComplex><<<int(nrows / kBlock), kBlock, 0, s>>>(nout, A, x, y);
+  else if (A.st) k_spmv<T, kFormStencil><<<int(nrows / kBlock), kBlock, 0, s>>>(nout, A, x, y);
   else k_spmv<T, kFormSplit><<<int(nrows / kBlock), kBlock, 0, s>>>(nout, A, x, y);
   HZ_HIP(hipGetLastError());
   return HZ_OK;

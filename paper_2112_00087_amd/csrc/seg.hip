@@ -63,6 +63,7 @@ int true_residual(hz_ctx ctx, const SegHost& S, const SellOp<double>& A, const z
   DevBuf* res = ctx->buf("tres.out", sizeof(double) * S.nseg, &rc);
   if (rc) return rc;
   if (A.val) k_true_resid<kFormComplex><<<S.nblk, kBlock, 0, ctx->stream>>>(S.dev, A, f, u, r, part->as<double>());
+  else if (A.st) k_true_resid<kFormStencil><<<S.nblk, kBlock, 0, ctx->stream>>>(S.dev, A, f, u, r, part->as<double>());
   else k_true_resid<kFormSplit><<<S.nblk, kBlock, 0, ctx->stream>>>(S.dev, A, f, u, r, part->as<double>());
   k_seg_fin1<<<S.nseg, kFinBlock, 0, ctx->stream>>>(S.dev, part->as<double>(), res->as<double>());
   HZ_HIP(hipGetLastError());

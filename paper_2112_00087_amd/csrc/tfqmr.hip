@@ -324,9 +324,11 @@ int tfqmr_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
   auto enqueue_restart = [&](int all) -> int {
     k_tq_mark<<<ceil_div(S.nseg, kBlock), kBlock, 0, s>>>(S.nseg, st, all);
     if (A.val) k_tq_resid<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    else if (A.st) k_tq_resid<T, kFormStencil><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     else k_tq_resid<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     k_tq_resid_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     if (A.val) k_tq_resid_prod<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    else if (A.st) k_tq_resid_prod<T, kFormStencil><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     else k_tq_resid_prod<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     k_tq_alpha_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt, 1);
     HZ_HIP(hipGetLastError());
@@ -337,11 +339,13 @@ int tfqmr_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
     k_tq_even1<T><<<grid, kBlock, 0, s>>>(L, st, V, pt);
     k_tq_qmr_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     if (A.val) k_tq_even2<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V);
+    else if (A.st) k_tq_even2<T, kFormStencil><<<grid, kBlock, 0, s>>>(L, A, st, V);
     else k_tq_even2<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V);
     k_tq_odd1<T><<<grid, kBlock, 0, s>>>(L, st, V, pt);
     k_tq_odd_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt);
     k_tq_odd2<T><<<grid, kBlock, 0, s>>>(L, st, V);
     if (A.val) k_tq_odd3<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
+    else if (A.st) k_tq_odd3<T, kFormStencil><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     else k_tq_odd3<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V, pt);
     k_tq_alpha_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, pt, 0);
     HZ_HIP(hipGetLastError());

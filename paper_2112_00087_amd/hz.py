@@ -26,7 +26,7 @@ HZ_JACOBI, HZ_NONE = 0, 1
 
 METHODS = {"gmres": HZ_GMRES, "bicgstab": HZ_BICGSTAB, "schwarz": HZ_SCHWARZ, "bicgstabl": HZ_BICGSTABL, "tfqmr": HZ_TFQMR}
 PRECISIONS = {"fp64": HZ_FP64, "mixed": HZ_MIXED}
-SPMV_FORMS = {"solver": 0, "complex": 1, "split": 2}
+SPMV_FORMS = {"solver": 0, "complex": 1, "split": 2, "stencil": 3}
 ORDERS = {"given": 0, "rcm": 1}
 HZ_HEX8, HZ_TET4 = 0, 1
 
@@ -282,7 +282,8 @@ class Helmholtz:
 
     def time_spmv(self, reps=100, precision="fp64", form="solver"):
         """Average duration (ms) of one sparse product of the given storage form
-        ("solver", "complex" or "split"), HIP events on the context stream."""
+        ("solver", "complex", "split" or "stencil"), HIP events on the context
+        stream."""
         ms = C.c_double()
         check(lib().hz_time_spmv(self.ctx, int(reps), PRECISIONS[precision], SPMV_FORMS[form], C.byref(ms)),
               False)

@@ -42,21 +42,24 @@ MESHES = [(1, 1, 1), (2, 2, 2), (4, 3, 2), (20, 12, 10), (33, 17, 9)]
 
 
 def _model_in_form(P, mesh, beta, eta, form):
-    """A context whose solvers use the given storage form: "split" (no
-    absorption field), "complex" (split form switched off by HZ_SPLIT=0), or
+    """A context whose solvers use the given storage form: "stencil" (a box,
+    no absorption field), "split" (stencil form switched off by
+    HZ_STENCIL=0), "complex" (split form switched off by HZ_SPLIT=0), or
     "eta" (absorption field: every entry complex, complex form)."""
-    old = os.environ.get("HZ_SPLIT")
-    os.environ["HZ_SPLIT"] = "0" if form == "complex" else "1"
+    env = {"HZ_SPLIT": "0" if form == "complex" else "1", "HZ_STENCIL": "1" if form == "stencil" else "0"}
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
     try:
         return _gpu_model(P, mesh, beta, eta)
     finally:
-        if old is None:
-            del os.environ["HZ_SPLIT"]
-        else:
-            os.environ["HZ_SPLIT"] = old
+        for k, v in old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
 
 
-@pytest.mark.parametrize("form", ["eta", "split", "complex"])
+@pytest.mark.parametrize("form", ["eta", "split", "stencil", "complex"])
 @pytest.mark.parametrize("elems", MESHES)
 def test_spmv_diag_load_parity(P, elems, form):
     say("spmv parity", elems, form)
@@ -137,35 +140,40 @@ def test_solve_workload0(c0, method, precision):
     assert err <= 1e-6
 
 
+@pytest.mark.parametrize("form", ["complex", "split"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_complex_form_solve_matches_oracle(P, c0, precision):
-    """The same solve with the split storage form switched off."""
+def test_other_form_solve_matches_oracle(P, c0, precision, form):
+    """The same solve with the stencil (and split) storage forms switched off."""
     wl = c0["wl"]
-    m = _model_in_form(P, wl["mesh"], wl["beta"], None, "complex")
+    m = _model_in_form(P, wl["mesh"], wl["beta"], None, form)
     m.set_frequency(wl["freqs"][0])
-    assert m.spmv_bytes("fp64", "solver") == m.spmv_bytes("fp64", "complex")
+    assert m.spmv_bytes("fp64", "solver") == m.spmv_bytes("fp64", form)
     p, info = m.solve(_t(c0["f"]), method="bicgstab", precision=precision, tol=1e-8)
     p = _np(p)
     rel = H.relres(c0["A"], p, c0["f"])
     err = np.linalg.norm(p - c0["x"]) / np.linalg.norm(c0["x"])
-    say(f"  complex form {precision}: info={info} relres={rel:.3e} relerr={err:.3e}")
+    say(f"  {form} form {precision}: info={info} relres={rel:.3e} relerr={err:.3e}")
     assert info["status"] == 0 and rel <= 1e-8 and err <= 1e-6
     m.close()
 
 
-def test_split_form_bytes(c0):
-    """The solvers run the split form when there is no absorption field; its
-    algorithmic bytes follow the documented formula."""
+def test_split_and_stencil_form_bytes(c0):
+    """On a box without absorption field the solvers run the stencil form
+    (split values at implied neighbour columns); the algorithmic bytes of
+    each form follow the documented formulas."""
     m = c0["model"]
     n, nnz = m.sizes()["n_nodes"], m.sizes()["nnz"]
     bs, bc = m.spmv_bytes("fp64", "split"), m.spmv_bytes("fp64", "complex")
+    bst = m.spmv_bytes("fp64", "stencil")
     assert bc == 20 * nnz + 4 * (n + 1) + 32 * n
-    assert m.spmv_bytes("fp64", "solver") == bs < bc
+    assert m.spmv_bytes("fp64", "solver") == bst < bs < bc
+    assert bs - bst == 2 * nnz                      # the int16 column offsets
     # every wall node's row is in the imaginary list; interior rows two layers
     # in are not: n_imag lies between the wall entries and all entries
     n_imag = (bs - 10 * nnz - 4 * (n + 1) - 32 * n) / 12
     assert n_imag == int(n_imag) and 0 < n_imag < nnz
     assert m.spmv_bytes("mixed", "split") == 6 * nnz + 8 * n_imag + 4 * (n + 1) + 16 * n
+    assert m.spmv_bytes("mixed", "stencil") == 4 * nnz + 8 * n_imag + 4 * (n + 1) + 16 * n
 
 
 @pytest.mark.parametrize("l,precision", [(1, "fp64"), (2, "fp64"), (4, "fp64"), (8, "fp64"), (4, "mixed"),
