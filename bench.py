@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the FP64 product on this workload, per storage form,
 # from the FETCH_SIZE / WRITE_SIZE passes recorded in profiles/ (calibrated
 # against a 1 GiB device copy); None until measured for the current kernel.
-MEASURED_TRAFFIC = {"stencil": 454.5e6, "split": 516.8e6, "complex": 827.0e6}
+MEASURED_TRAFFIC = {"stencil": 452.9e6, "split": 516.8e6, "complex": 827.0e6}
 
 
 def log(*a):
@@ -271,6 +271,27 @@ def _calib_copy():
     del src, dst
 
 
+def _copy_rate(total_bytes, reps=50):
+    """A plain device copy moving about total_bytes (half read, half
+    written), timed on torch's stream: the bandwidth a streaming kernel of
+    that size reaches on this GPU, as context for the roofline fraction."""
+    import torch
+    half = max(1 << 20, int(total_bytes) // 2 // (1 << 20) * (1 << 20))
+    src = torch.ones(half // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    gbs = 2 * half / (ms * 1e-3) / 1e9
+    return {"bytes": 2 * half, "ms": ms, "GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+
 def _unstructured_legs(args):
     return {W_NAMES.get(int(c), c): unstructured_leg(log, _layouts(args.un_layouts), not args.un_spmv_only, int(c))
             for c in args.un_workloads.split(",")}
@@ -399,7 +420,9 @@ def main():
         log(f"solve roofline: {per_it / 1e6:.0f} MB per iteration, {solve_roof['achieved']:.0f} GB/s "
             f"({100 * solve_roof['frac']:.1f}% of HBM peak)")
 
-    extra = {}
+    extra = {"device_copy": _copy_rate(byts)}
+    log(f"device copy of {extra['device_copy']['bytes'] / 1e6:.0f} MB: {extra['device_copy']['ms'] * 1e3:.1f} us, "
+        f"{extra['device_copy']['GBs']:.0f} GB/s")
     if form != "complex":
         msc = model.time_spmv(args.spmv_reps, "fp64", "complex")
         bc = model.spmv_bytes("fp64", "complex")

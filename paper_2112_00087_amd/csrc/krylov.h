@@ -121,6 +121,8 @@ __device__ __forceinline__ cx<T> sell_row_form(const SellOp<T>& A, int64_t row, 
     return acc;
   }
   T ar = T(0), ai = T(0);
+  // bounds of the row's imaginary list, loaded ahead of the real-part sweep
+  const int q0 = A.iptr[row], q1 = A.iptr[row + 1];
   if constexpr (F == kFormStencil) {
     // slot k: neighbour row + soff[k]; a missing neighbour's slot is 0, its
     // gather is clamped into the vector (any row; it is multiplied by 0)
@@ -141,12 +143,27 @@ __device__ __forceinline__ cx<T> sell_row_form(const SellOp<T>& A, int64_t row, 
     if (A.dcol) split_real(A.dcol + beg + lane, A.re + beg + lane, w, row, x, ar, ai);
     else split_real(A.col + beg + lane, A.re + beg + lane, w, row, x, ar, ai);
   }
-  const int q1 = A.iptr[row + 1];
-  for (int q = A.iptr[row]; q < q1; ++q) {
-    T b = A.iim[q];                 // i b x = -b x.im + i b x.re
-    cx<T> xv = x[A.icol[q]];
-    ar = fma(-b, xv.im, ar);
-    ai = fma(b, xv.re, ai);
+  // imaginary entries, four at a time: the four index loads, then the four
+  // gathers, issue back to back (a lane past the list's end gathers x[0] and
+  // adds nothing); the terms are added in list order as one at a time
+  for (int q = q0; q < q1; q += 4) {
+    T b[4];
+    int c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool on = q + u < q1;
+      b[u] = on ? A.iim[q + u] : T(0);
+      c[u] = on ? A.icol[q + u] : 0;
+    }
+    cx<T> xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xv[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q + u < q1) {             // i b x = -b x.im + i b x.re
+        ar = fma(-b[u], xv[u].im, ar);
+        ai = fma(b[u], xv[u].re, ai);
+      }
   }
   return cx<T>{ar, ai};
 }
