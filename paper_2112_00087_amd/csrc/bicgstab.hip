@@ -104,9 +104,10 @@ __global__ void HZ_PRODUCT_BOUNDS k_v(Seg L, SellOp<T> A, const BiSt* st, BiV<T>
 
 __global__ void k_alpha_fin(Seg L, BiSt* st, const double* part) {
   int s = blockIdx.x;
-  if (st[s].done) return;
+  const int done = st[s].done;
   double o[2];
   seg_sums<2>(L, part, s, o);
+  if (done) return;
   if (threadIdx.x == 0) {
     const double re = o[0], im = o[1];
     BiSt& S = st[s];
@@ -148,9 +149,10 @@ __global__ void HZ_PRODUCT_BOUNDS k_t(Seg L, SellOp<T> A, const BiSt* st, BiV<T>
 // (then x += alpha p completes the iteration).
 __global__ void k_omega_fin(Seg L, BiSt* st, const double* part) {
   int s = blockIdx.x;
-  if (st[s].done) return;
+  const int done = st[s].done;
   double o[4];
   seg_sums<4>(L, part, s, o);
+  if (done) return;
   if (threadIdx.x == 0) {
     const double re = o[0], im = o[1], tt = o[2], ss = o[3];
     BiSt& S = st[s];
@@ -184,7 +186,9 @@ __global__ void k_rho_fin(Seg L, BiSt* st, const double* part) {
   int s = blockIdx.x;
   BiSt& S = st[s];
   const int done = S.done, early = S.early;
-  __syncthreads();   // every thread has read the flags before thread 0 rewrites them
+  double o[3];
+  // (its barriers also see every thread's flags read before thread 0 rewrites them)
+  seg_sums<3>(L, part, s, o);
   if (done) return;
   if (early) {
     if (threadIdx.x == 0) {
@@ -195,8 +199,6 @@ __global__ void k_rho_fin(Seg L, BiSt* st, const double* part) {
     }
     return;
   }
-  double o[3];
-  seg_sums<3>(L, part, s, o);
   if (threadIdx.x == 0) {
     const double re = o[0], im = o[1], rr = o[2];
     S.iter += 1;

@@ -212,11 +212,15 @@ constexpr int kFinBlock = 1024;
 
 // Sum every quantity of this segment's partials in one pass (thread t takes
 // tiles t, t + blockDim, ...; then wave sums and the waves in order); the
-// totals are valid in thread 0.
+// totals are valid in thread 0.  Finalize kernels call it before they branch
+// on the segment's state (read into registers first), so the partials'
+// loads do not wait for the state's; the sums of a segment that is off are
+// simply not used.
 template <int NQ>
 __device__ __forceinline__ void seg_sums(const Seg& L, const double* partial, int seg, double (&out)[NQ]) {
   __shared__ double lds[NQ][kFinBlock / kWave];
-  const int b0 = L.seg_blk[seg], b1 = L.seg_blk[seg + 1];
+  // one segment spans every block: no dependent load of its block range
+  const int b0 = L.nseg == 1 ? 0 : L.seg_blk[seg], b1 = L.nseg == 1 ? L.nblk : L.seg_blk[seg + 1];
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
@@ -248,7 +252,7 @@ __device__ __forceinline__ void seg_sums(const Seg& L, const double* partial, in
 template <int NQ>
 __device__ __forceinline__ double seg_sum(const Seg& L, const double* partial, int seg, int q) {
   __shared__ double lds[kFinBlock / kWave];
-  int b0 = L.seg_blk[seg], b1 = L.seg_blk[seg + 1];
+  const int b0 = L.nseg == 1 ? 0 : L.seg_blk[seg], b1 = L.nseg == 1 ? L.nblk : L.seg_blk[seg + 1];
   return block_sum_strided(partial + int64_t(b0) * NQ + q, b1 - b0, NQ, lds);
 }
 

@@ -72,6 +72,9 @@ int true_residual(hz_ctx ctx, const SegHost& S, const SellOp<double>& A, const z
 
 int seg_upload(hz_ctx ctx, SegHost* S, const std::string& tag) {
   int rc = 0;
+  // the segments tile the blocks (the finalize kernels rely on it)
+  if (int(S->seg_blk.size()) != S->nseg + 1 || S->seg_blk.front() != 0 || S->seg_blk.back() != S->nblk)
+    return hz_fail(HZ_ERR_INVALID, "segment table does not tile the %d blocks", S->nblk);
   std::vector<int> blk_seg(S->nblk);
   for (int s = 0; s < S->nseg; ++s)
     for (int b = S->seg_blk[s]; b < S->seg_blk[s + 1]; ++b) blk_seg[b] = s;

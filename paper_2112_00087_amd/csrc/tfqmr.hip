@@ -135,12 +135,11 @@ __global__ void k_tq_alpha_fin(Seg L, TqSt* st, const double* part, int after_re
   const int go = after_restart ? (S0.restart && !S0.done) : !tq_off(S0);
   const int clear = after_restart && S0.restart;
   const int done = S0.done;
-  __syncthreads();
+  double o[2];
+  seg_sums<2>(L, part, s, o);   // its barriers: every thread has read the flags
   if (threadIdx.x == 0 && clear) st[s].restart = 0;
   if (threadIdx.x == 0 && done) st[s].last = 0;
   if (!go) return;
-  double o[2];
-  seg_sums<2>(L, part, s, o);
   if (threadIdx.x == 0) {
     TqSt& S = st[s];
     const z_t sg = {o[0], o[1]};
@@ -171,13 +170,12 @@ __global__ void k_tq_qmr_fin(Seg L, TqSt* st, const double* part) {
   const int s = blockIdx.x;
   const TqSt& S0 = st[s];
   const int off = tq_off(S0), done = S0.done;
-  __syncthreads();
+  double o[1];
+  seg_sums<1>(L, part, s, o);   // its barriers: every thread has read the flags
   if (off) {
     if (threadIdx.x == 0 && done) st[s].last = 0;
     return;
   }
-  double o[1];
-  seg_sums<1>(L, part, s, o);
   if (threadIdx.x == 0) tq_qmr(st[s], o[0]);
 }
 
@@ -215,13 +213,12 @@ __global__ void k_tq_odd_fin(Seg L, TqSt* st, const double* part) {
   const int s = blockIdx.x;
   const TqSt& S0 = st[s];
   const int off = tq_off(S0), done = S0.done;
-  __syncthreads();
+  double o[3];
+  seg_sums<3>(L, part, s, o);   // its barriers: every thread has read the flags
   if (off) {
     if (threadIdx.x == 0 && done) st[s].last = 0;
     return;
   }
-  double o[3];
-  seg_sums<3>(L, part, s, o);
   if (threadIdx.x == 0) {
     TqSt& S = st[s];
     tq_qmr(S, o[0]);
