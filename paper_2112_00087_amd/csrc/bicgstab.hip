@@ -41,7 +41,7 @@ template <typename T> __device__ __forceinline__ cx<T> zt(z_t a) { return ccast<
 // r = f - A u; restart: rhat = r, p = v = 0.  Partial ||r||^2.
 template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_resid(Seg L, SellOp<T> A, BiV<T> V, double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   z_t y = zd(sell_row_form<F>(A, t.row, V.u));
   z_t r = zd(V.f[t.row]) - y;
   cx<T> rs = zt<T>(r);
@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(kBlock) k_resid(Seg L, SellOp<T> A, BiV<T> V, 
   V.v[t.row] = cx<T>{T(0), T(0)};
   z_t rr = zd(rs);
   double q[1] = {norm2(rr)};
-  store_partials<1>(q, part, t.tile);
+  store_partials<1>(q, part, t);
 }
 
 __global__ void k_resid_fin(Seg L, BiSt* st, const double* part) {
@@ -93,13 +93,13 @@ __global__ void __launch_bounds__(kBlock) k_p(Seg L, const BiSt* st, BiV<T> V) {
 // form per kernel keeps the register count, hence the occupancy, of that form).
 template <typename T, int F>
 __global__ void HZ_PRODUCT_BOUNDS k_v(Seg L, SellOp<T> A, const BiSt* st, BiV<T> V, double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   if (st[t.seg].done) return;
   cx<T> y = sell_row_form<F>(A, t.row, V.p);
   V.v[t.row] = y;
   z_t a = zd(V.rhat[t.row]), b = zd(y);
   double q[2] = {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
-  store_partials<2>(q, part, t.tile);
+  store_partials<2>(q, part, t);
 }
 
 __global__ void k_alpha_fin(Seg L, BiSt* st, const double* part) {
@@ -135,14 +135,14 @@ __global__ void __launch_bounds__(kBlock) k_s(Seg L, const BiSt* st, BiV<T> V) {
 // t = A s; partials t^H s, t^H t, s^H s (per storage form F, as k_v).
 template <typename T, int F>
 __global__ void HZ_PRODUCT_BOUNDS k_t(Seg L, SellOp<T> A, const BiSt* st, BiV<T> V, double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   const BiSt& S = st[t.seg];
   if (S.done) return;
   cx<T> y = sell_row_form<F>(A, t.row, V.s);
   V.t[t.row] = y;
   z_t a = zd(y), b = zd(V.s[t.row]);
   double q[4] = {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re, norm2(a), norm2(b)};
-  store_partials<4>(q, part, t.tile);
+  store_partials<4>(q, part, t);
 }
 
 // omega = t^H s / t^H t, or the early exit when ||s|| already meets the target
@@ -165,7 +165,7 @@ __global__ void k_omega_fin(Seg L, BiSt* st, const double* part) {
 // u += alpha p + omega s; r = s - omega t; partials rhat^H r, ||r||^2.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_xr(Seg L, const BiSt* st, BiV<T> V, double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   const BiSt& S = st[t.seg];
   if (S.done) return;
   z_t u = zd(V.u[t.row]) + S.alpha * zd(V.p[t.row]);
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kBlock) k_xr(Seg L, const BiSt* st, BiV<T> V, 
   V.r[t.row] = r;
   z_t a = zd(V.rhat[t.row]), b = zd(r);
   double q[3] = {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re, norm2(b)};
-  store_partials<3>(q, part, t.tile);
+  store_partials<3>(q, part, t);
 }
 
 __global__ void k_rho_fin(Seg L, BiSt* st, const double* part) {

@@ -93,7 +93,7 @@ __global__ void k_bl_mark(int nseg, BlSt* st, int all) {
 // r_0 = f - B x, rt = r_0, u_0 = 0; partial ||r_0||^2.
 template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_bl_resid(Seg L, SellOp<T> A, const BlSt* st, BlV<T> V, double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   if (!st[t.seg].restart) return;
   z_t r = zd(V.f[t.row]) - zd(sell_row_form<F>(A, t.row, V.x));
   cx<T> rs = zt<T>(r);
@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(kBlock) k_bl_resid(Seg L, SellOp<T> A, const B
   V.rt[t.row] = rs;
   V.u[0][t.row] = cx<T>{T(0), T(0)};
   double q[1] = {norm2(zd(rs))};
-  store_partials<1>(q, part, t.tile);
+  store_partials<1>(q, part, t);
 }
 
 __global__ void k_bl_resid_fin(Seg L, BlSt* st, const double* part) {
@@ -143,13 +143,13 @@ template <typename T, int F>
 __global__ void HZ_PRODUCT_BOUNDS k_bl_prod(Seg L, SellOp<T> A, const BlSt* st, const cx<T>* __restrict__ yj,
                                                     cx<T>* __restrict__ yj1, const cx<T>* __restrict__ rt,
                                                     double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   if (bl_off(st[t.seg])) return;
   cx<T> y = sell_row_form<F>(A, t.row, yj);
   yj1[t.row] = y;
   double q[2] = {0.0, 0.0};
   acc_dot(q, zd(rt[t.row]), zd(y));
-  store_partials<2>(q, part, t.tile);
+  store_partials<2>(q, part, t);
 }
 
 // alpha = rho0 / rt^H u_{j+1}
@@ -205,7 +205,7 @@ template <int LL> constexpr int gram_nq() { return 2 * (LL + LL * (LL + 1) / 2);
 
 template <typename T, int LL>
 __global__ void __launch_bounds__(kBlock) k_bl_gram(Seg L, const BlSt* st, BlV<T> V, double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   if (bl_off(st[t.seg])) return;
   constexpr int NQ = gram_nq<LL>();
   z_t r[LL + 1];
@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(kBlock) k_bl_gram(Seg L, const BlSt* st, BlV<T
       k += 2;
     }
   }
-  store_partials<NQ>(q, part, t.tile);
+  store_partials<NQ>(q, part, t);
 }
 
 // Cholesky solve of G gamma = c (G Hermitian, LL x LL), truncated at the
@@ -301,7 +301,7 @@ __global__ void k_bl_mr_fin(Seg L, BlSt* st, const double* part, double piv) {
 // partials rt^H r_0, ||r_0||^2
 template <typename T, int LL>
 __global__ void __launch_bounds__(kBlock) k_bl_update(Seg L, const BlSt* st, BlV<T> V, double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   const BlSt& S = st[t.seg];
   if (bl_off(S)) return;
   z_t x = zd(V.x[t.row]), r0 = zd(V.r[0][t.row]), u0 = zd(V.u[0][t.row]);
@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(kBlock) k_bl_update(Seg L, const BlSt* st, BlV
   const z_t rv = zd(rs);
   acc_dot(q, zd(V.rt[t.row]), rv);
   q[2] = norm2(rv);
-  store_partials<3>(q, part, t.tile);
+  store_partials<3>(q, part, t);
 }
 
 __global__ void k_bl_cycle_fin(Seg L, BlSt* st, const double* part) {

@@ -39,12 +39,12 @@ template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_resid(Seg L, SellOp<T> A, const cx<T>* __restrict__ f,
                                                   const cx<T>* __restrict__ u, cx<T>* __restrict__ V0,
                                                   double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   z_t r = zd(f[t.row]) - zd(sell_row_form<F>(A, t.row, u));
   cx<T> rs = ccast<T>(r);
   V0[t.row] = rs;
   double q[1] = {norm2(zd(rs))};
-  store_partials<1>(q, part, t.tile);
+  store_partials<1>(q, part, t);
 }
 
 __global__ void k_beta_fin(Seg L, GmSt* st, GmArr G, const double* part) {
@@ -92,7 +92,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_mdot(Seg L, const GmSt* st, const cx<T>* __restrict__ V,
                                                  int64_t ld, int j, const cx<T>* __restrict__ w,
                                                  double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   if (st[t.seg].cyc) return;
   int i0 = blockIdx.y * NV;
   z_t wv = zd(w[t.row]);
@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(kBlock) k_mdot(Seg L, const GmSt* st, const cx
     q[2 * c] = a.re * wv.re + a.im * wv.im;
     q[2 * c + 1] = a.re * wv.im - a.im * wv.re;
   }
-  store_partials<2 * NV>(q, part + int64_t(blockIdx.y) * L.nblk * 2 * NV, t.tile);
+  store_partials<2 * NV>(q, part + int64_t(blockIdx.y) * L.nblk * 2 * NV, t);
 }
 
 // block (s, i): coefficient i of segment s.  pass 1 -> h1; pass 2 -> h2 and H[:, j] = h1 + h2.
@@ -133,7 +133,7 @@ template <typename T, bool NORM>
 __global__ void __launch_bounds__(kBlock) k_axpy(Seg L, const GmSt* st, GmArr G, const cx<T>* __restrict__ V,
                                                  int64_t ld, int j, int pass, cx<T>* __restrict__ w,
                                                  double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   if (st[t.seg].cyc) return;
   const z_t* h = (pass == 1 ? G.h1 : G.h2) + int64_t(t.seg) * (G.m + 1);
   z_t acc = zd(w[t.row]);
@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(kBlock) k_axpy(Seg L, const GmSt* st, GmArr G,
   w[t.row] = ws;
   if (NORM) {
     double q[1] = {norm2(zd(ws))};
-    store_partials<1>(q, part, t.tile);
+    store_partials<1>(q, part, t);
   }
 }
 

@@ -177,18 +177,25 @@ struct Tile {
   int seg;
   int64_t row;
 };
-// Count of this block's waves that have stored their sums in store_partials.
-__device__ __forceinline__ int* block_wave_count() {
-  __shared__ int n;
-  return &n;
-}
-// Every segmented kernel starts here (all its threads, before any return):
-// the block's wave count is zeroed behind a barrier.
 __device__ __forceinline__ Tile tile_of(const Seg& L) {
   Tile t;
   t.tile = blockIdx.x;
   t.seg = L.blk_seg[t.tile];
   t.row = int64_t(t.tile) * kBlock + threadIdx.x;
+  return t;
+}
+// Count of this block's waves that have stored their sums in store_partials.
+__device__ __forceinline__ int* block_wave_count() {
+  __shared__ int n;
+  return &n;
+}
+// The tile of a kernel that stores block partials (store_partials takes
+// only this type): all its threads call it first, before any return, and
+// the block's wave count is zeroed behind a barrier.
+struct SumTile : Tile {};
+__device__ __forceinline__ SumTile tile_of_sums(const Seg& L) {
+  SumTile t;
+  static_cast<Tile&>(t) = tile_of(L);
   if (threadIdx.x == 0) *block_wave_count() = 0;
   __syncthreads();
   return t;
@@ -202,9 +209,11 @@ __device__ __forceinline__ Tile tile_of(const Seg& L) {
 // leaves at once instead of holding its slot until the block's slowest wave
 // finishes (measured 79 -> 75 us for the 27-point product with four sums).
 // Called once per kernel, by every wave of the block or by none (the
-// callers return early only for a whole segment, hence a whole block).
+// callers return early only for a whole segment, hence a whole block), with
+// the tile from tile_of_sums, which zeroed the count.
 template <int NQ>
-__device__ __forceinline__ void store_partials(double (&v)[NQ], double* partial, int tile) {
+__device__ __forceinline__ void store_partials(double (&v)[NQ], double* partial, const SumTile& t) {
+  const int tile = t.tile;
   constexpr int kWaves = kBlock / kWave;
   __shared__ double lds[NQ][kWaves];
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;

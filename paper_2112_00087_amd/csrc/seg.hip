@@ -5,9 +5,9 @@ namespace {
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_norm_part(Seg L, const cx<T>* __restrict__ x, double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   double q[1] = {norm2(ccast<double>(x[t.row]))};
-  store_partials<1>(q, part, t.tile);
+  store_partials<1>(q, part, t);
 }
 
 __global__ void k_seg_fin1(Seg L, const double* part, double* out) {
@@ -22,11 +22,11 @@ template <int F>
 __global__ void __launch_bounds__(kBlock) k_true_resid(Seg L, SellOp<double> A, const z_t* __restrict__ f,
                                                        const z_t* __restrict__ u, z_t* __restrict__ r,
                                                        double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   z_t v = f[t.row] - sell_row_form<F>(A, t.row, u);
   if (r) r[t.row] = v;
   double q[1] = {norm2(v)};
-  store_partials<1>(q, part, t.tile);
+  store_partials<1>(q, part, t);
 }
 
 int fetch_seg(hz_ctx ctx, const SegHost& S, const double* dev, std::vector<double>* out) {

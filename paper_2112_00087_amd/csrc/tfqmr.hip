@@ -78,7 +78,7 @@ __global__ void k_tq_mark(int nseg, TqSt* st, int all) {
 // r0 = f - B x; r* = w = u = r0; d = 0; partial ||r0||^2
 template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_tq_resid(Seg L, SellOp<T> A, const TqSt* st, TqV<T> V, double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   if (!st[t.seg].restart) return;
   const cx<T> r = zt<T>(zd(V.f[t.row]) - zd(sell_row_form<F>(A, t.row, V.x)));
   V.rs[t.row] = r;
@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(kBlock) k_tq_resid(Seg L, SellOp<T> A, const T
   V.u[t.row] = r;
   V.d[t.row] = cx<T>{T(0), T(0)};
   double q[1] = {norm2(zd(r))};
-  store_partials<1>(q, part, t.tile);
+  store_partials<1>(q, part, t);
 }
 
 __global__ void k_tq_resid_fin(Seg L, TqSt* st, const double* part) {
@@ -117,7 +117,7 @@ __global__ void k_tq_resid_fin(Seg L, TqSt* st, const double* part) {
 template <typename T, int F>
 __global__ void HZ_PRODUCT_BOUNDS k_tq_resid_prod(Seg L, SellOp<T> A, const TqSt* st, TqV<T> V,
                                                           double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   const TqSt& S = st[t.seg];
   if (!S.restart || S.done) return;
   const cx<T> y = sell_row_form<F>(A, t.row, V.u);
@@ -125,7 +125,7 @@ __global__ void HZ_PRODUCT_BOUNDS k_tq_resid_prod(Seg L, SellOp<T> A, const TqSt
   V.uh[t.row] = y;
   double q[2] = {0.0, 0.0};
   acc_dot(q, zd(V.rs[t.row]), zd(y));
-  store_partials<2>(q, part, t.tile);
+  store_partials<2>(q, part, t);
 }
 
 // alpha = rho / r*^H v (after a restart, or after the odd half-step's product)
@@ -152,7 +152,7 @@ __global__ void k_tq_alpha_fin(Seg L, TqSt* st, const double* part, int after_re
 // u' = u - alpha v; w -= alpha uhat; d = u + (theta^2/alpha) eta d; partial ||w||^2
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_tq_even1(Seg L, const TqSt* st, TqV<T> V, double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   const TqSt& S = st[t.seg];
   if (tq_off(S)) return;
   const z_t a = S.alpha;
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(kBlock) k_tq_even1(Seg L, const TqSt* st, TqV<
   const z_t g = (S.theta * S.theta) * cdiv(S.eta, a);
   V.d[t.row] = zt<T>(u + g * zd(V.d[t.row]));
   double q[1] = {norm2(zd(w))};
-  store_partials<1>(q, part, t.tile);
+  store_partials<1>(q, part, t);
 }
 
 __global__ void k_tq_qmr_fin(Seg L, TqSt* st, const double* part) {
@@ -195,7 +195,7 @@ __global__ void HZ_PRODUCT_BOUNDS k_tq_even2(Seg L, SellOp<T> A, const TqSt* st,
 // w -= alpha uhat; d = u + (theta^2/alpha) eta d; partials ||w||^2, r*^H w
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_tq_odd1(Seg L, const TqSt* st, TqV<T> V, double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   const TqSt& S = st[t.seg];
   if (tq_off(S)) return;
   const z_t a = S.alpha;
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(kBlock) k_tq_odd1(Seg L, const TqSt* st, TqV<T
   const z_t wv = zd(w);
   double q[3] = {norm2(wv), 0.0, 0.0};
   acc_dot(q + 1, zd(V.rs[t.row]), wv);
-  store_partials<3>(q, part, t.tile);
+  store_partials<3>(q, part, t);
 }
 
 __global__ void k_tq_odd_fin(Seg L, TqSt* st, const double* part) {
@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(kBlock) k_tq_odd2(Seg L, const TqSt* st, TqV<T
 // uhat = B u; v = vt + uhat; partial r*^H v
 template <typename T, int F>
 __global__ void HZ_PRODUCT_BOUNDS k_tq_odd3(Seg L, SellOp<T> A, const TqSt* st, TqV<T> V, double* part) {
-  Tile t = tile_of(L);
+  SumTile t = tile_of_sums(L);
   if (tq_off(st[t.seg])) return;
   const cx<T> y = sell_row_form<F>(A, t.row, V.u);
   V.uh[t.row] = y;
@@ -256,7 +256,7 @@ __global__ void HZ_PRODUCT_BOUNDS k_tq_odd3(Seg L, SellOp<T> A, const TqSt* st, 
   V.v[t.row] = v;
   double q[2] = {0.0, 0.0};
   acc_dot(q, zd(V.rs[t.row]), zd(v));
-  store_partials<2>(q, part, t.tile);
+  store_partials<2>(q, part, t);
 }
 
 __global__ void k_tq_set_thr(int nseg, TqSt* st, const double* fn2, double tol) {
