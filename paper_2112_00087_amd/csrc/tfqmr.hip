@@ -5,12 +5,15 @@
 // Half-steps come in pairs (m even, m + 1 odd), one product each:
 //   even:  alpha known;  u' = u - alpha v;  w -= alpha uhat;  d = u + (theta^2/alpha) eta d
 //          theta = ||w|| / tau, c = 1/sqrt(1 + theta^2), tau *= theta c, eta = c^2 alpha
-//          x += eta d;  uhat = B u';  u = u'
-//   odd:   w -= alpha uhat;  d = u + (theta^2/alpha) eta d;  theta, c, tau, eta as above
-//          x += eta d;  rho' = r*^H w, beta = rho'/rho;  u = w + beta u
+//          x += eta d;  uhat = B u'
+//   odd:   w -= alpha uhat;  d = u' + (theta^2/alpha) eta d;  theta, c, tau, eta as above
+//          x += eta d;  rho' = r*^H w, beta = rho'/rho;  u = w + beta u'
 //          v = beta uhat + beta^2 v + B u;  uhat = B u;  alpha = rho' / r*^H v
 // Kernels: 3 vector, 2 product (with fused dot), 3 one-block-per-segment
-// finalize per pair.  A segment whose quasi-residual bound tau sqrt(m+1)
+// finalize per pair.  u' lives in its own buffer for the odd half-step (it
+// is never copied back into u), and the odd product reads B u' from uhat
+// and writes B u over it row by row, so v needs no staging buffer: 29
+// vector passes per pair.  A segment whose quasi-residual bound tau sqrt(m+1)
 // meets the target applies its last x update and stops; the host confirms
 // with the true residual (restarting a segment that has not converged), and
 // restarts segments that broke down (r*^H v or rho zero).
@@ -35,8 +38,7 @@ struct TqV {
   cx<T>* u;
   cx<T>* un;      // u' of the even half-step
   cx<T>* v;
-  cx<T>* vt;      // beta uhat + beta^2 v before the product is added
-  cx<T>* uh;      // B u
+  cx<T>* uh;      // B u, then B u'
   cx<T>* d;
 };
 
@@ -179,7 +181,7 @@ __global__ void k_tq_qmr_fin(Seg L, TqSt* st, const double* part) {
   if (threadIdx.x == 0) tq_qmr(st[s], o[0]);
 }
 
-// x += eta d; then (unless stopping) uhat = B u', u = u'
+// x += eta d; then (unless stopping) uhat = B u'
 template <typename T, int F>
 __global__ void HZ_PRODUCT_BOUNDS k_tq_even2(Seg L, SellOp<T> A, const TqSt* st, TqV<T> V) {
   Tile t = tile_of(L);
@@ -188,11 +190,10 @@ __global__ void HZ_PRODUCT_BOUNDS k_tq_even2(Seg L, SellOp<T> A, const TqSt* st,
   V.x[t.row] = zt<T>(zd(V.x[t.row]) + S.eta * zd(V.d[t.row]));
   if (S.done) return;
   V.uh[t.row] = sell_row_form<F>(A, t.row, V.un);
-  V.u[t.row] = V.un[t.row];
 }
 
 // ---------------------------------------------------------------- odd half-step
-// w -= alpha uhat; d = u + (theta^2/alpha) eta d; partials ||w||^2, r*^H w
+// w -= alpha uhat; d = u' + (theta^2/alpha) eta d; partials ||w||^2, r*^H w
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_tq_odd1(Seg L, const TqSt* st, TqV<T> V, double* part) {
   SumTile t = tile_of_sums(L);
@@ -202,7 +203,7 @@ __global__ void __launch_bounds__(kBlock) k_tq_odd1(Seg L, const TqSt* st, TqV<T
   const cx<T> w = zt<T>(zd(V.w[t.row]) - a * zd(V.uh[t.row]));
   V.w[t.row] = w;
   const z_t g = (S.theta * S.theta) * cdiv(S.eta, a);
-  V.d[t.row] = zt<T>(zd(V.u[t.row]) + g * zd(V.d[t.row]));
+  V.d[t.row] = zt<T>(zd(V.un[t.row]) + g * zd(V.d[t.row]));
   const z_t wv = zd(w);
   double q[3] = {norm2(wv), 0.0, 0.0};
   acc_dot(q + 1, zd(V.rs[t.row]), wv);
@@ -232,7 +233,7 @@ __global__ void k_tq_odd_fin(Seg L, TqSt* st, const double* part) {
   }
 }
 
-// x += eta d; then (unless stopping) u = w + beta u, vt = beta uhat + beta^2 v
+// x += eta d; then (unless stopping) u = w + beta u'
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_tq_odd2(Seg L, const TqSt* st, TqV<T> V) {
   Tile t = tile_of(L);
@@ -240,19 +241,22 @@ __global__ void __launch_bounds__(kBlock) k_tq_odd2(Seg L, const TqSt* st, TqV<T
   if (S.brk || S.nan || (S.done && !S.last)) return;
   V.x[t.row] = zt<T>(zd(V.x[t.row]) + S.eta * zd(V.d[t.row]));
   if (S.done) return;
-  const z_t b = S.beta;
-  V.u[t.row] = zt<T>(zd(V.w[t.row]) + b * zd(V.u[t.row]));
-  V.vt[t.row] = zt<T>(b * zd(V.uh[t.row]) + (b * b) * zd(V.v[t.row]));
+  V.u[t.row] = zt<T>(zd(V.w[t.row]) + S.beta * zd(V.un[t.row]));
 }
 
-// uhat = B u; v = vt + uhat; partial r*^H v
+// uhat = B u over B u' (each row reads its old value first); v = beta B u'
+// + beta^2 v + B u, the first two terms rounded to the storage type before
+// the product is added; partial r*^H v
 template <typename T, int F>
 __global__ void HZ_PRODUCT_BOUNDS k_tq_odd3(Seg L, SellOp<T> A, const TqSt* st, TqV<T> V, double* part) {
   SumTile t = tile_of_sums(L);
-  if (tq_off(st[t.seg])) return;
+  const TqSt& S = st[t.seg];
+  if (tq_off(S)) return;
+  const z_t b = S.beta;
+  const cx<T> vt = zt<T>(b * zd(V.uh[t.row]) + (b * b) * zd(V.v[t.row]));
   const cx<T> y = sell_row_form<F>(A, t.row, V.u);
   V.uh[t.row] = y;
-  const cx<T> v = zt<T>(zd(V.vt[t.row]) + zd(y));
+  const cx<T> v = zt<T>(zd(vt) + zd(y));
   V.v[t.row] = v;
   double q[2] = {0.0, 0.0};
   acc_dot(q, zd(V.rs[t.row]), zd(v));
@@ -279,9 +283,9 @@ int tfqmr_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
   TqV<T> V = {};
   V.f = f;
   V.x = x;
-  cx<T>** vecs[8] = {&V.rs, &V.w, &V.u, &V.un, &V.v, &V.vt, &V.uh, &V.d};
-  const char* names[8] = {"rs", "w", "u", "un", "v", "vt", "uh", "d"};
-  for (int i = 0; i < 8; ++i) {
+  cx<T>** vecs[7] = {&V.rs, &V.w, &V.u, &V.un, &V.v, &V.uh, &V.d};
+  const char* names[7] = {"rs", "w", "u", "un", "v", "uh", "d"};
+  for (int i = 0; i < 7; ++i) {
     DevBuf* b = ctx->buf(p + names[i], vb, &rc);
     if (rc) return rc;
     *vecs[i] = b->as<cx<T>>();

@@ -110,6 +110,29 @@ def test_dotc_parity_and_determinism(P):
     model.close()
 
 
+@pytest.mark.parametrize("method,kw", [("bicgstab", {}), ("tfqmr", {}), ("bicgstabl", dict(restart=4)),
+                                       ("gmres", dict(restart=30))])
+def test_solves_are_bitwise_reproducible(P, method, kw):
+    """Every reduction has a fixed order (a block's wave sums added in wave
+    order by whichever wave finishes last, then the blocks in order), so the
+    same solve run twice gives the same iterate and counts bit for bit, on a
+    mesh of many blocks (21,525 nodes: 85 blocks of 256 rows).  Converged or
+    not within the cap, the two runs must agree."""
+    say("bitwise reproducible", method)
+    wl = W.workload(1, elems=(40, 24, 20))
+    m = _gpu_model(P, wl["mesh"], wl["beta"])
+    m.set_frequency(150.0)
+    f = m.load(_t(wl["g"]))
+    runs = [m.solve(f, method=method, tol=1e-8, max_matvec=4000, **kw) for _ in range(2)]
+    (p1, i1), (p2, i2) = runs
+    say(f"  {i1}")
+    assert np.isfinite(i1["relres_true"])
+    assert torch.equal(p1, p2)
+    for key in ("status", "iters", "matvecs", "relres_true"):
+        assert i1[key] == i2[key], (key, i1, i2)
+    m.close()
+
+
 @pytest.fixture(scope="module")
 def c0(P):
     wl = W.workload(0)
