@@ -111,7 +111,8 @@ struct hz_ctx_s {
   bool split_on = true;              // HZ_SPLIT=0 in the environment turns it off
   bool split_dcol = false;           // every |col - row| fits int16
   int64_t n_imag = 0;                // entries with a possibly nonzero imaginary part
-  DevBuf d_dcol, d_iptr, d_icol, d_ipos;
+  int64_t n_islots = 0;              // their interleaved slots (lists padded per slice)
+  DevBuf d_dcol, d_imeta, d_icol, d_ipos;   // per slot: column, position in A (-1: padding)
   DevBuf d_R, d_R32, d_I, d_I32;
   bool have_split = false, have_split32 = false;   // values match the current A / A32
 

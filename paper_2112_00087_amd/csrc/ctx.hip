@@ -170,9 +170,45 @@ int ctx_upload(hz_ctx ctx) {
     ctx->n_imag = int64_t(icol.size());
     ctx->split_dcol = fits;
     if (fits) HZ_TRY(put(ctx, ctx->d_dcol, dcol.data(), dcol.size()));
-    HZ_TRY(put(ctx, ctx->d_iptr, iptr.data(), iptr.size()));
-    HZ_TRY(put(ctx, ctx->d_icol, icol.data(), icol.size()));
-    HZ_TRY(put(ctx, ctx->d_ipos, ipos.data(), ipos.size()));
+    // interleave each slice's lists (ImSlice): entry k of the j-th listed
+    // lane at base + k nl + j, shorter lists padded with position -1 (value
+    // 0) and the row itself as column
+    const int64_t nsl = nrows / kWave;
+    std::vector<ImSlice> meta(nsl);
+    std::vector<int32_t> pcol, ppos;
+    for (int64_t sl = 0; sl < nsl; ++sl) {
+      ImSlice m{int32_t(pcol.size()), 0, 0, 0, 0ull};
+      for (int l = 0; l < kWave; ++l) {
+        const int64_t r = sl * kWave + l;
+        const int len = iptr[r + 1] - iptr[r];
+        if (len > 0) {
+          m.mask |= 1ull << l;
+          ++m.nl;
+          m.w = std::max(m.w, len);
+        }
+      }
+      const size_t at0 = pcol.size();
+      pcol.resize(at0 + size_t(m.w) * m.nl);
+      ppos.resize(at0 + size_t(m.w) * m.nl);
+      int j = 0;
+      for (int l = 0; l < kWave; ++l) {
+        if (!((m.mask >> l) & 1ull)) continue;
+        const int64_t r = sl * kWave + l;
+        for (int k = 0; k < m.w; ++k) {
+          const size_t at = at0 + size_t(k) * m.nl + j;
+          const int64_t q = iptr[r] + k;
+          pcol[at] = q < iptr[r + 1] ? icol[q] : int32_t(r);
+          ppos[at] = q < iptr[r + 1] ? ipos[q] : -1;
+        }
+        ++j;
+      }
+      meta[sl] = m;
+    }
+    if (pcol.size() > size_t(INT32_MAX)) return hz_fail(HZ_ERR_INVALID, "too many imaginary entries");
+    ctx->n_islots = int64_t(pcol.size());
+    HZ_TRY(put(ctx, ctx->d_imeta, meta.data(), meta.size()));
+    HZ_TRY(put(ctx, ctx->d_icol, pcol.data(), pcol.size()));
+    HZ_TRY(put(ctx, ctx->d_ipos, ppos.data(), ppos.size()));
   }
   {
     // Stencil form: a box in its own numbering stores the split values in 27

@@ -27,7 +27,7 @@ struct Seg {
 //  complex form (val != NULL): one complex value per stored entry.
 //  split form (val == NULL): the real part of every stored entry (re) plus,
 //    per row, a short list of the entries whose imaginary part can be
-//    nonzero (iptr/icol/iim).  Without an absorption field only the entries
+//    nonzero (imeta/icol/iim, interleaved per slice).  Without an absorption field only the entries
 //    that touch the absorbing walls are complex (the wall term and the
 //    Jacobi scaling of wall columns), so this form streams 8 (FP64) or 4
 //    (FP32) bytes per entry instead of 16 or 8.
@@ -43,6 +43,16 @@ constexpr int kStencil = 27;
 struct StencilOffsets {
   int o[kStencil];
 };
+// Imaginary entries of one 64-row slice (split and stencil forms).  The
+// lanes whose row has any (bit l of mask) keep their lists interleaved:
+// entry k of the j-th such lane at base + k nl + j, every list padded with
+// zero values (column: the row itself) to the slice's longest, w.  Each step
+// of the lists' loop then loads consecutive values and columns across the
+// lanes, instead of one scattered list per lane.
+struct ImSlice {
+  int base, nl, w, pad;
+  unsigned long long mask;
+};
 template <typename T>
 struct SellOp {
   const int* ptr = nullptr;       // [nrows / 64 + 1] slice offsets
@@ -50,8 +60,8 @@ struct SellOp {
   const cx<T>* val = nullptr;
   const T* re = nullptr;          // split form
   const int16_t* dcol = nullptr;  // split form: column - row (NULL: use col)
-  const int* iptr = nullptr;      // [nrows + 1] imaginary entries of each row
-  const int* icol = nullptr;
+  const ImSlice* imeta = nullptr; // [nrows / 64] imaginary entries of each slice
+  const int* icol = nullptr;      // their columns and values, interleaved per slice
   const T* iim = nullptr;
   const T* st = nullptr;          // stencil form
   int64_t nrows = 0;              // stencil form: rows of the vectors (gathers are clamped to them)
@@ -121,8 +131,8 @@ __device__ __forceinline__ cx<T> sell_row_form(const SellOp<T>& A, int64_t row, 
     return acc;
   }
   T ar = T(0), ai = T(0);
-  // bounds of the row's imaginary list, loaded ahead of the real-part sweep
-  const int q0 = A.iptr[row], q1 = A.iptr[row + 1];
+  // the slice's imaginary-list descriptor, loaded ahead of the real-part sweep
+  const ImSlice im = A.imeta[slice];
   if constexpr (F == kFormStencil) {
     // slot k: neighbour row + soff[k]; a missing neighbour's slot is 0, its
     // gather is clamped into the vector (any row; it is multiplied by 0)
@@ -143,27 +153,33 @@ __device__ __forceinline__ cx<T> sell_row_form(const SellOp<T>& A, int64_t row, 
     if (A.dcol) split_real(A.dcol + beg + lane, A.re + beg + lane, w, row, x, ar, ai);
     else split_real(A.col + beg + lane, A.re + beg + lane, w, row, x, ar, ai);
   }
-  // imaginary entries, four at a time: the four index loads, then the four
-  // gathers, issue back to back (a lane past the list's end gathers x[0] and
-  // adds nothing); the terms are added in list order as one at a time
-  for (int q = q0; q < q1; q += 4) {
-    T b[4];
-    int c[4];
+  // imaginary entries, four steps at a time: the four value/column loads,
+  // then the four gathers, issue back to back (a step past the slice's
+  // longest list gathers x[0] and adds nothing; a padded entry adds zero);
+  // the terms are added in list order
+  if ((im.mask >> lane) & 1ull) {
+    const int j = __builtin_popcountll(im.mask & ((1ull << lane) - 1ull));
+    const T* __restrict__ pb = A.iim + im.base + j;
+    const int* __restrict__ pc = A.icol + im.base + j;
+    for (int k = 0; k < im.w; k += 4) {
+      T b[4];
+      int c[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const bool on = q + u < q1;
-      b[u] = on ? A.iim[q + u] : T(0);
-      c[u] = on ? A.icol[q + u] : 0;
-    }
-    cx<T> xv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) xv[u] = x[c[u]];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (q + u < q1) {             // i b x = -b x.im + i b x.re
-        ar = fma(-b[u], xv[u].im, ar);
-        ai = fma(b[u], xv[u].re, ai);
+      for (int u = 0; u < 4; ++u) {
+        const bool on = k + u < im.w;
+        b[u] = on ? pb[(k + u) * im.nl] : T(0);
+        c[u] = on ? pc[(k + u) * im.nl] : 0;
       }
+      cx<T> xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = x[c[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (k + u < im.w) {         // i b x = -b x.im + i b x.re
+          ar = fma(-b[u], xv[u].im, ar);
+          ai = fma(b[u], xv[u].re, ai);
+        }
+    }
   }
   return cx<T>{ar, ai};
 }

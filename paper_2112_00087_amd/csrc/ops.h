@@ -47,7 +47,7 @@ inline SellOp<T> op_split(hz_ctx ctx) {
   A.ptr = ctx->d_sptr.as<int>();
   A.col = ctx->d_scol.as<int>();
   A.dcol = ctx->split_dcol ? ctx->d_dcol.as<int16_t>() : nullptr;
-  A.iptr = ctx->d_iptr.as<int>();
+  A.imeta = ctx->d_imeta.as<ImSlice>();
   A.icol = ctx->d_icol.as<int>();
   A.re = sizeof(T) == 8 ? static_cast<T*>(ctx->d_R.p) : static_cast<T*>(ctx->d_R32.p);
   A.iim = sizeof(T) == 8 ? static_cast<T*>(ctx->d_I.p) : static_cast<T*>(ctx->d_I32.p);

@@ -64,7 +64,8 @@ __global__ void k_split_im(int64_t ni, const int* __restrict__ ipos, const z_t* 
                            double* __restrict__ I, float* __restrict__ I32) {
   int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (q >= ni) return;
-  double v = A[ipos[q]].im;
+  const int at = ipos[q];
+  double v = at >= 0 ? A[at].im : 0.0;   // padding slot: 0
   I[q] = v;
   if (I32) I32[q] = float(v);
 }
@@ -90,7 +91,7 @@ int grow(hz_ctx ctx, DevBuf& b, size_t bytes) {
 
 int op_set_frequency(hz_ctx ctx, const OpParts& P, double k, int scale, bool want32) {
   const bool split = ctx->split_on && !ctx->have_eta;
-  const int64_t npad = ctx->sell.n_pad, ni = ctx->n_imag;
+  const int64_t npad = ctx->sell.n_pad, ni = ctx->n_islots;
   if (split) {
     HZ_TRY(grow(ctx, ctx->d_R, sizeof(double) * npad));
     HZ_TRY(grow(ctx, ctx->d_I, sizeof(double) * std::max<int64_t>(ni, 1)));
