@@ -27,10 +27,10 @@ struct Seg {
 //  complex form (val != NULL): one complex value per stored entry.
 //  split form (val == NULL): the real part of every stored entry (re) plus,
 //    per row, a short list of the entries whose imaginary part can be
-//    nonzero (imeta/icol/iim, interleaved per slice).  Without an absorption field only the entries
-//    that touch the absorbing walls are complex (the wall term and the
-//    Jacobi scaling of wall columns), so this form streams 8 (FP64) or 4
-//    (FP32) bytes per entry instead of 16 or 8.
+//    nonzero (imeta/icol/iim, interleaved per slice).  Without an absorption
+//    field only the entries that touch the absorbing walls are complex (the
+//    wall term and the Jacobi scaling of wall columns), so this form streams
+//    8 (FP64) or 4 (FP32) bytes per entry instead of 16 or 8.
 //  Column indices are int32 (col) or, when every |col - row| fits, int16
 //  offsets from the row (dcol).
 //  stencil form (st != NULL, structured boxes): the split form's real parts
@@ -246,6 +246,8 @@ __device__ __forceinline__ void store_partials(double (&v)[NQ], double* partial,
   }
   last = __shfl(last, 0, kWave);
   if (!last) return;
+  // every lane of the last wave reads the other waves' sums after the count
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   for (int q = lane; q < NQ; q += kWave) {
     double t = 0.0;
 #pragma unroll
