@@ -103,6 +103,18 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
   return x * q + (x < r ? x : r) + idx;
 }
 
+// Chunked variant: each XCD takes runs of kXcdChunk consecutive tiles, the
+// XCDs' runs interleaved (tiles [8 C g + C x, 8 C g + C x + C) on XCD x);
+// the tail past the last whole round of 8 C tiles keeps dispatch order.
+constexpr int kXcdChunk = 8;
+__device__ __forceinline__ int xcd_chunk_tile(int b, int nblocks) {
+  constexpr int span = kNumXcd * kXcdChunk;
+  const int full = nblocks / span * span;
+  if (b >= full) return b;
+  const int x = b % kNumXcd, i = b / kNumXcd;
+  return ((i / kXcdChunk) * kNumXcd + x) * kXcdChunk + i % kXcdChunk;
+}
+
 // ---------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

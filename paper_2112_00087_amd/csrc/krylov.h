@@ -195,7 +195,7 @@ struct Tile {
 };
 __device__ __forceinline__ Tile tile_of(const Seg& L) {
   Tile t;
-  t.tile = blockIdx.x;
+  t.tile = xcd_chunk_tile(blockIdx.x, gridDim.x);
   t.seg = L.blk_seg[t.tile];
   t.row = int64_t(t.tile) * kBlock + threadIdx.x;
   return t;

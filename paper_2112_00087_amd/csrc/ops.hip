@@ -135,7 +135,7 @@ int op_set_frequency(hz_ctx ctx, const OpParts& P, double k, int scale, bool wan
 template <typename T, int F>
 __global__ void __launch_bounds__(kBlock) k_spmv(int64_t nout, SellOp<T> A, const cx<T>* __restrict__ x,
                                                  cx<T>* __restrict__ y) {
-  int64_t row = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  int64_t row = int64_t(xcd_chunk_tile(blockIdx.x, gridDim.x)) * kBlock + threadIdx.x;
   cx<T> v = sell_row_form<F>(A, row, x);
   if (row < nout) y[row] = v;
 }
