@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the FP64 product on this workload, per storage form,
 # from the FETCH_SIZE / WRITE_SIZE passes recorded in profiles/ (calibrated
 # against a 1 GiB device copy); None until measured for the current kernel.
-MEASURED_TRAFFIC = {"stencil": 450.5e6, "split": None, "complex": 827.0e6}
+MEASURED_TRAFFIC = {"stencil": 350.9e6, "split": None, "complex": 732.8e6}
 
 
 def log(*a):
