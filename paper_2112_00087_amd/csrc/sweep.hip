@@ -560,6 +560,18 @@ __global__ void k_update(int64_t total, int s, const SwCol* __restrict__ st, SwA
 // storage, a reliable update that replaces the recursive residual by the true
 // one and keeps the Krylov recurrence (Sleijpen and van der Vorst's reliable
 // updates).  Other columns keep iterating meanwhile.
+// At the product cap: every column still inside an inner solve ends it, so
+// that one more refinement step adds the correction reached so far to X and
+// measures the column's FP64 residual (a capped column reports the residual
+// of its best iterate, never that of x0).
+template <typename C>
+__global__ void k_end_inner(int s, C* st) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= s) return;
+  C& S = st[c];
+  if (!S.done && !S.nan && !S.idone) S.idone = 1;
+}
+
 struct BcCol {
   double k, k2, fn2, thr2, scale, ithr2, rr, ss, rhat2, beta;
   z_t rho, rho_old, alpha, omega;
@@ -1634,6 +1646,7 @@ int run_sweep_bicgstab(hz_ctx ctx, SweepData& D, int nf, const double* freqs, co
   int rc = 0;
   mapb = ctx->buf("swb.map", sizeof(int) * 128, &rc);
   if (rc) return rc;
+  bool capped = false;
   bool stop = false;
   while (!stop) {
     HZ_HIP(hipMemcpyAsync(hs, W.st, sizeof(BcCol) * W.s, hipMemcpyDeviceToHost, q));
@@ -1654,7 +1667,14 @@ int run_sweep_bicgstab(hz_ctx ctx, SweepData& D, int nf, const double* freqs, co
       HZ_TRY(outer(q));
       continue;
     }
-    if (mx + 2 * chunk + 1 > o.max_matvec) break;
+    // two products stay in reserve for the refinement step at the cap
+    if (mx + 2 * chunk + 3 > o.max_matvec) {
+      if (capped) break;
+      capped = true;
+      k_end_inner<BcCol><<<1, 64, 0, q>>>(W.s, W.st);
+      HZ_TRY(outer(q));
+      continue;
+    }
     if (active <= W.s / 2) {
       // compaction: finished columns leave, the rest move to a narrower width
       std::vector<int> keep, gone_j, gone_f;
@@ -2291,6 +2311,7 @@ int run_sweep_bicgstabl(hz_ctx ctx, SweepData& D, int nf, const double* freqs, c
   int rc = 0;
   DevBuf* mapb = ctx->buf("swl.map", sizeof(int) * 128, &rc);
   if (rc) return rc;
+  bool capped = false;
   for (;;) {
     HZ_HIP(hipMemcpyAsync(hs, W.st, sizeof(SlCol) * W.s, hipMemcpyDeviceToHost, q));
     HZ_HIP(hipStreamSynchronize(q));
@@ -2310,7 +2331,14 @@ int run_sweep_bicgstabl(hz_ctx ctx, SweepData& D, int nf, const double* freqs, c
       HZ_TRY(outer(q));
       continue;
     }
-    if (mx + 2 * int64_t(l) * chunk + 1 > o.max_matvec) break;
+    // two products stay in reserve for the refinement step at the cap
+    if (mx + 2 * int64_t(l) * chunk + 3 > o.max_matvec) {
+      if (capped) break;
+      capped = true;
+      k_end_inner<SlCol><<<1, 64, 0, q>>>(W.s, W.st);
+      HZ_TRY(outer(q));
+      continue;
+    }
     if (active <= W.s / 2) {
       // compaction: finished columns leave, the rest move to a narrower width
       std::vector<int> keep, gone_j, gone_f;
@@ -2414,10 +2442,17 @@ int run_sweep_bicgstabl(hz_ctx ctx, SweepData& D, int nf, const double* freqs, c
 // its last update and the host runs the refinement step (X += scale D^-1 y,
 // R = F - A X in FP64): done, or restart.  A breakdown also ends the inner
 // solve with a refinement step.
+// Stagnation test of complex64 inner TFQMR solves: checkpoint spacing in
+// half-steps (a bound that has not halved over one spacing ends the solve).
+constexpr int kTsStagHalfSteps = 1024;
+
 struct TsCol {
   z_t alpha, rho, beta, eta;
   double theta, tau, ithr, fn2, thr2, scale, beta_true, rr;
+  double chk;    // quasi-residual bound at the last stagnation checkpoint
   int done, idone, nan, m, iters, outer, restart_now, last;
+  int mchk;      // half-step count at that checkpoint
+  int stag;      // checkpoint spacing in half-steps (0: no stagnation test)
 };
 
 template <typename T>
@@ -2530,6 +2565,8 @@ __global__ void k_ts_start_fin(int G_, int s, TsCol* st, const double* __restric
   S.eta = z_t{0.0, 0.0};
   S.rho = z_t{1.0, 0.0};            // r*^H r0
   S.m = 0;
+  S.chk = 1.0;
+  S.mchk = 0;
   const z_t sg = {re, im};
   if (norm2(sg) == 0.0 || !isfinite(re) || !isfinite(im)) S.nan = 1;
   else S.alpha = cdiv(S.rho, sg);
@@ -2545,9 +2582,20 @@ __device__ __forceinline__ void ts_qmr(TsCol& S, double ww) {
     S.nan = 1;
     return;
   }
-  if (S.tau * sqrt(double(S.m + 1)) <= S.ithr) {
+  const double bound = S.tau * sqrt(double(S.m + 1));
+  if (bound <= S.ithr) {
     S.idone = 1;
     S.last = 1;
+  } else if (S.stag > 0 && S.m - S.mchk >= S.stag) {
+    // complex64 inner solve: a bound that has not halved over the last
+    // checkpoint interval ends the inner solve, so the refinement step adds
+    // the correction reached so far and restarts from the FP64 residual
+    if (bound > 0.5 * S.chk) {
+      S.idone = 1;
+      S.last = 1;
+    }
+    S.chk = bound;
+    S.mchk = S.m;
   }
   S.m += 1;
 }
@@ -2715,11 +2763,12 @@ __global__ void k_ts_alpha_fin(int G_, int s, TsCol* st, const double* __restric
   else S.alpha = cdiv(S.rho, sg);
 }
 
-__global__ void k_ts_init(int s, TsCol* st, const double* fn2, double tol) {
+__global__ void k_ts_init(int s, TsCol* st, const double* fn2, double tol, int stag) {
   const int c = threadIdx.x;
   if (c >= s) return;
   st[c].fn2 = fn2[c];
   st[c].thr2 = tol * tol * fn2[c];
+  st[c].stag = stag;
   st[c].idone = 1;                 // every column starts with a refinement step
 }
 
@@ -2802,7 +2851,7 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
   k_colnorm<double><<<W.Gr, kBlock, 0, cs>>>(W.total, s, W.Fs, W.part);
   k_colsum<<<s, kBlock, 0, cs>>>(W.Gr, s, W.part, W.cn);
   HZ_HIP(hipMemsetAsync(W.st, 0, sizeof(TsCol) * s, cs));
-  k_ts_init<<<1, 64, 0, cs>>>(s, W.st, W.cn, o.tol);
+  k_ts_init<<<1, 64, 0, cs>>>(s, W.st, W.cn, o.tol, sizeof(T) == 4 ? kTsStagHalfSteps : 0);
   HZ_HIP(hipGetLastError());
   HZ_TRY(autotune<T>(ctx, cs, nrows, s, AT, W.kc, W.V.Z, W.V.uh, &W.vin));
 
@@ -2865,6 +2914,7 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
   int rc = 0;
   DevBuf* mapb = ctx->buf("swt.map", sizeof(int) * 128, &rc);
   if (rc) return rc;
+  bool capped = false;
   for (;;) {
     HZ_HIP(hipMemcpyAsync(hs, W.st, sizeof(TsCol) * W.s, hipMemcpyDeviceToHost, q));
     HZ_HIP(hipStreamSynchronize(q));
@@ -2884,7 +2934,14 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
       HZ_TRY(outer(q));
       continue;
     }
-    if (mx + 2 * chunk + 1 > o.max_matvec) break;
+    // two products stay in reserve for the refinement step at the cap
+    if (mx + 2 * chunk + 3 > o.max_matvec) {
+      if (capped) break;
+      capped = true;
+      k_end_inner<TsCol><<<1, 64, 0, q>>>(W.s, W.st);
+      HZ_TRY(outer(q));
+      continue;
+    }
     if (active <= W.s / 2) {
       std::vector<int> keep, gone_j, gone_f;
       for (int j = 0; j < nreal; ++j) {

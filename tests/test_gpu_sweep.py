@@ -126,3 +126,62 @@ def test_sweep_full_size_residuals_by_oracle(P):
         rel = H.relres(A, Pg[:, j], fo)
         assert infos[j]["status"] == 0 and rel <= 1e-8 * 1.01, (j, fr, rel, infos[j])
     model.close()
+
+
+@pytest.mark.parametrize("precision,method", [("mixed", "tfqmr"), ("fp64", "tfqmr"), ("mixed", "bicgstab"),
+                                              ("fp64", "bicgstab"), ("mixed", "bicgstabl"),
+                                              ("fp64", "bicgstabl")])
+def test_sweep_capped_columns_keep_their_progress(P, precision, method):
+    """A column stopped by the product cap in the middle of an inner solve
+    still receives that solve's correction: it reports NOT_CONVERGED with the
+    FP64 residual of its best iterate, which is below 1 (never x0's) and is
+    the residual the oracle recomputes."""
+    say("capped sweep", precision, method)
+    wl = W.workload(2, elems=(20, 12, 10))
+    mesh = wl["mesh"]
+    freqs = np.linspace(20, 300, 9)
+    S = H.System(mesh, wl["beta"])
+    f = S.load(wl["g"])
+    F = np.repeat(f[:, None], freqs.size, axis=1)
+    model = P.Helmholtz(mesh, wl["beta"])
+    Pg, infos = model.solve_sweep(freqs, _t(F), method=method, restart=4 if method == "bicgstabl" else 30,
+                                  tol=1e-13, precision=precision, inner_tol=1e-7, max_matvec=110)
+    say("  status", [i["status"] for i in infos], "relres", [f"{i['relres_true']:.1e}" for i in infos])
+    Pg = Pg.cpu().numpy()
+    capped = 0
+    for j, fr in enumerate(freqs):
+        A = S.operator(W.wavenumber(fr))
+        rel = H.relres(A, Pg[:, j], F[:, j])
+        assert infos[j]["status"] in (0, 1), (j, infos[j])
+        capped += infos[j]["status"] == 1
+        assert rel < 0.99, (j, fr, rel)       # x0 = 0 would leave exactly 1
+        assert abs(infos[j]["relres_true"] - rel) <= 1e-2 * rel + 1e-15, (j, rel, infos[j])
+    assert capped > 0
+    model.close()
+
+
+def test_sweep_mixed_tfqmr_tight_inner_tolerance(P):
+    """Complex64 inner TFQMR solves asked for 1e-7 (about complex64's
+    roundoff): every column converges, or reports NOT_CONVERGED with a
+    residual below 1 that the oracle confirms."""
+    wl = W.workload(2, elems=(40, 24, 20))
+    mesh = wl["mesh"]
+    freqs = np.linspace(20, 300, 9)
+    S = H.System(mesh, wl["beta"])
+    f = S.load(wl["g"])
+    F = np.repeat(f[:, None], freqs.size, axis=1)
+    model = P.Helmholtz(mesh, wl["beta"])
+    Pg, infos = model.solve_sweep(freqs, _t(F), method="tfqmr", tol=1e-8, precision="mixed", inner_tol=1e-7,
+                                  max_matvec=20000)
+    say("  tight inner tol: status", [i["status"] for i in infos], "iters", [i["iters"] for i in infos])
+    Pg = Pg.cpu().numpy()
+    for j, fr in enumerate(freqs):
+        A = S.operator(W.wavenumber(fr))
+        rel = H.relres(A, Pg[:, j], F[:, j])
+        assert abs(infos[j]["relres_true"] - rel) <= 1e-2 * rel + 1e-15, (j, rel, infos[j])
+        if infos[j]["status"] == 0:
+            assert rel <= 1e-8 * 1.01, (j, fr, rel)
+        else:
+            assert infos[j]["status"] == 1 and rel < 1.0, (j, fr, rel, infos[j])
+    assert sum(i["status"] == 0 for i in infos) == len(freqs)
+    model.close()
