@@ -232,6 +232,22 @@ int hz_load(hz_ctx ctx, const hz_c128* g_dev, hz_c128* f_dev);
 int hz_dotc(hz_ctx ctx, int64_t n, const hz_c128* a_dev, const hz_c128* b_dev,
             hz_c128* out);
 
+/* Allocation-free form of hz_dotc, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops that forbid
+ * hipMalloc): out_dev[0] = a^H b over n complex128 entries, written to
+ * device memory (16 bytes, caller-owned), stream-ordered on the context's
+ * stream, no synchronisation.  Same kernels, grid and summation order as
+ * hz_dotc, so the two results are bitwise equal.  The reduction's partial
+ * sums live in a static device array of the library (16 KiB per GPU, held
+ * until the process ends: at most 1024 blocks of partial sums, which covers
+ * every n >= 0; a larger need is rejected with HZ_ERR_INVALID).  The call
+ * allocates nothing.  Every call on one GPU shares that GPU's array: calls
+ * that overlap in time on one GPU (two streams, or two threads) race and
+ * give wrong results; calls ordered on one stream are safe.  Each call
+ * writes every partial sum it reads, so no state carries over between
+ * calls.  Errors: HZ_ERR_INVALID (null pointer, n < 0), HZ_ERR_HIP. */
+int hz_dotc_noalloc(hz_ctx ctx, int64_t n, const hz_c128* a_dev, const hz_c128* b_dev, hz_c128* out_dev);
+
 /* Solves A(k) p = f at the current frequency (paper Sec. 4: preconditioned
  * Krylov methods and the optimised Schwarz method, complex double).
  *   f_dev  [n_nodes] right-hand side (not modified)

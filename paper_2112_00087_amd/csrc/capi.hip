@@ -26,6 +26,8 @@ int adjoint_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* p, const z_t* g
     return hz_fail(HZ_ERR_INVALID, "unexpected exception in the library");    \
   }
 
+int noalloc_setup(int device);
+
 int validate_opts(const hz_solve_opts* o) {
   if (!o) return hz_fail(HZ_ERR_INVALID, "opts is NULL");
   if (o->method < HZ_GMRES || o->method > HZ_TFQMR) return hz_fail(HZ_ERR_INVALID, "unknown method %d", o->method);
@@ -82,6 +84,7 @@ int hz_assemble(const hz_mesh* mesh, const hz_c128* beta, const double* eta, voi
   // host-side validation and assembly first: bad input never touches the GPU
   HZ_TRY(host_assemble(mesh, eta, &ctx->h, 6, &ctx->perm));
   HZ_HIP(hipGetDevice(&ctx->device));
+  HZ_TRY(noalloc_setup(ctx->device));   // static scratch of hz_dotc_noalloc on this device
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   ctx->c = mesh->c;
   ctx->rho = mesh->rho;

@@ -83,6 +83,9 @@ int op_fill(hipStream_t s, int64_t n, z_t* y, z_t v);
 int op_copy(hipStream_t s, int64_t n, const z_t* x, z_t* y);
 int op_load(hz_ctx ctx, const z_t* g, z_t* f);
 int op_dotc(hz_ctx ctx, int64_t n, const z_t* a, const z_t* b, double* out_dev);
+// The same two kernels with the caller's partial-sum buffer (2 reduce_grid(n)
+// doubles) on the given stream.
+int op_dotc_into(hipStream_t stream, int64_t n, const z_t* a, const z_t* b, double* part, double* out_dev);
 
 // ---------------------------------------------------------------- solvers
 // Per-segment controls and results of one Krylov run.

@@ -245,14 +245,18 @@ __global__ void k_dot_fin(int nb, const double* __restrict__ part, double* __res
   }
 }
 
-int op_dotc(hz_ctx ctx, int64_t n, const z_t* a, const z_t* b, double* out_dev /*2*/) {
-  int rc = 0;
-  int g = reduce_grid(n);
-  DevBuf* part = ctx->buf("dot.part", sizeof(double) * 2 * g, &rc);
-  if (rc) return rc;
-  k_dot_part<double><<<g, kBlock, 0, ctx->stream>>>(n, a, b, part->as<double>());
+int op_dotc_into(hipStream_t stream, int64_t n, const z_t* a, const z_t* b, double* part, double* out_dev) {
+  const int g = reduce_grid(n);
+  k_dot_part<double><<<g, kBlock, 0, stream>>>(n, a, b, part);
   HZ_HIP(hipGetLastError());
-  k_dot_fin<<<1, kBlock, 0, ctx->stream>>>(g, part->as<double>(), out_dev);
+  k_dot_fin<<<1, kBlock, 0, stream>>>(g, part, out_dev);
   HZ_HIP(hipGetLastError());
   return HZ_OK;
+}
+
+int op_dotc(hz_ctx ctx, int64_t n, const z_t* a, const z_t* b, double* out_dev /*2*/) {
+  int rc = 0;
+  DevBuf* part = ctx->buf("dot.part", sizeof(double) * 2 * reduce_grid(n), &rc);
+  if (rc) return rc;
+  return op_dotc_into(ctx->stream, n, a, b, part->as<double>(), out_dev);
 }

@@ -103,6 +103,7 @@ def lib():
         "hz_get_diag": (C.c_int, [VP, VP]),
         "hz_load": (C.c_int, [VP, VP, VP]),
         "hz_dotc": (C.c_int, [VP, C.c_int64, VP, VP, P(hz_c128)]),
+        "hz_dotc_noalloc": (C.c_int, [VP, C.c_int64, VP, VP, VP]),
         "hz_solve": (C.c_int, [VP, P(hz_solve_opts), VP, VP, P(hz_solve_info)]),
         "hz_solve_sweep": (C.c_int, [VP, C.c_int32, P(C.c_double), VP, VP, P(hz_solve_opts),
                                      P(hz_solve_info)]),
