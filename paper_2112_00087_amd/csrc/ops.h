@@ -94,6 +94,10 @@ struct KrylovCtl {
   int max_matvec = 20000;
   int restart = 30;               // GMRES
   int ell = 4;                    // BiCGStab(l)
+  // TFQMR: a quasi-residual bound that has not halved over this many
+  // half-steps ends the solve (0: never).  Set for complex64 inner solves
+  // of the refinement, whose bound can stall above the inner tolerance.
+  int stall_halfsteps = 0;
 };
 struct KrylovOut {
   std::vector<int> iters, matvecs, status;

@@ -26,7 +26,10 @@ namespace {
 struct TqSt {
   z_t alpha, rho, beta, eta;
   double theta, tau, thr, thr2, rr;
+  double chk;           // quasi-residual bound at the last stall checkpoint
   int m, iter, done, last, brk, nan, restart, pad;
+  int mchk, stall_win;  // half-step of that checkpoint; its spacing (0: off)
+  int stalled, pad2;    // the bound stalled: the solve ends unconfirmed
 };
 
 template <typename T>
@@ -63,9 +66,18 @@ __device__ __forceinline__ void tq_qmr(TqSt& S, double ww) {
     S.nan = 1;
     return;
   }
-  if (S.tau * sqrt(double(S.m + 1)) <= S.thr) {
+  const double bound = S.tau * sqrt(double(S.m + 1));
+  if (bound <= S.thr) {
     S.done = 1;       // quasi-residual bound met: the last x update follows
     S.last = 1;
+  } else if (S.stall_win > 0 && S.m - S.mchk >= S.stall_win) {
+    if (bound > 0.5 * S.chk) {
+      S.done = 1;     // stalled: stop with the iterate reached (last x update follows)
+      S.last = 1;
+      S.stalled = 1;
+    }
+    S.chk = bound;
+    S.mchk = S.m;
   }
   S.m += 1;
 }
@@ -111,6 +123,8 @@ __global__ void k_tq_resid_fin(Seg L, TqSt* st, const double* part) {
     S.eta = z_t{0.0, 0.0};
     S.rho = z_t{rr, 0.0};
     S.m = 0;
+    S.chk = S.tau;
+    S.mchk = 0;
     // restart stays set until the first product (v = uhat = B u) is formed
   }
 }
@@ -263,12 +277,14 @@ __global__ void HZ_PRODUCT_BOUNDS k_tq_odd3(Seg L, SellOp<T> A, const TqSt* st, 
   store_partials<2>(q, part, t);
 }
 
-__global__ void k_tq_set_thr(int nseg, TqSt* st, const double* fn2, double tol) {
+__global__ void k_tq_set_thr(int nseg, TqSt* st, const double* fn2, double tol, int stall_win) {
   int s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= nseg) return;
   st[s].thr2 = tol * tol * fn2[s];
   st[s].thr = tol * sqrt(fn2[s]);
   st[s].iter = 0;
+  st[s].stall_win = stall_win;
+  st[s].stalled = 0;
 }
 
 }  // namespace
@@ -307,7 +323,8 @@ int tfqmr_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
   for (int i = 0; i < S.nseg; ++i) out->fnorm[i] = std::sqrt(fn2[i]);
   HZ_HIP(hipMemcpyAsync(fnb->p, fn2.data(), sizeof(double) * S.nseg, hipMemcpyHostToDevice, s));
   HZ_HIP(hipMemsetAsync(stb->p, 0, sizeof(TqSt) * S.nseg, s));
-  k_tq_set_thr<<<ceil_div(S.nseg, kBlock), kBlock, 0, s>>>(S.nseg, st, fnb->as<double>(), ctl.tol);
+  k_tq_set_thr<<<ceil_div(S.nseg, kBlock), kBlock, 0, s>>>(S.nseg, st, fnb->as<double>(), ctl.tol,
+                                                            ctl.stall_halfsteps);
   HZ_HIP(hipGetLastError());
 
   void* hp = nullptr;
@@ -357,13 +374,15 @@ int tfqmr_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
   HZ_TRY(enqueue_restart(1));
   HZ_TRY(read_state());
   for (;;) {
-    bool all_done = true, any_brk = false;
+    bool all_done = true, any_brk = false, any_stalled = false;
     for (int i = 0; i < S.nseg; ++i) {
       all_done = all_done && hst[i].done;
       any_brk = any_brk || (hst[i].brk && !hst[i].done);
+      any_stalled = any_stalled || hst[i].stalled;
     }
     // products so far: two per restart, two per queued pair (stopped segments idle)
     const int64_t mv = 2 * restarts + 2 * pairs;
+    if (all_done && any_stalled) break;   // hand the iterate reached back to the refinement
     if (all_done) {
       HZ_TRY(enqueue_restart(1));   // confirm with the true residual
       HZ_TRY(read_state());
@@ -393,7 +412,7 @@ int tfqmr_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
     out->matvecs[i] = hst[i].iter + 2 * int(restarts);
     const double fnv = out->fnorm[i];
     out->relres_est[i] = fnv > 0 ? std::sqrt(hst[i].rr) / fnv : 0.0;
-    out->status[i] = hst[i].nan ? HZ_BREAKDOWN : (hst[i].done ? HZ_OK : HZ_NOT_CONVERGED);
+    out->status[i] = hst[i].nan ? HZ_BREAKDOWN : (hst[i].done && !hst[i].stalled ? HZ_OK : HZ_NOT_CONVERGED);
   }
   return HZ_OK;
 }
