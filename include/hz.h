@@ -210,8 +210,12 @@ int hz_assemble(const hz_mesh* mesh, const hz_c128* beta, const double* eta,
  * next solve until hz_set_frequency is called again). */
 int hz_set_params(hz_ctx ctx, const hz_c128* beta, const double* eta);
 
-/* Forms A(k) for k = 2 pi freq_hz / c on the device (one pass over the
- * nonzeros) and its diagonal; later solves and hz_apply use it.
+/* Forms A(k) = K - k^2 M + i k^2 M_eta + i k B_beta for k = 2 pi freq_hz / c
+ * on the device (one pass over the nonzeros) and its diagonal: the
+ * finite-element operator of the Fourier-transformed wave equation at one
+ * frequency (paper Sec. 3.2, the Helmholtz equation and its discretisation;
+ * the wall and absorption terms are the Robin admittances and loss factors
+ * described at the top of this header).  Later solves and hz_apply use it.
  * freq_hz must be finite and >= 0.  Errors: HZ_ERR_INVALID, HZ_ERR_HIP. */
 int hz_set_frequency(hz_ctx ctx, double freq_hz);
 
@@ -259,7 +263,10 @@ int hz_dotc_noalloc(hz_ctx ctx, int64_t n, const hz_c128* a_dev, const hz_c128* 
 int hz_solve(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* f_dev,
              hz_c128* p_dev, hz_solve_info* info);
 
-/* Frequency sweep: solves A(k_j) P[:, j] = F[:, j] for j < nfreq (1..64)
+/* Frequency sweep (an addition to the paper's method, which solves one
+ * frequency at a time: no passage defines it; each column is the system of
+ * hz_set_frequency at its own frequency): solves A(k_j) P[:, j] = F[:, j]
+ * for j < nfreq (1..64)
  * with all columns advanced together: one multi-vector sparse product per
  * Krylov step shares the real K, M (and M_eta) values across columns, and
  * each chunk of inner iterations is replayed from a captured HIP graph.
@@ -292,7 +299,10 @@ int hz_solve_sweep(hz_ctx ctx, int32_t nfreq, const double* freqs_host,
                    const hz_c128* F_dev, hz_c128* P_dev,
                    const hz_solve_opts* opts, hz_solve_info* infos);
 
-/* Adjoint solve and gradient at the current frequency.  With the forward
+/* Adjoint solve and gradient at the current frequency (an addition to the
+ * paper's method: no passage defines it; it differentiates the solution of
+ * the Sec. 3.2 system with respect to the wall admittances and the
+ * absorption field).  With the forward
  * solution p (A p = f) and the objective's derivative g = dJ/dconj(p)
  * (for J = sum_r |p_r|^2: g = p on the receivers, 0 elsewhere), solves
  * A^H lambda = g (as A mu = conj(g), lambda = conj(mu), A being complex
@@ -308,6 +318,19 @@ int hz_solve_sweep(hz_ctx ctx, int32_t nfreq, const double* freqs_host,
 int hz_solve_adjoint(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* p_dev,
                      const hz_c128* g_dev, hz_c128* lambda_dev, double* dJ_dbeta,
                      double* dJ_deta_dev, hz_solve_info* info);
+
+/* Receiver objective of the adjoint gradient (an addition to the paper's
+ * method, no defining passage): with p_dev the solution at one frequency,
+ *     *J += sum_r |p[receivers[r]]|^2                    (host, accumulated)
+ *     g_dev = dJ/dconj(p): p on the receiver nodes, 0 elsewhere
+ * g_dev is the right-hand side hz_solve_adjoint takes.
+ *   n_rec      number of receivers (>= 0)
+ *   receivers  [n_rec] host array of distinct node ids (caller's numbering)
+ *   p_dev, g_dev  [n_nodes] device vectors (must not overlap)
+ * J is summed in a fixed order (bitwise reproducible).  Synchronises.
+ * Errors: HZ_ERR_INVALID (null pointer, id out of range or repeated). */
+int hz_receiver_energy(hz_ctx ctx, int32_t n_rec, const int32_t* receivers, const hz_c128* p_dev, double* J,
+                       hz_c128* g_dev);
 
 /* Optimised Robin coefficients for a Schwarz interface (host computation,
  * no context, no GPU): the interface modes xi in [pi/H, pi/h] (H subdomain

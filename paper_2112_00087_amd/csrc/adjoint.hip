@@ -111,7 +111,48 @@ __global__ void k_grad_beta_fin(int nblk, const double* __restrict__ part, doubl
   }
 }
 
+// Receiver objective J = sum_r |p_r|^2 and its derivative g = dJ/dconj(p):
+// g_r = p_r on the (distinct) receiver nodes, 0 elsewhere (g is cleared
+// before this kernel).  One block: J in a fixed summation order.
+__global__ void __launch_bounds__(kBlock) k_receivers(int nrec, const int* __restrict__ rec,
+                                                      const z_t* __restrict__ p, z_t* __restrict__ g,
+                                                      double* __restrict__ J) {
+  __shared__ double lds[kBlock / kWave];
+  double acc = 0.0;
+  for (int r = threadIdx.x; r < nrec; r += kBlock) {
+    const z_t v = p[rec[r]];
+    g[rec[r]] = v;
+    acc = fma(v.re, v.re, fma(v.im, v.im, acc));
+  }
+  const double s = block_sum(acc, lds);
+  if (threadIdx.x == 0) J[0] = s;
+}
+
 }  // namespace
+
+int receiver_objective(hz_ctx ctx, int nrec, const int* rec_host, const z_t* p, double* J_host, z_t* g) {
+  int rc = 0;
+  const int64_t n = ctx->h.n;
+  std::vector<char> seen(size_t(n), 0);
+  for (int r = 0; r < nrec; ++r) {
+    if (rec_host[r] < 0 || rec_host[r] >= n) return hz_fail(HZ_ERR_INVALID, "receiver %d out of range", rec_host[r]);
+    if (seen[size_t(rec_host[r])]++) return hz_fail(HZ_ERR_INVALID, "receiver %d listed twice", rec_host[r]);
+  }
+  DevBuf* rb = ctx->buf("rec.ids", sizeof(int) * size_t(std::max(nrec, 1)), &rc);
+  if (rc) return rc;
+  DevBuf* jb = ctx->buf("rec.J", sizeof(double), &rc);
+  if (rc) return rc;
+  void* hp = nullptr;
+  HZ_TRY(ctx_pinned(ctx, sizeof(double), &hp));
+  HZ_HIP(hipMemcpyAsync(rb->p, rec_host, sizeof(int) * size_t(nrec), hipMemcpyHostToDevice, ctx->stream));
+  HZ_TRY(op_fill(ctx->stream, n, g, z_t{0.0, 0.0}));
+  k_receivers<<<1, kBlock, 0, ctx->stream>>>(nrec, rb->as<int>(), p, g, jb->as<double>());
+  HZ_HIP(hipGetLastError());
+  HZ_HIP(hipMemcpyAsync(hp, jb->p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HZ_HIP(hipStreamSynchronize(ctx->stream));
+  *J_host += *static_cast<double*>(hp);
+  return HZ_OK;
+}
 
 int adjoint_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* p, const z_t* g, z_t* lam, double* dJ_dbeta,
                   double* dJ_deta, hz_solve_info* info) {

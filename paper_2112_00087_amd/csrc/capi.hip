@@ -15,6 +15,7 @@ int sweep_solve(hz_ctx ctx, int nfreq, const double* freqs, const z_t* F, z_t* P
                 hz_solve_info* infos);
 int adjoint_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* p, const z_t* g, z_t* lam, double* dJ_dbeta,
                   double* dJ_deta, hz_solve_info* info);
+int receiver_objective(hz_ctx ctx, int nrec, const int* rec_host, const z_t* p, double* J_host, z_t* g);
 
 #define HZ_GUARD_BEGIN try {
 #define HZ_GUARD_END                                                          \
@@ -238,6 +239,17 @@ int hz_solve_adjoint(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* p_dev
   if (!ctx->have_freq) return hz_fail(HZ_ERR_STATE, "no frequency set (call hz_set_frequency first)");
   return adjoint_solve(ctx, *opts, reinterpret_cast<const z_t*>(p_dev), reinterpret_cast<const z_t*>(g_dev),
                        reinterpret_cast<z_t*>(lambda_dev), dJ_dbeta, dJ_deta_dev, info);
+  HZ_GUARD_END
+}
+
+int hz_receiver_energy(hz_ctx ctx, int32_t n_rec, const int32_t* receivers, const hz_c128* p_dev, double* J,
+                       hz_c128* g_dev) {
+  HZ_GUARD_BEGIN
+  HZ_TRY(check_ctx(ctx));
+  if (n_rec < 0 || (n_rec > 0 && !receivers) || !p_dev || !g_dev || !J)
+    return hz_fail(HZ_ERR_INVALID, "bad arguments");
+  return receiver_objective(ctx, n_rec, receivers, reinterpret_cast<const z_t*>(p_dev), J,
+                            reinterpret_cast<z_t*>(g_dev));
   HZ_GUARD_END
 }
 

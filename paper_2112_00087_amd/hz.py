@@ -112,6 +112,7 @@ def lib():
         "hz_time_spmv": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_int32, P(C.c_double)]),
         "hz_spmv_bytes": (C.c_int, [VP, C.c_int32, C.c_int32, P(C.c_int64)]),
         "hz_dd_alpha": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int32, P(hz_c128)]),
+        "hz_receiver_energy": (C.c_int, [VP, C.c_int32, P(C.c_int32), VP, P(C.c_double), VP]),
         "hz_node_order": (C.c_int, [P(hz_mesh), P(C.c_int32)]),
         "hz_layout": (C.c_int, [VP, P(C.c_int32), P(C.c_int64), P(C.c_int64), P(C.c_int64)]),
         "hz_sizes": (C.c_int, [VP, P(C.c_int64), P(C.c_int64), P(C.c_int64), P(C.c_int64)]),
@@ -331,6 +332,19 @@ class Helmholtz:
         out = hz_c128()
         check(lib().hz_dotc(self.ctx, a.numel(), _dev(a, a.dtype), _dev(b, b.dtype), C.byref(out)), False)
         return complex(out.re, out.im)
+
+    def receiver_energy(self, p, receivers):
+        """J = sum_r |p_r|^2 over distinct receiver node ids and its
+        derivative g = dJ/dconj(p) (hz_receiver_energy)."""
+        p = self._vec(p)
+        if hasattr(receivers, "detach"):
+            receivers = receivers.detach().cpu().numpy()
+        rec = np.ascontiguousarray(np.asarray(receivers, dtype=np.int64).ravel(), dtype=np.int32)
+        g = self._vec()
+        J = C.c_double(0.0)
+        check(lib().hz_receiver_energy(self.ctx, rec.size, _np_ptr(rec, C.c_int32), _dev(p, p.dtype),
+                                       C.byref(J), _dev(g, g.dtype)), False)
+        return J.value, g
 
     def solve(self, f, x0=None, **opts):
         f = self._vec(f)

@@ -46,9 +46,12 @@ def _gpu_gradient(model, wl, eta, freqs, tol, method="gmres"):
         model.set_frequency(fr)
         p, info = model.solve(f, method=method, tol=tol, restart=60, max_matvec=200000)
         assert info["status"] == 0, info
-        J += float((p[rec].abs() ** 2).sum())
-        g = torch.zeros_like(p)
-        g[rec] = p[rec]
+        Jf, g = model.receiver_energy(p, rec)       # the library's objective and adjoint source
+        g_ref = torch.zeros_like(p)
+        g_ref[rec] = p[rec]
+        assert torch.equal(g, g_ref)
+        assert abs(Jf - float((p[rec].abs() ** 2).sum())) <= 1e-13 * Jf
+        J += Jf
         lam, dbf, info = model.solve_adjoint(p, g, dJ_deta=deta, method=method, tol=tol, restart=60,
                                              max_matvec=200000)
         assert info["status"] == 0, info
@@ -148,4 +151,16 @@ def test_full_size_gradient_kernels(P):
             dbo[w] += [2 * k * val.imag, 2 * k * val.real]
     assert np.linalg.norm(de - deo) <= 1e-10 * np.linalg.norm(deo)
     assert np.linalg.norm(db - dbo) <= 1e-10 * np.linalg.norm(dbo)
+    model.close()
+
+
+def test_receiver_energy_rejects_bad_receivers(P):
+    wl, freqs = _case((6, 4, 4), 1)
+    model = P.Helmholtz(wl["mesh"], wl["beta"])
+    p = _t(np.ones(wl["mesh"]["n_nodes"]))
+    J, g = model.receiver_energy(p, [3, 5])
+    assert J == 2.0 and float(g.abs().sum()) == 2.0
+    for bad in ([3, 3], [-1], [wl["mesh"]["n_nodes"]]):
+        with pytest.raises(P.HzError):
+            model.receiver_energy(p, bad)
     model.close()
