@@ -120,3 +120,61 @@ def test_schwarz_rejects_unstructured_or_bad_parts(P):
     with pytest.raises(P.HzError):
         model.solve(_t(f), method="schwarz")
     model.close()
+
+
+def _pair(P, k, mesh, parts):
+    """The optimised two-sided coefficients for a partition (smallest
+    subdomain width, smallest mesh spacing), as the library's default."""
+    nx, ny, nz = mesh["elems"]
+    sp = [1.8 / nx, 1.2 / ny, 1.0 / nz]
+    H_sub = min(sp[d] * (mesh["elems"][d] // parts[d]) for d in range(3))
+    return P.dd_alpha(k, H_sub, min(sp), sides=2)
+
+
+@pytest.mark.parametrize("precision,itol", [("fp64", 1e-12), ("mixed", 1e-10)])
+def test_schwarz_4x3x2_partition_matches_global_solution(P, precision, itol):
+    """The configured partition, 4 x 3 x 2 = 24 subdomains (interior parts
+    with 5 face neighbours, cross points where 8 subdomains meet), on a
+    40x24x20 box (subdomains of 10x8x10 elements) at 150 Hz: interface GMRES
+    with the optimised two-sided coefficients and BiCGStab(4) local solves,
+    complex128 or complex64 with FP64 refinement, against the oracle's direct
+    solution of the global system."""
+    say("schwarz 4x3x2", precision)
+    wl, mesh, et, k, A, f = _case((40, 24, 20), 150.0)
+    model = P.Helmholtz(mesh, wl["beta"], parts=(4, 3, 2))
+    model.set_frequency(150.0)
+    p, info = model.solve(_t(f), method="schwarz", restart=300, tol=1e-8, inner_tol=itol, precision=precision,
+                          dd_inner="bicgstabl", inner_restart=4, max_matvec=300)
+    say("  ", info)
+    p = p.cpu().numpy()
+    x = direct.SparseLU(A).solve(f)
+    rel = H.relres(A, p, f)
+    err = np.linalg.norm(p - x) / np.linalg.norm(x)
+    say(f"  oracle relres {rel:.3e}, relerr vs direct {err:.3e}")
+    assert info["status"] == 0 and rel <= 1e-8 * 1.01
+    assert abs(info["relres_true"] - rel) <= 1e-3 * rel
+    assert err <= 1e-6
+    model.close()
+
+
+def test_schwarz_4x3x2_plain_iteration_matches_oracle_history(P):
+    """Plain Schwarz iterations on the 4 x 3 x 2 partition (20x12x10 box,
+    subdomains of 5x4x5 elements) with the optimised two-sided pair: the GPU
+    iterate equals the oracle's (direct local solves) after 1, 4 and 10
+    iterations, and so do the global residuals."""
+    wl, mesh, et, k, A, f = _case((20, 12, 10), 150.0)
+    parts = (4, 3, 2)
+    a_lo, a_hi = _pair(P, k, mesh, parts)
+    say(f"  pair {a_lo:.4g} {a_hi:.4g}")
+    D = schwarz.Schwarz(mesh, parts, wl["beta"], None, k, f, alpha=(a_lo, a_hi))
+    model = P.Helmholtz(mesh, wl["beta"], parts=parts)
+    model.set_frequency(150.0)
+    for n_it in (1, 4, 10):
+        p, info = model.solve(_t(f), method="schwarz", tol=1e-12, inner_tol=1e-13, dd_inner="gmres",
+                              inner_restart=60, dd_richardson=n_it, dd_alpha=a_lo, dd_alpha2=a_hi)
+        u, lams, hist = D.richardson(n_it + 1, A, f)
+        err = np.linalg.norm(p.cpu().numpy() - u) / np.linalg.norm(u)
+        say(f"  plain Schwarz {n_it}: rel diff {err:.2e}, oracle relres {hist[-1, 1]:.3e}, gpu {info['relres_true']:.3e}")
+        assert err <= 1e-8
+        assert abs(info["relres_true"] - hist[-1, 1]) <= 1e-6 * hist[-1, 1]
+    model.close()

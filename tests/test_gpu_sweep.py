@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import direct, helmholtz as H
+from oracle import direct, helmholtz as H, krylov
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -108,23 +108,53 @@ def test_sweep_x0_and_autotune_cache(P, tmp_path, monkeypatch):
     model.close()
 
 
-def test_sweep_full_size_residuals_by_oracle(P):
+@pytest.fixture(scope="module")
+def c2():
+    """Workload 2 (80x48x40, 64 frequencies in 20-300 Hz, floor admittance,
+    patch forcing): the oracle's operator and load, and reference solutions
+    of three columns (20, 162 and 300 Hz) by the oracle's TFQMR to relres
+    1e-12 (its direct LU takes minutes on one core at this size)."""
     wl = W.workload(2)
+    S = H.System(wl["mesh"], wl["beta"])
+    fo = S.load(wl["g"])
+    refs = {}
+    for j in (0, 32, 63):
+        A = S.operator(W.wavenumber(wl["freqs"][j])).tocsr()
+        r = krylov.tfqmr(A, fo, tol=1e-12, max_matvec=60000)
+        assert H.relres(A, r.x, fo) <= 1e-12
+        refs[j] = r.x
+        say(f"  oracle reference column {j} ({wl['freqs'][j]:.1f} Hz): {r.matvecs} products")
+    return wl, S, fo, refs
+
+
+@pytest.mark.parametrize("method,precision,itol", [("bicgstab", "fp64", 0.0), ("tfqmr", "fp64", 0.0),
+                                                   ("tfqmr", "mixed", 1e-5)])
+def test_sweep_full_size_residuals_by_oracle(P, c2, method, precision, itol):
+    """The 64-frequency sweep at full size; TFQMR FP64 and TFQMR with
+    complex64 inner solves to 1e-5 are the benchmark's setting.  Every
+    column's residual by the oracle's operator; the relative error of three
+    columns against the oracle's reference solutions (stated per result)."""
+    wl, S, fo, refs = c2
     mesh = wl["mesh"]
     model = P.Helmholtz(mesh, wl["beta"])
     f = model.load(_t(wl["g"]))
     freqs = wl["freqs"]
     F = f[:, None].repeat(1, freqs.size).contiguous()
-    Pg, infos = model.solve_sweep(freqs, F, method="bicgstab", tol=1e-8, precision="fp64",
-                                  max_matvec=100000)
-    say("full-size sweep", infos[0]["seconds"], [i["iters"] for i in infos[:8]])
+    opts = dict(method=method, tol=1e-8, precision=precision, max_matvec=100000)
+    if itol:
+        opts.update(inner_tol=itol, max_matvec=20000)
+    Pg, infos = model.solve_sweep(freqs, F, **opts)
+    say(f"full-size sweep {method} {precision}", infos[0]["seconds"], [i["iters"] for i in infos[:8]])
     Pg = Pg.cpu().numpy()
-    S = H.System(mesh, wl["beta"])
-    fo = S.load(wl["g"])
     for j, fr in enumerate(freqs):
         A = S.operator(W.wavenumber(fr))
         rel = H.relres(A, Pg[:, j], fo)
         assert infos[j]["status"] == 0 and rel <= 1e-8 * 1.01, (j, fr, rel, infos[j])
+        assert abs(infos[j]["relres_true"] - rel) <= 1e-2 * rel, (j, rel, infos[j])
+    for j, x in refs.items():
+        err = np.linalg.norm(Pg[:, j] - x) / np.linalg.norm(x)
+        say(f"  column {j} ({freqs[j]:.1f} Hz): relerr vs oracle {err:.2e}")
+        assert err <= 1e-6, (j, err)
     model.close()
 
 
