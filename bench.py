@@ -8,9 +8,14 @@ are assembled and resident in HBM before the timed region.
 
 Printed as one JSON line: the solve time (value, s), the sparse product's
 achieved algorithmic bandwidth against the 8 TB/s HBM peak (roofline), the
-oracle's CPU time on a bounded sample (cpu_baseline), and secondary numbers
-(GMRES(50), mixed precision, the batched 64-frequency sweep against 64
-per-frequency FP64 solves, and on request the Schwarz and adjoint legs).
+oracle's CPU time on a bounded sample (cpu_baseline: one thread and all host
+cores, plus direct solves), and secondary numbers (GMRES(50), the paper's
+other Krylov methods, mixed precision, the batched 64-frequency sweep
+against 64 per-frequency FP64 solves with the errors of sampled columns
+against the oracle, the 24-subdomain Schwarz solve and the 16-frequency
+adjoint gradient).  Two CPU-side processes (the oracle's direct solve of the
+80x48x40 mesh and its reference solutions of two sweep columns) start before
+the GPU is touched and run beside the GPU legs.
 """
 from __future__ import annotations
 
@@ -44,24 +49,145 @@ def best_solve(t_bicgstab, extra):
     return best
 
 
-def cpu_baseline(wl, gpu_iters, iters):
-    """The oracle's BiCGStab (complex128 CSR, SciPy matvec, one thread) timed
-    on `iters` iterations of the same system, scaled to the GPU's count."""
-    from oracle import helmholtz as H, krylov
+def host_cores():
+    """Cores this process may run on, capped at a one-GPU machine's share (16)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(wl, gpu_iters, iters, side=None):
+    """The oracle's BiCGStab (complex128 CSR, SciPy product) timed on `iters`
+    iterations of the same system, scaled to the GPU's count: on one thread,
+    and on all host cores (the product cut into row blocks, one per thread;
+    bitwise the same iterates).  Plus the oracle's direct solves: SuperLU on
+    the 20x12x10 workload here, and the 80x48x40 sweep mesh from the CPU-side
+    process that ran beside the GPU work (`side`)."""
+    from oracle import direct, helmholtz as H, krylov
+    from oracle.parallel import RowBlockOperator
     import workloads as W
     t = time.perf_counter()
     S = H.System(wl["mesh"], wl["beta"])
-    A = S.operator(W.wavenumber(wl["freqs"][0]))
+    A = S.operator(W.wavenumber(wl["freqs"][0])).tocsr()
     f = S.load(wl["g"])
     log(f"cpu baseline: oracle assembly {time.perf_counter() - t:.1f}s")
     t = time.perf_counter()
     r = krylov.bicgstab(A, f, tol=1e-8, max_iters=iters)
+    dt1 = time.perf_counter() - t
+    per1 = dt1 / max(r.iters, 1)
+    cores = host_cores()
+    B = RowBlockOperator(A, cores)
+    t = time.perf_counter()
+    rm = krylov.bicgstab(B, f, tol=1e-8, max_iters=iters)
+    dtm = time.perf_counter() - t
+    B.close()
+    perm = dtm / max(rm.iters, 1)
+    out = {"value": perm * gpu_iters, "unit": "s", "cores": cores, "kind": "oracle",
+           "host_cpus": os.cpu_count(),
+           "sample": f"{r.iters} BiCGStab iterations of the same system timed on {cores} threads "
+                     f"({dtm:.1f} s, {perm * 1e3:.1f} ms/iteration; product in row blocks) and on 1 thread "
+                     f"({dt1:.1f} s, {per1 * 1e3:.1f} ms/iteration), scaled to the GPU's {gpu_iters} iterations",
+           "one_thread": {"value": per1 * gpu_iters, "unit": "s", "cores": 1}}
+    # direct solve of the small workload (oracle SuperLU, one thread)
+    w0 = W.workload(0)
+    S0 = H.System(w0["mesh"], w0["beta"])
+    A0 = S0.operator(W.wavenumber(w0["freqs"][0]))
+    f0 = S0.load(w0["g"])
+    t = time.perf_counter()
+    x0 = direct.SparseLU(A0).solve(f0)
+    out["direct_20x12x10_s"] = time.perf_counter() - t
+    out["direct_20x12x10_relres"] = H.relres(A0, x0, f0)
+    if side:
+        out.update({k: v for k, v in side.items() if k.startswith("direct_") or k.startswith("oracle_sweep")})
+    return out
+
+
+def cpu_side_direct(outdir):
+    """CPU-side process: the oracle's SuperLU solve (minimum-degree column
+    ordering on the symmetric pattern, one thread) of the 80x48x40 sweep
+    mesh at 250 Hz, timed."""
+    from oracle import direct, helmholtz as H
+    import workloads as W
+    wl = W.workload(2)
+    S = H.System(wl["mesh"], wl["beta"])
+    A = S.operator(W.wavenumber(250.0))
+    f = S.load(wl["g"])
+    t = time.perf_counter()
+    lu = direct.SparseLU(A, ordering="MMD_AT_PLUS_A")
+    x = lu.solve(f)
     dt = time.perf_counter() - t
-    per_iter = dt / max(r.iters, 1)
-    return {"value": per_iter * gpu_iters, "unit": "s", "cores": 1, "kind": "oracle",
-            "host_cpus": os.cpu_count(),
-            "sample": f"{r.iters} BiCGStab iterations of the same system timed ({dt:.1f} s, "
-                      f"{per_iter * 1e3:.1f} ms/iteration), scaled to the GPU's {gpu_iters} iterations"}
+    res = {"direct_80x48x40_s": dt, "direct_80x48x40_relres": H.relres(A, x, f),
+           "direct_80x48x40_ordering": "MMD_AT_PLUS_A"}
+    with open(os.path.join(outdir, "direct.json"), "w") as fh:
+        json.dump(res, fh)
+
+
+SWEEP_REF_COLS = (0, 63)
+
+
+def cpu_side_sweep_ref(outdir):
+    """CPU-side process: the oracle's TFQMR (complex128 CSR, one thread) to
+    relres 1e-12 on sweep columns 0 and 63 (20 and 300 Hz), timed; the
+    solutions are the FP64 references the sweep leg's errors are stated
+    against."""
+    from oracle import helmholtz as H, krylov
+    import workloads as W
+    wl = W.workload(2)
+    S = H.System(wl["mesh"], wl["beta"])
+    f = S.load(wl["g"])
+    res = {}
+    for j in SWEEP_REF_COLS:
+        A = S.operator(W.wavenumber(wl["freqs"][j])).tocsr()
+        t = time.perf_counter()
+        r = krylov.tfqmr(A, f, tol=1e-12, max_matvec=60000)
+        res[f"oracle_sweep_col{j}"] = {"freq_hz": float(wl["freqs"][j]), "s": time.perf_counter() - t,
+                                       "matvecs": r.matvecs, "relres": H.relres(A, r.x, f)}
+        np.save(os.path.join(outdir, f"ref{j}.npy"), r.x)
+    with open(os.path.join(outdir, "sweep_ref.json"), "w") as fh:
+        json.dump(res, fh)
+
+
+def start_cpu_side(no_cpu):
+    """Starts the CPU-side processes before this process touches the GPU
+    (they run on other host cores while the GPU legs run)."""
+    import subprocess
+    import tempfile
+    if no_cpu:
+        return None
+    outdir = tempfile.mkdtemp(prefix="hz_bench_cpu_")
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-side", kind, outdir],
+                              env=env, stdout=subprocess.DEVNULL, stderr=subprocess.PIPE)
+             for kind in ("direct", "sweep-ref")]
+    return {"dir": outdir, "procs": procs, "t0": time.perf_counter()}
+
+
+def collect_cpu_side(side, wait_s):
+    """Results of the CPU-side processes; a process still running after
+    wait_s more seconds is stopped and its result reported as missing."""
+    if side is None:
+        return {}
+    out = {}
+    deadline = time.perf_counter() + wait_s
+    for p in side["procs"]:
+        try:
+            p.wait(timeout=max(1.0, deadline - time.perf_counter()))
+        except Exception:
+            p.kill()
+            p.wait()
+    for name in ("direct.json", "sweep_ref.json"):
+        path = os.path.join(side["dir"], name)
+        if os.path.exists(path):
+            with open(path) as fh:
+                out.update(json.load(fh))
+        else:
+            out[f"missing_{name}"] = f"not finished within the bench's wait ({wait_s:.0f} s after the GPU legs)"
+    out["refs"] = {j: os.path.join(side["dir"], f"ref{j}.npy") for j in SWEEP_REF_COLS
+                   if os.path.exists(os.path.join(side["dir"], f"ref{j}.npy"))}
+    log(f"cpu side: {({k: v for k, v in out.items() if k != 'refs'})}")
+    return out
 
 
 def sweep_leg(log_fn, precisions=("fp64", "mixed"), method="tfqmr", ell=8):
@@ -106,19 +232,45 @@ def sweep_leg(log_fn, precisions=("fp64", "mixed"), method="tfqmr", ell=8):
     log_fn(f"sweep A (64 x FP64 {method}): {T_A:.2f}s, converged {a_ok}/64")
     out = {"workload": wl["name"], "method": label,
            "T_A_s": T_A, "converged_A": a_ok, "iters_A": a_iters}
+    sols = {}
     for prec in precisions:
         t = time.perf_counter()
         o = mixed_opts(opts) if prec == "mixed" else opts
-        _, infos = m.solve_sweep(freqs, F, precision=prec, **o)
+        Pb, infos = m.solve_sweep(freqs, F, precision=prec, **o)
         torch.cuda.synchronize()
         T_B = time.perf_counter() - t
+        sols[prec] = Pb
         b_ok = sum(i["status"] == 0 for i in infos)
         worst = max(i["relres_true"] for i in infos)
         log_fn(f"sweep B (batched {prec} {method}): {T_B:.2f}s, converged {b_ok}/64, worst relres {worst:.2e}")
         out[f"batched_{prec}"] = {"T_B_s": T_B, "speedup": T_A / T_B, "converged": b_ok, "worst_relres": worst,
                                   "iters": [i["iters"] for i in infos]}
+    if "fp64" in sols and "mixed" in sols:
+        # per-column relative difference of the mixed solution from the FP64
+        # batched one (both to relres 1e-8); the error of each against the
+        # oracle is added on the sampled columns once the CPU side is done
+        d = torch.linalg.norm(sols["mixed"] - sols["fp64"], dim=0) / torch.linalg.norm(sols["fp64"], dim=0)
+        out["batched_mixed"]["reldiff_vs_fp64"] = [float(v) for v in d.cpu()]
+        log_fn(f"mixed vs FP64 batched: max column relative difference {float(d.max()):.2e}")
+    out["_columns"] = {prec: {j: sols[prec][:, j].cpu().numpy() for j in SWEEP_REF_COLS} for prec in sols}
     m.close()
     return out
+
+
+def sweep_errors(sweep, side):
+    """Relative errors of the sampled batched columns against the oracle's
+    FP64 references (relres 1e-12) computed by the CPU-side process."""
+    cols = sweep.pop("_columns", {})
+    refs = (side or {}).get("refs", {})
+    for prec, byj in cols.items():
+        errs = {}
+        for j, x in byj.items():
+            if j in refs:
+                ref = np.load(refs[j])
+                errs[f"col{j}"] = float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+        if errs:
+            sweep[f"batched_{prec}"]["relerr_vs_oracle"] = errs
+            log(f"sweep {prec}: relative error vs the oracle on sampled columns {errs}")
 
 
 def schwarz_leg(log_fn, max_matvec=300):
@@ -325,8 +477,13 @@ def main():
     ap.add_argument("--sweep-method", default="tfqmr", choices=["bicgstabl", "bicgstab", "gmres", "tfqmr"],
                     help="Krylov method of both sides of the sweep comparison")
     ap.add_argument("--sweep-l", type=int, default=8, help="l of BiCGStab(l) in the sweep comparison")
-    ap.add_argument("--schwarz", action="store_true", help="also run the 24-subdomain Schwarz solve")
-    ap.add_argument("--adjoint", action="store_true", help="also run the 16-frequency adjoint gradient")
+    ap.add_argument("--schwarz", action="store_true", help="(default) run the 24-subdomain Schwarz leg")
+    ap.add_argument("--adjoint", action="store_true", help="(default) run the 16-frequency adjoint leg")
+    ap.add_argument("--no-schwarz", action="store_true", help="skip the 24-subdomain Schwarz leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the 16-frequency adjoint leg")
+    ap.add_argument("--cpu-side", nargs=2, metavar=("KIND", "DIR"), help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-wait", type=float, default=150.0,
+                    help="seconds to wait after the GPU legs for the CPU-side direct solve")
     ap.add_argument("--unstructured", action="store_true",
                     help="also run the unstructured-mesh leg (product per row numbering, solves)")
     ap.add_argument("--un-layouts", default="given:0,rcm:0,rcm:256",
@@ -338,10 +495,20 @@ def main():
                     help="skip the headline solve: run only the sweep (unless --no-sweep), Schwarz and adjoint "
                          "legs that are asked for and print them as one JSON line")
     args = ap.parse_args()
+    if args.cpu_side:
+        kind, outdir = args.cpu_side
+        (cpu_side_direct if kind == "direct" else cpu_side_sweep_ref)(outdir)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
               "of this solver is a design, not a built path", file=sys.stderr)
         sys.exit(2)
+
+    do_schwarz = not args.no_schwarz
+    do_adjoint = not args.no_adjoint
+    side = None
+    if not args.legs_only and not args.spmv_only:
+        side = start_cpu_side(args.no_cpu)
 
     import torch
     import workloads as W
@@ -358,6 +525,8 @@ def main():
             legs["schwarz"] = schwarz_leg(log)
         if args.adjoint:
             legs["adjoint"] = adjoint_leg(log)
+        if "sweep" in legs:
+            legs["sweep"].pop("_columns", None)
         if args.unstructured:
             legs["unstructured"] = _unstructured_legs(args)
         print(json.dumps(legs), flush=True)
@@ -456,16 +625,19 @@ def main():
     sweep = None
     if not args.no_sweep and not args.spmv_only:
         sweep = sweep_leg(log, method=args.sweep_method, ell=args.sweep_l)
-    if args.schwarz and not args.spmv_only:
+    if do_schwarz and not args.spmv_only:
         extra["schwarz"] = schwarz_leg(log)
-    if args.adjoint and not args.spmv_only:
+    if do_adjoint and not args.spmv_only:
         extra["adjoint"] = adjoint_leg(log)
     if args.unstructured and not args.spmv_only:
         extra["unstructured"] = _unstructured_legs(args)
 
     cpu = None
+    side_res = collect_cpu_side(side, args.cpu_wait)
+    if sweep is not None:
+        sweep_errors(sweep, side_res)
     if not args.no_cpu and not args.spmv_only:
-        cpu = cpu_baseline(wl, infos[-1]["iters"], args.cpu_iters)
+        cpu = cpu_baseline(wl, infos[-1]["iters"], args.cpu_iters, side_res)
         log(f"cpu baseline: {cpu}")
 
     out = {

@@ -276,3 +276,27 @@ def test_tfqmr_converges_to_direct_solution():
     res = krylov.tfqmr(A, f, tol=1e-8, max_matvec=20000)
     assert res.status == 0 and res.relres <= 1e-8
     assert np.linalg.norm(res.x - x) <= 1e-6 * np.linalg.norm(x)
+
+
+def test_row_block_operator_is_bitwise_the_csr_product():
+    """The threaded product used to time the oracle on all host cores gives
+    the same bits as A @ x, so the timed solver takes the same iterates."""
+    import workloads as W
+    from oracle import helmholtz as H, krylov
+    from oracle.parallel import RowBlockOperator
+    wl = W.workload(0)
+    S = H.System(wl["mesh"], wl["beta"])
+    A = S.operator(W.wavenumber(100.0)).tocsr()
+    f = S.load(wl["g"])
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+    for t in (1, 3, 8):
+        B = RowBlockOperator(A, t)
+        assert np.array_equal(B @ x, A @ x)
+        assert np.array_equal(B.diagonal(), A.diagonal())
+        B.close()
+    B = RowBlockOperator(A, 4)
+    r1 = krylov.bicgstab(A, f, tol=1e-8)
+    r2 = krylov.bicgstab(B, f, tol=1e-8)
+    B.close()
+    assert r1.iters == r2.iters and np.array_equal(r1.x, r2.x)
