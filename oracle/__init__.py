@@ -18,7 +18,11 @@ Modules
 fem        Q1 trilinear hexahedra: element and boundary-face matrices,
            assembly of K, M, per-wall boundary mass, patch mass (COO->CSR).
 helmholtz  the operator A(k) = K - k^2 M + i k^2 M_eta + i k B_beta,
-           the patch load, a matrix-free element-by-element apply.
+           the patch load (Neumann datum, or a Dirichlet condition on the
+           source faces by symmetric elimination), the Galerkin
+           least-squares mass coefficient, a matrix-free element-by-element
+           apply.
+parallel   a row-block threaded CSR product (timing on all host cores).
 direct     banded LU with partial pivoting (own code) and a SuperLU wrapper.
 krylov     right-Jacobi restarted GMRES(m) (MGS + complex Givens) and BiCGStab.
 adjoint    receiver energy J and its adjoint gradient.

@@ -11,11 +11,31 @@ with ``k = w / c``.  The readings taken where the paper is silent:
   absorbs.  This gives the boundary term ``+ i k sum_w beta_w B0_w``.
 * An optional per-element loss factor ``eta_e`` turns the element's ``k^2``
   into ``k^2 (1 - i eta_e)``, i.e. the term ``+ i k^2 sum_e eta_e M_e``.
-* The sun-roof forcing is a Neumann datum ``g`` on the roof patch (the paper's
-  Dirichlet spectrum data is not available), nodal-interpolated, so the load
-  is ``f = Mpatch g``.
+* The sun-roof forcing is a Neumann datum ``g`` on the roof patch,
+  nodal-interpolated, so the load is ``f = Mpatch g`` (the default).
+* Or, as the paper states it, a Dirichlet condition on the opening
+  (``dirichlet=True``): the pressure is prescribed, ``p = g``, at every node
+  of the source faces (set D; the paper's spectrum values are not available,
+  synthetic nodal values stand in).  The condition is imposed by symmetric
+  elimination: with F the other nodes, ``A_FF p_F = -A_FD g_D``, written as
+  one system of the full size whose D rows and columns are those of the
+  identity, ``A' p = f'`` with ``f'_F = -A_FD g_D`` and ``f'_D = g_D``
+  (A' stays complex symmetric).
+* The paper discretises with stabilised finite elements without giving the
+  scheme.  ``gls=True`` takes the Galerkin least-squares method of Harari
+  and Hughes for the Helmholtz operator (Comput. Methods Appl. Mech. Engrg.
+  98, 1992): it adds ``tau (L w, L p)`` element by element with
+  ``L = -lap - k^2``.  The Laplacian of a trilinear (or linear) shape
+  function vanishes inside an element, so the added term is
+  ``tau k^4 M``: the mass coefficient ``k^2`` becomes ``k^2 (1 - tau k^2)``.
+  Their ``tau`` for linear elements makes the 1-D discrete dispersion
+  relation exact: ``tau k^2 = 1 - 6 (1 - cos kh) / ((kh)^2 (2 + cos kh))``;
+  ``h`` is taken as the mean element edge length of the mesh (one value for
+  the mesh, exact for the uniform boxes here).  The absorption term keeps
+  ``k^2``.
 
-So ``A(k) = K - k^2 M + i k^2 M_eta + i k B_beta`` (complex symmetric) and
+So ``A(k) = K - m(k) M + i k^2 M_eta + i k B_beta`` with ``m(k) = k^2``
+(Galerkin) or ``k^2 (1 - tau k^2)`` (GLS), complex symmetric, and
 ``A(k) p = f``.
 """
 from __future__ import annotations
@@ -26,14 +46,53 @@ import scipy.sparse as sp
 from . import fem
 
 
-class System:
-    """Assembled real parts of one mesh plus the complex parameters."""
+def gls_tau_k2(kh):
+    """Harari-Hughes GLS parameter ``tau k^2`` of linear elements of size h
+    at wavenumber k (``1 - 6 (1 - cos kh) / ((kh)^2 (2 + cos kh))``; its
+    small-kh limit is ``-(kh)^2 / 12``)."""
+    t = float(kh)
+    if t == 0.0:
+        return 0.0
+    return 1.0 - 6.0 * (1.0 - np.cos(t)) / (t * t * (2.0 + np.cos(t)))
 
-    def __init__(self, mesh, beta, eta=None):
+
+def mean_edge_length(mesh):
+    """Mean length of the element edges (hexahedra: the 12 pairs of tensor
+    corners differing in one index; tetrahedra: the 6 vertex pairs)."""
+    el = fem.elements(mesh)
+    xyz = mesh["xyz"]
+    if el.shape[1] == 8:
+        pairs = [(a, a | b) for b in (1, 2, 4) for a in range(8) if not a & b]
+    else:
+        pairs = [(a, b) for a in range(4) for b in range(a + 1, 4)]
+    lens = [np.linalg.norm(xyz[el[:, a]] - xyz[el[:, b]], axis=1) for a, b in pairs]
+    return float(np.mean(np.stack(lens)))
+
+
+def dirichlet_nodes(mesh):
+    """Sorted ids of the nodes of the source faces (the Dirichlet set D)."""
+    return np.unique(mesh["bface"][mesh["bface_src"] == 1].ravel()).astype(np.int64)
+
+
+class System:
+    """Assembled real parts of one mesh plus the complex parameters.
+    ``dirichlet``: prescribe p on the source faces' nodes instead of a
+    Neumann datum; ``gls``: Galerkin least-squares mass coefficient."""
+
+    def __init__(self, mesh, beta, eta=None, dirichlet=False, gls=False):
         self.mesh = mesh
         self.asm = fem.assemble(mesh, with_element_mass=eta is not None)
         self.n = mesh["xyz"].shape[0]
+        self.dirichlet = bool(dirichlet)
+        self.D = dirichlet_nodes(mesh) if self.dirichlet else np.zeros(0, dtype=np.int64)
+        self.gls_h = mean_edge_length(mesh) if gls else 0.0
         self.set_params(beta, eta)
+
+    def mass_coefficient(self, k):
+        """m(k): k^2, or k^2 (1 - tau k^2) with the GLS tau."""
+        if self.gls_h == 0.0:
+            return k * k
+        return k * k * (1.0 - gls_tau_k2(k * self.gls_h))
 
     def set_params(self, beta, eta=None):
         self.beta = np.asarray(beta, dtype=np.complex128).copy()
@@ -46,19 +105,37 @@ class System:
         else:
             self.Meta = None
 
-    def operator(self, k):
-        """A(k) as a complex128 CSR matrix."""
+    def operator(self, k, eliminate=True):
+        """A(k) as a complex128 CSR matrix; with a Dirichlet set (and
+        eliminate) the rows and columns of D replaced by the identity's."""
         K, M = self.asm["K"], self.asm["M"]
-        A = K.astype(np.complex128) - (k * k) * M + (1j * k) * self.Bbeta
+        A = K.astype(np.complex128) - self.mass_coefficient(k) * M + (1j * k) * self.Bbeta
         if self.Meta is not None:
             A = A + (1j * k * k) * self.Meta
+        if self.dirichlet and eliminate:
+            keep = np.ones(self.n)
+            keep[self.D] = 0.0
+            Pf = sp.diags(keep)
+            A = Pf @ A @ Pf + sp.diags(1.0 - keep)
         A = sp.csr_matrix(A)
+        if self.dirichlet and eliminate:
+            A.eliminate_zeros()
         A.sort_indices()
         return A
 
-    def load(self, g):
-        """f = Mpatch g (g: nodal Neumann amplitudes on the roof patch)."""
-        return self.asm["Mpatch"] @ np.asarray(g, dtype=np.complex128)
+    def load(self, g, k=None):
+        """Neumann: f = Mpatch g (g: nodal amplitudes on the roof patch).
+        Dirichlet (needs k): f'_F = -A_FD g_D, f'_D = g_D."""
+        g = np.asarray(g, dtype=np.complex128)
+        if not self.dirichlet:
+            return self.asm["Mpatch"] @ g
+        if k is None:
+            raise ValueError("the Dirichlet load depends on the frequency: pass k")
+        gD = np.zeros(self.n, dtype=np.complex128)
+        gD[self.D] = g[self.D]
+        f = -(self.operator(k, eliminate=False) @ gD)
+        f[self.D] = g[self.D]
+        return f
 
 
 def relres(A, x, f):
