@@ -71,6 +71,8 @@ enum { HZ_FP64 = 0, HZ_MIXED = 1 };
 enum { HZ_JACOBI = 0, HZ_NONE = 1 };
 enum { HZ_ORDER_GIVEN = 0, HZ_ORDER_RCM = 1 };
 enum { HZ_HEX8 = 0, HZ_TET4 = 1 };
+enum { HZ_SRC_NEUMANN = 0, HZ_SRC_DIRICHLET = 1 };
+enum { HZ_GALERKIN = 0, HZ_GLS = 1 };
 
 /* Mesh of trilinear hexahedra (Q1) or linear tetrahedra (P1).  All arrays
  * are host arrays read during hz_assemble only.
@@ -102,10 +104,29 @@ enum { HZ_HEX8 = 0, HZ_TET4 = 1 };
  *   elem_type                HZ_HEX8 (Q1, 2x2x2 Gauss) or HZ_TET4 (P1,
  *                            closed-form integrals; paper Sec. 3.2 solves on
  *                            an unstructured mesh)
+ *   src_kind                 HZ_SRC_NEUMANN: the source faces carry a Neumann
+ *                            datum g, f = M_patch g.  HZ_SRC_DIRICHLET: the
+ *                            pressure is prescribed, p = g, on every node of
+ *                            the source faces (set D; paper Sec. 3.2 imposes
+ *                            the sun-roof spectrum as a Dirichlet
+ *                            condition), by symmetric elimination: the
+ *                            operator's D rows and columns are the
+ *                            identity's and the load is f_F = -A_FD g_D,
+ *                            f_D = g_D (hz_load then needs a frequency)
+ *   fe_scheme                HZ_GALERKIN, or HZ_GLS: Galerkin least-squares
+ *                            stabilisation (paper Sec. 3.2 uses stabilised
+ *                            finite elements without naming the scheme; GLS
+ *                            of Harari and Hughes, 1992, is taken): the
+ *                            Laplacian of a linear or trilinear shape
+ *                            function vanishes in an element, so the mass
+ *                            coefficient k^2 becomes k^2 (1 - tau k^2) with
+ *                            tau k^2 = 1 - 6 (1 - cos kh) / ((kh)^2
+ *                            (2 + cos kh)), h the mean element edge length
+ *                            of the mesh (the absorption term keeps k^2)
  *   Every device vector of the API stays in the mesh's node numbering
  *   whatever order and sigma are; the Schwarz method needs order
- *   HZ_ORDER_GIVEN and sigma 0 (its partition uses the structured ids) and
- *   hexahedra.                                                             */
+ *   HZ_ORDER_GIVEN and sigma 0 (its partition uses the structured ids),
+ *   hexahedra, a Neumann source and the Galerkin scheme.                   */
 typedef struct {
   int32_t n_nodes, n_elems, n_bfaces;
   const double* xyz;
@@ -119,6 +140,8 @@ typedef struct {
   int32_t order;
   int32_t sigma;
   int32_t elem_type;
+  int32_t src_kind;
+  int32_t fe_scheme;
 } hz_mesh;
 
 /* Solver options (host struct).
@@ -314,7 +337,11 @@ int hz_solve_sweep(hz_ctx ctx, int32_t nfreq, const double* freqs_host,
  *   p_dev, g_dev    [n_nodes] device inputs
  *   lambda_dev      [n_nodes] device output (adjoint state)
  *   dJ_dbeta        [6][2] host, accumulated (may be NULL)
- *   dJ_deta_dev     [n_elems] device FP64, accumulated (may be NULL)     */
+ *   dJ_deta_dev     [n_elems] device FP64, accumulated (may be NULL)
+ * With a Dirichlet source the parameters act on the free rows only (the
+ * lifting -A_FD g_D included): lambda is the adjoint state of the
+ * eliminated system with its D entries set to zero, and the formulas
+ * above hold with the full p (p = g on D).                              */
 int hz_solve_adjoint(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* p_dev,
                      const hz_c128* g_dev, hz_c128* lambda_dev, double* dJ_dbeta,
                      double* dJ_deta_dev, hz_solve_info* info);

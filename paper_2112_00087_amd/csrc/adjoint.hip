@@ -111,6 +111,13 @@ __global__ void k_grad_beta_fin(int nblk, const double* __restrict__ part, doubl
   }
 }
 
+// Adjoint state of a system with an eliminated Dirichlet set: the
+// parameters act on the free rows only, so lambda is zero on D.
+__global__ void k_zero_dir(int64_t n, const uint8_t* __restrict__ dir, z_t* __restrict__ lam) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n && dir[i]) lam[i] = z_t{0.0, 0.0};
+}
+
 // Receiver objective J = sum_r |p_r|^2 and its derivative g = dJ/dconj(p):
 // g_r = p_r on the (distinct) receiver nodes, 0 elsewhere (g is cleared
 // before this kernel).  One block: J in a fixed summation order.
@@ -168,6 +175,10 @@ int adjoint_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* p, const z_t* g
   if (st < 0) return st;
   k_conj<<<ceil_div(n, kBlock), kBlock, 0, ctx->stream>>>(n, lam, lam);
   HZ_HIP(hipGetLastError());
+  if (ctx->dirichlet) {
+    k_zero_dir<<<ceil_div(n, kBlock), kBlock, 0, ctx->stream>>>(n, ctx->d_dirmesh.as<uint8_t>(), lam);
+    HZ_HIP(hipGetLastError());
+  }
   const double k = ctx->k;
   if (dJ_deta) {
     if (ctx->h.npe == 4)

@@ -153,6 +153,10 @@ int host_assemble(const hz_mesh* m, const double* eta, HostAsm* out, int ntags, 
     return hz_fail(HZ_ERR_INVALID, "hz_assemble: null or empty mesh arrays");
   if (m->elem_type != HZ_HEX8 && m->elem_type != HZ_TET4)
     return hz_fail(HZ_ERR_INVALID, "hz_assemble: unknown element type %d", m->elem_type);
+  if (m->src_kind != HZ_SRC_NEUMANN && m->src_kind != HZ_SRC_DIRICHLET)
+    return hz_fail(HZ_ERR_INVALID, "hz_assemble: unknown source kind %d", m->src_kind);
+  if (m->fe_scheme != HZ_GALERKIN && m->fe_scheme != HZ_GLS)
+    return hz_fail(HZ_ERR_INVALID, "hz_assemble: unknown finite-element scheme %d", m->fe_scheme);
   a.npe = m->elem_type == HZ_TET4 ? 4 : 8;
   a.npf = m->elem_type == HZ_TET4 ? 3 : 4;
   a.n = m->n_nodes;
@@ -258,6 +262,42 @@ int host_assemble(const hz_mesh* m, const double* eta, HostAsm* out, int ntags, 
     a.pval.push_back(kv.second);
   }
   if (last >= 0) a.pptr.push_back(int32_t(a.pcol.size()));
+  // Dirichlet set: the nodes of the source faces
+  a.dir.clear();
+  if (m->src_kind == HZ_SRC_DIRICHLET) {
+    a.dir.assign(a.n, 0);
+    for (int64_t f = 0; f < a.nb; ++f)
+      if (a.bsrc[f])
+        for (int l = 0; l < a.npf; ++l) a.dir[a.bface[f * a.npf + l]] = 1;
+  }
+  // GLS element size: the mean edge length (hexahedra: the 12 pairs of
+  // tensor corners that differ in one index; tetrahedra: the 6 vertex pairs)
+  a.gls_h = 0.0;
+  if (m->fe_scheme == HZ_GLS) {
+    double sum = 0.0;
+    int64_t cnt = 0;
+    auto edge = [&](int32_t u, int32_t v) {
+      double d2 = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        const double t = a.xyz[int64_t(u) * 3 + d] - a.xyz[int64_t(v) * 3 + d];
+        d2 += t * t;
+      }
+      sum += std::sqrt(d2);
+      ++cnt;
+    };
+    for (int64_t e = 0; e < a.ne; ++e) {
+      const int32_t* v = &a.hex[e * a.npe];
+      if (a.npe == 8) {
+        for (int bit = 1; bit < 8; bit <<= 1)
+          for (int c = 0; c < 8; ++c)
+            if (!(c & bit)) edge(v[c], v[c | bit]);
+      } else {
+        for (int c = 0; c < 4; ++c)
+          for (int d = c + 1; d < 4; ++d) edge(v[c], v[d]);
+      }
+    }
+    a.gls_h = sum / double(std::max<int64_t>(cnt, 1));
+  }
   return HZ_OK;
 }
 

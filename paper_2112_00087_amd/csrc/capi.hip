@@ -180,6 +180,19 @@ int hz_load(hz_ctx ctx, const hz_c128* g_dev, hz_c128* f_dev) {
   HZ_GUARD_BEGIN
   HZ_TRY(check_ctx(ctx));
   if (!g_dev || !f_dev) return hz_fail(HZ_ERR_INVALID, "null vector");
+  if (ctx->dirichlet) {
+    // the lifting -A_FD g_D depends on the frequency
+    if (!ctx->have_freq) return hz_fail(HZ_ERR_STATE, "a Dirichlet load needs a frequency (call hz_set_frequency)");
+    int rc = 0;
+    const int64_t n = ctx->h.n, nr = ctx->sell.n_rows;
+    DevBuf* gi = ctx->buf("lift.g", sizeof(z_t) * nr, &rc);
+    if (rc) return rc;
+    DevBuf* fi = ctx->buf("lift.f", sizeof(z_t) * nr, &rc);
+    if (rc) return rc;
+    HZ_TRY(pad_in(ctx, n, nr, reinterpret_cast<const z_t*>(g_dev), nullptr, gi->as<z_t>()));
+    HZ_TRY(op_lift(ctx, gi->as<z_t>(), fi->as<z_t>()));
+    return unpad_out(ctx, n, fi->as<z_t>(), nullptr, reinterpret_cast<z_t*>(f_dev));
+  }
   return op_load(ctx, reinterpret_cast<const z_t*>(g_dev), reinterpret_cast<z_t*>(f_dev));
   HZ_GUARD_END
 }
@@ -210,7 +223,11 @@ int hz_solve(hz_ctx ctx, const hz_solve_opts* opts, const hz_c128* f_dev, hz_c12
   if (!ctx->have_freq) return hz_fail(HZ_ERR_STATE, "no frequency set (call hz_set_frequency first)");
   const z_t* f = reinterpret_cast<const z_t*>(f_dev);
   z_t* p = reinterpret_cast<z_t*>(p_dev);
-  if (opts->method == HZ_SCHWARZ) return schwarz_solve(ctx, *opts, f, p, info);
+  if (opts->method == HZ_SCHWARZ) {
+    if (ctx->dirichlet || ctx->h.gls_h > 0.0)
+      return hz_fail(HZ_ERR_INVALID, "the Schwarz method takes a Neumann source and the Galerkin scheme");
+    return schwarz_solve(ctx, *opts, f, p, info);
+  }
   return solve_single(ctx, *opts, f, p, info);
   HZ_GUARD_END
 }
@@ -223,6 +240,9 @@ int hz_solve_sweep(hz_ctx ctx, int32_t nfreq, const double* freqs_host, const hz
   if (nfreq < 1 || nfreq > 64) return hz_fail(HZ_ERR_INVALID, "nfreq %d not in 1..64", nfreq);
   if (!freqs_host || !F_dev || !P_dev) return hz_fail(HZ_ERR_INVALID, "null argument");
   if (opts->method == HZ_SCHWARZ) return hz_fail(HZ_ERR_INVALID, "the sweep runs GMRES, BiCGStab, BiCGStab(l) or TFQMR");
+  if (ctx->dirichlet) return hz_fail(HZ_ERR_INVALID, "the sweep takes a Neumann source");
+  if (ctx->h.gls_h > 0.0 && ctx->have_eta)
+    return hz_fail(HZ_ERR_INVALID, "the sweep takes the GLS scheme only without an absorption field");
   for (int j = 0; j < nfreq; ++j)
     if (!std::isfinite(freqs_host[j]) || freqs_host[j] < 0) return hz_fail(HZ_ERR_INVALID, "bad frequency");
   return sweep_solve(ctx, nfreq, freqs_host, reinterpret_cast<const z_t*>(F_dev), reinterpret_cast<z_t*>(P_dev),

@@ -46,6 +46,9 @@ struct HostAsm {
   // node -> elements adjacency (ascending element id)
   std::vector<int64_t> n2e_ptr;
   std::vector<int32_t> n2e;
+  // Dirichlet source: 1 for the nodes of the source faces (empty: Neumann)
+  std::vector<uint8_t> dir;
+  double gls_h = 0.0;                // GLS element size (0: Galerkin)
 };
 
 // Validates and assembles a mesh.  With perm non-NULL the mesh's order and
@@ -95,6 +98,10 @@ struct hz_ctx_s {
   DevBuf d_bmass;   // [nbe][6] per-wall masses (for gradients)
   // patch load CSR
   DevBuf d_prow, d_pptr, d_pcol, d_pval;
+  // Dirichlet source: per stored entry 0 keep, 1 zero, 2 one (a D row's
+  // diagonal); per internal row and per mesh node 1 for the nodes of D
+  bool dirichlet = false;
+  DevBuf d_emask, d_dirrow, d_dirmesh;
   // mesh on device (gradients)
   DevBuf d_xyz, d_hex, d_bface, d_btag;
 

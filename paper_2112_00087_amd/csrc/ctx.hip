@@ -244,6 +244,30 @@ int ctx_upload(hz_ctx ctx) {
     }
   }
   HZ_TRY(put(ctx, ctx->d_bmass, a.bmass.data(), a.bmass.size()));
+  ctx->dirichlet = false;
+  if (!a.dir.empty()) {
+    // Dirichlet source: entries of D rows become the identity's, entries in
+    // D columns of the other rows zero (symmetric elimination)
+    ctx->dirichlet = true;
+    std::vector<uint8_t> em(s.n_pad, 0), drow(nrows, 0), dmesh(a.n, 0);
+    for (int64_t i = 0; i < a.n; ++i) {
+      drow[i] = a.dir[i];
+      dmesh[ctx->perm.empty() ? i : ctx->perm[i]] = a.dir[i];
+    }
+    for (int64_t i = 0; i < a.n; ++i) {
+      const int64_t sl = i / kWave, l = i % kWave, w = (s.ptr[sl + 1] - s.ptr[sl]) / kWave;
+      for (int64_t k = 0; k < w; ++k) {
+        const int64_t p = s.ptr[sl] + k * kWave + l;
+        if (s.src[p] < 0) continue;
+        const int32_t j = s.col[p];
+        if (a.dir[i]) em[p] = j == i ? 2 : 1;
+        else if (a.dir[j]) em[p] = 1;
+      }
+    }
+    HZ_TRY(put(ctx, ctx->d_emask, em.data(), em.size()));
+    HZ_TRY(put(ctx, ctx->d_dirrow, drow.data(), drow.size()));
+    HZ_TRY(put(ctx, ctx->d_dirmesh, dmesh.data(), dmesh.size()));
+  }
   // The load and the gradient kernels work on caller-ordered vectors: their
   // node ids go up in the mesh's own numbering.
   const std::vector<int32_t>& P = ctx->perm;

@@ -12,7 +12,21 @@ struct OpParts {
   const int* bidx = nullptr;      // per stored entry: boundary slot or -1
   const z_t* Bb = nullptr;        // per boundary slot: sum_w beta_w B0_w
   const int* diag = nullptr;      // per row: stored position of the diagonal
+  const uint8_t* emask = nullptr; // Dirichlet elimination per entry (NULL: none)
+  double gls_h = 0.0;             // GLS element size (0: Galerkin mass coefficient)
 };
+
+// Mass coefficient m(k) of A = K - m(k) M + ...: k^2, or with the Galerkin
+// least-squares stabilisation of Harari and Hughes (1992) for linear
+// elements k^2 (1 - tau k^2), tau k^2 = 1 - 6 (1 - cos kh) / ((kh)^2 (2 +
+// cos kh)), the value that makes the 1-D discrete dispersion exact.
+inline double mass_coefficient(double k, double gls_h) {
+  const double k2 = k * k;
+  if (!(gls_h > 0.0) || k == 0.0) return k2;
+  const double t = k * gls_h, c = std::cos(t);
+  const double tau_k2 = 1.0 - 6.0 * (1.0 - c) / (t * t * (2.0 + c));
+  return k2 * (1.0 - tau_k2);
+}
 
 inline OpParts op_parts(hz_ctx ctx) {
   OpParts P;
@@ -22,6 +36,8 @@ inline OpParts op_parts(hz_ctx ctx) {
   P.bidx = ctx->d_bidx.as<int>();
   P.Bb = ctx->d_Bb.as<z_t>();
   P.diag = ctx->d_diag.as<int>();
+  P.emask = ctx->dirichlet ? ctx->d_emask.as<uint8_t>() : nullptr;
+  P.gls_h = ctx->h.gls_h;
   return P;
 }
 
@@ -83,6 +99,10 @@ int op_fill(hipStream_t s, int64_t n, z_t* y, z_t v);
 int op_copy(hipStream_t s, int64_t n, const z_t* x, z_t* y);
 int op_load(hz_ctx ctx, const z_t* g, z_t* f);
 int op_dotc(hz_ctx ctx, int64_t n, const z_t* a, const z_t* b, double* out_dev);
+// Dirichlet load in the internal numbering (padded vectors of nrows):
+// f_i = g_i on D rows, f_i = -sum_{j in D} A_ij g_j on the others, with the
+// entries of A before the elimination (paper Sec. 3.2 Dirichlet source).
+int op_lift(hz_ctx ctx, const z_t* g, z_t* f);
 // The same two kernels with the caller's partial-sum buffer (2 reduce_grid(n)
 // doubles) on the given stream.
 int op_dotc_into(hipStream_t stream, int64_t n, const z_t* a, const z_t* b, double* part, double* out_dev);

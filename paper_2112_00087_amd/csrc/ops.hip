@@ -3,10 +3,11 @@
 #include "ops.h"
 
 // ---------------------------------------------------------------- set_frequency
-// Value of A(k) = K - k^2 M + i k^2 M_eta + i k B_beta at stored entry p.
-__device__ __forceinline__ z_t entry_value(int64_t p, const OpParts& P, double k) {
-  double k2 = k * k;
-  z_t a = {P.K[p] - k2 * P.M[p], 0.0};
+// Value of A(k) = K - m M + i k^2 M_eta + i k B_beta at stored entry p, m the
+// mass coefficient (k^2, or the GLS one), before any Dirichlet elimination.
+__device__ __forceinline__ z_t raw_entry_value(int64_t p, const OpParts& P, double k, double m) {
+  const double k2 = k * k;
+  z_t a = {P.K[p] - m * P.M[p], 0.0};
   if (P.Meta) a.im += k2 * P.Meta[p];
   int b = P.bidx[p];
   if (b >= 0) {
@@ -16,13 +17,23 @@ __device__ __forceinline__ z_t entry_value(int64_t p, const OpParts& P, double k
   }
   return a;
 }
+// The same after the elimination of a Dirichlet set: the entries of its rows
+// and columns are those of the identity.
+__device__ __forceinline__ z_t entry_value(int64_t p, const OpParts& P, double k, double m) {
+  if (P.emask) {
+    const int e = P.emask[p];
+    if (e == 1) return z_t{0.0, 0.0};
+    if (e == 2) return z_t{1.0, 0.0};
+  }
+  return raw_entry_value(p, P, k, m);
+}
 
-__global__ void k_diag(int n, int64_t nrows, OpParts P, double k, z_t* __restrict__ d,
+__global__ void k_diag(int n, int64_t nrows, OpParts P, double k, double m, z_t* __restrict__ d,
                        z_t* __restrict__ dinv) {
   int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= nrows) return;
   if (i < n && P.diag[i] >= 0) {
-    z_t v = entry_value(P.diag[i], P, k);
+    z_t v = entry_value(P.diag[i], P, k, m);
     d[i] = v;
     dinv[i] = crecip(v);
   } else {
@@ -34,12 +45,12 @@ __global__ void k_diag(int n, int64_t nrows, OpParts P, double k, z_t* __restric
 // One pass over the stored entries: A (optionally with column j scaled by
 // dinv[j], i.e. the right-Jacobi operator A D^-1), its complex64 copy and the
 // real parts of the split form.
-__global__ void k_combine(int64_t npad, const int* __restrict__ col, OpParts P, double k,
+__global__ void k_combine(int64_t npad, const int* __restrict__ col, OpParts P, double k, double m,
                           const z_t* __restrict__ dinv, int scale, z_t* __restrict__ A,
                           c_t* __restrict__ A32, double* __restrict__ R, float* __restrict__ R32) {
   int64_t stride = int64_t(gridDim.x) * kBlock;
   for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < npad; p += stride) {
-    z_t a = entry_value(p, P, k);
+    z_t a = entry_value(p, P, k, m);
     if (scale) a = a * dinv[col[p]];
     A[p] = a;
     if (A32) A32[p] = ccast<float>(a);
@@ -72,10 +83,11 @@ __global__ void k_split_im(int64_t ni, const int* __restrict__ ipos, const z_t* 
 
 int op_form(hipStream_t s, int64_t n, int64_t nrows, int64_t npad, const int* col, const OpParts& P, double k,
             int scale, z_t* A, c_t* A32, z_t* d, z_t* dinv, double* R, float* R32) {
-  k_diag<<<ceil_div(nrows, kBlock), kBlock, 0, s>>>(int(n), nrows, P, k, d, dinv);
+  const double m = mass_coefficient(k, P.gls_h);
+  k_diag<<<ceil_div(nrows, kBlock), kBlock, 0, s>>>(int(n), nrows, P, k, m, d, dinv);
   HZ_HIP(hipGetLastError());
   int grid = int(std::min<int64_t>(ceil_div(npad, kBlock), 16384));
-  k_combine<<<grid, kBlock, 0, s>>>(npad, col, P, k, dinv, scale, A, A32, R, R32);
+  k_combine<<<grid, kBlock, 0, s>>>(npad, col, P, k, m, dinv, scale, A, A32, R, R32);
   HZ_HIP(hipGetLastError());
   return HZ_OK;
 }
@@ -210,6 +222,47 @@ int op_load(hz_ctx ctx, const z_t* g, z_t* f) {
                                                             ctx->d_pcol.as<int>(), ctx->d_pval.as<double>(), g, f);
     HZ_HIP(hipGetLastError());
   }
+  return HZ_OK;
+}
+
+// ---------------------------------------------------------------- Dirichlet load
+// One thread per internal row: f_i = g_i on the Dirichlet set, otherwise
+// -sum over the row's stored entries in Dirichlet columns of A_ij g_j (the
+// entries before the elimination); padding rows get 0.
+__global__ void k_lift(int n, int64_t nrows, const int* __restrict__ ptr, const int* __restrict__ col, OpParts P,
+                       double k, double m, const uint8_t* __restrict__ dir, const z_t* __restrict__ g,
+                       z_t* __restrict__ f) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= nrows) return;
+  if (i >= n) {
+    f[i] = z_t{0.0, 0.0};
+    return;
+  }
+  if (dir[i]) {
+    f[i] = g[i];
+    return;
+  }
+  const int sl = int(i >> 6), lane = int(i & 63);
+  const int beg = ptr[sl], w = (ptr[sl + 1] - beg) >> 6;
+  z_t acc = {0.0, 0.0};
+  for (int q = 0; q < w; ++q) {
+    const int64_t p = beg + (q << 6) + lane;
+    const int j = col[p];
+    if (!dir[j]) continue;
+    const z_t a = raw_entry_value(p, P, k, m);
+    cfma(acc, a, g[j]);
+  }
+  f[i] = z_t{-acc.re, -acc.im};
+}
+
+int op_lift(hz_ctx ctx, const z_t* g, z_t* f) {
+  const OpParts P = op_parts(ctx);
+  const int64_t nr = ctx->sell.n_rows;
+  k_lift<<<ceil_div(nr, kBlock), kBlock, 0, ctx->stream>>>(int(ctx->h.n), nr, ctx->d_sptr.as<int>(),
+                                                          ctx->d_scol.as<int>(), P, ctx->k,
+                                                          mass_coefficient(ctx->k, P.gls_h),
+                                                          ctx->d_dirrow.as<uint8_t>(), g, f);
+  HZ_HIP(hipGetLastError());
   return HZ_OK;
 }
 

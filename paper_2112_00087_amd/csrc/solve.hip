@@ -106,7 +106,7 @@ int ir_run(hz_ctx ctx, const SegHost& S, const SellOp<double>& A64, const SellOp
   ic.tol = o.inner_tol > 0 ? o.inner_tol : 1e-4;
   ic.restart = o.inner_restart > 0 ? o.inner_restart : 30;
   ic.ell = o.restart;                  // BiCGStab(l): l (validated 1..8)
-  ic.stall_halfsteps = 1024;           // complex64 TFQMR: end a stalled inner solve
+  ic.stall_halfsteps = 4096;           // complex64 TFQMR: end a stalled inner solve
   const int max_outer = 200;
   for (;;) {
     HZ_TRY(true_residual(ctx, S, A64, f, u, rb->as<z_t>(), &rr));

@@ -1312,7 +1312,7 @@ int sweep_setup(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const z_t
   for (int c = 0; c < nf; ++c) {
     double k = 2.0 * M_PI * freqs[c] / ctx->c;
     kc[2 * c] = k;
-    kc[2 * c + 1] = k * k;
+    kc[2 * c + 1] = mass_coefficient(k, ctx->h.gls_h);
   }
   HZ_HIP(hipMemcpyAsync(W->kc, kc.data(), sizeof(double) * 2 * s, hipMemcpyHostToDevice, cs));
   k_in<<<ceil_div(total, kBlock), kBlock, 0, cs>>>(W->n, W->nrows, s, nf, D.perm.as<int>(), Pio, Fin, W->X, W->Fs);
@@ -1562,7 +1562,7 @@ int run_sweep_bicgstab(hz_ctx ctx, SweepData& D, int nf, const double* freqs, co
     for (size_t j = 0; j < cols.size(); ++j) {
       double k = 2.0 * M_PI * freqs[cols[j]] / ctx->c;
       kc[2 * j] = k;
-      kc[2 * j + 1] = k * k;
+      kc[2 * j + 1] = mass_coefficient(k, ctx->h.gls_h);
     }
     HZ_HIP(hipMemcpyAsync(w.kc, kc.data(), sizeof(double) * 2 * w.s, hipMemcpyHostToDevice, q));
     HZ_HIP(hipStreamSynchronize(q));
@@ -2217,7 +2217,7 @@ int run_sweep_bicgstabl(hz_ctx ctx, SweepData& D, int nf, const double* freqs, c
     for (size_t j = 0; j < cols.size(); ++j) {
       double k = 2.0 * M_PI * freqs[cols[j]] / ctx->c;
       kc[2 * j] = k;
-      kc[2 * j + 1] = k * k;
+      kc[2 * j + 1] = mass_coefficient(k, ctx->h.gls_h);
     }
     HZ_HIP(hipMemcpyAsync(w.kc, kc.data(), sizeof(double) * 2 * w.s, hipMemcpyHostToDevice, q));
     HZ_HIP(hipStreamSynchronize(q));
@@ -2444,7 +2444,7 @@ int run_sweep_bicgstabl(hz_ctx ctx, SweepData& D, int nf, const double* freqs, c
 // solve with a refinement step.
 // Stagnation test of complex64 inner TFQMR solves: checkpoint spacing in
 // half-steps (a bound that has not halved over one spacing ends the solve).
-constexpr int kTsStagHalfSteps = 1024;
+constexpr int kTsStagHalfSteps = 4096;
 
 struct TsCol {
   z_t alpha, rho, beta, eta;
@@ -2837,7 +2837,7 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
     for (size_t j = 0; j < cols.size(); ++j) {
       double k = 2.0 * M_PI * freqs[cols[j]] / ctx->c;
       kc[2 * j] = k;
-      kc[2 * j + 1] = k * k;
+      kc[2 * j + 1] = mass_coefficient(k, ctx->h.gls_h);
     }
     HZ_HIP(hipMemcpyAsync(w.kc, kc.data(), sizeof(double) * 2 * w.s, hipMemcpyHostToDevice, q));
     HZ_HIP(hipStreamSynchronize(q));

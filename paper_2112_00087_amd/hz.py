@@ -49,7 +49,8 @@ class hz_mesh(C.Structure):
                 ("bface", C.POINTER(C.c_int32)), ("bface_tag", C.POINTER(C.c_int32)),
                 ("bface_src", C.POINTER(C.c_uint8)), ("c", C.c_double), ("rho", C.c_double),
                 ("elems", C.c_int32 * 3), ("parts", C.c_int32 * 3), ("order", C.c_int32),
-                ("sigma", C.c_int32), ("elem_type", C.c_int32)]
+                ("sigma", C.c_int32), ("elem_type", C.c_int32), ("src_kind", C.c_int32),
+                ("fe_scheme", C.c_int32)]
 
 
 class hz_solve_opts(C.Structure):
@@ -204,10 +205,13 @@ def _dev(t, dtype):
 class Helmholtz:
     """One assembled mesh on the GPU (wraps an ``hz_ctx``)."""
 
-    def __init__(self, mesh, beta, eta=None, c=340.0, rho=1.2, parts=None, order="given", sigma=0):
+    def __init__(self, mesh, beta, eta=None, c=340.0, rho=1.2, parts=None, order="given", sigma=0,
+                 dirichlet=False, gls=False):
         """``order`` "given" or "rcm" and ``sigma`` (0 or a multiple of 64)
         choose the internal row numbering; vectors stay in the mesh's node
-        order either way."""
+        order either way.  ``dirichlet``: the source faces' nodes carry a
+        prescribed pressure (load needs a frequency); ``gls``: Galerkin
+        least-squares stabilisation."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Helmholtz needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -239,6 +243,8 @@ class Helmholtz:
         m.order = ORDERS[order] if isinstance(order, str) else int(order)
         m.sigma = int(sigma)
         m.elem_type = et
+        m.src_kind = 1 if dirichlet else 0
+        m.fe_scheme = 1 if gls else 0
         self.n = m.n_nodes
         self.ne = m.n_elems
         self.device = torch.device("cuda", torch.cuda.current_device())
