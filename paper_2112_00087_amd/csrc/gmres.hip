@@ -1,14 +1,23 @@
 // Restarted GMRES(m) on the right-Jacobi operator, for every segment of a
 // segmented system (added beside the paper's Sec. 4 solvers).
 //
-// Arnoldi uses classical Gram-Schmidt with one re-orthogonalisation (CGS2):
-// each pass is a multi-dot  h = V^H w  (one read of w per chunk of 8 basis
-// vectors, FP64 accumulation) and a multi-axpy  w -= V h.  The Hessenberg
-// column, the complex Givens rotations and the least-squares solve stay on
-// the device in FP64, so a whole restart cycle is queued without a host
-// round trip; the host reads the per-segment state once per cycle.
-// With storage type float the basis and the operator are complex64 while
-// the Gram-Schmidt coefficients, H and the rotations remain FP64.
+// Arnoldi uses classical Gram-Schmidt with one re-orthogonalisation (CGS2),
+// h1 = V^H w, w1 = w - V h1, h2 = V^H w1, w2 = w1 - V h2, in three passes
+// over the basis per step instead of four:
+//   1. the product w = A v_j, and h1's partial sums from the same rows;
+//   2. w1 formed in registers from the row's basis entries, which stay in
+//      registers for h2's partial sums (no write of w1);
+//   3. w2 = w - V (h1 + h2) written as the next basis vector, with the
+//      partial sums of ||w2||^2.
+// The basis is stored unnormalised: v_i = s_i V_i with s_i = 1 / ||w2|| of
+// the step that made it (1 / beta for V_0), applied wherever V is read, so
+// no pass rescales it.  Each pass is followed by one small finalize kernel
+// (coefficients; then the Hessenberg column, the complex Givens rotations
+// and the residual estimate, in FP64 on the device), so a whole restart
+// cycle is queued without a host round trip; the host reads the
+// per-segment state once per cycle.  With storage type float the basis and
+// the operator are complex64 while the Gram-Schmidt coefficients, H and
+// the rotations remain FP64.
 #include "ops.h"
 
 namespace {
@@ -29,6 +38,7 @@ struct GmArr {         // per-segment small arrays (FP64)
   z_t* y;              // [m]
   z_t* h1;             // [m+1] first-pass coefficients
   z_t* h2;             // [m+1] second-pass coefficients
+  double* vs;          // [m+1] scale of each stored basis vector (v_i = vs_i V_i)
   int m;
 };
 
@@ -62,34 +72,217 @@ __global__ void k_beta_fin(Seg L, GmSt* st, GmArr G, const double* part) {
     S.done = (rr <= S.thr2) || S.nan;
     S.cyc = S.done;
     S.inv_next = b > 0.0 ? 1.0 / b : 0.0;
+    G.vs[int64_t(s) * (G.m + 1)] = S.inv_next;
     z_t* g = G.g + int64_t(s) * (G.m + 1);
     g[0] = z_t{b, 0.0};
     for (int i = 1; i <= G.m; ++i) g[i] = z_t{0.0, 0.0};
   }
 }
 
-// V_j *= inv_next
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_scale(Seg L, const GmSt* st, cx<T>* __restrict__ Vj) {
-  Tile t = tile_of(L);
-  const GmSt& S = st[t.seg];
-  if (S.cyc) return;
-  z_t v = zd(Vj[t.row]);
-  Vj[t.row] = ccast<T>(S.inv_next * v);
+// Partial sums of 2 (j + 1) quantities, 16 per chunk of 8 basis vectors:
+// chunk_to_lds reduces one chunk's 16 values within each wave and puts the
+// waves' sums in LDS; after all chunks, lds_to_partials (one barrier) adds
+// the waves in order and stores chunk c's partials at part + c * nblk * 16 +
+// tile * 16, the layout k_mdot_fin reads.  Fixed summation order.
+constexpr int kMaxChunks = (128 + 1 + NV - 1) / NV;
+typedef double ChunkLds[kMaxChunks][2 * NV][kBlock / kWave];
+
+// Wave sums of 16 quantities by recursive halving: at each of the first
+// four exchanges (lane distance 32, 16, 8, 4) a lane keeps half of its
+// quantities, adds its partner's copies of them and hands over the other
+// half, so 8 + 4 + 2 + 1 values cross lanes instead of 16 x 6; then lane
+// distances 2 and 1 finish the one quantity each lane holds.  Afterwards
+// lane l holds the wave sum of quantity 8 b5 + 4 b4 + 2 b3 + b2 (b = the
+// bits of l).  A fixed order: the result does not depend on timing.
+__device__ __forceinline__ double wave_sum16(const double (&q)[2 * NV], int lane, int* which) {
+  double a[8], b[4], c[2], d;
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8, h2 = lane & 4;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const double keep = h5 ? q[8 + k] : q[k], give = h5 ? q[k] : q[8 + k];
+    a[k] = keep + __shfl_xor(give, 32, kWave);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double keep = h4 ? a[4 + k] : a[k], give = h4 ? a[k] : a[4 + k];
+    b[k] = keep + __shfl_xor(give, 16, kWave);
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double keep = h3 ? b[2 + k] : b[k], give = h3 ? b[k] : b[2 + k];
+    c[k] = keep + __shfl_xor(give, 8, kWave);
+  }
+  {
+    const double keep = h2 ? c[1] : c[0], give = h2 ? c[0] : c[1];
+    d = keep + __shfl_xor(give, 4, kWave);
+  }
+  d += __shfl_xor(d, 2, kWave);
+  d += __shfl_xor(d, 1, kWave);
+  *which = 8 * h5 + 4 * h4 + 2 * h3 + h2;
+  return d;
 }
 
-// w = A V_j
+__device__ __forceinline__ void chunk_to_lds(const double (&q)[2 * NV], int c, ChunkLds& lds) {
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  int u = 0;
+  const double v = wave_sum16(q, lane, &u);
+  if ((lane & 3) == 0) lds[c][u][w] = v;
+}
+
+__device__ __forceinline__ void lds_to_partials(const ChunkLds& lds, int nchunk, double* part, int nblk, int tile) {
+  __syncthreads();
+  for (int e = threadIdx.x; e < nchunk * 2 * NV; e += kBlock) {
+    const int c = e / (2 * NV), u = e % (2 * NV);
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) t += lds[c][u][i];
+    part[(int64_t(c) * nblk + tile) * 2 * NV + u] = t;
+  }
+}
+
+// conj(a) b accumulated into q[0] (re), q[1] (im)
+__device__ __forceinline__ void dot_acc(double* q, z_t a, z_t b) {
+  q[0] = fma(a.re, b.re, fma(a.im, b.im, q[0]));
+  q[1] = fma(a.re, b.im, fma(-a.im, b.re, q[1]));
+}
+
+// Pass 1: w = A v_j = s_j (A V_j), and the partial sums of h1_i = v_i^H w
+// (i <= j) from the same rows.
 template <typename T, int F>
-__global__ void HZ_PRODUCT_BOUNDS k_arnoldi_spmv(Seg L, SellOp<T> A, const GmSt* st,
-                                                         const cx<T>* __restrict__ Vj, cx<T>* __restrict__ w) {
+__global__ void HZ_PRODUCT_BOUNDS k_gs_prod(Seg L, SellOp<T> A, const GmSt* st, GmArr G,
+                                                    const cx<T>* __restrict__ V, int64_t ld, int j,
+                                                    cx<T>* __restrict__ w, double* __restrict__ part) {
+  __shared__ ChunkLds lds;
   Tile t = tile_of(L);
   if (st[t.seg].cyc) return;
-  w[t.row] = sell_row_form<F>(A, t.row, Vj);
+  const double* vs = G.vs + int64_t(t.seg) * (G.m + 1);
+  const z_t y = vs[j] * zd(sell_row_form<F>(A, t.row, V + int64_t(j) * ld));
+  const cx<T> ys = ccast<T>(y);
+  w[t.row] = ys;
+  const z_t wv = zd(ys);
+  const int nchunk = (j + NV) / NV;
+  for (int c = 0; c < nchunk; ++c) {
+    double q[2 * NV];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int i = c * NV + u;
+      q[2 * u] = q[2 * u + 1] = 0.0;
+      if (i <= j) dot_acc(&q[2 * u], vs[i] * zd(V[int64_t(i) * ld + t.row]), wv);
+    }
+    chunk_to_lds(q, c, lds);
+  }
+  lds_to_partials(lds, nchunk, part, L.nblk, t.tile);
+}
+
+// Pass 2 with R threads per row (R = 4 or 8), for j + 1 <= R Q: a block of
+// 256 threads walks its 256-row tile 256 / R rows at a time; thread (row r,
+// part p) holds basis vectors p Qa .. p Qa + Qa - 1 (Qa = ceil((j + 1) / R))
+// of its row in registers; the R parts' sums of h1_i v_i meet by lane
+// exchanges (the same value in all R lanes), giving w1; each thread
+// accumulates its part's dots v_i^H w1 over its rows, and only then are
+// they summed over the wave's rows of that part and over the block's waves
+// in order (a fixed order), and stored in the chunk layout of k_mdot_fin.
+template <typename T, int R, int Q>
+__global__ void __launch_bounds__(kBlock) k_gs_second(Seg L, const GmSt* st, GmArr G, const cx<T>* __restrict__ V,
+                                                      int64_t ld, int j, const cx<T>* __restrict__ w,
+                                                      double* __restrict__ part) {
+  constexpr int kW = kBlock / kWave;
+  constexpr int kRowsPerWave = kWave / R;
+  __shared__ double lds[R * Q][2][kW];
+  const int tile = xcd_chunk_tile(blockIdx.x, gridDim.x);
+  const int seg = L.blk_seg[tile];
+  if (st[seg].cyc) return;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int p = lane / kRowsPerWave, rl = lane % kRowsPerWave;
+  const int n = j + 1, qa = (n + R - 1) / R, i0 = p * qa;
+  const double* vs = G.vs + int64_t(seg) * (G.m + 1);
+  const z_t* h1 = G.h1 + int64_t(seg) * (G.m + 1);
+  double d[Q][2];
+#pragma unroll
+  for (int u = 0; u < Q; ++u) d[u][0] = d[u][1] = 0.0;
+#pragma unroll(Q <= 4 ? 2 : 1)
+  for (int r0 = 0; r0 < kBlock; r0 += kW * kRowsPerWave) {
+    const int64_t row = int64_t(tile) * kBlock + r0 + wave * kRowsPerWave + rl;
+    cx<T> v[Q];
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+      const int i = i0 + u;
+      v[u] = (u < qa && i < n) ? V[int64_t(i) * ld + row] : cx<T>{T(0), T(0)};
+    }
+    z_t acc = p == 0 ? zd(w[row]) : z_t{0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+      const int i = i0 + u;
+      if (u < qa && i < n) {
+        const z_t h = vs[i] * h1[i], x = zd(v[u]);
+        acc.re -= h.re * x.re - h.im * x.im;
+        acc.im -= h.re * x.im + h.im * x.re;
+      }
+    }
+#pragma unroll
+    for (int o = kRowsPerWave; o < kWave; o <<= 1) {
+      acc.re += __shfl_xor(acc.re, o, kWave);
+      acc.im += __shfl_xor(acc.im, o, kWave);
+    }
+    const z_t w1 = zd(ccast<T>(acc));   // the storage precision's w1, as if stored
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+      const int i = i0 + u;
+      if (u < qa && i < n) dot_acc(d[u], vs[i] * zd(v[u]), w1);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < Q; ++u) {
+#pragma unroll
+    for (int o = kRowsPerWave / 2; o > 0; o >>= 1) {
+      d[u][0] += __shfl_xor(d[u][0], o, kWave);
+      d[u][1] += __shfl_xor(d[u][1], o, kWave);
+    }
+    const int i = i0 + u;
+    if (rl == 0 && u < qa && i < n) {
+      lds[i][0][wave] = d[u][0];
+      lds[i][1][wave] = d[u][1];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 2 * n; e += kBlock) {
+    const int i = e >> 1, ri = e & 1;
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < kW; ++k) t += lds[i][ri][k];
+    part[(int64_t(i / NV) * L.nblk + tile) * 2 * NV + 2 * (i % NV) + ri] = t;
+  }
+}
+
+// Pass 3: w2 = w1 - sum_i h2_i v_i with w1 = w - sum_i h1_i v_i, written in
+// place of w (the next stored basis vector); partial ||w2||^2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gs_third(Seg L, const GmSt* st, GmArr G, const cx<T>* __restrict__ V,
+                                                     int64_t ld, int j, cx<T>* __restrict__ w, double* part) {
+  SumTile t = tile_of_sums(L);
+  if (st[t.seg].cyc) return;
+  const double* vs = G.vs + int64_t(t.seg) * (G.m + 1);
+  const z_t* h1 = G.h1 + int64_t(t.seg) * (G.m + 1);
+  const z_t* h2 = G.h2 + int64_t(t.seg) * (G.m + 1);
+  z_t a1 = zd(w[t.row]), a2 = {0.0, 0.0};
+  for (int i = 0; i <= j; ++i) {
+    const z_t v = vs[i] * zd(V[int64_t(i) * ld + t.row]);
+    const z_t p = h1[i], r = h2[i];
+    a1.re -= p.re * v.re - p.im * v.im;
+    a1.im -= p.re * v.im + p.im * v.re;
+    a2.re -= r.re * v.re - r.im * v.im;
+    a2.im -= r.re * v.im + r.im * v.re;
+  }
+  const z_t w1 = zd(ccast<T>(a1));
+  const cx<T> ws = ccast<T>(w1 + a2);
+  w[t.row] = ws;
+  double q[1] = {norm2(zd(ws))};
+  store_partials<1>(q, part, t);
 }
 
 // partial h_i = V_i^H w for i in chunk blockIdx.y (i <= j)
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_mdot(Seg L, const GmSt* st, const cx<T>* __restrict__ V,
+__global__ void __launch_bounds__(kBlock) k_mdot(Seg L, const GmSt* st, GmArr G, const cx<T>* __restrict__ V,
                                                  int64_t ld, int j, const cx<T>* __restrict__ w,
                                                  double* part) {
   SumTile t = tile_of_sums(L);
@@ -101,7 +294,7 @@ __global__ void __launch_bounds__(kBlock) k_mdot(Seg L, const GmSt* st, const cx
   for (int c = 0; c < NV; ++c) {
     int i = i0 + c;
     z_t a = {0.0, 0.0};
-    if (i <= j) a = zd(V[int64_t(i) * ld + t.row]);
+    if (i <= j) a = G.vs[int64_t(t.seg) * (G.m + 1) + i] * zd(V[int64_t(i) * ld + t.row]);
     q[2 * c] = a.re * wv.re + a.im * wv.im;
     q[2 * c + 1] = a.re * wv.im - a.im * wv.re;
   }
@@ -136,9 +329,10 @@ __global__ void __launch_bounds__(kBlock) k_axpy(Seg L, const GmSt* st, GmArr G,
   SumTile t = tile_of_sums(L);
   if (st[t.seg].cyc) return;
   const z_t* h = (pass == 1 ? G.h1 : G.h2) + int64_t(t.seg) * (G.m + 1);
+  const double* vs = G.vs + int64_t(t.seg) * (G.m + 1);
   z_t acc = zd(w[t.row]);
   for (int i = 0; i <= j; ++i) {
-    z_t v = zd(V[int64_t(i) * ld + t.row]);
+    z_t v = vs[i] * zd(V[int64_t(i) * ld + t.row]);
     z_t hi = h[i];
     acc.re -= hi.re * v.re - hi.im * v.im;
     acc.im -= hi.re * v.im + hi.im * v.re;
@@ -204,6 +398,7 @@ __global__ void k_givens_fin(Seg L, GmSt* st, GmArr G, const double* part, int j
   if (bad) S.nan = 1;
   if (bad || hn == 0.0 || S.est * S.est <= S.thr2) S.cyc = 1;
   S.inv_next = hn > 0.0 ? 1.0 / hn : 0.0;
+  G.vs[int64_t(s) * (m + 1) + j + 1] = S.inv_next;
 }
 
 // y = H(0:k,0:k)^-1 g(0:k)
@@ -231,9 +426,10 @@ __global__ void __launch_bounds__(kBlock) k_update(Seg L, const GmSt* st, GmArr 
   const GmSt& S = st[t.seg];
   if (S.done || S.nan || S.k == 0) return;
   const z_t* y = G.y + int64_t(t.seg) * G.m;
+  const double* vs = G.vs + int64_t(t.seg) * (G.m + 1);
   z_t acc = zd(u[t.row]);
   for (int i = 0; i < S.k; ++i) {
-    z_t v = zd(V[int64_t(i) * ld + t.row]);
+    z_t v = vs[i] * zd(V[int64_t(i) * ld + t.row]);
     z_t yi = y[i];
     acc.re += yi.re * v.re - yi.im * v.im;
     acc.im += yi.re * v.im + yi.im * v.re;
@@ -247,6 +443,17 @@ __global__ void k_init_st(int nseg, GmSt* st, const double* fn2, double tol) {
   GmSt z = {};
   z.thr2 = tol * tol * fn2[s];
   st[s] = z;
+}
+
+// pass 1 in the operator's storage form
+template <typename T>
+int gs_pass1(hipStream_t s, const Seg& L, const SellOp<T>& A, const GmSt* st, const GmArr& G, const cx<T>* V,
+             int64_t ld, int j, cx<T>* w, double* pt, int grid) {
+  if (A.val) k_gs_prod<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, G, V, ld, j, w, pt);
+  else if (A.st) k_gs_prod<T, kFormStencil><<<grid, kBlock, 0, s>>>(L, A, st, G, V, ld, j, w, pt);
+  else k_gs_prod<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, G, V, ld, j, w, pt);
+  HZ_HIP(hipGetLastError());
+  return HZ_OK;
 }
 
 }  // namespace
@@ -269,7 +476,7 @@ int gmres_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
   const int64_t ns = S.nseg;
   DevBuf* small = ctx->buf(p + "small",
                            sizeof(z_t) * ns * ((m + 1) * m + m + (m + 1) + m + 2 * (m + 1)) +
-                               sizeof(double) * ns * m, &rc);
+                               sizeof(double) * ns * (m + (m + 1)), &rc);
   if (rc) return rc;
   DevBuf* fnb = ctx->buf(p + "fn2", sizeof(double) * S.nseg, &rc);
   if (rc) return rc;
@@ -283,6 +490,7 @@ int gmres_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
   G.h1 = zp; zp += ns * (m + 1);
   G.h2 = zp; zp += ns * (m + 1);
   G.cs = reinterpret_cast<double*>(zp);
+  G.vs = G.cs + ns * m;
   GmSt* st = stb->as<GmSt>();
   cx<T>* V = Vb->as<cx<T>>();
   double* pt = part->as<double>();
@@ -312,22 +520,24 @@ int gmres_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
     HZ_HIP(hipGetLastError());
     int mc = int(std::min<int64_t>(m, ctl.max_matvec - mv_max - 1));
     if (mc >= 1) {
-      k_scale<T><<<grid, kBlock, 0, s>>>(L, st, V);
       for (int j = 0; j < mc; ++j) {
         cx<T>* w = V + int64_t(j + 1) * ld;
         dim3 gd(grid, ceil_div(j + 1, NV));
         dim3 gf(S.nseg, j + 1);
-        if (A.val) k_arnoldi_spmv<T, kFormComplex><<<grid, kBlock, 0, s>>>(L, A, st, V + int64_t(j) * ld, w);
-        else if (A.st) k_arnoldi_spmv<T, kFormStencil><<<grid, kBlock, 0, s>>>(L, A, st, V + int64_t(j) * ld, w);
-        else k_arnoldi_spmv<T, kFormSplit><<<grid, kBlock, 0, s>>>(L, A, st, V + int64_t(j) * ld, w);
-        k_mdot<T><<<gd, kBlock, 0, s>>>(L, st, V, ld, j, w, pt);
+        HZ_TRY(gs_pass1<T>(s, L, A, st, G, V, ld, j, w, pt, grid));
         k_mdot_fin<<<gf, kFinBlock, 0, s>>>(L, st, G, pt, j, 1);
-        k_axpy<T, false><<<grid, kBlock, 0, s>>>(L, st, G, V, ld, j, 1, w, pt);
-        k_mdot<T><<<gd, kBlock, 0, s>>>(L, st, V, ld, j, w, pt);
+        if (j + 1 <= 16) k_gs_second<T, 4, 4><<<grid, kBlock, 0, s>>>(L, st, G, V, ld, j, w, pt);
+        else if (j + 1 <= 32) k_gs_second<T, 8, 4><<<grid, kBlock, 0, s>>>(L, st, G, V, ld, j, w, pt);
+        else if (j + 1 <= 56) k_gs_second<T, 8, 7><<<grid, kBlock, 0, s>>>(L, st, G, V, ld, j, w, pt);
+        else {
+          // beyond 56 basis vectors: w1 stored, then a multi-dot pass
+          k_axpy<T, false><<<grid, kBlock, 0, s>>>(L, st, G, V, ld, j, 1, w, pt);
+          k_mdot<T><<<gd, kBlock, 0, s>>>(L, st, G, V, ld, j, w, pt);
+        }
         k_mdot_fin<<<gf, kFinBlock, 0, s>>>(L, st, G, pt, j, 2);
-        k_axpy<T, true><<<grid, kBlock, 0, s>>>(L, st, G, V, ld, j, 2, w, pt);
+        if (j + 1 <= 56) k_gs_third<T><<<grid, kBlock, 0, s>>>(L, st, G, V, ld, j, w, pt);
+        else k_axpy<T, true><<<grid, kBlock, 0, s>>>(L, st, G, V, ld, j, 2, w, pt);
         k_givens_fin<<<S.nseg, kFinBlock, 0, s>>>(L, st, G, pt, j);
-        k_scale<T><<<grid, kBlock, 0, s>>>(L, st, w);
         HZ_HIP(hipGetLastError());
       }
       k_solve_fin<<<ceil_div(S.nseg, 64), 64, 0, s>>>(st, G, S.nseg);
