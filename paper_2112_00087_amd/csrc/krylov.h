@@ -133,19 +133,40 @@ __device__ __forceinline__ cx<T> sell_row_form(const SellOp<T>& A, int64_t row, 
   T ar = T(0), ai = T(0);
   // the slice's imaginary-list descriptor, loaded ahead of the real-part sweep
   const ImSlice im = A.imeta[slice];
+  const bool listed = (im.mask >> lane) & 1ull;
+  const int jl = __builtin_popcountll(im.mask & ((1ull << lane) - 1ull));
   if constexpr (F == kFormStencil) {
-    // slot k: neighbour row + soff[k]; a missing neighbour's slot is 0, its
-    // gather is clamped into the vector (any row; it is multiplied by 0)
+    // Slots 3 t, 3 t + 1, 3 t + 2 are one line of the box (offsets o - 1,
+    // o, o + 1).  The wave's 64 consecutive rows load the centre x[row + o]
+    // once; the left and right neighbours come from the adjacent lanes,
+    // and only the wave's two end lanes load their outer value (one load
+    // with two lanes active).  Terms are added in slot order, as before.
+    // Every caller runs this with all 64 lanes of the wave active.
     const T* __restrict__ v = A.st + int64_t(slice) * (kStencil * 64) + lane;
     const int64_t last = A.nrows - 1;
-#pragma unroll 9
-    for (int k = 0; k < kStencil; ++k) {
-      int64_t j = row + A.soff.o[k];
-      j = j < 0 ? 0 : (j > last ? last : j);
-      const T a = ld_stream(v + (k << 6));
-      const cx<T> xv = x[j];
-      ar = fma(a, xv.re, ar);
-      ai = fma(a, xv.im, ai);
+    auto clampi = [last](int64_t j) { return j < 0 ? int64_t(0) : (j > last ? last : j); };
+#pragma unroll 3
+    for (int t = 0; t < kStencil / 3; ++t) {
+      const int o = A.soff.o[3 * t + 1];
+      const cx<T> xc = x[clampi(row + o)];
+      cx<T> xe = {T(0), T(0)};
+      if (lane == 0 || lane == kWave - 1) xe = x[clampi(lane == 0 ? row + o - 1 : row + o + 1)];
+      cx<T> xl, xr;
+      xl.re = __shfl_up(xc.re, 1, kWave);
+      xl.im = __shfl_up(xc.im, 1, kWave);
+      xr.re = __shfl_down(xc.re, 1, kWave);
+      xr.im = __shfl_down(xc.im, 1, kWave);
+      if (lane == 0) xl = xe;
+      if (lane == kWave - 1) xr = xe;
+      const T a0 = ld_stream(v + ((3 * t) << 6));
+      const T a1 = ld_stream(v + ((3 * t + 1) << 6));
+      const T a2 = ld_stream(v + ((3 * t + 2) << 6));
+      ar = fma(a0, xl.re, ar);
+      ai = fma(a0, xl.im, ai);
+      ar = fma(a1, xc.re, ar);
+      ai = fma(a1, xc.im, ai);
+      ar = fma(a2, xr.re, ar);
+      ai = fma(a2, xr.im, ai);
     }
   } else {
     const int beg = A.ptr[slice];
@@ -157,10 +178,9 @@ __device__ __forceinline__ cx<T> sell_row_form(const SellOp<T>& A, int64_t row, 
   // then the four gathers, issue back to back (a step past the slice's
   // longest list gathers x[0] and adds nothing; a padded entry adds zero);
   // the terms are added in list order
-  if ((im.mask >> lane) & 1ull) {
-    const int j = __builtin_popcountll(im.mask & ((1ull << lane) - 1ull));
-    const T* __restrict__ pb = A.iim + im.base + j;
-    const int* __restrict__ pc = A.icol + im.base + j;
+  if (listed) {
+    const T* __restrict__ pb = A.iim + im.base + jl;
+    const int* __restrict__ pc = A.icol + im.base + jl;
     for (int k = 0; k < im.w; k += 4) {
       T b[4];
       int c[4];
