@@ -398,6 +398,21 @@ enum { HZ_SPMV_SOLVER = 0, HZ_SPMV_COMPLEX = 1, HZ_SPMV_SPLIT = 2, HZ_SPMV_STENC
  * stream. */
 int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, int32_t format, double* avg_ms);
 
+/* Measurement of the frequency sweep's multi-vector product (the sparse
+ * product dominates, paper Sec. 4; the sweep is an addition to the paper's
+ * method).  For nfreq (1..64) frequencies freqs_host (Hz), with s = nfreq
+ * rounded up to a power of two, runs the product Y = A(k_c) X on every
+ * column c of an internal [n][s] block in the variant the sweep's
+ * autotuner picks (tuning first if needed), `reps` times (1..100000)
+ * between two HIP events on the context's stream, and returns the average
+ * duration of one product (ms).  bytes (may be NULL) receives its
+ * algorithmic bytes with CSR storage (FP64: 20 nnz + 4 (n + 1) + 32 n s;
+ * HZ_MIXED complex64: 12 nnz + 4 (n + 1) + 16 n s); variant (may be NULL)
+ * the tuned variant's code.  Leaves the current frequency unset, like
+ * hz_solve_sweep.  Synchronises. */
+int hz_time_spmm(hz_ctx ctx, int32_t nfreq, const double* freqs_host, int32_t precision, int32_t reps,
+                 double* avg_ms, int64_t* bytes, int32_t* variant);
+
 /* Algorithmic bytes of one product of the given precision and form: every
  * stored value, index and row pointer read once, x read once and y written
  * once (n = n_nodes, nnz = CSR nonzeros, r = 8 for FP64 or 4 for FP32):

@@ -16,6 +16,8 @@ int sweep_solve(hz_ctx ctx, int nfreq, const double* freqs, const z_t* F, z_t* P
 int adjoint_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* p, const z_t* g, z_t* lam, double* dJ_dbeta,
                   double* dJ_deta, hz_solve_info* info);
 int receiver_objective(hz_ctx ctx, int nrec, const int* rec_host, const z_t* p, double* J_host, z_t* g);
+int sweep_time_spmm(hz_ctx ctx, int nfreq, const double* freqs, int precision, int reps, double* avg_ms,
+                    int32_t* variant);
 
 #define HZ_GUARD_BEGIN try {
 #define HZ_GUARD_END                                                          \
@@ -333,6 +335,28 @@ int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, int32_t format, do
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *avg_ms = double(ms) / reps;
+  return HZ_OK;
+  HZ_GUARD_END
+}
+
+int hz_time_spmm(hz_ctx ctx, int32_t nfreq, const double* freqs_host, int32_t precision, int32_t reps,
+                 double* avg_ms, int64_t* bytes, int32_t* variant) {
+  HZ_GUARD_BEGIN
+  HZ_TRY(check_ctx(ctx));
+  if (!avg_ms || !freqs_host || nfreq < 1 || nfreq > 64 || reps < 1 || reps > 100000)
+    return hz_fail(HZ_ERR_INVALID, "bad arguments");
+  if (precision != HZ_FP64 && precision != HZ_MIXED) return hz_fail(HZ_ERR_INVALID, "bad precision");
+  if (ctx->dirichlet) return hz_fail(HZ_ERR_INVALID, "the sweep takes a Neumann source");
+  for (int j = 0; j < nfreq; ++j)
+    if (!std::isfinite(freqs_host[j]) || freqs_host[j] < 0) return hz_fail(HZ_ERR_INVALID, "bad frequency");
+  ctx->have_freq = false;   // as after a sweep
+  HZ_TRY(sweep_time_spmm(ctx, nfreq, freqs_host, precision, reps, avg_ms, variant));
+  if (bytes) {
+    int s = 1;
+    while (s < nfreq) s <<= 1;
+    const int64_t n = ctx->h.n, nnz = int64_t(ctx->h.col.size());
+    *bytes = precision == HZ_MIXED ? 12 * nnz + 4 * (n + 1) + 16 * n * s : 20 * nnz + 4 * (n + 1) + 32 * n * s;
+  }
   return HZ_OK;
   HZ_GUARD_END
 }

@@ -112,6 +112,8 @@ def lib():
                                        P(hz_solve_info)]),
         "hz_time_spmv": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_int32, P(C.c_double)]),
         "hz_spmv_bytes": (C.c_int, [VP, C.c_int32, C.c_int32, P(C.c_int64)]),
+        "hz_time_spmm": (C.c_int, [VP, C.c_int32, P(C.c_double), C.c_int32, C.c_int32, P(C.c_double),
+                                   P(C.c_int64), P(C.c_int32)]),
         "hz_dd_alpha": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int32, P(hz_c128)]),
         "hz_receiver_energy": (C.c_int, [VP, C.c_int32, P(C.c_int32), VP, P(C.c_double), VP]),
         "hz_node_order": (C.c_int, [P(hz_mesh), P(C.c_int32)]),
@@ -296,6 +298,15 @@ class Helmholtz:
         check(lib().hz_time_spmv(self.ctx, int(reps), PRECISIONS[precision], SPMV_FORMS[form], C.byref(ms)),
               False)
         return ms.value
+
+    def time_spmm(self, freqs, reps=50, precision="fp64"):
+        """(average ms, algorithmic bytes, variant code) of the sweep's
+        multi-vector product for these frequencies (hz_time_spmm)."""
+        f = np.ascontiguousarray(freqs, dtype=np.float64)
+        ms, b, v = C.c_double(), C.c_int64(), C.c_int32()
+        check(lib().hz_time_spmm(self.ctx, f.size, _np_ptr(f, C.c_double), PRECISIONS[precision], int(reps),
+                                 C.byref(ms), C.byref(b), C.byref(v)), False)
+        return ms.value, b.value, v.value
 
     def spmv_bytes(self, precision="fp64", form="solver"):
         """Algorithmic bytes of one sparse product of the given form."""

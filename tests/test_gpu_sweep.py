@@ -48,6 +48,18 @@ def test_sweep_staged_product(P, nfreq, precision, method, monkeypatch):
     _sweep_parity(P, nfreq, precision, method)
 
 
+# variant codes: one lane per column, 256 threads, XCD-contiguous rows; two
+# columns per lane, 128 threads, rows in dispatch order
+@pytest.mark.parametrize("code", ["11256", "2128"])
+@pytest.mark.parametrize("nfreq,precision,method", [(64, "fp64", "tfqmr"), (33, "mixed", "bicgstabl"),
+                                                    (16, "fp64", "gmres")])
+def test_sweep_forced_product_variant(P, code, nfreq, precision, method, monkeypatch):
+    """The same parity with one gathering product variant forced
+    (HZ_SPMM_VARIANT) instead of the autotuner's pick."""
+    monkeypatch.setenv("HZ_SPMM_VARIANT", code)
+    _sweep_parity(P, nfreq, precision, method)
+
+
 def _sweep_parity(P, nfreq, precision, method):
     say("sweep parity", nfreq, precision, method)
     wl = W.workload(2, elems=(20, 12, 10))
