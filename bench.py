@@ -273,6 +273,25 @@ def sweep_errors(sweep, side):
             log(f"sweep {prec}: relative error vs the oracle on sampled columns {errs}")
 
 
+def spmm_leg(log_fn, reps=50):
+    """The sweep's multi-vector product at workload 2 (80x48x40, 64
+    columns), FP64 and complex64, timed with HIP events on the context's
+    stream (hz_time_spmm), against the CSR algorithmic bytes."""
+    import workloads as W
+    from paper_2112_00087_amd import Helmholtz
+    wl = W.workload(2)
+    m = Helmholtz(wl["mesh"], wl["beta"])
+    out = {"workload": wl["name"], "columns": int(wl["freqs"].size)}
+    for prec in ("fp64", "mixed"):
+        ms, b, v = m.time_spmm(wl["freqs"], reps, prec)
+        gbs = b / (ms * 1e-3) / 1e9
+        out[prec] = {"us": ms * 1e3, "bytes": b, "GBs": gbs, "frac": gbs / HBM_PEAK_GBS, "variant": v}
+        log_fn(f"multi-vector product {prec}: {ms * 1e3:.1f} us, {b / 1e6:.1f} MB, {gbs:.0f} GB/s "
+               f"({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak), variant {v}")
+    m.close()
+    return out
+
+
 def schwarz_leg(log_fn, max_matvec=300):
     """Workload 3: 24 subdomains on one GPU, interface GMRES(300) in complex128
     with batched local solves (FP64, and complex64 with FP64 refinement), next
@@ -484,6 +503,10 @@ def main():
     ap.add_argument("--cpu-side", nargs=2, metavar=("KIND", "DIR"), help=argparse.SUPPRESS)
     ap.add_argument("--cpu-wait", type=float, default=150.0,
                     help="seconds to wait after the GPU legs for the CPU-side direct solve")
+    ap.add_argument("--extras", default="",
+                    help="comma list of the extra solves to run (default: all), e.g. gmres50,tfqmr")
+    ap.add_argument("--spmm-only", action="store_true",
+                    help="only time the sweep's multi-vector product (hardware-counter runs)")
     ap.add_argument("--unstructured", action="store_true",
                     help="also run the unstructured-mesh leg (product per row numbering, solves)")
     ap.add_argument("--un-layouts", default="given:0,rcm:0,rcm:256",
@@ -515,6 +538,11 @@ def main():
     from paper_2112_00087_amd import Helmholtz
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.spmm_only:
+        if args.calib_copy:
+            _calib_copy()
+        print(json.dumps(spmm_leg(log, reps=args.spmv_reps)), flush=True)
+        return
     if args.legs_only:
         if args.calib_copy:
             _calib_copy()
@@ -548,8 +576,9 @@ def main():
     if args.calib_copy:
         _calib_copy()
     if args.spmv_only:
-        model.set_frequency(freq)
         args.steps = 0
+    # the product timings below need an operator even when no solve is timed
+    model.set_frequency(freq)
     for _ in range(args.warmup if not args.spmv_only else 0):
         _, info = step()
         log(f"warmup: {info}")
@@ -603,6 +632,7 @@ def main():
         ms32 = model.time_spmv(args.spmv_reps, "mixed", form)
         b32 = model.spmv_bytes("mixed", form)
         extra["spmv_fp32_GBs"] = b32 / (ms32 * 1e-3) / 1e9
+        wanted = set(x for x in args.extras.split(",") if x)
         for label, o in (("gmres50", dict(method="gmres", restart=50)),
                          ("bicgstabl2", dict(method="bicgstabl", restart=2)),
                          ("bicgstabl4", dict(method="bicgstabl", restart=4)),
@@ -612,6 +642,8 @@ def main():
                          ("bicgstabl4_mixed", dict(method="bicgstabl", restart=4, precision="mixed", inner_tol=1e-2)),
                          ("bicgstab_mixed", dict(method="bicgstab", precision="mixed")),
                          ("gmres50_mixed", dict(method="gmres", restart=50, precision="mixed"))):
+            if wanted and label not in wanted:
+                continue
             model.set_frequency(freq)
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -620,11 +652,23 @@ def main():
             extra[label] = {"s": time.perf_counter() - t, "status": inf["status"], "iters": inf["iters"],
                             "matvecs": inf["matvecs"], "inner_matvecs": inf["inner_matvecs"],
                             "relres_true": inf["relres_true"]}
+            if label.startswith("gmres") and "mixed" not in label and inf["iters"] > 0:
+                # bytes of an Arnoldi step in the three-pass CGS2 form: the
+                # product, then j + (j + 3) + (j + 3) complex128 vector passes
+                # (dots against v_0..v_{j-1}; update + second dots with w read
+                # and written; update into v_{j+1}), j averaged over the cycle
+                m = o["restart"]
+                per_step = byts + (3 * (m - 1) / 2 + 6) * 16 * n
+                us = extra[label]["s"] / inf["iters"] * 1e6
+                extra[label].update(us_per_step=us, cgs2_bytes_per_step=per_step,
+                                    cgs2_GBs=per_step / (us * 1e-6) / 1e9,
+                                    cgs2_frac=per_step / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
             log(f"{label}: {extra[label]}")
 
     sweep = None
     if not args.no_sweep and not args.spmv_only:
         sweep = sweep_leg(log, method=args.sweep_method, ell=args.sweep_l)
+        sweep["product"] = spmm_leg(log)
     if do_schwarz and not args.spmv_only:
         extra["schwarz"] = schwarz_leg(log)
     if do_adjoint and not args.spmv_only:
