@@ -406,12 +406,35 @@ int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, int32_t format, do
  * autotuner picks (tuning first if needed), `reps` times (1..100000)
  * between two HIP events on the context's stream, and returns the average
  * duration of one product (ms).  bytes (may be NULL) receives its
- * algorithmic bytes with CSR storage (FP64: 20 nnz + 4 (n + 1) + 32 n s;
- * HZ_MIXED complex64: 12 nnz + 4 (n + 1) + 16 n s); variant (may be NULL)
- * the tuned variant's code.  Leaves the current frequency unset, like
- * hz_solve_sweep.  Synchronises. */
+ * algorithmic bytes in the picked variant's storage, with w = 8 (HZ_FP64)
+ * or 4 (HZ_MIXED, complex64) bytes per real value: values 2 w nnz (3 w nnz
+ * with an absorption field), column indices and row pointers 4 nnz +
+ * 4 (n + 1) for the row-wise variants (none for the stencil form of a box
+ * in its own numbering), boundary lists 4 (n + 1) + (4 + 2 w) nb for nb
+ * boundary entries, and 4 w n s for one read of X and one write of Y.
+ * variant (may be NULL) receives the tuned variant's code.  Leaves the
+ * current frequency unset, like hz_solve_sweep.  Synchronises. */
 int hz_time_spmm(hz_ctx ctx, int32_t nfreq, const double* freqs_host, int32_t precision, int32_t reps,
                  double* avg_ms, int64_t* bytes, int32_t* variant);
+
+/* One multi-vector product of the frequency sweep (the sparse product of
+ * paper Sec. 4 applied to nfreq right-hand sides; an addition to the
+ * paper's method, like the sweep itself): for nfreq (1..64) frequencies
+ * freqs_host (Hz), y_dev[i * nfreq + c] = (A(k_c) x)[i] for every node i
+ * and column c, where x is column c of x_dev ([n_nodes][nfreq] row-major
+ * complex128, caller-owned device memory; y_dev the same shape, not
+ * overlapping x_dev) and A(k) the unpreconditioned operator K - k^2 M +
+ * i k B (+ i k^2 M_eta) of the current parameters.  precision HZ_FP64 runs
+ * the sweep's complex128 product; HZ_MIXED rounds x and the operator to
+ * complex64 and runs the mixed sweep's inner product (stiffness in
+ * difference form), returning its result widened to complex128.  The
+ * variant is the one the sweep's autotuner picks for this width (the
+ * environment variable HZ_SPMM_VARIANT forces one); variant (may be NULL)
+ * receives its code.  Leaves the current frequency unset.  Synchronises.
+ * Errors: HZ_ERR_INVALID (null pointer, nfreq out of range, bad frequency
+ * or precision, a Dirichlet source), HZ_ERR_OOM, HZ_ERR_HIP. */
+int hz_apply_sweep(hz_ctx ctx, int32_t nfreq, const double* freqs_host, int32_t precision,
+                   const hz_c128* x_dev, hz_c128* y_dev, int32_t* variant);
 
 /* Algorithmic bytes of one product of the given precision and form: every
  * stored value, index and row pointer read once, x read once and y written

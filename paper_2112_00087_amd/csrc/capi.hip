@@ -17,7 +17,9 @@ int adjoint_solve(hz_ctx ctx, const hz_solve_opts& o, const z_t* p, const z_t* g
                   double* dJ_deta, hz_solve_info* info);
 int receiver_objective(hz_ctx ctx, int nrec, const int* rec_host, const z_t* p, double* J_host, z_t* g);
 int sweep_time_spmm(hz_ctx ctx, int nfreq, const double* freqs, int precision, int reps, double* avg_ms,
-                    int32_t* variant);
+                    int32_t* variant, int64_t* bytes);
+int sweep_apply(hz_ctx ctx, int nfreq, const double* freqs, int precision, const z_t* X, z_t* Y,
+                int32_t* variant);
 
 #define HZ_GUARD_BEGIN try {
 #define HZ_GUARD_END                                                          \
@@ -350,14 +352,23 @@ int hz_time_spmm(hz_ctx ctx, int32_t nfreq, const double* freqs_host, int32_t pr
   for (int j = 0; j < nfreq; ++j)
     if (!std::isfinite(freqs_host[j]) || freqs_host[j] < 0) return hz_fail(HZ_ERR_INVALID, "bad frequency");
   ctx->have_freq = false;   // as after a sweep
-  HZ_TRY(sweep_time_spmm(ctx, nfreq, freqs_host, precision, reps, avg_ms, variant));
-  if (bytes) {
-    int s = 1;
-    while (s < nfreq) s <<= 1;
-    const int64_t n = ctx->h.n, nnz = int64_t(ctx->h.col.size());
-    *bytes = precision == HZ_MIXED ? 12 * nnz + 4 * (n + 1) + 16 * n * s : 20 * nnz + 4 * (n + 1) + 32 * n * s;
-  }
+  HZ_TRY(sweep_time_spmm(ctx, nfreq, freqs_host, precision, reps, avg_ms, variant, bytes));
   return HZ_OK;
+  HZ_GUARD_END
+}
+
+int hz_apply_sweep(hz_ctx ctx, int32_t nfreq, const double* freqs_host, int32_t precision, const hz_c128* x_dev,
+                   hz_c128* y_dev, int32_t* variant) {
+  HZ_GUARD_BEGIN
+  HZ_TRY(check_ctx(ctx));
+  if (!freqs_host || !x_dev || !y_dev || nfreq < 1 || nfreq > 64) return hz_fail(HZ_ERR_INVALID, "bad arguments");
+  if (precision != HZ_FP64 && precision != HZ_MIXED) return hz_fail(HZ_ERR_INVALID, "bad precision");
+  if (ctx->dirichlet) return hz_fail(HZ_ERR_INVALID, "the sweep takes a Neumann source");
+  for (int j = 0; j < nfreq; ++j)
+    if (!std::isfinite(freqs_host[j]) || freqs_host[j] < 0) return hz_fail(HZ_ERR_INVALID, "bad frequency");
+  ctx->have_freq = false;   // as after a sweep
+  return sweep_apply(ctx, nfreq, freqs_host, precision, reinterpret_cast<const z_t*>(x_dev),
+                     reinterpret_cast<z_t*>(y_dev), variant);
   HZ_GUARD_END
 }
 

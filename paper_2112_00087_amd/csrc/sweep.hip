@@ -48,6 +48,17 @@ struct RowOp {
   const int16_t* lidx = nullptr;   // per entry: position of its column in the block's halo
   const int16_t* blidx = nullptr;  // per boundary entry: the same
   int hblocks = 0, hmax = 0;
+  // stencil form (a box in its own numbering, rows x fastest): per row and
+  // slot t, KM[27 row + t] = (K, M) of the entry coupling the row with its
+  // neighbour (dx, dy, dz), t = 9 (dz + 1) + 3 (dy + 1) + dx + 1, and
+  // SE[27 row + t] its M_eta; zero slots for missing neighbours
+  const cx<R>* KM = nullptr;
+  const R* SE = nullptr;
+  // boundary terms in slot form: BSI[row] indexes BSV[27 * BSI[row] + t]
+  // (sum_w beta_w B0_w of slot t) for the rows on absorbing walls, -1 else
+  const int* BSI = nullptr;
+  const cx<R>* BSV = nullptr;
+  int bx = 0, by = 0, bz = 0;      // box nodes per direction (0: no stencil form)
 };
 
 struct SwCol {
@@ -249,6 +260,180 @@ __global__ void __launch_bounds__(kHaloRows) k_spmm_lds(int64_t nrows, int s, Ro
     }
     __syncthreads();
   }
+}
+
+// ---------------------------------------------------------------- stencil-form product
+// On a box in its own numbering (row = x + bx (y + by z)) the 64-column
+// product runs in the stencil form, one wave per (x, y) line with one column
+// per lane.  The wave marches along z: at plane p it holds the 9 in-plane
+// neighbours of its line (each a contiguous 1 KiB node row of the 64
+// columns) and adds them, with the matrix pairs of the three rows they couple
+// with, to the partial sums of its rows in planes p + 1, p and p - 1, kept in
+// registers; the row in plane p - 1 is then complete and is written.  The 27
+// matrix pairs a plane step needs (9 of each row, stored row by row) come in
+// with one vector load, lane t holding pair t, and reach every lane by
+// readlane; the next plane's neighbours and pairs are loaded while the
+// current plane is computed.  Each (K, M) pair and each input row thus
+// crosses L2 about once per tile of lines sharing it, and the input is read
+// 9 times per row from L1 (27 times in the row-wise product).  Boundary
+// terms are stored in the same slot form for the rows that have them.
+// Blocks are patches of PW x PH lines (whose waves share neighbours in L1),
+// mapped to XCD-contiguous ranges.
+struct ZlGeom {
+  int npx = 0, npy = 0;    // patches along x and y
+  int zc = 0, nzc = 0;     // planes per wave, z chunks
+};
+
+__device__ __forceinline__ double lane_bcast(double v, int t) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(b), t));
+  const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(b >> 32), t));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+__device__ __forceinline__ float lane_bcast(float v, int t) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), t));
+}
+
+// Everything one plane step reads: the plane's 9 neighbours (this lane's
+// column), pair / loss / boundary value of slot t = lane (lanes 0..26), and
+// for the difference form the next row's own value.
+template <typename T>
+struct ZlStep {
+  cx<T> zv[9];
+  cx<T> km, bv, zn;
+  T ev;
+};
+
+template <typename T, int PW, int PH, bool ETA>
+__global__ void __launch_bounds__(PW * PH * kWave)
+    k_spmm_zl(int bx, int by, int bz, ZlGeom g, const cx<T>* __restrict__ KM, const T* __restrict__ SE,
+              const int* __restrict__ BSI, const cx<T>* __restrict__ BSV, const double* __restrict__ kc,
+              const cx<T>* __restrict__ Z, cx<T>* __restrict__ Y) {
+  constexpr int S = kWave;        // columns
+  constexpr bool DIFF = kDiffK<T>;
+  // block -> patch (XCD-contiguous), wave -> line of the patch
+  int L = xcd_tile(blockIdx.x, gridDim.x);
+  const int px = L % g.npx;
+  L /= g.npx;
+  const int py = L % g.npy;
+  const int izc = L / g.npy;
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
+  const int x = px * PW + w % PW, y = py * PH + w / PW;
+  if (x >= bx || y >= by) return;   // whole wave: this kernel has no barrier
+  const int z0 = izc * g.zc, z1 = min(z0 + g.zc, bz);
+  const int c = int(threadIdx.x) % kWave;
+  const int64_t plane = int64_t(bx) * by;
+  const int64_t line = int64_t(x) + int64_t(bx) * y;
+  const T k = T(kc[2 * c]), k2 = T(kc[2 * c + 1]);
+
+  // boundary-slot index of the row in plane zr (-1: none or not ours)
+  auto bsi_at = [&](int zr) -> int {
+    const int v = zr >= z0 && zr < z1 ? BSI[line + plane * zr] : -1;
+    return __builtin_amdgcn_readfirstlane(v);
+  };
+  // loads of plane step p; bn, bc, bp: boundary indices of rows p + 1, p, p - 1
+  auto fetch = [&](int p, int bn, int bc, int bp, ZlStep<T>& st) {
+    const int64_t rowp = line + plane * p;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      const int dy = j / 3 - 1, dx = j % 3 - 1;
+      const bool in = x + dx >= 0 && x + dx < bx && y + dy >= 0 && y + dy < by;   // wave-uniform
+      st.zv[j] = in ? Z[(rowp + dx + int64_t(bx) * dy) * S + c] : cx<T>{T(0), T(0)};
+    }
+    // slot t = lane: rows p + 1 (t < 9, dz = -1), p (dz = 0), p - 1 (dz = +1)
+    const int o = c / 9, zr = p + 1 - o;
+    const bool ok = c < kStencil && zr >= z0 && zr < z1;
+    const int64_t at = (line + plane * zr) * kStencil + c;
+    st.km = ok ? KM[at] : cx<T>{T(0), T(0)};
+    if (ETA) st.ev = ok ? SE[at] : T(0);
+    const int bi = o == 0 ? bn : (o == 1 ? bc : bp);
+    st.bv = ok && bi >= 0 ? BSV[int64_t(bi) * kStencil + c] : cx<T>{T(0), T(0)};
+    if (DIFF) st.zn = p + 1 < z1 ? Z[(rowp + plane) * S + c] : cx<T>{T(0), T(0)};
+  };
+
+  // rows in planes p + 1 (0), p (1), p - 1 (2): partial sums and own values
+  cx<T> acc[3], accM[3], accE[3], accB[3], zc[3];
+#pragma unroll
+  for (int o = 0; o < 3; ++o) acc[o] = accM[o] = accE[o] = accB[o] = zc[o] = cx<T>{T(0), T(0)};
+
+  auto write_row = [&](int zr) {
+    cx<T> yv;
+    if (DIFF) yv = {acc[2].re - k2 * accM[2].re, acc[2].im - k2 * accM[2].im};
+    else yv = acc[2];
+    if (ETA) {
+      yv.re -= k2 * accE[2].im;   // + i k^2 M_eta z
+      yv.im += k2 * accE[2].re;
+    }
+    yv.re -= k * accB[2].im;   // + i k (B z)
+    yv.im += k * accB[2].re;
+    Y[(line + plane * zr) * S + c] = yv;
+  };
+
+  const int pa = max(z0 - 1, 0), pb = min(z1, bz - 1);
+  // boundary indices of rows p - 1, p, p + 1, p + 2 (p: the current step)
+  int bq[4] = {bsi_at(pa - 1), bsi_at(pa), bsi_at(pa + 1), bsi_at(pa + 2)};
+  ZlStep<T> cur, nxt;
+  fetch(pa, bq[2], bq[1], bq[0], cur);
+  for (int p = pa; p <= pb; ++p) {
+    const int bnew = bsi_at(p + 3);
+    if (p < pb) fetch(p + 1, bq[3], bq[2], bq[1], nxt);
+    const bool vn = p + 1 >= z0 && p + 1 < z1;   // wave-uniform
+    const bool vc = p >= z0 && p < z1;
+    const bool vp = p - 1 >= z0 && p - 1 < z1;
+    if (DIFF) {
+      // the rows' own values, for the stiffness in difference form
+      zc[1] = cur.zv[4];
+      zc[0] = cur.zn;
+    }
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      const cx<T> z = cur.zv[j];
+      auto add = [&](int o, int bi) {
+        const int t = 9 * o + j;   // o = 0: dz = -1 for the row in plane p + 1; 1: dz = 0; 2: dz = +1
+        const T K = lane_bcast(cur.km.re, t), M = lane_bcast(cur.km.im, t);
+        if (DIFF) {
+          acc[o].re = fma(K, z.re - zc[o].re, acc[o].re);
+          acc[o].im = fma(K, z.im - zc[o].im, acc[o].im);
+          accM[o].re = fma(M, z.re, accM[o].re);
+          accM[o].im = fma(M, z.im, accM[o].im);
+        } else {
+          const T a = fma(-k2, M, K);   // K - k^2 M
+          acc[o].re = fma(a, z.re, acc[o].re);
+          acc[o].im = fma(a, z.im, acc[o].im);
+        }
+        if (ETA) {
+          const T E = lane_bcast(cur.ev, t);
+          accE[o].re = fma(E, z.re, accE[o].re);
+          accE[o].im = fma(E, z.im, accE[o].im);
+        }
+        if (bi >= 0) cfma(accB[o], cx<T>{lane_bcast(cur.bv.re, t), lane_bcast(cur.bv.im, t)}, z);
+      };
+      if (vn) add(0, bq[2]);
+      if (vc) add(1, bq[1]);
+      if (vp) add(2, bq[0]);
+    }
+    if (vp) write_row(p - 1);
+    acc[2] = acc[1];
+    acc[1] = acc[0];
+    acc[0] = cx<T>{T(0), T(0)};
+    accM[2] = accM[1];
+    accM[1] = accM[0];
+    accM[0] = cx<T>{T(0), T(0)};
+    accE[2] = accE[1];
+    accE[1] = accE[0];
+    accE[0] = cx<T>{T(0), T(0)};
+    accB[2] = accB[1];
+    accB[1] = accB[0];
+    accB[0] = cx<T>{T(0), T(0)};
+    zc[2] = zc[1];
+    bq[0] = bq[1];
+    bq[1] = bq[2];
+    bq[2] = bq[3];
+    bq[3] = bnew;
+    cur = nxt;
+  }
+  // the last plane of the box has no plane after it
+  if (pb == bz - 1 && pb >= z0 && pb < z1) write_row(pb);
 }
 
 // ---------------------------------------------------------------- vector kernels over [nrows][s]
@@ -908,6 +1093,8 @@ __global__ void k_out_cols(int64_t n, int s, int nf, int ncols, const int* __res
 struct Variant {
   int cpl = 1, bs = 256, xcd = 0;
   int lds = 0;          // > 0: LDS-staged product with lds columns per group
+  // zl > 0: stencil-form product, blocks of pw x ph line groups, nzc z chunks
+  int zl = 0, pw = 0, ph = 0, nzc = 0;
 };
 
 // LDS bytes the staged product needs for a column group of cg columns.
@@ -939,9 +1126,56 @@ int launch_lds(hipStream_t stream, int64_t nrows, int s, const RowOp<T>& A, cons
   return HZ_OK;
 }
 
+// Stencil-form variants: patches of pw x ph line groups (pw ph waves per block).
+struct ZlShape {
+  int pw, ph;
+};
+constexpr ZlShape kZlShapes[] = {{2, 2}, {4, 2}, {2, 4}, {8, 1}};
+
+inline ZlGeom zl_geom(int bx, int by, int bz, int pw, int ph, int nzc) {
+  ZlGeom g;
+  g.npx = ceil_div(bx, pw);
+  g.npy = ceil_div(by, ph);
+  g.nzc = std::max(1, std::min(nzc, bz));
+  g.zc = ceil_div(bz, g.nzc);
+  g.nzc = ceil_div(bz, g.zc);
+  return g;
+}
+
+template <typename T>
+bool zl_fits(const Variant& v, int s, const RowOp<T>& A) {
+  if (v.zl <= 0 || !A.KM || !A.BSI || A.bx <= 0 || s != kWave || v.nzc < 1) return false;
+  bool known = false;
+  for (const ZlShape& h : kZlShapes) known |= h.pw == v.pw && h.ph == v.ph;
+  return known;
+}
+
+template <typename T, int PW, int PH>
+int launch_zl(hipStream_t stream, const Variant& v, const RowOp<T>& A, const double* kc, const cx<T>* Z, cx<T>* Y) {
+  const ZlGeom g = zl_geom(A.bx, A.by, A.bz, PW, PH, v.nzc);
+  const int64_t nblk = int64_t(g.npx) * g.npy * g.nzc;
+  if (nblk > INT32_MAX) return hz_fail(HZ_ERR_INVALID, "stencil product grid too large");
+  const dim3 grid = dim3(unsigned(nblk)), block = dim3(PW * PH * kWave);
+  if (A.SE)
+    k_spmm_zl<T, PW, PH, true><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, A.SE, A.BSI, A.BSV, kc, Z, Y);
+  else
+    k_spmm_zl<T, PW, PH, false><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, nullptr, A.BSI, A.BSV, kc, Z,
+                                                            Y);
+  HZ_HIP(hipGetLastError());
+  return HZ_OK;
+}
+
 template <typename T, bool RESID>
 int launch_spmm(hipStream_t stream, const Variant& v, int64_t nrows, int s, const RowOp<T>& A, const double* st,
                 const cx<T>* Z, const cx<T>* F, cx<T>* Y, double* part, int* nblk_out) {
+  if (!RESID && v.zl > 0) {
+    if (!zl_fits<T>(v, s, A)) return hz_fail(HZ_ERR_INVALID, "bad stencil product variant");
+    if (v.pw == 2 && v.ph == 2) return launch_zl<T, 2, 2>(stream, v, A, st, Z, Y);
+    if (v.pw == 4 && v.ph == 2) return launch_zl<T, 4, 2>(stream, v, A, st, Z, Y);
+    if (v.pw == 2 && v.ph == 4) return launch_zl<T, 2, 4>(stream, v, A, st, Z, Y);
+    if (v.pw == 8 && v.ph == 1) return launch_zl<T, 8, 1>(stream, v, A, st, Z, Y);
+    return hz_fail(HZ_ERR_INVALID, "no stencil product variant");
+  }
   if (!RESID && v.lds > 0) {
     if (A.hblocks <= 0 || s % v.lds || lds_bytes(A, v.lds) > lds_limit())
       return hz_fail(HZ_ERR_INVALID, "bad staged product variant");
@@ -984,7 +1218,26 @@ struct SweepData {
   DevBuf hptr, hidx, lidx, blidx;   // halos of the blocks of kHaloRows rows
   int hblocks = 0, hmax = 0;
   bool eta = false;
+  // stencil form (boxes in their own numbering): slot-major (K, M) pairs and M_eta
+  DevBuf KM64, KM32, SE64, SE32, BSI, BSV64, BSV32;
+  int box[3] = {0, 0, 0};
+  int64_t nnz = 0, nb = 0;          // stored entries, boundary entries
 };
+
+// Algorithmic bytes of one multi-vector product over s columns in variant
+// v: the operator's values (K, M, with M_eta when present; column indices
+// and row pointers for the row-wise forms, none for the stencil form, whose
+// zero slots are not counted), the boundary lists, one read of the input
+// and one write of the output.
+int64_t spmm_bytes(const Variant& v, const SweepData& D, int s, int tsize) {
+  const int64_t n = D.nrows, vals = (D.eta ? 3 : 2) * int64_t(tsize) * D.nnz;
+  // row-wise: row pointers, columns and values of the boundary lists;
+  // stencil form: the per-row slot index and the listed values
+  const int64_t bnd = v.zl > 0 ? 4 * n + 2 * int64_t(tsize) * D.nb : 4 * (n + 1) + (4 + 2 * int64_t(tsize)) * D.nb;
+  const int64_t vec = 2 * 2 * int64_t(tsize) * n * s;
+  const int64_t idx = v.zl > 0 ? 0 : 4 * D.nnz + 4 * (n + 1);
+  return vals + idx + bnd + vec;
+}
 
 template <typename V>
 int upload(DevBuf& b, const std::vector<V>& h) {
@@ -1130,6 +1383,65 @@ int build_sweep_data(hz_ctx ctx, SweepData* D) {
   HZ_TRY(upload(D->B32, B32));
   HZ_TRY(upload(D->Bdiag, Bd));
   HZ_TRY(upload(D->dpos, dpos));
+  D->nnz = nnz;
+  D->nb = int64_t(bcol.size());
+  if (ctx->stencil_ok) {
+    // the rows are the box's nodes (x fastest): each entry goes to the slot
+    // of its neighbour's offset
+    const int64_t bx = ctx->elems[0] + 1, by = ctx->elems[1] + 1, bz = ctx->elems[2] + 1;
+    if (bx * by * bz != n) return hz_fail(HZ_ERR_INVALID, "stencil box does not match the mesh");
+    std::vector<z_t> km(size_t(kStencil) * nrows, z_t{0.0, 0.0});
+    std::vector<c_t> km32(km.size(), c_t{0.f, 0.f});
+    std::vector<double> se(D->eta ? km.size() : 0, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t x = i % bx, y = i / bx % by, z = i / (bx * by);
+      for (int q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+        const int64_t j = col[q];
+        const int64_t dx = j % bx - x, dy = j / bx % by - y, dz = j / (bx * by) - z;
+        if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1)
+          return hz_fail(HZ_ERR_INVALID, "entry outside the 27-point stencil");
+        const size_t at = size_t(i) * kStencil + size_t(9 * (dz + 1) + 3 * (dy + 1) + dx + 1);
+        km[at] = z_t{K[q], M[q]};
+        km32[at] = c_t{float(K[q]), float(M[q])};
+        if (D->eta) se[at] = E[q];
+      }
+    }
+    HZ_TRY(upload(D->KM64, km));
+    HZ_TRY(upload(D->KM32, km32));
+    // boundary entries of the rows on absorbing walls, in slot form
+    std::vector<int> bsi(nrows, -1);
+    std::vector<z_t> bsv;
+    std::vector<c_t> bsv32;
+    for (int64_t i = 0; i < n; ++i) {
+      if (bptr[i] == bptr[i + 1]) continue;
+      bsi[i] = int(bsv.size() / kStencil);
+      bsv.resize(bsv.size() + kStencil, z_t{0.0, 0.0});
+      const int64_t x = i % bx, y = i / bx % by, z = i / (bx * by);
+      for (int q = bptr[i]; q < bptr[i + 1]; ++q) {
+        const int64_t j = bcol[q];
+        const int64_t dx = j % bx - x, dy = j / bx % by - y, dz = j / (bx * by) - z;
+        if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1)
+          return hz_fail(HZ_ERR_INVALID, "boundary entry outside the 27-point stencil");
+        z_t& v = bsv[size_t(bsi[i]) * kStencil + size_t(9 * (dz + 1) + 3 * (dy + 1) + dx + 1)];
+        v.re += B64[q].re;
+        v.im += B64[q].im;
+      }
+    }
+    bsv32.resize(bsv.size());
+    for (size_t t = 0; t < bsv.size(); ++t) bsv32[t] = c_t{float(bsv[t].re), float(bsv[t].im)};
+    HZ_TRY(upload(D->BSI, bsi));
+    HZ_TRY(upload(D->BSV64, bsv));
+    HZ_TRY(upload(D->BSV32, bsv32));
+    if (D->eta) {
+      HZ_TRY(upload(D->SE64, se));
+      std::vector<float> se32(se.size());
+      for (size_t t = 0; t < se.size(); ++t) se32[t] = float(se[t]);
+      HZ_TRY(upload(D->SE32, se32));
+    }
+    D->box[0] = int(bx);
+    D->box[1] = int(by);
+    D->box[2] = int(bz);
+  }
   // halos of the blocks of kHaloRows rows
   const int64_t nblk = (nrows + kHaloRows - 1) / kHaloRows;
   std::vector<int> hptr(nblk + 1, 0), hidx, cols;
@@ -1179,16 +1491,29 @@ void add_halo(const SweepData& D, RowOp<T>* A) {
     A->blidx = D.blidx.as<int16_t>();
   }
 }
+template <typename T>
+void add_stencil(const SweepData& D, const DevBuf& km, const DevBuf& se, RowOp<T>* A) {
+  if (D.box[0] <= 0) return;
+  A->KM = km.as<cx<T>>();
+  A->SE = D.eta ? se.as<T>() : nullptr;
+  A->BSI = D.BSI.as<int>();
+  A->BSV = (sizeof(T) == 8 ? D.BSV64 : D.BSV32).as<cx<T>>();
+  A->bx = D.box[0];
+  A->by = D.box[1];
+  A->bz = D.box[2];
+}
 template <> RowOp<double> row_op<double>(const SweepData& D) {
   RowOp<double> A = {D.rowptr.as<int>(), D.col.as<int>(), D.K64.as<double>(), D.M64.as<double>(),
                      D.eta ? D.E64.as<double>() : nullptr, D.bptr.as<int>(), D.bcol.as<int>(), D.B64.as<z_t>()};
   add_halo(D, &A);
+  add_stencil(D, D.KM64, D.SE64, &A);
   return A;
 }
 template <> RowOp<float> row_op<float>(const SweepData& D) {
   RowOp<float> A = {D.rowptr.as<int>(), D.col.as<int>(), D.K32.as<float>(), D.M32.as<float>(),
                     D.eta ? D.E32.as<float>() : nullptr, D.bptr.as<int>(), D.bcol.as<int>(), D.B32.as<c_t>()};
   add_halo(D, &A);
+  add_stencil(D, D.KM32, D.SE32, &A);
   return A;
 }
 
@@ -1204,10 +1529,21 @@ inline int log2p1(int v) {
   }
   return r;
 }
-inline int variant_code(const Variant& v) { return ((log2p1(v.lds) * 10 + v.xcd) * 10 + v.cpl) * 1000 + v.bs; }
+// A stencil-form variant has eight digits: 10, pw, ph, then four of nzc.
+inline int variant_code(const Variant& v) {
+  if (v.zl > 0) return 10000000 + v.pw * 100000 + v.ph * 10000 + v.nzc;
+  return ((log2p1(v.lds) * 10 + v.xcd) * 10 + v.cpl) * 1000 + v.bs;
+}
 inline Variant variant_decode(int code) {
   auto un = [](int d) { return d == 0 ? 0 : 1 << (d - 1); };
   Variant v;
+  if (code >= 10000000) {
+    v.zl = 1;
+    v.nzc = code % 10000;
+    v.ph = code / 10000 % 10;
+    v.pw = code / 100000 % 10;
+    return v;
+  }
   v.bs = code % 1000;
   code /= 1000;
   v.cpl = code % 10;
@@ -1219,7 +1555,7 @@ inline Variant variant_decode(int code) {
 }
 std::string tune_key(int64_t n, int64_t nnz, int s, int bytes) {
   std::ostringstream o;
-  o << "spmm4 n=" << n << " nnz=" << nnz << " s=" << s << " t=" << bytes;
+  o << "spmm5 n=" << n << " nnz=" << nnz << " s=" << s << " t=" << bytes;
   return o.str();
 }
 
@@ -1249,8 +1585,9 @@ int autotune(hz_ctx ctx, hipStream_t stream, int64_t nrows, int s, const RowOp<T
   if (const char* fv = std::getenv("HZ_SPMM_VARIANT")) {
     // one given variant (tests and measurements), if it fits this width
     const Variant v = variant_decode(std::atoi(fv));
-    const bool fits = v.lds > 0 ? (A.hblocks > 0 && s % v.lds == 0 && lds_bytes(A, v.lds) <= lds_limit())
-                                : (v.cpl <= s && v.bs >= s / v.cpl);
+    const bool fits = v.zl > 0    ? zl_fits<T>(v, s, A)
+                      : v.lds > 0 ? (A.hblocks > 0 && s % v.lds == 0 && lds_bytes(A, v.lds) <= lds_limit())
+                                  : (v.cpl <= s && v.bs >= s / v.cpl);
     if (fits) {
       *best = v;
       return HZ_OK;
@@ -1283,6 +1620,16 @@ int autotune(hz_ctx ctx, hipStream_t stream, int64_t nrows, int s, const RowOp<T
         v.bs = kHaloRows;
         v.lds = cg;
         cands.push_back(v);
+      }
+  if (!(force && force[0] == '1'))
+    for (const ZlShape& h : kZlShapes)
+      for (int nzc : {1, 2, 4, 8}) {
+        Variant v;
+        v.zl = 1;
+        v.pw = h.pw;
+        v.ph = h.ph;
+        v.nzc = nzc;
+        if (zl_fits<T>(v, s, A)) cands.push_back(v);
       }
   if (cands.empty()) cands.push_back(Variant{});
   hipEvent_t e0, e1;
@@ -3114,7 +3461,7 @@ int sweep_solve(hz_ctx ctx, int nfreq, const double* freqs, const z_t* F, z_t* P
 // Measurement of the sweep's multi-vector product (declared in hz.h).
 template <typename T>
 static int time_spmm_t(hz_ctx ctx, SweepData& D, int nf, const double* freqs, int reps, double* avg_ms,
-                       int32_t* variant) {
+                       int32_t* variant, int64_t* bytes) {
   int s = 1;
   while (s < nf) s <<= 1;
   const int64_t total = D.nrows * s;
@@ -3155,11 +3502,12 @@ static int time_spmm_t(hz_ctx ctx, SweepData& D, int nf, const double* freqs, in
   (void)hipEventDestroy(e1);
   *avg_ms = double(ms) / reps;
   if (variant) *variant = variant_code(v);
+  if (bytes) *bytes = spmm_bytes(v, D, s, int(sizeof(T)));
   return HZ_OK;
 }
 
-int sweep_time_spmm(hz_ctx ctx, int nfreq, const double* freqs, int precision, int reps, double* avg_ms,
-                    int32_t* variant) {
+// The sweep's operator data for the current parameters (built on first use).
+static int sweep_data_for(hz_ctx ctx, SweepData** out) {
   if (!ctx->sweep_data || ctx->sweep_version != ctx->params_version) {
     ctx->sweep_data.reset();
     std::shared_ptr<void> d(new SweepData(), [](void* q) { delete static_cast<SweepData*>(q); });
@@ -3167,7 +3515,85 @@ int sweep_time_spmm(hz_ctx ctx, int nfreq, const double* freqs, int precision, i
     ctx->sweep_data = d;
     ctx->sweep_version = ctx->params_version;
   }
-  SweepData& D = *static_cast<SweepData*>(ctx->sweep_data.get());
-  return precision == HZ_MIXED ? time_spmm_t<float>(ctx, D, nfreq, freqs, reps, avg_ms, variant)
-                               : time_spmm_t<double>(ctx, D, nfreq, freqs, reps, avg_ms, variant);
+  *out = static_cast<SweepData*>(ctx->sweep_data.get());
+  return HZ_OK;
+}
+
+int sweep_time_spmm(hz_ctx ctx, int nfreq, const double* freqs, int precision, int reps, double* avg_ms,
+                    int32_t* variant, int64_t* bytes) {
+  SweepData* D = nullptr;
+  HZ_TRY(sweep_data_for(ctx, &D));
+  return precision == HZ_MIXED ? time_spmm_t<float>(ctx, *D, nfreq, freqs, reps, avg_ms, variant, bytes)
+                               : time_spmm_t<double>(ctx, *D, nfreq, freqs, reps, avg_ms, variant, bytes);
+}
+
+// ---------------------------------------------------------------- one multi-vector product
+template <typename T>
+__global__ void k_apply_in(int64_t nrows, int64_t n, int s, int nf, const int* __restrict__ perm,
+                           const z_t* __restrict__ P, cx<T>* __restrict__ X) {
+  const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= nrows * s) return;
+  const int64_t row = e / s;
+  const int c = int(e % s);
+  z_t v = {0.0, 0.0};
+  if (row < n && c < nf) v = P[int64_t(perm[row]) * nf + c];
+  X[e] = cx<T>{T(v.re), T(v.im)};
+}
+
+template <typename T>
+__global__ void k_apply_out(int64_t n, int s, int nf, const int* __restrict__ perm, const cx<T>* __restrict__ Y,
+                            z_t* __restrict__ P) {
+  const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= n * nf) return;
+  const int64_t row = e / nf;
+  const int c = int(e % nf);
+  const cx<T> y = Y[row * s + c];
+  P[int64_t(perm[row]) * nf + c] = z_t{double(y.re), double(y.im)};
+}
+
+template <typename T>
+static int apply_t(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const z_t* X, z_t* Y,
+                   int32_t* variant) {
+  int s = 1;
+  while (s < nf) s <<= 1;
+  const int64_t n = ctx->h.n, total = D.nrows * s;
+  int rc = 0;
+  const std::string p = std::string("aspmm.") + (sizeof(T) == 8 ? "z" : "c");
+  DevBuf* xb = ctx->buf(p + ".x", sizeof(cx<T>) * total, &rc);
+  if (rc) return rc;
+  DevBuf* yb = ctx->buf(p + ".y", sizeof(cx<T>) * total, &rc);
+  if (rc) return rc;
+  DevBuf* kb = ctx->buf(p + ".kc", sizeof(double) * 2 * s, &rc);
+  if (rc) return rc;
+  std::vector<double> kc(2 * s, 0.0);
+  for (int c = 0; c < nf; ++c) {
+    const double k = 2.0 * M_PI * freqs[c] / ctx->c;
+    kc[2 * c] = k;
+    kc[2 * c + 1] = mass_coefficient(k, ctx->h.gls_h);
+  }
+  hipStream_t q = ctx->stream;
+  HZ_HIP(hipMemcpyAsync(kb->p, kc.data(), sizeof(double) * 2 * s, hipMemcpyHostToDevice, q));
+  const int* perm = D.perm.as<int>();
+  k_apply_in<T><<<ceil_div(total, kBlock), kBlock, 0, q>>>(D.nrows, n, s, nf, perm, X, xb->as<cx<T>>());
+  HZ_HIP(hipGetLastError());
+  const RowOp<T> A = row_op<T>(D);
+  Variant v;
+  HZ_TRY(autotune<T>(ctx, q, D.nrows, s, A, kb->as<double>(), xb->as<cx<T>>(), yb->as<cx<T>>(), &v));
+  HZ_TRY((launch_spmm<T, false>(q, v, D.nrows, s, A, kb->as<double>(), xb->as<cx<T>>(), nullptr, yb->as<cx<T>>(),
+                                nullptr, nullptr)));
+  if (n * nf > 0) {
+    k_apply_out<T><<<ceil_div(n * nf, kBlock), kBlock, 0, q>>>(n, s, nf, perm, yb->as<cx<T>>(), Y);
+    HZ_HIP(hipGetLastError());
+  }
+  HZ_HIP(hipStreamSynchronize(q));
+  if (variant) *variant = variant_code(v);
+  return HZ_OK;
+}
+
+int sweep_apply(hz_ctx ctx, int nfreq, const double* freqs, int precision, const z_t* X, z_t* Y,
+                int32_t* variant) {
+  SweepData* D = nullptr;
+  HZ_TRY(sweep_data_for(ctx, &D));
+  return precision == HZ_MIXED ? apply_t<float>(ctx, *D, nfreq, freqs, X, Y, variant)
+                               : apply_t<double>(ctx, *D, nfreq, freqs, X, Y, variant);
 }

@@ -114,6 +114,7 @@ def lib():
         "hz_spmv_bytes": (C.c_int, [VP, C.c_int32, C.c_int32, P(C.c_int64)]),
         "hz_time_spmm": (C.c_int, [VP, C.c_int32, P(C.c_double), C.c_int32, C.c_int32, P(C.c_double),
                                    P(C.c_int64), P(C.c_int32)]),
+        "hz_apply_sweep": (C.c_int, [VP, C.c_int32, P(C.c_double), C.c_int32, VP, VP, P(C.c_int32)]),
         "hz_dd_alpha": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int32, P(hz_c128)]),
         "hz_receiver_energy": (C.c_int, [VP, C.c_int32, P(C.c_int32), VP, P(C.c_double), VP]),
         "hz_node_order": (C.c_int, [P(hz_mesh), P(C.c_int32)]),
@@ -386,6 +387,22 @@ class Helmholtz:
         check(code)
         self.freq = None
         return P, [infos[j].as_dict() for j in range(nf)]
+
+    def apply_sweep(self, freqs, X, precision="fp64"):
+        """(Y, variant code): Y[:, c] = A(k_c) X[:, c] with the sweep's
+        multi-vector product (hz_apply_sweep); X is [n_nodes, nfreq]."""
+        import torch
+        freqs = np.ascontiguousarray(freqs, dtype=np.float64)
+        nf = freqs.size
+        X = torch.as_tensor(X, dtype=torch.complex128, device=self.device).contiguous()
+        if X.shape != (self.n, nf):
+            raise ValueError(f"X must be [n_nodes, nfreq] = {(self.n, nf)}")
+        Y = torch.empty_like(X)
+        v = C.c_int32()
+        check(lib().hz_apply_sweep(self.ctx, nf, _np_ptr(freqs, C.c_double), PRECISIONS[precision],
+                                   _dev(X, X.dtype), _dev(Y, Y.dtype), C.byref(v)), False)
+        self.freq = None
+        return Y, v.value
 
     def solve_adjoint(self, p, g, dJ_deta=None, **opts):
         """Returns (lambda, dJ_dbeta (6,2) numpy, info); dJ_deta (float64 device
