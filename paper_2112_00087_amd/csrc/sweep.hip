@@ -1130,7 +1130,7 @@ int launch_lds(hipStream_t stream, int64_t nrows, int s, const RowOp<T>& A, cons
 struct ZlShape {
   int pw, ph;
 };
-constexpr ZlShape kZlShapes[] = {{2, 2}, {4, 2}, {2, 4}, {8, 1}};
+constexpr ZlShape kZlShapes[] = {{1, 1}, {2, 1}, {2, 2}, {4, 2}};
 
 inline ZlGeom zl_geom(int bx, int by, int bz, int pw, int ph, int nzc) {
   ZlGeom g;
@@ -1170,10 +1170,10 @@ int launch_spmm(hipStream_t stream, const Variant& v, int64_t nrows, int s, cons
                 const cx<T>* Z, const cx<T>* F, cx<T>* Y, double* part, int* nblk_out) {
   if (!RESID && v.zl > 0) {
     if (!zl_fits<T>(v, s, A)) return hz_fail(HZ_ERR_INVALID, "bad stencil product variant");
+    if (v.pw == 1 && v.ph == 1) return launch_zl<T, 1, 1>(stream, v, A, st, Z, Y);
+    if (v.pw == 2 && v.ph == 1) return launch_zl<T, 2, 1>(stream, v, A, st, Z, Y);
     if (v.pw == 2 && v.ph == 2) return launch_zl<T, 2, 2>(stream, v, A, st, Z, Y);
     if (v.pw == 4 && v.ph == 2) return launch_zl<T, 4, 2>(stream, v, A, st, Z, Y);
-    if (v.pw == 2 && v.ph == 4) return launch_zl<T, 2, 4>(stream, v, A, st, Z, Y);
-    if (v.pw == 8 && v.ph == 1) return launch_zl<T, 8, 1>(stream, v, A, st, Z, Y);
     return hz_fail(HZ_ERR_INVALID, "no stencil product variant");
   }
   if (!RESID && v.lds > 0) {
@@ -1623,7 +1623,7 @@ int autotune(hz_ctx ctx, hipStream_t stream, int64_t nrows, int s, const RowOp<T
       }
   if (!(force && force[0] == '1'))
     for (const ZlShape& h : kZlShapes)
-      for (int nzc : {1, 2, 4, 8}) {
+      for (int nzc : {2, 4, 8, 16}) {
         Variant v;
         v.zl = 1;
         v.pw = h.pw;

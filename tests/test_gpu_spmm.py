@@ -44,7 +44,7 @@ def zl_code(pw, ph, nzc):
     return 10000000 + pw * 100000 + ph * 10000 + nzc
 
 
-ZL_FORCED = [zl_code(2, 2, 1), zl_code(4, 2, 3), zl_code(2, 4, 2), zl_code(8, 1, 4)]
+ZL_FORCED = [zl_code(1, 1, 1), zl_code(2, 1, 3), zl_code(2, 2, 2), zl_code(4, 2, 16)]
 ROWWISE = [11256, 2128]   # one lane per column / 256 threads / XCD rows; two per lane / 128 threads
 
 
