@@ -407,11 +407,13 @@ int hz_time_spmv(hz_ctx ctx, int32_t reps, int32_t precision, int32_t format, do
  * between two HIP events on the context's stream, and returns the average
  * duration of one product (ms).  bytes (may be NULL) receives its
  * algorithmic bytes in the picked variant's storage, with w = 8 (HZ_FP64)
- * or 4 (HZ_MIXED, complex64) bytes per real value: values 2 w nnz (3 w nnz
- * with an absorption field), column indices and row pointers 4 nnz +
- * 4 (n + 1) for the row-wise variants (none for the stencil form of a box
- * in its own numbering), boundary lists 4 (n + 1) + (4 + 2 w) nb for nb
- * boundary entries, and 4 w n s for one read of X and one write of Y.
+ * or 4 (HZ_MIXED, complex64) bytes per real value and nb boundary entries:
+ * values 2 w nnz (3 w nnz with an absorption field), and 4 w n s for one
+ * read of X and one write of Y; the row-wise variants add column indices
+ * and row pointers 4 nnz + 4 (n + 1) and boundary lists 4 (n + 1) +
+ * (4 + 2 w) nb, the stencil form of a box in its own numbering (no
+ * indices; its zero slots for missing neighbours not counted) a per-row
+ * boundary index and the boundary values, 4 n + 2 w nb.
  * variant (may be NULL) receives the tuned variant's code.  Leaves the
  * current frequency unset, like hz_solve_sweep.  Synchronises. */
 int hz_time_spmm(hz_ctx ctx, int32_t nfreq, const double* freqs_host, int32_t precision, int32_t reps,

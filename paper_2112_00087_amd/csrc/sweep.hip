@@ -1218,10 +1218,10 @@ struct SweepData {
   DevBuf hptr, hidx, lidx, blidx;   // halos of the blocks of kHaloRows rows
   int hblocks = 0, hmax = 0;
   bool eta = false;
-  // stencil form (boxes in their own numbering): slot-major (K, M) pairs and M_eta
+  // stencil form (boxes in their own numbering): (K, M) pairs and M_eta, 27 slots per row
   DevBuf KM64, KM32, SE64, SE32, BSI, BSV64, BSV32;
   int box[3] = {0, 0, 0};
-  int64_t nnz = 0, nb = 0;          // stored entries, boundary entries
+  int64_t n = 0, nnz = 0, nb = 0;   // mesh nodes, stored entries, boundary entries
 };
 
 // Algorithmic bytes of one multi-vector product over s columns in variant
@@ -1230,7 +1230,7 @@ struct SweepData {
 // zero slots are not counted), the boundary lists, one read of the input
 // and one write of the output.
 int64_t spmm_bytes(const Variant& v, const SweepData& D, int s, int tsize) {
-  const int64_t n = D.nrows, vals = (D.eta ? 3 : 2) * int64_t(tsize) * D.nnz;
+  const int64_t n = D.n, vals = (D.eta ? 3 : 2) * int64_t(tsize) * D.nnz;
   // row-wise: row pointers, columns and values of the boundary lists;
   // stencil form: the per-row slot index and the listed values
   const int64_t bnd = v.zl > 0 ? 4 * n + 2 * int64_t(tsize) * D.nb : 4 * (n + 1) + (4 + 2 * int64_t(tsize)) * D.nb;
@@ -1383,6 +1383,7 @@ int build_sweep_data(hz_ctx ctx, SweepData* D) {
   HZ_TRY(upload(D->B32, B32));
   HZ_TRY(upload(D->Bdiag, Bd));
   HZ_TRY(upload(D->dpos, dpos));
+  D->n = n;
   D->nnz = nnz;
   D->nb = int64_t(bcol.size());
   if (ctx->stencil_ok) {
