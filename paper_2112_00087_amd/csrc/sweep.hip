@@ -304,7 +304,10 @@ struct ZlStep {
   T ev;
 };
 
-template <typename T, int PW, int PH, bool ETA>
+// LDS: false, the lanes take pair t by readlane (vector instructions);
+// true, the wave stores its 27 pairs in LDS and every lane reads pair t at
+// the same address (a broadcast read on the LDS pipe).
+template <typename T, int PW, int PH, bool ETA, bool LDS>
 __global__ void __launch_bounds__(PW * PH * kWave)
     k_spmm_zl(int bx, int by, int bz, ZlGeom g, const cx<T>* __restrict__ KM, const T* __restrict__ SE,
               const int* __restrict__ BSI, const cx<T>* __restrict__ BSV, const double* __restrict__ kc,
@@ -351,6 +354,10 @@ __global__ void __launch_bounds__(PW * PH * kWave)
     if (DIFF) st.zn = p + 1 < z1 ? Z[(rowp + plane) * S + c] : cx<T>{T(0), T(0)};
   };
 
+  // per wave: the plane step's pairs, loss and boundary values (LDS form)
+  __shared__ cx<T> kmS[PW * PH][kStencil], bvS[PW * PH][kStencil];
+  __shared__ T evS[PW * PH][kStencil];
+
   // rows in planes p + 1 (0), p (1), p - 1 (2): partial sums and own values
   cx<T> acc[3], accM[3], accE[3], accB[3], zc[3];
 #pragma unroll
@@ -385,12 +392,26 @@ __global__ void __launch_bounds__(PW * PH * kWave)
       zc[1] = cur.zv[4];
       zc[0] = cur.zn;
     }
+    if (LDS && c < kStencil) {
+      // the same wave writes and then reads these slots: LDS keeps its order
+      kmS[w][c] = cur.km;
+      if (ETA) evS[w][c] = cur.ev;
+      bvS[w][c] = cur.bv;
+    }
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
       const cx<T> z = cur.zv[j];
       auto add = [&](int o, int bi) {
         const int t = 9 * o + j;   // o = 0: dz = -1 for the row in plane p + 1; 1: dz = 0; 2: dz = +1
-        const T K = lane_bcast(cur.km.re, t), M = lane_bcast(cur.km.im, t);
+        T K, M;
+        if (LDS) {
+          const cx<T> km = kmS[w][t];
+          K = km.re;
+          M = km.im;
+        } else {
+          K = lane_bcast(cur.km.re, t);
+          M = lane_bcast(cur.km.im, t);
+        }
         if (DIFF) {
           acc[o].re = fma(K, z.re - zc[o].re, acc[o].re);
           acc[o].im = fma(K, z.im - zc[o].im, acc[o].im);
@@ -402,11 +423,11 @@ __global__ void __launch_bounds__(PW * PH * kWave)
           acc[o].im = fma(a, z.im, acc[o].im);
         }
         if (ETA) {
-          const T E = lane_bcast(cur.ev, t);
+          const T E = LDS ? evS[w][t] : lane_bcast(cur.ev, t);
           accE[o].re = fma(E, z.re, accE[o].re);
           accE[o].im = fma(E, z.im, accE[o].im);
         }
-        if (bi >= 0) cfma(accB[o], cx<T>{lane_bcast(cur.bv.re, t), lane_bcast(cur.bv.im, t)}, z);
+        if (bi >= 0) cfma(accB[o], LDS ? bvS[w][t] : cx<T>{lane_bcast(cur.bv.re, t), lane_bcast(cur.bv.im, t)}, z);
       };
       if (vn) add(0, bq[2]);
       if (vc) add(1, bq[1]);
@@ -1093,8 +1114,9 @@ __global__ void k_out_cols(int64_t n, int s, int nf, int ncols, const int* __res
 struct Variant {
   int cpl = 1, bs = 256, xcd = 0;
   int lds = 0;          // > 0: LDS-staged product with lds columns per group
-  // zl > 0: stencil-form product, blocks of pw x ph line groups, nzc z chunks
-  int zl = 0, pw = 0, ph = 0, nzc = 0;
+  // zl > 0: stencil-form product, blocks of pw x ph lines, nzc z chunks,
+  // pairs broadcast by readlane (bc 0) or through LDS (bc 1)
+  int zl = 0, pw = 0, ph = 0, nzc = 0, bc = 0;
 };
 
 // LDS bytes the staged product needs for a column group of cg columns.
@@ -1144,7 +1166,7 @@ inline ZlGeom zl_geom(int bx, int by, int bz, int pw, int ph, int nzc) {
 
 template <typename T>
 bool zl_fits(const Variant& v, int s, const RowOp<T>& A) {
-  if (v.zl <= 0 || !A.KM || !A.BSI || A.bx <= 0 || s != kWave || v.nzc < 1) return false;
+  if (v.zl <= 0 || !A.KM || !A.BSI || A.bx <= 0 || s != kWave || v.nzc < 1 || v.bc < 0 || v.bc > 1) return false;
   bool known = false;
   for (const ZlShape& h : kZlShapes) known |= h.pw == v.pw && h.ph == v.ph;
   return known;
@@ -1156,11 +1178,17 @@ int launch_zl(hipStream_t stream, const Variant& v, const RowOp<T>& A, const dou
   const int64_t nblk = int64_t(g.npx) * g.npy * g.nzc;
   if (nblk > INT32_MAX) return hz_fail(HZ_ERR_INVALID, "stencil product grid too large");
   const dim3 grid = dim3(unsigned(nblk)), block = dim3(PW * PH * kWave);
-  if (A.SE)
-    k_spmm_zl<T, PW, PH, true><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, A.SE, A.BSI, A.BSV, kc, Z, Y);
-  else
-    k_spmm_zl<T, PW, PH, false><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, nullptr, A.BSI, A.BSV, kc, Z,
-                                                            Y);
+  if (A.SE) {
+    if (v.bc) k_spmm_zl<T, PW, PH, true, true><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, A.SE, A.BSI,
+                                                                            A.BSV, kc, Z, Y);
+    else k_spmm_zl<T, PW, PH, true, false><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, A.SE, A.BSI,
+                                                                       A.BSV, kc, Z, Y);
+  } else {
+    if (v.bc) k_spmm_zl<T, PW, PH, false, true><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, nullptr,
+                                                                             A.BSI, A.BSV, kc, Z, Y);
+    else k_spmm_zl<T, PW, PH, false, false><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, nullptr, A.BSI,
+                                                                        A.BSV, kc, Z, Y);
+  }
   HZ_HIP(hipGetLastError());
   return HZ_OK;
 }
@@ -1530,9 +1558,10 @@ inline int log2p1(int v) {
   }
   return r;
 }
-// A stencil-form variant has eight digits: 10, pw, ph, then four of nzc.
+// A stencil-form variant has eight digits: 1, the broadcast (0 readlane,
+// 1 LDS), pw, ph, then four of nzc.
 inline int variant_code(const Variant& v) {
-  if (v.zl > 0) return 10000000 + v.pw * 100000 + v.ph * 10000 + v.nzc;
+  if (v.zl > 0) return 10000000 + v.bc * 1000000 + v.pw * 100000 + v.ph * 10000 + v.nzc;
   return ((log2p1(v.lds) * 10 + v.xcd) * 10 + v.cpl) * 1000 + v.bs;
 }
 inline Variant variant_decode(int code) {
@@ -1540,6 +1569,7 @@ inline Variant variant_decode(int code) {
   Variant v;
   if (code >= 10000000) {
     v.zl = 1;
+    v.bc = code / 1000000 % 10;
     v.nzc = code % 10000;
     v.ph = code / 10000 % 10;
     v.pw = code / 100000 % 10;
@@ -1623,15 +1653,17 @@ int autotune(hz_ctx ctx, hipStream_t stream, int64_t nrows, int s, const RowOp<T
         cands.push_back(v);
       }
   if (!(force && force[0] == '1'))
-    for (const ZlShape& h : kZlShapes)
-      for (int nzc : {2, 4, 8, 16}) {
-        Variant v;
-        v.zl = 1;
-        v.pw = h.pw;
-        v.ph = h.ph;
-        v.nzc = nzc;
-        if (zl_fits<T>(v, s, A)) cands.push_back(v);
-      }
+    for (int bc : {0, 1})
+      for (const ZlShape& h : kZlShapes)
+        for (int nzc : {2, 4, 8, 16}) {
+          Variant v;
+          v.zl = 1;
+          v.bc = bc;
+          v.pw = h.pw;
+          v.ph = h.ph;
+          v.nzc = nzc;
+          if (zl_fits<T>(v, s, A)) cands.push_back(v);
+        }
   if (cands.empty()) cands.push_back(Variant{});
   hipEvent_t e0, e1;
   HZ_HIP(hipEventCreate(&e0));

@@ -38,13 +38,14 @@ def P():
     return pkg
 
 
-# stencil-form variant codes: 10, blocks of pw x ph line groups, four digits
-# of z chunks
-def zl_code(pw, ph, nzc):
-    return 10000000 + pw * 100000 + ph * 10000 + nzc
+# stencil-form variant codes: 1, the pairs' broadcast (0 readlane, 1 LDS),
+# blocks of pw x ph lines, four digits of z chunks
+def zl_code(pw, ph, nzc, bc=0):
+    return 10000000 + bc * 1000000 + pw * 100000 + ph * 10000 + nzc
 
 
-ZL_FORCED = [zl_code(1, 1, 1), zl_code(2, 1, 3), zl_code(2, 2, 2), zl_code(4, 2, 16)]
+ZL_FORCED = [zl_code(1, 1, 1), zl_code(2, 1, 3), zl_code(2, 2, 2), zl_code(4, 2, 16),
+             zl_code(1, 1, 2, 1), zl_code(2, 1, 5, 1), zl_code(4, 2, 8, 1)]
 ROWWISE = [11256, 2128]   # one lane per column / 256 threads / XCD rows; two per lane / 128 threads
 
 
