@@ -22,6 +22,8 @@
 
 namespace {
 
+constexpr int kGmMaxM = 128;   // largest restart length
+
 constexpr int NV = 8;    // basis vectors per multi-dot chunk
 
 struct GmSt {
@@ -82,8 +84,9 @@ __global__ void k_beta_fin(Seg L, GmSt* st, GmArr G, const double* part) {
 // Partial sums of 2 (j + 1) quantities, 16 per chunk of 8 basis vectors:
 // chunk_to_lds reduces one chunk's 16 values within each wave and puts the
 // waves' sums in LDS; after all chunks, lds_to_partials (one barrier) adds
-// the waves in order and stores chunk c's partials at part + c * nblk * 16 +
-// tile * 16, the layout k_mdot_fin reads.  Fixed summation order.
+// the waves in order and stores quantity u of chunk c at
+// part[(16 c + u) nblk + tile]: each quantity's block partials contiguous,
+// the layout k_mdot_fin reads.  Fixed summation order.
 constexpr int kMaxChunks = (128 + 1 + NV - 1) / NV;
 typedef double ChunkLds[kMaxChunks][2 * NV][kBlock / kWave];
 
@@ -136,7 +139,7 @@ __device__ __forceinline__ void lds_to_partials(const ChunkLds& lds, int nchunk,
     double t = 0.0;
 #pragma unroll
     for (int i = 0; i < kBlock / kWave; ++i) t += lds[c][u][i];
-    part[(int64_t(c) * nblk + tile) * 2 * NV + u] = t;
+    part[(int64_t(c) * 2 * NV + u) * nblk + tile] = t;
   }
 }
 
@@ -250,7 +253,7 @@ __global__ void __launch_bounds__(kBlock) k_gs_second(Seg L, const GmSt* st, GmA
     double t = 0.0;
 #pragma unroll
     for (int k = 0; k < kW; ++k) t += lds[i][ri][k];
-    part[(int64_t(i / NV) * L.nblk + tile) * 2 * NV + 2 * (i % NV) + ri] = t;
+    part[(int64_t(i / NV) * 2 * NV + 2 * (i % NV) + ri) * L.nblk + tile] = t;
   }
 }
 
@@ -298,18 +301,43 @@ __global__ void __launch_bounds__(kBlock) k_mdot(Seg L, const GmSt* st, GmArr G,
     q[2 * c] = a.re * wv.re + a.im * wv.im;
     q[2 * c + 1] = a.re * wv.im - a.im * wv.re;
   }
-  store_partials<2 * NV>(q, part + int64_t(blockIdx.y) * L.nblk * 2 * NV, t);
+  store_partials_qmajor<2 * NV>(q, part + int64_t(blockIdx.y) * L.nblk * 2 * NV, L.nblk, t);
 }
 
 // block (s, i): coefficient i of segment s.  pass 1 -> h1; pass 2 -> h2 and H[:, j] = h1 + h2.
-__global__ void k_mdot_fin(Seg L, const GmSt* st, GmArr G, const double* part, int j, int pass) {
+// The real and imaginary block partials of a coefficient are two
+// contiguous runs: coalesced loads, several in flight per thread, then the
+// block's sum in a fixed order.
+__global__ void __launch_bounds__(kFinBlock) k_mdot_fin(Seg L, const GmSt* st, GmArr G, const double* part, int j,
+                                                        int pass) {
   int s = blockIdx.x, i = blockIdx.y;
-  if (st[s].cyc) return;
+  const int cyc = st[s].cyc;
   int c = i / NV, q = i % NV;
-  const double* base = part + int64_t(c) * L.nblk * 2 * NV;
-  double re = seg_sum<2 * NV>(L, base, s, 2 * q);
-  double im = seg_sum<2 * NV>(L, base, s, 2 * q + 1);
+  const double* pre = part + (int64_t(c) * 2 * NV + 2 * q) * L.nblk;
+  const double* pim = pre + L.nblk;
+  const int b0 = L.nseg == 1 ? 0 : L.seg_blk[s], b1 = L.nseg == 1 ? L.nblk : L.seg_blk[s + 1];
+  double ar = 0.0, ai = 0.0;
+#pragma unroll 4
+  for (int b = b0 + int(threadIdx.x); b < b1; b += kFinBlock) {
+    ar += pre[b];
+    ai += pim[b];
+  }
+  __shared__ double lds[2][kFinBlock / kWave];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  ar = wave_sum(ar);
+  ai = wave_sum(ai);
+  if (lane == 0) {
+    lds[0][w] = ar;
+    lds[1][w] = ai;
+  }
+  __syncthreads();
+  if (cyc) return;
   if (threadIdx.x == 0) {
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < kFinBlock / kWave; ++k) {
+      re += lds[0][k];
+      im += lds[1][k];
+    }
     z_t h = {re, im};
     if (pass == 1) {
       G.h1[int64_t(s) * (G.m + 1) + i] = h;
@@ -347,29 +375,40 @@ __global__ void __launch_bounds__(kBlock) k_axpy(Seg L, const GmSt* st, GmArr G,
 
 // New Hessenberg column j: subdiagonal, previous rotations, new rotation,
 // residual estimate |g_{j+1}|.
-__global__ void k_givens_fin(Seg L, GmSt* st, GmArr G, const double* part, int j) {
+// The column and the previous rotations are staged in LDS by the whole
+// block, so the sequential rotation loop of thread 0 reads no global memory.
+__global__ void __launch_bounds__(kFinBlock) k_givens_fin(Seg L, GmSt* st, GmArr G, const double* part, int j) {
   int s = blockIdx.x;
   const int cyc = st[s].cyc;
-  __syncthreads();
-  if (cyc) return;
-  double o[1];
-  seg_sums<1>(L, part, s, o);
-  if (threadIdx.x != 0) return;
-  const double ww = o[0];
-  GmSt& S = st[s];
   const int m = G.m;
   z_t* H = G.H + int64_t(s) * (m + 1) * m + int64_t(j) * (m + 1);
   double* cs = G.cs + int64_t(s) * m;
   z_t* sn = G.sn + int64_t(s) * m;
   z_t* g = G.g + int64_t(s) * (m + 1);
+  __shared__ z_t hS[kGmMaxM + 1], snS[kGmMaxM];
+  __shared__ double csS[kGmMaxM];
+  if (!cyc)
+    for (int i = threadIdx.x; i <= j; i += kFinBlock) {
+      hS[i] = H[i];
+      if (i < j) {
+        csS[i] = cs[i];
+        snS[i] = sn[i];
+      }
+    }
+  double o[1];
+  seg_sums<1>(L, part, s, o);   // its barriers also order the staging above
+  if (cyc || threadIdx.x != 0) return;
+  const double ww = o[0];
+  GmSt& S = st[s];
   double hn = sqrt(ww);
-  H[j + 1] = z_t{hn, 0.0};
+  hS[j + 1] = z_t{hn, 0.0};
   for (int i = 0; i < j; ++i) {
-    z_t a = H[i], b = H[i + 1];
-    H[i] = cs[i] * a + sn[i] * b;
-    H[i + 1] = (-1.0 * (conj(sn[i]) * a)) + cs[i] * b;
+    z_t a = hS[i], b = hS[i + 1];
+    hS[i] = csS[i] * a + snS[i] * b;
+    hS[i + 1] = (-1.0 * (conj(snS[i]) * a)) + csS[i] * b;
   }
-  z_t a = H[j], b = H[j + 1];
+  for (int i = 0; i < j; ++i) H[i] = hS[i];
+  z_t a = hS[j], b = hS[j + 1];
   double rho = sqrt(norm2(a) + norm2(b));
   double c;
   z_t sv;
@@ -463,7 +502,7 @@ int gmres_run(hz_ctx ctx, const SegHost& S, const SellOp<T>& A, const cx<T>* f, 
               const KrylovCtl& ctl, KrylovOut* out, const std::string& tag) {
   int rc = 0;
   const int m = ctl.restart;
-  if (m < 1 || m > 128) return hz_fail(HZ_ERR_INVALID, "GMRES restart %d not in 1..128", m);
+  if (m < 1 || m > kGmMaxM) return hz_fail(HZ_ERR_INVALID, "GMRES restart %d not in 1..%d", m, kGmMaxM);
   const int64_t ld = S.nrows;
   const std::string p = "gm." + tag + (sizeof(T) == 8 ? ".z." : ".c.");
   DevBuf* Vb = ctx->buf(p + "V", sizeof(cx<T>) * ld * (m + 1), &rc);

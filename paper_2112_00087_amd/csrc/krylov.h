@@ -279,6 +279,38 @@ __device__ __forceinline__ void store_partials(double (&v)[NQ], double* partial,
   }
 }
 
+// The same, storing quantity q at partial[q * qstride + tile] (each
+// quantity's block partials contiguous, for finalize kernels that reduce one
+// quantity per block).
+template <int NQ>
+__device__ __forceinline__ void store_partials_qmajor(double (&v)[NQ], double* partial, int64_t qstride,
+                                                      const SumTile& t) {
+  const int tile = t.tile;
+  constexpr int kWaves = kBlock / kWave;
+  __shared__ double lds[NQ][kWaves];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  double s[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) s[q] = wave_sum(v[q]);
+  int last = 0;
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) lds[q][w] = s[q];
+    last = __hip_atomic_fetch_add(block_wave_count(), 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) ==
+           kWaves - 1;
+  }
+  last = __shfl(last, 0, kWave);
+  if (!last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  for (int q = lane; q < NQ; q += kWave) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i)
+      t += __hip_atomic_load(&lds[q][i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    partial[int64_t(q) * qstride + tile] = t;
+  }
+}
+
 // Finalize kernels run with kFinBlock threads, one block per segment.
 constexpr int kFinBlock = 1024;
 
