@@ -425,8 +425,9 @@ int hz_time_spmm(hz_ctx ctx, int32_t nfreq, const double* freqs_host, int32_t pr
  * freqs_host (Hz), y_dev[i * nfreq + c] = (A(k_c) x)[i] for every node i
  * and column c, where x is column c of x_dev ([n_nodes][nfreq] row-major
  * complex128, caller-owned device memory; y_dev the same shape, not
- * overlapping x_dev) and A(k) the unpreconditioned operator K - k^2 M +
- * i k B (+ i k^2 M_eta) of the current parameters.  precision HZ_FP64 runs
+ * overlapping x_dev) and A(k) the unpreconditioned operator K - m(k) M +
+ * i k B (+ i k^2 M_eta) of the current parameters (m(k) = k^2, or
+ * k^2 (1 - tau k^2) with HZ_GLS).  precision HZ_FP64 runs
  * the sweep's complex128 product; HZ_MIXED rounds x and the operator to
  * complex64 and runs the mixed sweep's inner product (stiffness in
  * difference form), returning its result widened to complex128.  The
@@ -434,7 +435,8 @@ int hz_time_spmm(hz_ctx ctx, int32_t nfreq, const double* freqs_host, int32_t pr
  * environment variable HZ_SPMM_VARIANT forces one); variant (may be NULL)
  * receives its code.  Leaves the current frequency unset.  Synchronises.
  * Errors: HZ_ERR_INVALID (null pointer, nfreq out of range, bad frequency
- * or precision, a Dirichlet source), HZ_ERR_OOM, HZ_ERR_HIP. */
+ * or precision, a Dirichlet source, GLS with an absorption field),
+ * HZ_ERR_OOM, HZ_ERR_HIP. */
 int hz_apply_sweep(hz_ctx ctx, int32_t nfreq, const double* freqs_host, int32_t precision,
                    const hz_c128* x_dev, hz_c128* y_dev, int32_t* variant);
 

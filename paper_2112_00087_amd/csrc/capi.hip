@@ -364,6 +364,8 @@ int hz_apply_sweep(hz_ctx ctx, int32_t nfreq, const double* freqs_host, int32_t 
   if (!freqs_host || !x_dev || !y_dev || nfreq < 1 || nfreq > 64) return hz_fail(HZ_ERR_INVALID, "bad arguments");
   if (precision != HZ_FP64 && precision != HZ_MIXED) return hz_fail(HZ_ERR_INVALID, "bad precision");
   if (ctx->dirichlet) return hz_fail(HZ_ERR_INVALID, "the sweep takes a Neumann source");
+  if (ctx->h.gls_h > 0.0 && ctx->have_eta)
+    return hz_fail(HZ_ERR_INVALID, "the sweep takes the GLS scheme only without an absorption field");
   for (int j = 0; j < nfreq; ++j)
     if (!std::isfinite(freqs_host[j]) || freqs_host[j] < 0) return hz_fail(HZ_ERR_INVALID, "bad frequency");
   ctx->have_freq = false;   // as after a sweep

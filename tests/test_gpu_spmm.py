@@ -7,7 +7,8 @@ Bound, per output entry i and column c with k = k_c (Sec. 4, the product
 of the discretised operator): the FP64 product sums at most 27 stiffness,
 mass and absorption terms plus the boundary terms, each rounded a few
 times, so |y_i - y_ref,i| <= 1e-13 B_i with
-B_i = sum_j (|K_ij| + k^2 |M_ij| + k |(B beta)_ij| + k^2 |Meta_ij|) |x_j|
+B_i = sum_j (|K_ij| + |m(k)| |M_ij| + k |(B beta)_ij| + k^2 |Meta_ij|) |x_j|, m(k) = k^2 or,
+with Galerkin least-squares stabilisation, k^2 (1 - tau k^2)
 (about 450 unit roundoffs, far below the O(B_i / 27) error of one
 misplaced entry).  The complex64 product rounds x and the operator to
 24-bit mantissas and forms the stiffness in difference form
@@ -50,15 +51,22 @@ ROWWISE = [11256, 2128]   # one lane per column / 256 threads / XCD rows; two pe
 
 
 def _cases():
-    return {"box": (2, (20, 12, 10)), "box-eta": (4, (14, 9, 8)), "kuhn": (5, (6, 4, 4))}
+    # (workload, mesh size, Galerkin least-squares mass coefficient)
+    return {"box": (2, (20, 12, 10), False), "box-eta": (4, (14, 9, 8), False), "kuhn": (5, (6, 4, 4), False),
+            "box-gls": (2, (16, 10, 8), True)}
 
 
 @functools.lru_cache(maxsize=None)
 def _system(name):
-    cfg, elems = _cases()[name]
+    cfg, elems, gls = _cases()[name]
     wl = W.workload(cfg, elems=elems)
-    S = H.System(wl["mesh"], wl["beta"], wl["eta"])
+    S = H.System(wl["mesh"], wl["beta"], wl["eta"], gls=gls)
     return wl, S
+
+
+def _model(P, name):
+    wl, S = _system(name)
+    return P.Helmholtz(wl["mesh"], wl["beta"], wl["eta"], gls=_cases()[name][2])
 
 
 @functools.lru_cache(maxsize=None)
@@ -78,7 +86,8 @@ def _reference(name, nfreq):
         k = W.wavenumber(f)
         Y[:, c] = S.operator(k) @ X[:, c]
         ax = np.abs(X[:, c])
-        B[:, c] = aK @ ax + k * k * (aM @ ax) + k * (aB @ ax) + (0.0 if aE is None else k * k * (aE @ ax))
+        m = S.mass_coefficient(k)   # k^2, or k^2 (1 - tau k^2) with GLS
+        B[:, c] = aK @ ax + abs(m) * (aM @ ax) + k * (aB @ ax) + (0.0 if aE is None else k * k * (aE @ ax))
         Bd[:, c] = B[:, c] + ax * ksum
     return freqs, X, Y, B, Bd
 
@@ -103,14 +112,13 @@ def _fits(code, nfreq, precision, name):
     return s == 64
 
 
-@pytest.mark.parametrize("name", ["box", "box-eta", "kuhn"])
+@pytest.mark.parametrize("name", ["box", "box-eta", "kuhn", "box-gls"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("nfreq", [64, 33, 8, 4, 1])
 def test_apply_sweep_autotuned(P, name, precision, nfreq):
     say("apply_sweep autotuned", name, precision, nfreq)
-    wl, S = _system(name)
     freqs, X, _, _, _ = _reference(name, nfreq)
-    model = P.Helmholtz(wl["mesh"], wl["beta"], wl["eta"])
+    model = _model(P, name)
     Yg, v = model.apply_sweep(freqs, X, precision=precision)
     say("  variant", v)
     _check(name, nfreq, precision, Yg.cpu().numpy())
@@ -118,12 +126,11 @@ def test_apply_sweep_autotuned(P, name, precision, nfreq):
 
 
 @pytest.mark.parametrize("code", ZL_FORCED + ROWWISE)
-@pytest.mark.parametrize("name", ["box", "box-eta", "kuhn"])
+@pytest.mark.parametrize("name", ["box", "box-eta", "kuhn", "box-gls"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_apply_sweep_forced_variant(P, code, name, precision, monkeypatch):
     monkeypatch.setenv("HZ_SPMM_VARIANT", str(code))
-    wl, S = _system(name)
-    model = P.Helmholtz(wl["mesh"], wl["beta"], wl["eta"])
+    model = _model(P, name)
     for nfreq in (64, 33, 16, 5):
         say("apply_sweep forced", code, name, precision, nfreq)
         freqs, X, _, _, _ = _reference(name, nfreq)
