@@ -1172,8 +1172,24 @@ bool zl_fits(const Variant& v, int s, const RowOp<T>& A) {
   return known;
 }
 
+// Y[e] = 0 for the e < count given (the padding rows the stencil form does
+// not compute; the sweep's vector kernels run over them).  A kernel, not a
+// memset: the sweep's loops are captured in HIP graphs.
+template <typename T>
+__global__ void k_zero_tail(int64_t count, cx<T>* __restrict__ Y) {
+  const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e < count) Y[e] = cx<T>{T(0), T(0)};
+}
+
 template <typename T, int PW, int PH>
-int launch_zl(hipStream_t stream, const Variant& v, const RowOp<T>& A, const double* kc, const cx<T>* Z, cx<T>* Y) {
+int launch_zl(hipStream_t stream, const Variant& v, int64_t nrows, int s, const RowOp<T>& A, const double* kc,
+              const cx<T>* Z, cx<T>* Y) {
+  const int64_t n = int64_t(A.bx) * A.by * A.bz;
+  if (nrows > n) {
+    const int64_t tail = (nrows - n) * s;
+    k_zero_tail<T><<<ceil_div(tail, kBlock), kBlock, 0, stream>>>(tail, Y + n * s);
+    HZ_HIP(hipGetLastError());
+  }
   const ZlGeom g = zl_geom(A.bx, A.by, A.bz, PW, PH, v.nzc);
   const int64_t nblk = int64_t(g.npx) * g.npy * g.nzc;
   if (nblk > INT32_MAX) return hz_fail(HZ_ERR_INVALID, "stencil product grid too large");
@@ -1198,10 +1214,10 @@ int launch_spmm(hipStream_t stream, const Variant& v, int64_t nrows, int s, cons
                 const cx<T>* Z, const cx<T>* F, cx<T>* Y, double* part, int* nblk_out) {
   if (!RESID && v.zl > 0) {
     if (!zl_fits<T>(v, s, A)) return hz_fail(HZ_ERR_INVALID, "bad stencil product variant");
-    if (v.pw == 1 && v.ph == 1) return launch_zl<T, 1, 1>(stream, v, A, st, Z, Y);
-    if (v.pw == 2 && v.ph == 1) return launch_zl<T, 2, 1>(stream, v, A, st, Z, Y);
-    if (v.pw == 2 && v.ph == 2) return launch_zl<T, 2, 2>(stream, v, A, st, Z, Y);
-    if (v.pw == 4 && v.ph == 2) return launch_zl<T, 4, 2>(stream, v, A, st, Z, Y);
+    if (v.pw == 1 && v.ph == 1) return launch_zl<T, 1, 1>(stream, v, nrows, s, A, st, Z, Y);
+    if (v.pw == 2 && v.ph == 1) return launch_zl<T, 2, 1>(stream, v, nrows, s, A, st, Z, Y);
+    if (v.pw == 2 && v.ph == 2) return launch_zl<T, 2, 2>(stream, v, nrows, s, A, st, Z, Y);
+    if (v.pw == 4 && v.ph == 2) return launch_zl<T, 4, 2>(stream, v, nrows, s, A, st, Z, Y);
     return hz_fail(HZ_ERR_INVALID, "no stencil product variant");
   }
   if (!RESID && v.lds > 0) {

@@ -49,12 +49,14 @@ def test_sweep_staged_product(P, nfreq, precision, method, monkeypatch):
 
 
 # variant codes: one lane per column, 256 threads, XCD-contiguous rows; two
-# columns per lane, 128 threads, rows in dispatch order
-@pytest.mark.parametrize("code", ["11256", "2128"])
+# columns per lane, 128 threads, rows in dispatch order; the stencil form
+# (64 columns only) with the pairs through LDS, 2 x 1 lines, 3 z chunks, and
+# by readlane, 1 x 1 line, 2 z chunks, forced from the first product on
+@pytest.mark.parametrize("code", ["11256", "2128", "11210003", "10110002"])
 @pytest.mark.parametrize("nfreq,precision,method", [(64, "fp64", "tfqmr"), (33, "mixed", "bicgstabl"),
                                                     (16, "fp64", "gmres")])
 def test_sweep_forced_product_variant(P, code, nfreq, precision, method, monkeypatch):
-    """The same parity with one gathering product variant forced
+    """The same parity with one product variant forced
     (HZ_SPMM_VARIANT) instead of the autotuner's pick."""
     monkeypatch.setenv("HZ_SPMM_VARIANT", code)
     _sweep_parity(P, nfreq, precision, method)
