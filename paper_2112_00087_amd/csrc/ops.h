@@ -92,6 +92,9 @@ int op_set_frequency(hz_ctx ctx, const OpParts& P, double k, int scale, bool wan
 // system; rows i >= n or with diag[i] < 0 are padding (d = 1).
 int op_form(hipStream_t s, int64_t n, int64_t nrows, int64_t npad, const int* col, const OpParts& P, double k,
             int scale, z_t* A, c_t* A32, z_t* d, z_t* dinv, double* R = nullptr, float* R32 = nullptr);
+// I[q] = Im A[ipos[q]] (0 where ipos[q] < 0), and its FP32 copy when I32 is
+// given: the imaginary lists of a split-form operator.
+int op_split_im(hipStream_t s, int64_t ni, const int* ipos, const z_t* A, double* I, float* I32);
 template <typename T>
 int op_spmv(hipStream_t s, int64_t nrows, int64_t nout, const SellOp<T>& A, const cx<T>* x, cx<T>* y);
 int op_mul(hipStream_t s, int64_t n, const z_t* a, const z_t* b, z_t* c);

@@ -81,6 +81,13 @@ __global__ void k_split_im(int64_t ni, const int* __restrict__ ipos, const z_t* 
   if (I32) I32[q] = float(v);
 }
 
+int op_split_im(hipStream_t s, int64_t ni, const int* ipos, const z_t* A, double* I, float* I32) {
+  if (ni <= 0) return HZ_OK;
+  k_split_im<<<ceil_div(ni, kBlock), kBlock, 0, s>>>(ni, ipos, A, I, I32);
+  HZ_HIP(hipGetLastError());
+  return HZ_OK;
+}
+
 int op_form(hipStream_t s, int64_t n, int64_t nrows, int64_t npad, const int* col, const OpParts& P, double k,
             int scale, z_t* A, c_t* A32, z_t* d, z_t* dinv, double* R, float* R32) {
   const double m = mass_coefficient(k, P.gls_h);

@@ -60,6 +60,13 @@ struct DDData {
   int64_t nrows = 0, npad = 0;
   // stacked operator (device)
   DevBuf sptr, scol, K, M, E, bidx, diag, Bb, A, A32, d, dinv;
+  // split form of the stacked operator (no absorption field; HZ_SPLIT=0
+  // turns it off): real parts, int16 column offsets when they fit, and the
+  // interleaved lists of the entries that carry a wall or interface term or
+  // sit in such a node's column (their 1 / diag is complex)
+  bool split = false, dcol16 = false;
+  int64_t n_islots = 0;
+  DevBuf dcol, imeta, icol, ipos, R, R32, I, I32;
   std::vector<double> bmass;         // [nbe][NTAG] host
   bool eta = false;
   // interface maps (device)
@@ -222,6 +229,7 @@ int build_dd(hz_ctx ctx, DDData* D) {
   D->eta = !g.Meta.empty();
   // stacked sliced-ELL system
   std::vector<int32_t> sptr(1, 0), scol, bidx, dpos(row_off, -1), l2g(row_off, 0);
+  std::vector<uint8_t> real_slot;   // 1 for a stored entry (0: slice padding)
   std::vector<double> K, M, E, winv(row_off, 0.0);
   D->bmass.clear();
   int64_t slot_off = 0;
@@ -240,6 +248,7 @@ int build_dd(hz_ctx ctx, DDData* D) {
       M.push_back(q >= 0 ? U.a.M[q] : 0.0);
       if (D->eta) E.push_back(q >= 0 ? U.a.Meta[q] : 0.0);
       bidx.push_back(q >= 0 ? csr2b[q] : -1);
+      real_slot.push_back(q >= 0 ? 1 : 0);
     }
     for (int64_t i = 0; i < U.n; ++i) {
       dpos[U.row_off + i] = int32_t(base + sh.ptr[i / kWave] + (U.a.diag[i] - U.a.rowptr[i]) * kWave + (i % kWave));
@@ -260,6 +269,65 @@ int build_dd(hz_ctx ctx, DDData* D) {
   HZ_TRY(up(ctx, D->diag, dpos));
   HZ_TRY(up(ctx, D->l2g, l2g));
   HZ_TRY(up(ctx, D->winv, winv));
+  {
+    // split form (the global operator's layout, section of ctx_upload)
+    const char* env = std::getenv("HZ_SPLIT");
+    D->split = !D->eta && !(env && env[0] == '0');
+    if (D->split) {
+      const int64_t nsl = row_off / kWave;
+      std::vector<int16_t> dc(D->npad, 0);
+      bool fits = true;
+      std::vector<ImSlice> meta(nsl);
+      std::vector<int32_t> pcol, ppos;
+      std::vector<std::vector<std::pair<int32_t, int32_t>>> lists(kWave);   // per lane: (column, position)
+      int64_t lanes = 0;
+      for (int64_t sl = 0; sl < nsl; ++sl) {
+        const int64_t w = (sptr[sl + 1] - sptr[sl]) / kWave;
+        ImSlice m{int32_t(pcol.size()), 0, 0, int32_t(lanes), 0ull};
+        for (int l = 0; l < kWave; ++l) {
+          lists[l].clear();
+          const int64_t r = sl * kWave + l;
+          for (int64_t k = 0; k < w; ++k) {
+            const int64_t p = sptr[sl] + k * kWave + l;
+            if (!real_slot[p]) continue;   // padding: value 0, offset 0 (the row itself)
+            const int64_t d = int64_t(scol[p]) - r;
+            if (d < -32768 || d > 32767) fits = false;
+            else dc[p] = int16_t(d);
+            const int32_t cd = dpos[scol[p]];
+            if (bidx[p] >= 0 || (cd >= 0 && bidx[cd] >= 0)) lists[l].push_back({scol[p], int32_t(p)});
+          }
+          if (!lists[l].empty()) {
+            m.mask |= 1ull << l;
+            ++m.nl;
+            m.w = std::max<int32_t>(m.w, int32_t(lists[l].size()));
+          }
+        }
+        const size_t at0 = pcol.size();
+        pcol.resize(at0 + size_t(m.w) * m.nl);
+        ppos.resize(at0 + size_t(m.w) * m.nl);
+        int j = 0;
+        for (int l = 0; l < kWave; ++l) {
+          if (!((m.mask >> l) & 1ull)) continue;
+          for (int k = 0; k < m.w; ++k) {
+            const size_t at = at0 + size_t(k) * m.nl + j;
+            const bool on = k < int(lists[l].size());
+            pcol[at] = on ? lists[l][k].first : int32_t(sl * kWave + l);
+            ppos[at] = on ? lists[l][k].second : -1;
+          }
+          ++j;
+        }
+        meta[sl] = m;
+        lanes += m.nl;
+      }
+      if (pcol.size() > size_t(INT32_MAX)) return hz_fail(HZ_ERR_INVALID, "Schwarz: too many imaginary entries");
+      D->dcol16 = fits;
+      if (fits) HZ_TRY(up(ctx, D->dcol, dc));
+      HZ_TRY(up(ctx, D->imeta, meta));
+      HZ_TRY(up(ctx, D->icol, pcol));
+      HZ_TRY(up(ctx, D->ipos, ppos));
+      D->n_islots = int64_t(pcol.size());
+    }
+  }
   for (DevBuf* b : {&D->A, &D->A32}) {
     size_t before = b->bytes;
     HZ_TRY(b->ensure((b == &D->A ? sizeof(z_t) : sizeof(c_t)) * D->npad));
@@ -431,8 +499,20 @@ int form_dd_operator(hz_ctx ctx, DDData* D, std::complex<double> a_lo, std::comp
   P.bidx = D->bidx.as<int>();
   P.Bb = D->Bb.as<z_t>();
   P.diag = D->diag.as<int>();
+  if (D->split) {
+    HZ_TRY(D->R.ensure(sizeof(double) * D->npad));
+    HZ_TRY(D->I.ensure(sizeof(double) * std::max<int64_t>(D->n_islots, 1)));
+    if (want32) {
+      HZ_TRY(D->R32.ensure(sizeof(float) * D->npad));
+      HZ_TRY(D->I32.ensure(sizeof(float) * std::max<int64_t>(D->n_islots, 1)));
+    }
+  }
   HZ_TRY(op_form(ctx->stream, D->nrows, D->nrows, D->npad, D->scol.as<int>(), P, k, 1, D->A.as<z_t>(),
-                 want32 ? D->A32.as<c_t>() : nullptr, D->d.as<z_t>(), D->dinv.as<z_t>()));
+                 want32 ? D->A32.as<c_t>() : nullptr, D->d.as<z_t>(), D->dinv.as<z_t>(),
+                 D->split ? D->R.as<double>() : nullptr, D->split && want32 ? D->R32.as<float>() : nullptr));
+  if (D->split)
+    HZ_TRY(op_split_im(ctx->stream, D->n_islots, D->ipos.as<int>(), D->A.as<z_t>(), D->I.as<double>(),
+                       want32 ? D->I32.as<float>() : nullptr));
   D->alpha_k = k;
   D->alpha_lo = a_lo;
   D->alpha_hi = a_hi;
@@ -531,15 +611,25 @@ struct DDRun {
       HZ_HIP(hipGetLastError());
     }
     HZ_TRY(op_fill(s, nr, u, z_t{0.0, 0.0}));
+    // the split form when formed (no absorption field), else complex values
+    auto split_op = [&](auto* re, auto* im, auto& A) {
+      A.dcol = D->dcol16 ? D->dcol.as<int16_t>() : nullptr;
+      A.imeta = D->imeta.as<ImSlice>();
+      A.icol = D->icol.as<int>();
+      A.re = re;
+      A.iim = im;
+    };
     SellOp<double> A64;
     A64.ptr = D->sptr.as<int>();
     A64.col = D->scol.as<int>();
-    A64.val = D->A.as<z_t>();
+    if (D->split) split_op(D->R.as<double>(), D->I.as<double>(), A64);
+    else A64.val = D->A.as<z_t>();
     if (mixed) {
       SellOp<float> A32;
       A32.ptr = A64.ptr;
       A32.col = A64.col;
-      A32.val = D->A32.as<c_t>();
+      if (D->split) split_op(D->R32.as<float>(), D->I32.as<float>(), A32);
+      else A32.val = D->A32.as<c_t>();
       IrOut io;
       HZ_TRY(ir_run(ctx, D->S, A64, A32, rhs, u, lo, &io, "dd"));
       local_mv += io.matvecs + io.inner_matvecs;
