@@ -53,7 +53,7 @@ ROWWISE = [11256, 2128]   # one lane per column / 256 threads / XCD rows; two pe
 def _cases():
     # (workload, mesh size, Galerkin least-squares mass coefficient)
     return {"box": (2, (20, 12, 10), False), "box-eta": (4, (14, 9, 8), False), "kuhn": (5, (6, 4, 4), False),
-            "box-gls": (2, (16, 10, 8), True)}
+            "box-gls": (2, (16, 10, 8), True), "tet": (6, (6, 4, 4), False)}
 
 
 @functools.lru_cache(maxsize=None)
@@ -107,12 +107,12 @@ def _fits(code, nfreq, precision, name):
     s = 1 << int(np.ceil(np.log2(nfreq))) if nfreq > 1 else 1
     if code < 10000000:
         return True
-    if name == "kuhn":
+    if name in ("kuhn", "tet"):
         return False   # no stencil form off a box
     return s == 64
 
 
-@pytest.mark.parametrize("name", ["box", "box-eta", "kuhn", "box-gls"])
+@pytest.mark.parametrize("name", ["box", "box-eta", "kuhn", "box-gls", "tet"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("nfreq", [64, 33, 8, 4, 1])
 def test_apply_sweep_autotuned(P, name, precision, nfreq):
@@ -126,7 +126,7 @@ def test_apply_sweep_autotuned(P, name, precision, nfreq):
 
 
 @pytest.mark.parametrize("code", ZL_FORCED + ROWWISE)
-@pytest.mark.parametrize("name", ["box", "box-eta", "kuhn", "box-gls"])
+@pytest.mark.parametrize("name", ["box", "box-eta", "kuhn", "box-gls", "tet"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_apply_sweep_forced_variant(P, code, name, precision, monkeypatch):
     monkeypatch.setenv("HZ_SPMM_VARIANT", str(code))
