@@ -19,6 +19,7 @@
 #include <cstdlib>
 #include <fstream>
 #include <sstream>
+#include <type_traits>
 
 #include "ops.h"
 #include "solve.h"
@@ -307,32 +308,42 @@ struct ZlStep {
 // LDS: false, the lanes take pair t by readlane (vector instructions);
 // true, the wave stores its 27 pairs in LDS and every lane reads pair t at
 // the same address (a broadcast read on the LDS pipe).
-template <typename T, int PW, int PH, bool ETA, bool LDS>
+// R lines per wave (R = 1: 64 columns; R = 2: 32 columns, 32 lanes per
+// line, the lines x and x + 1 of a group; pairs through LDS only).
+template <typename T, int R, int PW, int PH, bool ETA, bool LDS>
 __global__ void __launch_bounds__(PW * PH * kWave)
     k_spmm_zl(int bx, int by, int bz, ZlGeom g, const cx<T>* __restrict__ KM, const T* __restrict__ SE,
               const int* __restrict__ BSI, const cx<T>* __restrict__ BSV, const double* __restrict__ kc,
               const cx<T>* __restrict__ Z, cx<T>* __restrict__ Y) {
-  constexpr int S = kWave;        // columns
+  static_assert(R == 1 || LDS, "several lines per wave take their pairs through LDS");
+  constexpr int S = kWave / R;    // columns (lanes per line)
+  constexpr int NP = R * kStencil;   // pairs of a plane step
+  static_assert(NP <= kWave, "one pair per lane");
   constexpr bool DIFF = kDiffK<T>;
-  // block -> patch (XCD-contiguous), wave -> line of the patch
+  // block -> patch (XCD-contiguous), wave -> line group of the patch
   int L = xcd_tile(blockIdx.x, gridDim.x);
   const int px = L % g.npx;
   L /= g.npx;
   const int py = L % g.npy;
   const int izc = L / g.npy;
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
-  const int x = px * PW + w % PW, y = py * PH + w / PW;
-  if (x >= bx || y >= by) return;   // whole wave: this kernel has no barrier
+  const int gx = px * PW + w % PW, y = py * PH + w / PW;
+  if (gx * R >= bx || y >= by) return;   // whole wave: this kernel has no barrier
   const int z0 = izc * g.zc, z1 = min(z0 + g.zc, bz);
-  const int c = int(threadIdx.x) % kWave;
+  const int lane = int(threadIdx.x) % kWave;
+  const int r = R == 1 ? 0 : lane / S, c = R == 1 ? lane : lane % S;
+  const bool live = R == 1 || gx * R + r < bx;
+  // a lane past the box's end loads the group's first line (one line: uniform)
+  const int x = R == 1 ? gx : (live ? gx * R + r : gx * R);
   const int64_t plane = int64_t(bx) * by;
   const int64_t line = int64_t(x) + int64_t(bx) * y;
+  const int64_t line0 = int64_t(gx) * R + int64_t(bx) * y;
   const T k = T(kc[2 * c]), k2 = T(kc[2 * c + 1]);
 
-  // boundary-slot index of the row in plane zr (-1: none or not ours)
+  // boundary-slot index of this lane's row in plane zr (-1: none or not ours)
   auto bsi_at = [&](int zr) -> int {
     const int v = zr >= z0 && zr < z1 ? BSI[line + plane * zr] : -1;
-    return __builtin_amdgcn_readfirstlane(v);
+    return R == 1 ? __builtin_amdgcn_readfirstlane(v) : v;
   };
   // loads of plane step p; bn, bc, bp: boundary indices of rows p + 1, p, p - 1
   auto fetch = [&](int p, int bn, int bc, int bp, ZlStep<T>& st) {
@@ -340,23 +351,31 @@ __global__ void __launch_bounds__(PW * PH * kWave)
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
       const int dy = j / 3 - 1, dx = j % 3 - 1;
-      const bool in = x + dx >= 0 && x + dx < bx && y + dy >= 0 && y + dy < by;   // wave-uniform
+      const bool in = x + dx >= 0 && x + dx < bx && y + dy >= 0 && y + dy < by;   // wave-uniform for R = 1
       st.zv[j] = in ? Z[(rowp + dx + int64_t(bx) * dy) * S + c] : cx<T>{T(0), T(0)};
     }
-    // slot t = lane: rows p + 1 (t < 9, dz = -1), p (dz = 0), p - 1 (dz = +1)
-    const int o = c / 9, zr = p + 1 - o;
-    const bool ok = c < kStencil && zr >= z0 && zr < z1;
-    const int64_t at = (line + plane * zr) * kStencil + c;
+    // lane t < NP: slot tt of line rr, for the rows p + 1 (tt < 9, dz = -1), p
+    // (dz = 0), p - 1 (dz = +1) of that line
+    const int rr = R == 1 ? 0 : lane / kStencil, tt = R == 1 ? lane : lane % kStencil;
+    const int o = tt / 9, zr = p + 1 - o;
+    const bool ok = lane < NP && (R == 1 || gx * R + rr < bx) && zr >= z0 && zr < z1;
+    const int64_t at = (line0 + rr + plane * zr) * kStencil + tt;
     st.km = ok ? KM[at] : cx<T>{T(0), T(0)};
     if (ETA) st.ev = ok ? SE[at] : T(0);
-    const int bi = o == 0 ? bn : (o == 1 ? bc : bp);
-    st.bv = ok && bi >= 0 ? BSV[int64_t(bi) * kStencil + c] : cx<T>{T(0), T(0)};
+    int bi = o == 0 ? bn : (o == 1 ? bc : bp);
+    if (R > 1) {
+      // the boundary indices of line rr's rows live in that line's lanes
+      const int src = (rr < R ? rr : 0) * S;
+      const int sn = __shfl(bn, src, kWave), sc = __shfl(bc, src, kWave), sp = __shfl(bp, src, kWave);
+      bi = o == 0 ? sn : (o == 1 ? sc : sp);
+    }
+    st.bv = ok && bi >= 0 ? BSV[int64_t(bi) * kStencil + tt] : cx<T>{T(0), T(0)};
     if (DIFF) st.zn = p + 1 < z1 ? Z[(rowp + plane) * S + c] : cx<T>{T(0), T(0)};
   };
 
   // per wave: the plane step's pairs, loss and boundary values (LDS form)
-  __shared__ cx<T> kmS[PW * PH][kStencil], bvS[PW * PH][kStencil];
-  __shared__ T evS[PW * PH][kStencil];
+  __shared__ cx<T> kmS[PW * PH][NP], bvS[PW * PH][NP];
+  __shared__ T evS[PW * PH][NP];
 
   // rows in planes p + 1 (0), p (1), p - 1 (2): partial sums and own values
   cx<T> acc[3], accM[3], accE[3], accB[3], zc[3];
@@ -373,7 +392,7 @@ __global__ void __launch_bounds__(PW * PH * kWave)
     }
     yv.re -= k * accB[2].im;   // + i k (B z)
     yv.im += k * accB[2].re;
-    Y[(line + plane * zr) * S + c] = yv;
+    if (live) Y[(line + plane * zr) * S + c] = yv;
   };
 
   const int pa = max(z0 - 1, 0), pb = min(z1, bz - 1);
@@ -392,11 +411,11 @@ __global__ void __launch_bounds__(PW * PH * kWave)
       zc[1] = cur.zv[4];
       zc[0] = cur.zn;
     }
-    if (LDS && c < kStencil) {
+    if (LDS && lane < NP) {
       // the same wave writes and then reads these slots: LDS keeps its order
-      kmS[w][c] = cur.km;
-      if (ETA) evS[w][c] = cur.ev;
-      bvS[w][c] = cur.bv;
+      kmS[w][lane] = cur.km;
+      if (ETA) evS[w][lane] = cur.ev;
+      bvS[w][lane] = cur.bv;
     }
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
@@ -405,7 +424,7 @@ __global__ void __launch_bounds__(PW * PH * kWave)
         const int t = 9 * o + j;   // o = 0: dz = -1 for the row in plane p + 1; 1: dz = 0; 2: dz = +1
         T K, M;
         if (LDS) {
-          const cx<T> km = kmS[w][t];
+          const cx<T> km = kmS[w][r * kStencil + t];
           K = km.re;
           M = km.im;
         } else {
@@ -423,11 +442,13 @@ __global__ void __launch_bounds__(PW * PH * kWave)
           acc[o].im = fma(a, z.im, acc[o].im);
         }
         if (ETA) {
-          const T E = LDS ? evS[w][t] : lane_bcast(cur.ev, t);
+          const T E = LDS ? evS[w][r * kStencil + t] : lane_bcast(cur.ev, t);
           accE[o].re = fma(E, z.re, accE[o].re);
           accE[o].im = fma(E, z.im, accE[o].im);
         }
-        if (bi >= 0) cfma(accB[o], LDS ? bvS[w][t] : cx<T>{lane_bcast(cur.bv.re, t), lane_bcast(cur.bv.im, t)}, z);
+        if (bi >= 0)
+          cfma(accB[o], LDS ? bvS[w][r * kStencil + t] : cx<T>{lane_bcast(cur.bv.re, t), lane_bcast(cur.bv.im, t)},
+               z);
       };
       if (vn) add(0, bq[2]);
       if (vc) add(1, bq[1]);
@@ -1154,9 +1175,9 @@ struct ZlShape {
 };
 constexpr ZlShape kZlShapes[] = {{1, 1}, {2, 1}, {2, 2}, {4, 2}};
 
-inline ZlGeom zl_geom(int bx, int by, int bz, int pw, int ph, int nzc) {
+inline ZlGeom zl_geom(int bx, int by, int bz, int R, int pw, int ph, int nzc) {
   ZlGeom g;
-  g.npx = ceil_div(bx, pw);
+  g.npx = ceil_div(ceil_div(bx, R), pw);
   g.npy = ceil_div(by, ph);
   g.nzc = std::max(1, std::min(nzc, bz));
   g.zc = ceil_div(bz, g.nzc);
@@ -1166,7 +1187,9 @@ inline ZlGeom zl_geom(int bx, int by, int bz, int pw, int ph, int nzc) {
 
 template <typename T>
 bool zl_fits(const Variant& v, int s, const RowOp<T>& A) {
-  if (v.zl <= 0 || !A.KM || !A.BSI || A.bx <= 0 || s != kWave || v.nzc < 1 || v.bc < 0 || v.bc > 1) return false;
+  if (v.zl <= 0 || !A.KM || !A.BSI || A.bx <= 0 || v.nzc < 1 || v.bc < 0 || v.bc > 1) return false;
+  // 64 columns (one line per wave), or 32 (two lines per wave, pairs through LDS)
+  if (!(s == kWave || (s == kWave / 2 && v.bc == 1))) return false;
   bool known = false;
   for (const ZlShape& h : kZlShapes) known |= h.pw == v.pw && h.ph == v.ph;
   return known;
@@ -1181,29 +1204,36 @@ __global__ void k_zero_tail(int64_t count, cx<T>* __restrict__ Y) {
   if (e < count) Y[e] = cx<T>{T(0), T(0)};
 }
 
-template <typename T, int PW, int PH>
+template <typename T, int R, int PW, int PH>
 int launch_zl(hipStream_t stream, const Variant& v, int64_t nrows, int s, const RowOp<T>& A, const double* kc,
               const cx<T>* Z, cx<T>* Y) {
+  if (s * R != kWave) return hz_fail(HZ_ERR_INVALID, "stencil product for %d columns", s);
   const int64_t n = int64_t(A.bx) * A.by * A.bz;
   if (nrows > n) {
     const int64_t tail = (nrows - n) * s;
     k_zero_tail<T><<<ceil_div(tail, kBlock), kBlock, 0, stream>>>(tail, Y + n * s);
     HZ_HIP(hipGetLastError());
   }
-  const ZlGeom g = zl_geom(A.bx, A.by, A.bz, PW, PH, v.nzc);
+  const ZlGeom g = zl_geom(A.bx, A.by, A.bz, R, PW, PH, v.nzc);
   const int64_t nblk = int64_t(g.npx) * g.npy * g.nzc;
   if (nblk > INT32_MAX) return hz_fail(HZ_ERR_INVALID, "stencil product grid too large");
   const dim3 grid = dim3(unsigned(nblk)), block = dim3(PW * PH * kWave);
-  if (A.SE) {
-    if (v.bc) k_spmm_zl<T, PW, PH, true, true><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, A.SE, A.BSI,
-                                                                            A.BSV, kc, Z, Y);
-    else k_spmm_zl<T, PW, PH, true, false><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, A.SE, A.BSI,
-                                                                       A.BSV, kc, Z, Y);
+  if constexpr (R > 1) {
+    if (!v.bc) return hz_fail(HZ_ERR_INVALID, "two lines per wave take their pairs through LDS");
+    if (A.SE) k_spmm_zl<T, R, PW, PH, true, true><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, A.SE,
+                                                                              A.BSI, A.BSV, kc, Z, Y);
+    else k_spmm_zl<T, R, PW, PH, false, true><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, nullptr,
+                                                                          A.BSI, A.BSV, kc, Z, Y);
+  } else if (A.SE) {
+    if (v.bc) k_spmm_zl<T, 1, PW, PH, true, true><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, A.SE,
+                                                                              A.BSI, A.BSV, kc, Z, Y);
+    else k_spmm_zl<T, 1, PW, PH, true, false><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, A.SE, A.BSI,
+                                                                          A.BSV, kc, Z, Y);
   } else {
-    if (v.bc) k_spmm_zl<T, PW, PH, false, true><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, nullptr,
-                                                                             A.BSI, A.BSV, kc, Z, Y);
-    else k_spmm_zl<T, PW, PH, false, false><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, nullptr, A.BSI,
-                                                                        A.BSV, kc, Z, Y);
+    if (v.bc) k_spmm_zl<T, 1, PW, PH, false, true><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, nullptr,
+                                                                               A.BSI, A.BSV, kc, Z, Y);
+    else k_spmm_zl<T, 1, PW, PH, false, false><<<grid, block, 0, stream>>>(A.bx, A.by, A.bz, g, A.KM, nullptr,
+                                                                           A.BSI, A.BSV, kc, Z, Y);
   }
   HZ_HIP(hipGetLastError());
   return HZ_OK;
@@ -1214,11 +1244,15 @@ int launch_spmm(hipStream_t stream, const Variant& v, int64_t nrows, int s, cons
                 const cx<T>* Z, const cx<T>* F, cx<T>* Y, double* part, int* nblk_out) {
   if (!RESID && v.zl > 0) {
     if (!zl_fits<T>(v, s, A)) return hz_fail(HZ_ERR_INVALID, "bad stencil product variant");
-    if (v.pw == 1 && v.ph == 1) return launch_zl<T, 1, 1>(stream, v, nrows, s, A, st, Z, Y);
-    if (v.pw == 2 && v.ph == 1) return launch_zl<T, 2, 1>(stream, v, nrows, s, A, st, Z, Y);
-    if (v.pw == 2 && v.ph == 2) return launch_zl<T, 2, 2>(stream, v, nrows, s, A, st, Z, Y);
-    if (v.pw == 4 && v.ph == 2) return launch_zl<T, 4, 2>(stream, v, nrows, s, A, st, Z, Y);
-    return hz_fail(HZ_ERR_INVALID, "no stencil product variant");
+    auto go = [&](auto Rc) -> int {
+      constexpr int R = decltype(Rc)::value;
+      if (v.pw == 1 && v.ph == 1) return launch_zl<T, R, 1, 1>(stream, v, nrows, s, A, st, Z, Y);
+      if (v.pw == 2 && v.ph == 1) return launch_zl<T, R, 2, 1>(stream, v, nrows, s, A, st, Z, Y);
+      if (v.pw == 2 && v.ph == 2) return launch_zl<T, R, 2, 2>(stream, v, nrows, s, A, st, Z, Y);
+      if (v.pw == 4 && v.ph == 2) return launch_zl<T, R, 4, 2>(stream, v, nrows, s, A, st, Z, Y);
+      return hz_fail(HZ_ERR_INVALID, "no stencil product variant");
+    };
+    return s == kWave ? go(std::integral_constant<int, 1>{}) : go(std::integral_constant<int, 2>{});
   }
   if (!RESID && v.lds > 0) {
     if (A.hblocks <= 0 || s % v.lds || lds_bytes(A, v.lds) > lds_limit())
