@@ -50,8 +50,9 @@ def test_sweep_staged_product(P, nfreq, precision, method, monkeypatch):
 
 # variant codes: one lane per column, 256 threads, XCD-contiguous rows; two
 # columns per lane, 128 threads, rows in dispatch order; the stencil form
-# (64 columns only) with the pairs through LDS, 2 x 1 lines, 3 z chunks, and
-# by readlane, 1 x 1 line, 2 z chunks, forced from the first product on
+# (64 or 32 columns) with the pairs through LDS, 2 x 1 lines, 3 z chunks, and
+# by readlane (64 columns), 1 x 1 line, 2 z chunks, forced from the first
+# product on
 @pytest.mark.parametrize("code", ["11256", "2128", "11210003", "10110002"])
 @pytest.mark.parametrize("nfreq,precision,method", [(64, "fp64", "tfqmr"), (33, "mixed", "bicgstabl"),
                                                     (16, "fp64", "gmres")])
