@@ -2936,19 +2936,53 @@ struct TsCol {
   int stag;      // checkpoint spacing in half-steps (0: no stagnation test)
 };
 
+// Diagonal of A(k_c) recomputed per element from four (five with an
+// absorption field) real values per row and the column's (k, m(k)), in place
+// of a stored n x s table of D^-1:
+//   A(k)_rr = K_rr - m(k) M_rr - k Im(B_rr) + i (k Re(B_rr) + m(k) E_rr).
+// Padding rows hold (1, 0, 0, 0): diagonal 1.
+struct TsDiag {
+  const double4* a;   // (K_rr, M_rr, Re B_rr, Im B_rr) per row
+  const double* e;    // E_rr per row, or null
+  const double* kc;   // (k, m(k)) per column
+  int ls;             // log2 of the width
+};
+
+__device__ __forceinline__ z_t ts_dg(const TsDiag& G, int64_t row, double k, double k2) {
+  const double4 r = G.a[row];
+  return z_t{r.x - k2 * r.y - k * r.w, k * r.z + (G.e ? k2 * G.e[row] : 0.0)};
+}
+
+__global__ void k_ts_rowdiag(int64_t n, int64_t nrows, const int* __restrict__ dpos, const double* __restrict__ K,
+                             const double* __restrict__ M, const double* __restrict__ E, const z_t* __restrict__ Bd,
+                             double4* __restrict__ a, double* __restrict__ e) {
+  int64_t row = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (row >= nrows) return;
+  if (row < n) {
+    const int64_t p = dpos[row];
+    a[row] = double4{K[p], M[p], Bd[row].re, Bd[row].im};
+    if (e) e[row] = E[p];
+  } else {
+    a[row] = double4{1.0, 0.0, 0.0, 0.0};
+    if (e) e[row] = 0.0;
+  }
+}
+
+// The two product inputs are stored already scaled by D^-1 (right Jacobi:
+// B = A D^-1): u holds D^-1 u and un holds D^-1 un; a kernel that needs u or
+// un itself multiplies by the diagonal.
 template <typename T>
 struct TsVec {
   cx<T>* y;      // inner iterate (scaled unknowns)
   cx<T>* rs;     // shadow vector
   cx<T>* w;
-  cx<T>* u;      // u at the start of a pair of half-steps
-  cx<T>* un;     // u after the even half-step
+  cx<T>* u;      // D^-1 u at the start of a pair of half-steps (odd product's input)
+  cx<T>* un;     // D^-1 un, un = u after the even half-step (even product's input)
   cx<T>* v;
-  cx<T>* uhe;    // B un (product of the even half-step)
+  cx<T>* uhe;    // B un = A (D^-1 un) (product of the even half-step)
   cx<T>* uh;     // B u (product of the odd half-step, or of a restart)
   cx<T>* d;
-  cx<T>* Z;      // D^-1 (product input)
-  const cx<T>* dT;
+  TsDiag G;
 };
 
 __device__ __forceinline__ bool ts_off(const TsCol& S) { return S.done || S.idone || S.nan; }
@@ -2960,9 +2994,11 @@ template <typename T>
 __global__ void k_ts_addx(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V, z_t* __restrict__ X) {
   int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (e >= total) return;
-  const TsCol& S = st[e & (s - 1)];
+  const int c = int(e & (s - 1));
+  const TsCol& S = st[c];
   if (!ts_pending(S) || S.scale == 0.0) return;
-  z_t d = ccast<double>(V.dT[e]) * ccast<double>(V.y[e]);
+  const z_t iv = crecip(ts_dg(V.G, e >> V.G.ls, V.G.kc[2 * c], V.G.kc[2 * c + 1]));
+  z_t d = iv * ccast<double>(V.y[e]);
   X[e] = z_t{fma(S.scale, d.re, X[e].re), fma(S.scale, d.im, X[e].im)};
 }
 
@@ -2989,22 +3025,23 @@ __global__ void k_ts_true(int nblk, int s, TsCol* st, const double* __restrict__
   S.ithr = delta > lim ? delta : lim;
 }
 
-// restart: r0 = R / scale; r* = w = u = r0; d = y = 0; Z = D^-1 u
+// restart: r0 = R / scale; r* = w = u = r0 (u stored as D^-1 u); d = y = 0
 template <typename T>
 __global__ void k_ts_start(int64_t total, int s, const TsCol* __restrict__ st, const z_t* __restrict__ R,
                            TsVec<T> V) {
   int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (e >= total) return;
-  const TsCol& S = st[e & (s - 1)];
+  const int c = int(e & (s - 1));
+  const TsCol& S = st[c];
   if (!S.restart_now) return;
   const cx<T> r = ccast<T>((1.0 / S.scale) * R[e]);
   const cx<T> z = {T(0), T(0)};
+  const z_t iv = crecip(ts_dg(V.G, e >> V.G.ls, V.G.kc[2 * c], V.G.kc[2 * c + 1]));
   V.rs[e] = r;
   V.w[e] = r;
-  V.u[e] = r;
+  V.u[e] = ccast<T>(iv * ccast<double>(r));
   V.d[e] = z;
   V.y[e] = z;
-  V.Z[e] = ccast<T>(ccast<double>(V.dT[e]) * ccast<double>(r));
 }
 
 // after the restart product uh = B u: v = uh; partial r*^H v
@@ -3081,12 +3118,13 @@ __device__ __forceinline__ void ts_qmr(TsCol& S, double ww) {
   S.m += 1;
 }
 
-// Buffers of a pair of half-steps: u holds u at the start of the pair, the
-// even half-step writes un (never copied back: the odd half-step reads it and
-// writes the next u into u), the even product writes uhe and the odd (or
-// restart) product writes uh, so the odd half-step's v needs no staging.
-// even half-step, part 1: un = u - alpha v; w -= alpha uh; d = u + g d;
-// Z = D^-1 un (the even product's input; unused if the column stops);
+// Buffers of a pair of half-steps: u holds D^-1 u at the start of the pair,
+// the even half-step writes D^-1 un into un (never copied back: the odd
+// half-step reads it and writes the next D^-1 u into u), the even product
+// writes uhe and the odd (or restart) product writes uh, so the odd
+// half-step's v needs no staging.
+// even half-step, part 1: un = u - alpha v (stored as D^-1 un, the even
+// product's input; unused if the column stops); w -= alpha uh; d = u + g d;
 // partial ||w||^2
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ts_even1(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V,
@@ -3098,11 +3136,11 @@ __global__ void __launch_bounds__(kBlock) k_ts_even1(int64_t total, int s, const
   if (!ts_off(S)) {
     const z_t a = S.alpha;
     const z_t g = (S.theta * S.theta) * cdiv(S.eta, a);
+    const double k = V.G.kc[2 * c], k2 = V.G.kc[2 * c + 1];
     for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
-      const z_t u = ccast<double>(V.u[e]);
-      const cx<T> un = ccast<T>(u - a * ccast<double>(V.v[e]));
-      V.un[e] = un;
-      V.Z[e] = ccast<T>(ccast<double>(V.dT[e]) * ccast<double>(un));
+      const z_t dg = ts_dg(V.G, e >> V.G.ls, k, k2);
+      const z_t u = dg * ccast<double>(V.u[e]);
+      V.un[e] = ccast<T>(crecip(dg) * (u - a * ccast<double>(V.v[e])));
       const cx<T> w = ccast<T>(ccast<double>(V.w[e]) - a * ccast<double>(V.uh[e]));
       V.w[e] = w;
       V.d[e] = ccast<T>(u + g * ccast<double>(V.d[e]));
@@ -3141,13 +3179,15 @@ __global__ void __launch_bounds__(kBlock) k_ts_odd1(int64_t total, int s, const 
     const z_t eta = S.eta;
     const z_t a = S.alpha;
     const z_t g = run ? (S.theta * S.theta) * cdiv(S.eta, a) : z_t{0.0, 0.0};
+    const double k = V.G.kc[2 * c], k2 = V.G.kc[2 * c + 1];
     for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
       const z_t dv = ccast<double>(V.d[e]);
       V.y[e] = ccast<T>(ccast<double>(V.y[e]) + eta * dv);
       if (!run) continue;
       const cx<T> w = ccast<T>(ccast<double>(V.w[e]) - a * ccast<double>(V.uhe[e]));
       V.w[e] = w;
-      V.d[e] = ccast<T>(ccast<double>(V.un[e]) + g * dv);
+      const z_t un = ts_dg(V.G, e >> V.G.ls, k, k2) * ccast<double>(V.un[e]);
+      V.d[e] = ccast<T>(un + g * dv);
       const z_t wv = ccast<double>(w), r = ccast<double>(V.rs[e]);
       q[0] += norm2(wv);
       q[1] = fma(r.re, wv.re, fma(r.im, wv.im, q[1]));
@@ -3187,19 +3227,20 @@ __global__ void k_ts_odd_fin(int G_, int s, TsCol* st, const double* __restrict_
   }
 }
 
-// odd half-step, part 2: y += eta d; then u = w + beta un, Z = D^-1 u
+// odd half-step, part 2: y += eta d; then u = w + beta un, stored as
+// D^-1 u = D^-1 w + beta (D^-1 un)
 template <typename T>
 __global__ void k_ts_odd2(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V) {
   int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (e >= total) return;
-  const TsCol& S = st[e & (s - 1)];
+  const int c = int(e & (s - 1));
+  const TsCol& S = st[c];
   if (!ts_apply(S)) return;
   V.y[e] = ccast<T>(ccast<double>(V.y[e]) + S.eta * ccast<double>(V.d[e]));
   if (S.idone) return;
   const z_t b = S.beta;
-  const cx<T> u = ccast<T>(ccast<double>(V.w[e]) + b * ccast<double>(V.un[e]));
-  V.u[e] = u;
-  V.Z[e] = ccast<T>(ccast<double>(V.dT[e]) * ccast<double>(u));
+  const z_t iv = crecip(ts_dg(V.G, e >> V.G.ls, V.G.kc[2 * c], V.G.kc[2 * c + 1]));
+  V.u[e] = ccast<T>(iv * ccast<double>(V.w[e]) + b * ccast<double>(V.un[e]));
 }
 
 // odd half-step, part 3 (after uh = B u): v = uh + beta uhe + beta^2 v; partial r*^H v
@@ -3253,12 +3294,13 @@ __global__ void k_ts_init(int s, TsCol* st, const double* fn2, double tol, int s
   st[c].idone = 1;                 // every column starts with a refinement step
 }
 
+constexpr int kTsVecs = 9;   // column vectors of a width (TsVec's pointers)
+
 template <typename T>
 struct TsWidth {
   int s = 0, Gr = 1;
   int64_t total = 0;
   z_t *X = nullptr, *Fs = nullptr, *R = nullptr;
-  cx<T>* dT = nullptr;
   double *kc = nullptr, *part = nullptr, *cn = nullptr;
   TsCol* st = nullptr;
   TsVec<T> V;
@@ -3266,7 +3308,7 @@ struct TsWidth {
 };
 
 template <typename T>
-int ts_alloc(hz_ctx ctx, int64_t nrows, int s, TsWidth<T>* W) {
+int ts_alloc(hz_ctx ctx, int64_t nrows, int s, const double4* rda, const double* rde, TsWidth<T>* W) {
   int rc = 0;
   const std::string p = std::string("swt.") + (sizeof(T) == 8 ? "z." : "c.") + std::to_string(s) + ".";
   const int64_t total = nrows * s;
@@ -3281,17 +3323,18 @@ int ts_alloc(hz_ctx ctx, int64_t nrows, int s, TsWidth<T>* W) {
   W->X = static_cast<z_t*>(buf("X", sizeof(z_t) * total));
   W->Fs = static_cast<z_t*>(buf("F", sizeof(z_t) * total));
   W->R = static_cast<z_t*>(buf("R", sizeof(z_t) * total));
-  W->dT = static_cast<cx<T>*>(buf("dT", sizeof(cx<T>) * total));
   W->kc = static_cast<double*>(buf("kc", sizeof(double) * 2 * s));
   W->cn = static_cast<double*>(buf("cn", sizeof(double) * s));
   W->part = static_cast<double*>(buf("part", sizeof(double) * std::max<int64_t>(int64_t(W->Gr) * 3, nblk_res) * s));
   W->st = static_cast<TsCol*>(buf("st", sizeof(TsCol) * s));
   W->V = TsVec<T>{};
-  cx<T>** vv[10] = {&W->V.y, &W->V.rs, &W->V.w, &W->V.u, &W->V.un, &W->V.v, &W->V.uhe, &W->V.uh, &W->V.d, &W->V.Z};
-  const char* names[10] = {"y", "rs", "w", "u", "un", "v", "uhe", "uh", "d", "Z"};
-  for (int i = 0; i < 10; ++i) *vv[i] = static_cast<cx<T>*>(buf(names[i], sizeof(cx<T>) * total));
+  cx<T>** vv[kTsVecs] = {&W->V.y, &W->V.rs, &W->V.w, &W->V.u, &W->V.un, &W->V.v, &W->V.uhe, &W->V.uh, &W->V.d};
+  const char* names[kTsVecs] = {"y", "rs", "w", "u", "un", "v", "uhe", "uh", "d"};
+  for (int i = 0; i < kTsVecs; ++i) *vv[i] = static_cast<cx<T>*>(buf(names[i], sizeof(cx<T>) * total));
   if (rc) return rc;
-  W->V.dT = W->dT;
+  int ls = 0;
+  while ((1 << ls) < s) ++ls;
+  W->V.G = TsDiag{rda, rde, W->kc, ls};
   W->vres.cpl = 1;
   W->vres.bs = kBlock;
   return HZ_OK;
@@ -3308,8 +3351,18 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
   const RowOp<T> AT = row_op<T>(D);
   int s = 1;
   while (s < nf) s <<= 1;
+  int rc = 0;
+  DevBuf* rdab = ctx->buf("swt.rda", sizeof(double4) * nrows, &rc);
+  if (rc) return rc;
+  DevBuf* rdeb = nullptr;
+  if (D.eta) {
+    rdeb = ctx->buf("swt.rde", sizeof(double) * nrows, &rc);
+    if (rc) return rc;
+  }
+  const double4* rda = static_cast<const double4*>(rdab->p);
+  const double* rde = rdeb ? static_cast<const double*>(rdeb->p) : nullptr;
   TsWidth<T> W;
-  HZ_TRY(ts_alloc<T>(ctx, nrows, s, &W));
+  HZ_TRY(ts_alloc<T>(ctx, nrows, s, rda, rde, &W));
   hipStream_t cs = ctx->stream;
   std::vector<int> cols(nf);
   for (int c = 0; c < nf; ++c) cols[c] = c;
@@ -3326,15 +3379,16 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
   };
   HZ_TRY(upload_kc(W, cs));
   k_in<<<ceil_div(W.total, kBlock), kBlock, 0, cs>>>(n, nrows, s, nf, D.perm.as<int>(), Pio, Fin, W.X, W.Fs);
-  k_diag<T><<<ceil_div(W.total, kBlock), kBlock, 0, cs>>>(n, nrows, s, D.dpos.as<int>(), D.K64.as<double>(),
-                                                         D.M64.as<double>(), D.eta ? D.E64.as<double>() : nullptr,
-                                                         D.Bdiag.as<z_t>(), W.kc, W.R, W.dT);
+  k_ts_rowdiag<<<ceil_div(nrows, kBlock), kBlock, 0, cs>>>(n, nrows, D.dpos.as<int>(), D.K64.as<double>(),
+                                                           D.M64.as<double>(), D.eta ? D.E64.as<double>() : nullptr,
+                                                           D.Bdiag.as<z_t>(), static_cast<double4*>(rdab->p),
+                                                           rdeb ? static_cast<double*>(rdeb->p) : nullptr);
   k_colnorm<double><<<W.Gr, kBlock, 0, cs>>>(W.total, s, W.Fs, W.part);
   k_colsum<<<s, kBlock, 0, cs>>>(W.Gr, s, W.part, W.cn);
   HZ_HIP(hipMemsetAsync(W.st, 0, sizeof(TsCol) * s, cs));
   k_ts_init<<<1, 64, 0, cs>>>(s, W.st, W.cn, o.tol, sizeof(T) == 4 ? kTsStagHalfSteps : 0);
   HZ_HIP(hipGetLastError());
-  HZ_TRY(autotune<T>(ctx, cs, nrows, s, AT, W.kc, W.V.Z, W.V.uh, &W.vin));
+  HZ_TRY(autotune<T>(ctx, cs, nrows, s, AT, W.kc, W.V.u, W.V.uh, &W.vin));
 
   auto pairs_body = [&](hipStream_t q) -> int {
     const int s_ = W.s, Gr = W.Gr, eb = ceil_div(W.total, kBlock);
@@ -3342,11 +3396,11 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
     for (int it = 0; it < chunk; ++it) {
       k_ts_even1<T><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V, W.part);
       k_ts_qmr_fin<<<s_, kBlock, 0, q>>>(Gr, s_, W.st, W.part);
-      HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.Z, nullptr, W.V.uhe, nullptr, nullptr)));
+      HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.un, nullptr, W.V.uhe, nullptr, nullptr)));
       k_ts_odd1<T><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V, W.part);
       k_ts_odd_fin<<<s_, kBlock, 0, q>>>(Gr, s_, W.st, W.part);
       k_ts_odd2<T><<<eb, kBlock, 0, q>>>(total, s_, W.st, W.V);
-      HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.Z, nullptr, W.V.uh, nullptr, nullptr)));
+      HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.u, nullptr, W.V.uh, nullptr, nullptr)));
       k_ts_odd3<T><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V, W.part);
       k_ts_alpha_fin<<<s_, kBlock, 0, q>>>(Gr, s_, W.st, W.part);
     }
@@ -3362,7 +3416,7 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
     HZ_TRY((launch_spmm<double, true>(q, W.vres, nrows, s_, A64, W.kc, W.X, W.Fs, W.R, W.part, &nb)));
     k_ts_true<<<s_, kBlock, 0, q>>>(nb, s_, W.st, W.part, o.tol, delta);
     k_ts_start<T><<<eb, kBlock, 0, q>>>(total, s_, W.st, W.R, W.V);
-    HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.Z, nullptr, W.V.uh, nullptr, nullptr)));
+    HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.u, nullptr, W.V.uh, nullptr, nullptr)));
     k_ts_v0<T><<<W.Gr, kBlock, 0, q>>>(total, s_, W.st, W.V, W.part);
     k_ts_start_fin<<<s_, kBlock, 0, q>>>(W.Gr, s_, W.st, W.part);
     HZ_HIP(hipGetLastError());
@@ -3392,7 +3446,6 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
     if (!std::isfinite(inf.relres_true)) inf.status = HZ_BREAKDOWN;
     res[cols[j]] = inf;
   };
-  int rc = 0;
   DevBuf* mapb = ctx->buf("swt.map", sizeof(int) * 128, &rc);
   if (rc) return rc;
   bool capped = false;
@@ -3448,7 +3501,7 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
       int s2 = 1;
       while (s2 < int(keep.size())) s2 <<= 1;
       TsWidth<T> W2;
-      HZ_TRY(ts_alloc<T>(ctx, nrows, s2, &W2));
+      HZ_TRY(ts_alloc<T>(ctx, nrows, s2, rda, rde, &W2));
       std::vector<int> map(s2, -1);
       for (size_t jn = 0; jn < keep.size(); ++jn) map[jn] = keep[jn];
       HZ_HIP(hipMemcpyAsync(mapb->p, map.data(), sizeof(int) * s2, hipMemcpyHostToDevice, q));
@@ -3456,10 +3509,9 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
       const int* mp = mapb->as<int>();
       k_gather_cols<z_t><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.X, W2.X);
       k_gather_cols<z_t><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.Fs, W2.Fs);
-      k_gather_cols<cx<T>><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, W.dT, W2.dT);
-      cx<T>* from[10] = {W.V.y, W.V.rs, W.V.w, W.V.u, W.V.un, W.V.v, W.V.uhe, W.V.uh, W.V.d, W.V.Z};
-      cx<T>* to[10] = {W2.V.y, W2.V.rs, W2.V.w, W2.V.u, W2.V.un, W2.V.v, W2.V.uhe, W2.V.uh, W2.V.d, W2.V.Z};
-      for (int i = 0; i < 10; ++i) k_gather_cols<cx<T>><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, from[i], to[i]);
+      cx<T>* from[kTsVecs] = {W.V.y, W.V.rs, W.V.w, W.V.u, W.V.un, W.V.v, W.V.uhe, W.V.uh, W.V.d};
+      cx<T>* to[kTsVecs] = {W2.V.y, W2.V.rs, W2.V.w, W2.V.u, W2.V.un, W2.V.v, W2.V.uhe, W2.V.uh, W2.V.d};
+      for (int i = 0; i < kTsVecs; ++i) k_gather_cols<cx<T>><<<gb, kBlock, 0, q>>>(nrows, W.s, s2, mp, from[i], to[i]);
       HZ_HIP(hipGetLastError());
       std::vector<TsCol> ns(s2);
       for (int jn = 0; jn < s2; ++jn) {
@@ -3476,7 +3528,7 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
       HZ_HIP(hipMemcpyAsync(W2.st, ns.data(), sizeof(TsCol) * s2, hipMemcpyHostToDevice, q));
       HZ_TRY(upload_kc(W2, q));
       // uhe is dead between pairs: scratch output of the tuning runs
-      HZ_TRY(autotune<T>(ctx, q, nrows, s2, AT, W2.kc, W2.V.Z, W2.V.uhe, &W2.vin));
+      HZ_TRY(autotune<T>(ctx, q, nrows, s2, AT, W2.kc, W2.V.u, W2.V.uhe, &W2.vin));
       W = W2;
       std::unique_ptr<Graph> G2(new Graph());
       HZ_TRY(G2->stream(q));
