@@ -2934,6 +2934,13 @@ struct TsCol {
   int done, idone, nan, m, iters, outer, restart_now, last;
   int mchk;      // half-step count at that checkpoint
   int stag;      // checkpoint spacing in half-steps (0: no stagnation test)
+  // The even half-step's d = u + ge d and the odd half-step's x-update are
+  // applied late, in the next odd kernel (d holds the previous odd
+  // half-step's d until then): ge and that odd half-step's eta are kept
+  // here, and yp marks an odd x-update not yet applied (the refinement step
+  // adds it when the column stops between pairs).
+  z_t ge, eta_o;
+  int yp, pad;
 };
 
 // Diagonal of A(k_c) recomputed per element from four (five with an
@@ -2998,7 +3005,9 @@ __global__ void k_ts_addx(int64_t total, int s, const TsCol* __restrict__ st, Ts
   const TsCol& S = st[c];
   if (!ts_pending(S) || S.scale == 0.0) return;
   const z_t iv = crecip(ts_dg(V.G, e >> V.G.ls, V.G.kc[2 * c], V.G.kc[2 * c + 1]));
-  z_t d = iv * ccast<double>(V.y[e]);
+  z_t y = ccast<double>(V.y[e]);
+  if (S.yp) y = y + S.eta * ccast<double>(V.d[e]);
+  z_t d = iv * y;
   X[e] = z_t{fma(S.scale, d.re, X[e].re), fma(S.scale, d.im, X[e].im)};
 }
 
@@ -3013,6 +3022,7 @@ __global__ void k_ts_true(int nblk, int s, TsCol* st, const double* __restrict__
   TsCol& S = st[c];
   const double b = sqrt(rr);
   S.beta_true = b;
+  S.yp = 0;        // k_ts_addx has applied any deferred x-update
   S.nan = S.nan || !isfinite(rr);
   S.done = (rr <= S.thr2) || S.fn2 == 0.0 || S.nan;
   if (S.done) return;
@@ -3081,6 +3091,9 @@ __global__ void k_ts_start_fin(int G_, int s, TsCol* st, const double* __restric
   S.tau = 1.0;                      // ||R / scale||
   S.theta = 0.0;
   S.eta = z_t{0.0, 0.0};
+  S.eta_o = z_t{0.0, 0.0};
+  S.ge = z_t{0.0, 0.0};
+  S.yp = 0;
   S.rho = z_t{1.0, 0.0};            // r*^H r0
   S.m = 0;
   S.chk = 1.0;
@@ -3122,9 +3135,10 @@ __device__ __forceinline__ void ts_qmr(TsCol& S, double ww) {
 // the even half-step writes D^-1 un into un (never copied back: the odd
 // half-step reads it and writes the next D^-1 u into u), the even product
 // writes uhe and the odd (or restart) product writes uh, so the odd
-// half-step's v needs no staging.
+// half-step's v needs no staging; d keeps the odd half-steps' d only (the
+// even half-step's is rebuilt from u where it is used).
 // even half-step, part 1: un = u - alpha v (stored as D^-1 un, the even
-// product's input; unused if the column stops); w -= alpha uh; d = u + g d;
+// product's input; unused if the column stops); w -= alpha uh;
 // partial ||w||^2
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ts_even1(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V,
@@ -3135,7 +3149,6 @@ __global__ void __launch_bounds__(kBlock) k_ts_even1(int64_t total, int s, const
   double ww = 0.0;
   if (!ts_off(S)) {
     const z_t a = S.alpha;
-    const z_t g = (S.theta * S.theta) * cdiv(S.eta, a);
     const double k = V.G.kc[2 * c], k2 = V.G.kc[2 * c + 1];
     for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
       const z_t dg = ts_dg(V.G, e >> V.G.ls, k, k2);
@@ -3143,7 +3156,6 @@ __global__ void __launch_bounds__(kBlock) k_ts_even1(int64_t total, int s, const
       V.un[e] = ccast<T>(crecip(dg) * (u - a * ccast<double>(V.v[e])));
       const cx<T> w = ccast<T>(ccast<double>(V.w[e]) - a * ccast<double>(V.uh[e]));
       V.w[e] = w;
-      V.d[e] = ccast<T>(u + g * ccast<double>(V.d[e]));
       ww += norm2(ccast<double>(w));
     }
   }
@@ -3161,12 +3173,18 @@ __global__ void k_ts_qmr_fin(int G_, int s, TsCol* st, const double* __restrict_
     return;
   }
   const double ww = sl_sum(G_, s, 1, part, c, 0, lds);
-  if (threadIdx.x == 0) ts_qmr(st[c], ww);
+  if (threadIdx.x != 0) return;
+  TsCol& S = st[c];
+  S.ge = (S.theta * S.theta) * cdiv(S.eta, S.alpha);   // the even half-step's d = u + ge d
+  S.eta_o = S.eta;                                      // the previous odd half-step's eta
+  ts_qmr(S, ww);
 }
 
-// odd half-step, part 1, with the even half-step's x-update folded in:
-// y += eta d (while the even half-step applies; eta, d of that half-step),
-// then (column running) w -= alpha uhe; d = un + g d; partials ||w||^2, r*^H w
+// odd half-step, part 1, with the x-updates of the previous odd half-step
+// and of the even half-step folded in (while the even half-step applies):
+// de = u + ge d (the even half-step's d; d holds the previous odd's);
+// y += eta_o d + eta de; then (column running) w -= alpha uhe;
+// d = un + g de; partials ||w||^2, r*^H w
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ts_odd1(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V,
                                                     double* __restrict__ part) {
@@ -3176,17 +3194,19 @@ __global__ void __launch_bounds__(kBlock) k_ts_odd1(int64_t total, int s, const 
   double q[3] = {0.0, 0.0, 0.0};
   const bool run = !ts_off(S);
   if (ts_apply(S)) {
-    const z_t eta = S.eta;
+    const z_t eta = S.eta, eta_o = S.eta_o, ge = S.ge;
     const z_t a = S.alpha;
     const z_t g = run ? (S.theta * S.theta) * cdiv(S.eta, a) : z_t{0.0, 0.0};
     const double k = V.G.kc[2 * c], k2 = V.G.kc[2 * c + 1];
     for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
-      const z_t dv = ccast<double>(V.d[e]);
-      V.y[e] = ccast<T>(ccast<double>(V.y[e]) + eta * dv);
+      const z_t dg = ts_dg(V.G, e >> V.G.ls, k, k2);
+      const z_t dold = ccast<double>(V.d[e]);
+      const z_t dv = dg * ccast<double>(V.u[e]) + ge * dold;
+      V.y[e] = ccast<T>(ccast<double>(V.y[e]) + (eta_o * dold + eta * dv));
       if (!run) continue;
       const cx<T> w = ccast<T>(ccast<double>(V.w[e]) - a * ccast<double>(V.uhe[e]));
       V.w[e] = w;
-      const z_t un = ts_dg(V.G, e >> V.G.ls, k, k2) * ccast<double>(V.un[e]);
+      const z_t un = dg * ccast<double>(V.un[e]);
       V.d[e] = ccast<T>(un + g * dv);
       const z_t wv = ccast<double>(w), r = ccast<double>(V.rs[e]);
       q[0] += norm2(wv);
@@ -3206,7 +3226,10 @@ __global__ void k_ts_odd_fin(int G_, int s, TsCol* st, const double* __restrict_
   const int off = ts_off(st[c]), idn = st[c].idone;
   __syncthreads();
   if (off) {
-    if (threadIdx.x == 0 && idn) st[c].last = 0;
+    if (threadIdx.x == 0 && idn) {
+      if (st[c].last) st[c].yp = 0;     // k_ts_odd1 applied the deferred x-update
+      st[c].last = 0;
+    }
     return;
   }
   const double ww = sl_sum(G_, s, 3, part, c, 0, lds);
@@ -3225,10 +3248,12 @@ __global__ void k_ts_odd_fin(int G_, int s, TsCol* st, const double* __restrict_
     S.beta = cdiv(rho1, S.rho);
     S.rho = rho1;
   }
+  S.yp = S.idone ? 0 : 1;   // a running column defers this half-step's x-update
 }
 
-// odd half-step, part 2: y += eta d; then u = w + beta un, stored as
-// D^-1 u = D^-1 w + beta (D^-1 un)
+// odd half-step, part 2: a column stopping here applies its x-update
+// y += eta d now; a running one defers it and forms u = w + beta un, stored
+// as D^-1 u = D^-1 w + beta (D^-1 un)
 template <typename T>
 __global__ void k_ts_odd2(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V) {
   int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
@@ -3236,8 +3261,10 @@ __global__ void k_ts_odd2(int64_t total, int s, const TsCol* __restrict__ st, Ts
   const int c = int(e & (s - 1));
   const TsCol& S = st[c];
   if (!ts_apply(S)) return;
-  V.y[e] = ccast<T>(ccast<double>(V.y[e]) + S.eta * ccast<double>(V.d[e]));
-  if (S.idone) return;
+  if (S.idone) {
+    V.y[e] = ccast<T>(ccast<double>(V.y[e]) + S.eta * ccast<double>(V.d[e]));
+    return;
+  }
   const z_t b = S.beta;
   const z_t iv = crecip(ts_dg(V.G, e >> V.G.ls, V.G.kc[2 * c], V.G.kc[2 * c + 1]));
   V.u[e] = ccast<T>(iv * ccast<double>(V.w[e]) + b * ccast<double>(V.un[e]));
