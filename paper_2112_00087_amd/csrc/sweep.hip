@@ -2960,6 +2960,13 @@ __device__ __forceinline__ z_t ts_dg(const TsDiag& G, int64_t row, double k, dou
   return z_t{r.x - k2 * r.y - k * r.w, k * r.z + (G.e ? k2 * G.e[row] : 0.0)};
 }
 
+// 1 / d as conj(d) / |d|^2: one division (a diagonal entry of these
+// operators is far from the range where |d|^2 over- or underflows)
+__device__ __forceinline__ z_t ts_inv(z_t d) {
+  const double q = 1.0 / fma(d.re, d.re, d.im * d.im);
+  return z_t{d.re * q, -d.im * q};
+}
+
 __global__ void k_ts_rowdiag(int64_t n, int64_t nrows, const int* __restrict__ dpos, const double* __restrict__ K,
                              const double* __restrict__ M, const double* __restrict__ E, const z_t* __restrict__ Bd,
                              double4* __restrict__ a, double* __restrict__ e) {
@@ -3004,7 +3011,7 @@ __global__ void k_ts_addx(int64_t total, int s, const TsCol* __restrict__ st, Ts
   const int c = int(e & (s - 1));
   const TsCol& S = st[c];
   if (!ts_pending(S) || S.scale == 0.0) return;
-  const z_t iv = crecip(ts_dg(V.G, e >> V.G.ls, V.G.kc[2 * c], V.G.kc[2 * c + 1]));
+  const z_t iv = ts_inv(ts_dg(V.G, e >> V.G.ls, V.G.kc[2 * c], V.G.kc[2 * c + 1]));
   z_t y = ccast<double>(V.y[e]);
   if (S.yp) y = y + S.eta * ccast<double>(V.d[e]);
   z_t d = iv * y;
@@ -3046,7 +3053,7 @@ __global__ void k_ts_start(int64_t total, int s, const TsCol* __restrict__ st, c
   if (!S.restart_now) return;
   const cx<T> r = ccast<T>((1.0 / S.scale) * R[e]);
   const cx<T> z = {T(0), T(0)};
-  const z_t iv = crecip(ts_dg(V.G, e >> V.G.ls, V.G.kc[2 * c], V.G.kc[2 * c + 1]));
+  const z_t iv = ts_inv(ts_dg(V.G, e >> V.G.ls, V.G.kc[2 * c], V.G.kc[2 * c + 1]));
   V.rs[e] = r;
   V.w[e] = r;
   V.u[e] = ccast<T>(iv * ccast<double>(r));
@@ -3153,7 +3160,7 @@ __global__ void __launch_bounds__(kBlock) k_ts_even1(int64_t total, int s, const
     for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += int64_t(gridDim.x) * kBlock) {
       const z_t dg = ts_dg(V.G, e >> V.G.ls, k, k2);
       const z_t u = dg * ccast<double>(V.u[e]);
-      V.un[e] = ccast<T>(crecip(dg) * (u - a * ccast<double>(V.v[e])));
+      V.un[e] = ccast<T>(ts_inv(dg) * (u - a * ccast<double>(V.v[e])));
       const cx<T> w = ccast<T>(ccast<double>(V.w[e]) - a * ccast<double>(V.uh[e]));
       V.w[e] = w;
       ww += norm2(ccast<double>(w));
@@ -3255,19 +3262,23 @@ __global__ void k_ts_odd_fin(int G_, int s, TsCol* st, const double* __restrict_
 // y += eta d now; a running one defers it and forms u = w + beta un, stored
 // as D^-1 u = D^-1 w + beta (D^-1 un)
 template <typename T>
-__global__ void k_ts_odd2(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V) {
-  int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (e >= total) return;
-  const int c = int(e & (s - 1));
+__global__ void __launch_bounds__(kBlock) k_ts_odd2(int64_t total, int s, const TsCol* __restrict__ st, TsVec<T> V) {
+  const int c = threadIdx.x & (s - 1);
   const TsCol& S = st[c];
   if (!ts_apply(S)) return;
+  const int64_t e0 = int64_t(blockIdx.x) * kBlock + threadIdx.x, stride = int64_t(gridDim.x) * kBlock;
   if (S.idone) {
-    V.y[e] = ccast<T>(ccast<double>(V.y[e]) + S.eta * ccast<double>(V.d[e]));
+    const z_t eta = S.eta;
+    for (int64_t e = e0; e < total; e += stride)
+      V.y[e] = ccast<T>(ccast<double>(V.y[e]) + eta * ccast<double>(V.d[e]));
     return;
   }
   const z_t b = S.beta;
-  const z_t iv = crecip(ts_dg(V.G, e >> V.G.ls, V.G.kc[2 * c], V.G.kc[2 * c + 1]));
-  V.u[e] = ccast<T>(iv * ccast<double>(V.w[e]) + b * ccast<double>(V.un[e]));
+  const double k = V.G.kc[2 * c], k2 = V.G.kc[2 * c + 1];
+  for (int64_t e = e0; e < total; e += stride) {
+    const z_t iv = ts_inv(ts_dg(V.G, e >> V.G.ls, k, k2));
+    V.u[e] = ccast<T>(iv * ccast<double>(V.w[e]) + b * ccast<double>(V.un[e]));
+  }
 }
 
 // odd half-step, part 3 (after uh = B u): v = uh + beta uhe + beta^2 v; partial r*^H v
@@ -3418,7 +3429,7 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
   HZ_TRY(autotune<T>(ctx, cs, nrows, s, AT, W.kc, W.V.u, W.V.uh, &W.vin));
 
   auto pairs_body = [&](hipStream_t q) -> int {
-    const int s_ = W.s, Gr = W.Gr, eb = ceil_div(W.total, kBlock);
+    const int s_ = W.s, Gr = W.Gr;
     const int64_t total = W.total;
     for (int it = 0; it < chunk; ++it) {
       k_ts_even1<T><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V, W.part);
@@ -3426,7 +3437,7 @@ int run_sweep_tfqmr(hz_ctx ctx, SweepData& D, int nf, const double* freqs, const
       HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.un, nullptr, W.V.uhe, nullptr, nullptr)));
       k_ts_odd1<T><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V, W.part);
       k_ts_odd_fin<<<s_, kBlock, 0, q>>>(Gr, s_, W.st, W.part);
-      k_ts_odd2<T><<<eb, kBlock, 0, q>>>(total, s_, W.st, W.V);
+      k_ts_odd2<T><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V);
       HZ_TRY((launch_spmm<T, false>(q, W.vin, nrows, s_, AT, W.kc, W.V.u, nullptr, W.V.uh, nullptr, nullptr)));
       k_ts_odd3<T><<<Gr, kBlock, 0, q>>>(total, s_, W.st, W.V, W.part);
       k_ts_alpha_fin<<<s_, kBlock, 0, q>>>(Gr, s_, W.st, W.part);
