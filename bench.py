@@ -207,9 +207,10 @@ def sweep_leg(log_fn, precisions=("fp64", "mixed"), method="tfqmr", ell=8):
     # once per column count a context meets, compaction included; graph
     # capture; allocations): one untimed pass of each batched sweep
     def mixed_opts(o):
-        # complex64 inner solves to 1e-5: of the inner tolerances 1e-2 .. 1e-7
-        # the only one with every TFQMR column converged, and the fastest;
-        # the cap bounds a column that stalls
+        # complex64 inner solves to 1e-5: the fastest of the inner tolerances
+        # 1e-3 .. 1e-6 (2.14, 1.68, 1.75, 1.16, 1.01, 1.08, 1.04 s for 1e-3,
+        # 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, each with every column
+        # converged); the cap bounds a column that stalls
         return dict(o, max_matvec=20000, inner_tol=1e-5)
 
     for prec in precisions:

@@ -59,6 +59,31 @@ def _model_in_form(P, mesh, beta, eta, form):
                 os.environ[k] = v
 
 
+@pytest.mark.parametrize("form", ["stencil", "split"])
+def test_spmv_full_vector_mid_size(P, form):
+    """80x48x40 box (162,729 rows: 636 blocks of 256 rows, past the 64
+    blocks at which the chunked XCD mapping of blocks to row ranges starts,
+    with a tail outside its whole rounds): every row of the product in both
+    box forms against the oracle's assembled operator, to the same entrywise
+    bound as the small meshes."""
+    say("spmv full vector 80x48x40", form)
+    wl = W.workload(1, elems=(80, 48, 40))
+    mesh = wl["mesh"]
+    S = H.System(mesh, wl["beta"], None)
+    model = _model_in_form(P, mesh, wl["beta"], None, form)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(mesh["n_nodes"]) + 1j * rng.standard_normal(mesh["n_nodes"])
+    for f in (0.0, 250.0):
+        A = S.operator(W.wavenumber(f))
+        model.set_frequency(f)
+        y = _np(model.apply(_t(x)))
+        yref = A @ x
+        bound = 1e-14 * (abs(A) @ np.abs(x)) + 1e-300
+        bad = np.flatnonzero(np.abs(y - yref) > bound)
+        assert bad.size == 0, (f, bad[:10], np.max(np.abs(y - yref) / bound))
+    model.close()
+
+
 @pytest.mark.parametrize("form", ["eta", "split", "stencil", "complex"])
 @pytest.mark.parametrize("elems", MESHES)
 def test_spmv_diag_load_parity(P, elems, form):
