@@ -417,6 +417,71 @@ __global__ void __launch_bounds__(PW * PH * kWave)
       if (ETA) evS[w][lane] = cur.ev;
       bvS[w][lane] = cur.bv;
     }
+    // pipelined reads where they measured faster: complex64, or two lines per
+    // wave (FP64 with one line per wave keeps 4 waves per SIMD without them)
+    if constexpr (LDS && (R > 1 || sizeof(T) == 4)) {
+      // LDS form: the matrix part of every row, also of rows outside the
+      // chunk (their pairs are zero and their sums are never written), one
+      // neighbour row's three pairs per group, two groups in flight: the
+      // reads of group j + 2 take their LDS address from an empty asm
+      // statement that consumes the sums after group j's FMAs, so group
+      // j + 1's reads run under group j's FMAs and the compiler can neither
+      // hoist all 27 pairs nor sink the FMAs below them.
+      int base = r * kStencil;
+      cx<T> kmg[2][3];
+      T evg[2][3];
+      auto ld = [&](int j, int b) {
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+          kmg[b][o] = kmS[w][base + 9 * o + j];
+          if (ETA) evg[b][o] = evS[w][base + 9 * o + j];
+        }
+      };
+      ld(0, 0);
+      ld(1, 1);
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        const int b = j & 1;
+        const cx<T> z = cur.zv[j];
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+          const T K = kmg[b][o].re, M = kmg[b][o].im;
+          if (DIFF) {
+            acc[o].re = fma(K, z.re - zc[o].re, acc[o].re);
+            acc[o].im = fma(K, z.im - zc[o].im, acc[o].im);
+            accM[o].re = fma(M, z.re, accM[o].re);
+            accM[o].im = fma(M, z.im, accM[o].im);
+          } else {
+            const T a = fma(-k2, M, K);   // K - k^2 M
+            acc[o].re = fma(a, z.re, acc[o].re);
+            acc[o].im = fma(a, z.im, acc[o].im);
+          }
+          if (ETA) {
+            accE[o].re = fma(evg[b][o], z.re, accE[o].re);
+            accE[o].im = fma(evg[b][o], z.im, accE[o].im);
+          }
+        }
+        if (j + 2 < 9) {
+          asm volatile(""
+                       : "+v"(base)
+                       : "v"(acc[0].re), "v"(acc[0].im), "v"(acc[1].re), "v"(acc[1].im), "v"(acc[2].re),
+                         "v"(acc[2].im), "v"(accM[0].re), "v"(accM[0].im), "v"(accM[1].re), "v"(accM[1].im),
+                         "v"(accM[2].re), "v"(accM[2].im), "v"(accE[0].re), "v"(accE[1].re), "v"(accE[2].re),
+                         "v"(accE[0].im), "v"(accE[1].im), "v"(accE[2].im));
+          ld(j + 2, b);
+        }
+      }
+      // boundary terms: rows on absorbing walls only
+#pragma unroll
+      for (int o = 0; o < 3; ++o) {
+        const int bi = bq[2 - o];
+        const bool v = o == 0 ? vn : (o == 1 ? vc : vp);
+        if (v && bi >= 0) {
+#pragma unroll
+          for (int j = 0; j < 9; ++j) cfma(accB[o], bvS[w][r * kStencil + 9 * o + j], cur.zv[j]);
+        }
+      }
+    } else {
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
       const cx<T> z = cur.zv[j];
@@ -453,6 +518,7 @@ __global__ void __launch_bounds__(PW * PH * kWave)
       if (vn) add(0, bq[2]);
       if (vc) add(1, bq[1]);
       if (vp) add(2, bq[0]);
+    }
     }
     if (vp) write_row(p - 1);
     acc[2] = acc[1];
